@@ -1,0 +1,134 @@
+/*
+ * FP64 CPU oracle for the treecode and fast multipole method of
+ * Yokota & Barba, "Treecode and fast multipole method for N-body simulation
+ * with CUDA".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the HIP path.  Only
+ * the tests, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it.  It shares no code, header, table or constant generator with the
+ * HIP library, and the HIP library never calls it.
+ *
+ * Conventions (all host memory, all FP64):
+ *  - Particles are SoA arrays x, y, z, m of length n, in the caller's order.
+ *  - Potential phi_i = sum_j m_j / |x_j - x_i| and acceleration
+ *    a_i = sum_j m_j (x_j - x_i) / |x_j - x_i|^3 (Eq. 1 per unit target mass,
+ *    with the sign of the single-pair kernel of Sec. 5.1); pairs at zero
+ *    separation are skipped; eps2 is added to r^2 as in Sec. 5.1.
+ *  - Expansion coefficients are complex, all orders m = -n..n stored, index
+ *    n*n + n + m, degrees n = 0..p-1 (p = number of terms, Eq. 4).  A complex
+ *    value is two doubles (re, im).
+ */
+#ifndef HFMM_ORACLE_H
+#define HFMM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- special functions (Eqs. 5-9) ---- */
+/* P[n*(nmax+1)+m] = P_n^m(x) for 0 <= m <= n <= nmax (Eqs. 7-9). */
+void oracle_legendre(int nmax, double x, double* P);
+/* Y[n*n+n+m] = Y_n^m(alpha, beta) for n <= nmax (Eq. 6), complex. */
+void oracle_ynm(int nmax, double alpha, double beta, double* Y);
+/* A_n^m of Eq. 5. */
+double oracle_anm(int n, int m);
+
+/* ---- single operators (Eqs. 2-4, translation theorems) ---- */
+void oracle_p2m(int p, const double c[3], int64_t n, const double* x,
+                const double* y, const double* z, const double* m, double* M);
+void oracle_p2l(int p, const double c[3], int64_t n, const double* x,
+                const double* y, const double* z, const double* m, double* L);
+void oracle_m2m(int p, const double c_child[3], const double c_parent[3],
+                const double* Mc, double* Mp /* accumulated */);
+void oracle_m2l(int p, const double c_src[3], const double c_tgt[3],
+                const double* M, double* L /* accumulated */);
+void oracle_l2l(int p, const double c_parent[3], const double c_child[3],
+                const double* Lp, double* Lc /* accumulated */);
+/* Evaluate at one point: out[0] = phi, out[1..3] = grad phi = acceleration. */
+void oracle_l2p(int p, const double c[3], const double* L, const double x[3],
+                double out[4]);
+void oracle_m2p(int p, const double c[3], const double* M, const double x[3],
+                double out[4]);
+
+/* ---- direct sum (Eq. 1) ---- */
+/* Targets are source indices tidx[0..nt) (all sources when tidx == NULL,
+ * nt == n). Summation over sources in ascending index order. */
+void oracle_direct(int64_t n, const double* x, const double* y,
+                   const double* z, const double* m, int64_t nt,
+                   const int64_t* tidx, double eps2, double* phi, double* ax,
+                   double* ay, double* az);
+/* Targets given by coordinates (any point; pairs at r == 0 skipped). */
+void oracle_direct_points(int64_t n, const double* x, const double* y,
+                          const double* z, const double* m, int64_t nt,
+                          const double* tx, const double* ty, const double* tz,
+                          double eps2, double* phi, double* ax, double* ay,
+                          double* az);
+
+/* ---- octree (Morton keys, adaptive split rule) ---- */
+typedef struct otree otree;
+otree* oracle_tree_build(int64_t n, const double* x, const double* y,
+                         const double* z, int leaf_max);
+void oracle_tree_free(otree* t);
+int64_t oracle_tree_ncells(const otree* t);
+int oracle_tree_depth(const otree* t);
+/* root[0..2] = lower corner b, root[3] = half width R */
+void oracle_tree_root(const otree* t, double root[4]);
+/* keys in the caller's order */
+void oracle_tree_keys(const otree* t, uint64_t* keys);
+/* perm[s] = caller index of the particle at sorted position s */
+void oracle_tree_perm(const otree* t, int64_t* perm);
+/* Cells in level order, Morton order within a level. */
+void oracle_tree_cells(const otree* t, int32_t* level, int32_t* ix,
+                       int32_t* iy, int32_t* iz, int64_t* first,
+                       int64_t* count, int32_t* parent, int32_t* first_child,
+                       int32_t* nchild);
+void oracle_tree_centres(const otree* t, double* cx, double* cy, double* cz,
+                         double* side);
+
+/* FMM lists U, V, W, X (which = 0..3). CSR: off[ncells+1], items[off[ncells]].
+ * Lists are computed on first request. */
+int64_t oracle_list_size(otree* t, int which);
+void oracle_list_get(otree* t, int which, int64_t* off, int32_t* items);
+/* Brute-force construction of the same lists straight from the definitions
+ * (quadratic in the number of cells; for small trees only). */
+int64_t oracle_list_size_bruteforce(otree* t, int which);
+void oracle_list_get_bruteforce(otree* t, int which, int64_t* off,
+                                int32_t* items);
+
+/* Barnes-Hut group lists for a target leaf: accepted cells (M2P, which = 0)
+ * and leaves interacted directly (P2P, which = 1).  Needs masses (caller
+ * order) for the centres of mass. CSR over all cells; non-leaves are empty. */
+int64_t oracle_bh_lists(otree* t, const double* m, double theta, int which,
+                        int64_t* off, int32_t* items);
+
+/* FP64 centre of mass of every cell (weights |m|; geometric centre if the
+ * cell's |m| sums to zero). */
+void oracle_tree_com(otree* t, const double* m, double* comx, double* comy,
+                     double* comz);
+
+/* ---- drivers ---- */
+/* All multipole (M) and local (L) expansions of the FMM for masses m
+ * (caller order); M and L hold ncells * p*p complex values. */
+int oracle_fmm_expansions(otree* t, const double* m, int p, double* M,
+                          double* L);
+/* Full FMM. Targets are caller indices tidx[0..nt) (all when tidx == NULL). */
+int oracle_fmm(int64_t n, const double* x, const double* y, const double* z,
+               const double* m, int leaf_max, int p, double eps2, int64_t nt,
+               const int64_t* tidx, double* phi, double* ax, double* ay,
+               double* az);
+/* Treecode. mode 0: group acceptance per target leaf; mode 1: per target
+ * particle. Expansions are centred at centres of mass. */
+int oracle_treecode(int64_t n, const double* x, const double* y,
+                    const double* z, const double* m, int leaf_max, int p,
+                    double theta, int mode, double eps2, int64_t nt,
+                    const int64_t* tidx, double* phi, double* ax, double* ay,
+                    double* az);
+
+/* Threads OpenMP will use (1 when built without OpenMP). */
+int oracle_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
