@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the FMM hot path on one MI355X.
+
+Workload: N = 1,048,576 particles uniform in the unit cube, masses 1/N,
+p = 10 expansion terms, leaves of at most 64 particles, FP32 far and near
+field (M2M/L2L in FP64).  One step = the whole path from device-resident
+FP64 inputs to device-resident outputs: tree build (bounding cube, keys,
+sort, cells), FMM lists, P2M, M2M, M2L, L2L, L2P, P2P and the scatter back
+to the caller's order.  The value is N / (time per step).
+
+Printed as one JSON line; see the keys below.  Only N = 1 GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp32_TFs": 157.3,   # FP32 vector (dual-issue/packed) and FP32 matrix
+    "fp64_TFs": 78.6,
+    "bf16_TFs": 2500.0,
+    "fp16_TFs": 2500.0,
+}
+P2P_FLOPS = 21  # per pair: the paper's 19 (Sec. 5.1) plus the potential
+
+
+def p2p_pairs(tree) -> int:
+    """sum over leaves of (targets in leaf) x (sources in its U list)."""
+    cells = tree.cells().cpu().numpy()
+    off, items = (a.cpu().numpy() for a in tree.fmm_list(0))
+    cnt = cells[:, 5].astype(np.int64)
+    cs = np.concatenate([[0], np.cumsum(cnt[items])])
+    src = cs[off[1:]] - cs[off[:-1]]
+    leaf = cells[:, 8] == 0
+    return int(np.sum(cnt[leaf] * src[leaf]))
+
+
+def cpu_baseline(p: int, leaf: int):
+    """The FP64 oracle FMM, as it stands, on a bounded sample of the workload."""
+    from oracle import oracle as O
+    from paper_1010_1482_amd import workloads as W
+    n = 16384  # 8^3 leaves of mean 32 particles: the 1M tree's leaf occupancy
+    x, y, z, m = W.uniform(n, 2)
+    t0 = time.perf_counter()
+    O.fmm(x, y, z, m, p, leaf)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "particles/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle FMM (FP64, Eq. 4 M2L as complex sums) on N={n} uniform "
+                      f"particles (mean 32 per leaf like the 1M workload), p={p}, "
+                      f"leaf<={leaf}, all targets; {dt:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--dist", default="uniform")
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--accuracy-targets", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1010_1482_amd import hfmm
+    from paper_1010_1482_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    n, p, leaf = args.n, args.p, args.leaf
+    prec = hfmm.PRECISIONS[args.precision]
+    x, y, z, m = W.make(args.dist, n, args.seed)
+    xd, yd, zd, md = (torch.from_numpy(a).to(dev) for a in (x, y, z, m))
+    dt = hfmm.out_dtype(prec)
+    out = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    arena = torch.empty(hfmm.arena_bytes(n, 0, leaf, p, hfmm.FMM, prec), dtype=torch.uint8,
+                        device=dev)
+    hfmm.set_timing(True)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        t = hfmm.Tree(xd, yd, zd, leaf_max=leaf, arena=arena)
+        t.upward(md, p, hfmm.FMM, prec)
+        t.evaluate(out=out)
+        return t
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat = []
+    phases = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = time.perf_counter()
+        tr = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+        phases.append(tr.stats()["phase_ms"])
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / args.steps * 1e3
+    stats = tr.stats()
+    ph = {k: float(np.mean([d[k] for d in phases])) for k in phases[-1]}
+
+    # dominant kernel and its roofline (algorithmic work per launch / its
+    # average device time over the timed steps)
+    pairs = p2p_pairs(tr)
+    m2l_pairs = stats["m2l_pairs"]
+    m2l_flops = 2.0 * p ** 4 * m2l_pairs
+    cand = {
+        "m2l": (ph.get("m2l", 0.0), m2l_flops, "mfma", PEAK["fp32_TFs"]),
+        "p2p": (ph.get("p2p", 0.0), P2P_FLOPS * pairs, "alu", PEAK["fp32_TFs"]),
+    }
+    dom = max(cand, key=lambda k: cand[k][0])
+    dms, dwork, dbound, dpeak = cand[dom]
+    ach = dwork / (dms * 1e-3) / 1e12
+    roof = {"bound": dbound, "achieved": ach, "peak": dpeak, "unit": "TFLOP/s",
+            "frac": ach / dpeak, "traffic": None, "kernel": dom,
+            "work_per_launch": dwork, "launch_ms": dms}
+
+    res = {
+        "metric": "particles/s, FMM N=1M at rel err<=1e-4 vs FP64; p50/p99 request latency",
+        "value": n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec != hfmm.FP64 else "f64", "data": "synthetic",
+        "config": {"workload": f"FMM N={n} {args.dist} unit cube, masses 1/N, p={p}, "
+                               f"leaf<={leaf}, {args.precision}",
+                   "n": n, "p": p, "leaf_max": leaf, "dist": args.dist,
+                   "precision": args.precision, "method": "fmm"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "phase_ms": ph,
+        "tree": {"cells": stats["n_cells"], "leaves": stats["n_leaves"],
+                 "depth": stats["depth"], "list_u": stats["list_u"],
+                 "list_v": stats["list_v"]},
+        "p2p_interactions_per_s": pairs / (ph.get("p2p", 1.0) * 1e-3),
+        "m2l_pairs_per_s": m2l_pairs / (ph.get("m2l", 1.0) * 1e-3),
+        "roofline": roof,
+    }
+
+    if not args.no_accuracy:
+        from oracle import oracle as O
+        tg = W.sample_targets(n, args.accuracy_targets, 100 + args.seed)
+        ref = O.direct(x, y, z, m, targets=tg)
+        got = [o.double().cpu().numpy()[tg] for o in out]
+        res["accuracy"] = {
+            "targets": len(tg), "reference": "FP64 oracle direct sum over all N",
+            "rel_l2_phi": O.rel_l2(got[0], ref[0]),
+            "rel_l2_acc": O.rel_l2(np.stack(got[1:]), np.stack(ref[1:]))}
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(p, leaf)
+    print(json.dumps(res), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

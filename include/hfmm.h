@@ -1,0 +1,203 @@
+/*
+ * hfmm: treecode and fast multipole method for the Laplace / gravitational
+ * N-body problem on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for every target particle i,
+ *     phi_i = sum_j m_j / r_ij          a_i = sum_j m_j (x_j - x_i) / r_ij^3
+ * (Eq. 1 of Yokota & Barba, "Treecode and fast multipole method for N-body
+ * simulation with CUDA", taken per unit target mass with the sign of the
+ * single-pair kernel of Sec. 5.1: a_i is the gradient of phi_i).  Pairs at
+ * zero separation are skipped; eps2 is added to r^2 as in Sec. 5.1.
+ *
+ * Methods (Sec. 2, Fig. flow_chart):
+ *   HFMM_DIRECT    all pairs (the P2P kernel of Sec. 5.1 over one source set)
+ *   HFMM_TREECODE  Barnes-Hut: P2M, M2M, M2P under the acceptance criterion
+ *                  l < theta * d of Sec. 4 (d from the cell's centre of mass to
+ *                  the target leaf), P2P for the rest
+ *   HFMM_FMM       P2M, M2M, M2L (Eq. 4), L2L, L2P and P2P over the adaptive
+ *                  U/V/W/X lists (Sec. 6 cites Cheng, Greengard and Rokhlin);
+ *                  on uniform data these are the 27-cell P2P and 189-cell M2L
+ *                  lists of Secs. 5.1 and 5.2
+ * p is the number of expansion terms: degrees n = 0..p-1 (Eq. 4).
+ *
+ * Memory and streams.  Every pointer argument named x, y, z, m, phi, ax, ay,
+ * az, arena or dst is a DEVICE pointer.  The caller allocates all device
+ * memory: inputs, outputs and one arena per tree; the library never
+ * allocates device memory.  Every call enqueues its work on `stream` (a
+ * hipStream_t passed as void*); build and evaluate also synchronise that
+ * stream for small size read-backs, other streams are never touched.  A tree
+ * handle is used by one stream at a time; different handles are independent
+ * and may run concurrently on different streams.
+ *
+ * Layouts.  Inputs are FP64 structure-of-arrays in the caller's order.
+ * Outputs are structure-of-arrays in the caller's order, FP64 when precision
+ * is HFMM_FP64 and FP32 otherwise.
+ *
+ * Errors.  Every function returns HFMM_OK (0) or a negative hfmm_status.  No
+ * function aborts or throws.  Argument errors are reported at the call;
+ * HFMM_E_NOMEM means the arena is too small and hfmm_required_bytes() then
+ * gives a size that is enough for the work done so far (retry with at least
+ * that much).  HIP runtime failures return HFMM_E_HIP.
+ */
+#ifndef HFMM_H
+#define HFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hfmm_tree_s* hfmm_tree;
+
+enum hfmm_method { HFMM_DIRECT = 0, HFMM_TREECODE = 1, HFMM_FMM = 2 };
+
+/* Arithmetic of the far field.  P2P, P2M, L2P, M2P run in FP32 for every
+ * precision but HFMM_FP64; M2M and L2L always run in FP64; the M2L variants
+ * differ only in the multipole-to-local product:
+ *   HFMM_FP32        FP32 matrix-core products
+ *   HFMM_M2L_BF16    BF16 operands, FP32 accumulation
+ *   HFMM_M2L_BF16X3  BF16 hi/lo split: hi*hi + hi*lo + lo*hi, FP32 accumulation
+ *   HFMM_M2L_FP16    FP16 operands (per-degree scaled), FP32 accumulation
+ *   HFMM_M2L_FP16X3  FP16 hi/lo split, FP32 accumulation
+ *   HFMM_FP64        everything in FP64 (outputs FP64)                      */
+enum hfmm_precision {
+    HFMM_FP64 = 0,
+    HFMM_FP32 = 1,
+    HFMM_M2L_BF16 = 2,
+    HFMM_M2L_BF16X3 = 3,
+    HFMM_M2L_FP16 = 4,
+    HFMM_M2L_FP16X3 = 5
+};
+
+enum hfmm_status {
+    HFMM_OK = 0,
+    HFMM_E_INVAL = -1,       /* bad argument (null pointer, n < 0, ...) */
+    HFMM_E_NOMEM = -2,       /* arena too small, see hfmm_required_bytes */
+    HFMM_E_UNSUPPORTED = -3, /* p outside [1, HFMM_MAX_P] or unknown mode */
+    HFMM_E_HIP = -4,         /* HIP runtime error */
+    HFMM_E_STATE = -5,       /* call order violated (e.g. evaluate before upward) */
+    HFMM_E_DATA = -6         /* non-finite coordinates */
+};
+
+#define HFMM_MAX_P 16
+#define HFMM_KEY_LEVELS 21   /* octree depth limit: 21 bits per axis */
+#define HFMM_PHASES 9
+
+/* Upper estimate of the arena bytes for one tree over n_src sources and
+ * n_tgt distinct targets (0 for self-evaluation) at order p.  Host only.  The
+ * estimate covers uniform and moderately clustered inputs; a tree that needs
+ * more returns HFMM_E_NOMEM. */
+int hfmm_arena_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p,
+                     int method, int precision, size_t* bytes);
+
+/* Build the octree (Sec. 3 "sort" and "other"): FP64 bounding cube and
+ * 63-bit Morton keys, radix sort, cells split while count > leaf_max (and
+ * level < 21).  Targets: tx == NULL evaluates at the sources themselves;
+ * otherwise the n_tgt target points are added to the tree as zero-mass
+ * particles.  The handle refers to the arena, which must stay alive and
+ * untouched until hfmm_tree_release. */
+int hfmm_build_tree(const double* x, const double* y, const double* z,
+                    int64_t n_src, const double* tx, const double* ty,
+                    const double* tz, int64_t n_tgt, int leaf_max, void* arena,
+                    size_t arena_bytes, void* stream, hfmm_tree* out);
+
+/* Upward pass: P2M at the leaves and M2M to the root (Sec. 2), FP64
+ * translation.  m holds the n_src source masses.  method selects the
+ * expansion centres: geometric cell centres (FMM) or centres of mass
+ * (treecode).  A later call with new masses replaces the expansions. */
+int hfmm_upward(hfmm_tree t, const double* m, int p, int method,
+                int precision, void* stream);
+
+/* Far and near field at the targets (Sec. 2): FMM (M2L, L2L, L2P, P2P) or
+ * treecode (M2P, P2P) with acceptance parameter theta.  p, method and
+ * precision must match the last hfmm_upward.  Outputs hold n_tgt values (or
+ * n_src for self-evaluation). */
+int hfmm_evaluate(hfmm_tree t, int p, double theta, int method, int precision,
+                  double eps2, void* phi, void* ax, void* ay, void* az,
+                  void* stream);
+
+/* build_tree + upward + evaluate in one call (self-evaluation when tx ==
+ * NULL).  The tree handle is released before returning. */
+int hfmm_solve(const double* x, const double* y, const double* z,
+               const double* m, int64_t n_src, const double* tx,
+               const double* ty, const double* tz, int64_t n_tgt, int leaf_max,
+               int p, double theta, int method, int precision, double eps2,
+               void* arena, size_t arena_bytes, void* phi, void* ax, void* ay,
+               void* az, void* stream);
+
+/* Direct sum of Eq. 1 (all pairs, P2P kernel of Sec. 5.1) over n sources at
+ * the n_tgt points (tx == NULL: at the sources).  precision HFMM_FP64 or
+ * HFMM_FP32.  Needs hfmm_direct_bytes() of arena. */
+int hfmm_direct_bytes(int64_t n_src, int64_t n_tgt, int precision,
+                      size_t* bytes);
+int hfmm_direct(const double* x, const double* y, const double* z,
+                const double* m, int64_t n_src, const double* tx,
+                const double* ty, const double* tz, int64_t n_tgt,
+                int precision, double eps2, void* arena, size_t arena_bytes,
+                void* phi, void* ax, void* ay, void* az, void* stream);
+
+/* Release the host handle (the arena belongs to the caller). */
+void hfmm_tree_release(hfmm_tree t);
+
+/* Arena bytes that would have sufficed for the failed call (after
+ * HFMM_E_NOMEM), or the bytes in use otherwise. */
+size_t hfmm_required_bytes(hfmm_tree t);
+/* same, for a failed build that returned no handle (per thread) */
+size_t hfmm_last_required_bytes(void);
+
+typedef struct {
+    int64_t n_particles;   /* sources + distinct targets in the tree */
+    int64_t n_cells;
+    int64_t n_leaves;
+    int32_t depth;         /* deepest level (root = 0) */
+    int32_t sort_bits;     /* key bits the radix sort ordered */
+    double root[4];        /* lower corner of the root cube and half width */
+    int64_t list_u, list_v, list_w, list_x;  /* FMM list entries */
+    int64_t list_m2p, list_p2p;              /* treecode list entries */
+    int64_t p2p_pairs;     /* particle pairs of the last P2P (incl. skipped) */
+    int64_t m2l_pairs;     /* cell pairs of the last M2L */
+    size_t arena_used;
+    /* device time of the phases of the last calls, in ms (-1 when not timed):
+     * 0 tree build, 1 FMM lists, 2 upward (P2M, M2M), 3 M2L operator tables,
+     * 4 M2L kernel, 5 downward (P2L, L2L), 6 far field (L2P, M2P),
+     * 7 P2P (+ output scatter), 8 treecode lists */
+    double phase_ms[HFMM_PHASES];
+} hfmm_stats;
+
+/* Turn per-phase device timers on or off for trees built afterwards
+ * (process-wide; HIP events recorded on the caller's stream around each
+ * phase).  Off by default. */
+void hfmm_set_timing(int on);
+
+int hfmm_get_stats(hfmm_tree t, hfmm_stats* s);
+
+const char* hfmm_strerror(int code);
+
+/* ---- inspection (tests and tools) ----
+ * All dst pointers are device pointers of the stated length; the copies are
+ * enqueued on `stream`.  Cells are in level order, Morton order within a
+ * level (root first). */
+/* perm[s] = caller index of the particle at sorted position s (n_particles;
+ * targets are numbered n_src + k). */
+int hfmm_export_perm(hfmm_tree t, int32_t* dst, void* stream);
+/* per cell: level, ix, iy, iz, first, count, parent, first_child, nchild
+ * (9 int32 per cell, cell-major) */
+int hfmm_export_cells(hfmm_tree t, int32_t* dst, void* stream);
+/* FMM list `which` (0 U, 1 V, 2 W, 3 X) as CSR: off (n_cells + 1 int32) and
+ * items (hfmm_stats.list_* int32), rows in cell order. */
+int hfmm_export_list(hfmm_tree t, int which, int32_t* off, int32_t* items,
+                     void* stream);
+/* Treecode lists (0 accepted/M2P, 1 P2P) per cell as CSR, like above. */
+int hfmm_export_bh_list(hfmm_tree t, int which, int32_t* off, int32_t* items,
+                        void* stream);
+/* Expansions in the paper's normalisation (Eqs. 2 and 3): which 0 = M
+ * (after hfmm_upward), 1 = L (after hfmm_evaluate with HFMM_FMM).  For every
+ * cell, n < p, m = 0..n: (Re, Im), i.e. p*(p+1) doubles per cell. */
+int hfmm_export_expansions(hfmm_tree t, int which, double* dst, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

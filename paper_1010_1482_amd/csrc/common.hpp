@@ -1,0 +1,339 @@
+// Shared definitions of the hfmm HIP library (gfx950).
+//
+// Internal expansion basis.  The device keeps expansions in the basis of the
+// Cartesian solid harmonics
+//     R_n^m(v) = r^n P_n^m(cos a) e^{i m b} / (n+m)!          (regular)
+//     S_n^m(v) = (n-m)! P_n^m(cos a) e^{i m b} / r^{n+1}       (irregular)
+// (P_n^m with the Condon-Shortley phase of Eq. 8).  In the paper's
+// normalisation (Eqs. 2, 3, 5, 6) r^n Y_n^m = R_n^m / A_n^m and
+// Y_n^m / r^{n+1} = A_n^m S_n^m for m >= 0 (the quantity tabulated for M2L in
+// Sec. 5.2 is S_n^m), so the device coefficients are
+//     Mb_n^m = A_n^m M_n^m = sum_j q_j conj(R_n^m(x_j - c))
+//     Lb_n^m = L_n^m / A_n^m = sum_j q_j conj(S_n^m(x_j - c))
+// and, per level, they are scaled by the cell side h:
+//     Mt_n = Mb_n / h^n,   Lt_n = Lb_n h^{n+1}.
+// In these variables every translation is independent of the level, P2M and
+// L2P work on (x - c)/h, and all magnitudes stay O(1).  Only m >= 0 is
+// stored: X_n^{-m} = (-1)^m conj(X_n^m).  Real layout per cell, degree by
+// degree: [Re X_n^0, Re X_n^1, Im X_n^1, ..., Re X_n^n, Im X_n^n], i.e. p*p
+// reals; index n*n for m = 0 and n*n + 2m - 1 (Re), n*n + 2m (Im) for m > 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <vector>
+
+#include "../../include/hfmm.h"
+
+#define HFMM_ALIGN 256
+
+namespace hfmm {
+
+// ---------------------------------------------------------------------
+// error handling
+// ---------------------------------------------------------------------
+struct HipError {
+    hipError_t e;
+};
+
+#define HIP_TRY(expr)                              \
+    do {                                           \
+        hipError_t _e = (expr);                    \
+        if (_e != hipSuccess) throw ::hfmm::HipError{_e}; \
+    } while (0)
+
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+struct Status {
+    int code;
+};
+
+// ---------------------------------------------------------------------
+// arena: persistent allocations grow upwards, per-call temporaries grow
+// downwards from the top and are released at the end of each call.
+// ---------------------------------------------------------------------
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, lo = 0, hi = 0;
+    size_t need = 0;  // bytes that would have sufficed (after a failure)
+
+    static size_t align(size_t b) { return (b + HFMM_ALIGN - 1) / HFMM_ALIGN * HFMM_ALIGN; }
+
+    void init(void* p, size_t bytes) {
+        base = (char*)p;
+        size_t skew = (HFMM_ALIGN - ((uintptr_t)base % HFMM_ALIGN)) % HFMM_ALIGN;
+        base += skew;
+        cap = bytes > skew ? (bytes - skew) / HFMM_ALIGN * HFMM_ALIGN : 0;
+        lo = 0;
+        hi = cap;
+        need = 0;
+    }
+    void fail(size_t bytes) {
+        size_t want = lo + align(bytes) + (cap - hi) + HFMM_ALIGN;
+        if (want > need) need = want;
+        throw Status{HFMM_E_NOMEM};
+    }
+    template <typename T>
+    T* up(size_t count) {
+        size_t b = align(count * sizeof(T) + 1);
+        if (lo + b > hi) fail(count * sizeof(T));
+        T* p = (T*)(base + lo);
+        lo += b;
+        return p;
+    }
+    template <typename T>
+    T* down(size_t count) {
+        size_t b = align(count * sizeof(T) + 1);
+        if (lo + b > hi) fail(count * sizeof(T));
+        hi -= b;
+        return (T*)(base + hi);
+    }
+    size_t free_bytes() const { return hi - lo; }
+    void release_temps() { hi = cap; }
+    size_t used() const { return lo + (cap - hi); }
+};
+
+// ---------------------------------------------------------------------
+// tree records
+// ---------------------------------------------------------------------
+struct Cell {
+    int32_t first, count;   // particle range in sorted order
+    int32_t parent, child;  // parent cell, first child (-1 for a leaf)
+    int32_t ix, iy, iz;     // integer coordinates at this level
+    int16_t level, nchild;
+};
+static_assert(sizeof(Cell) == 32, "Cell must be 32 bytes");
+
+struct Root {
+    double b[3];   // lower corner of the root cube
+    double R;      // half width
+    double scale;  // 2^21 / (2R)
+    double pad[3];
+};
+
+// per-call timing of the phases (host wall clock around synchronised steps
+// is not used; these are filled from hip events when enabled)
+struct Tree {
+    int device = 0;
+    int64_t n = 0, ns = 0, nt = 0;  // particles in tree, sources, targets
+    bool self = true;
+    int leaf_max = 64;
+    Arena arena;
+    Root root_h;
+    Root* root = nullptr;            // device copy
+    // particles, sorted
+    uint64_t* keys = nullptr;
+    int32_t* perm = nullptr;
+    double *xs = nullptr, *ys = nullptr, *zs = nullptr;
+    float4* p32 = nullptr;           // x, y, z, m (FP32)
+    double4* p64 = nullptr;          // x, y, z, m (FP64)
+    int32_t* leaf_of = nullptr;      // sorted particle -> leaf cell
+    int sort_bits = 0;
+    // cells
+    Cell* cells = nullptr;
+    int32_t ncells = 0, depth = 0;
+    std::vector<int32_t> level_start;  // host, depth + 2 entries
+    int32_t* leaves = nullptr;
+    int32_t nleaves = 0;
+    size_t mark_tree = 0;
+    // upward state
+    int up_p = 0, up_method = -1, up_prec = -1;
+    double* M = nullptr;             // [ncells][p*p] FP64 scaled R-basis
+    double* cen = nullptr;           // [ncells][4] expansion centre + side
+    void* Mk = nullptr;              // M2L operand copy [(ncells+1)][Kp]
+    size_t mark_up = 0;
+    // FMM lists (independent of p and masses)
+    bool fmm_lists = false;
+    int32_t* coll = nullptr;         // [ncells][27] colleagues, -1 padded
+    int32_t* vsrc = nullptr;         // [ncells][216] V list by slot, -1 empty
+    int32_t *u_off = nullptr, *u_items = nullptr;
+    int32_t *w_off = nullptr, *w_items = nullptr;
+    int32_t *x_off = nullptr, *x_items = nullptr;
+    int64_t n_u = 0, n_v = 0, n_w = 0, n_x = 0;
+    int32_t* m2l_order = nullptr;    // targets (level >= 2) by (level, octant)
+    int32_t* m2l_tiles = nullptr;    // per tile: start into m2l_order, count, octant
+    int32_t n_m2l_tiles = 0;
+    size_t mark_lists = 0;
+    // treecode lists
+    double bh_theta = -1.0;
+    int32_t *a_off = nullptr, *a_items = nullptr;   // accepted (M2P)
+    int32_t *b_off = nullptr, *b_items = nullptr;   // P2P
+    int64_t n_a = 0, n_b = 0;
+    // operator tables (per p and precision)
+    int ops_p = 0, ops_prec = -1;
+    void* T = nullptr;               // M2L matrices
+    size_t mark_ops = 0;
+    size_t mark_bh = 0;
+    // last evaluation
+    double* L = nullptr;             // [ncells][p*p] FP64 local expansions
+    int ev_p = 0;
+    int64_t p2p_pairs = 0, m2l_pairs = 0;
+    // phase timers (HIP events on the caller's stream)
+    bool timing = false;
+    hipEvent_t ev[2 * HFMM_PHASES] = {};
+    bool ev_used[HFMM_PHASES] = {};
+};
+
+enum Phase { PH_BUILD = 0, PH_LISTS, PH_UPWARD, PH_OPS, PH_M2L, PH_DOWN, PH_FAR, PH_P2P, PH_BH };
+
+// records an event pair around a scope when the tree is timed
+struct PhaseTimer {
+    Tree& t;
+    int ph;
+    hipStream_t s;
+    PhaseTimer(Tree& t_, int ph_, hipStream_t s_) : t(t_), ph(ph_), s(s_) {
+        if (t.timing) HIP_TRY(hipEventRecord(t.ev[2 * ph], s));
+    }
+    ~PhaseTimer() {
+        if (t.timing) {
+            if (hipEventRecord(t.ev[2 * ph + 1], s) == hipSuccess) t.ev_used[ph] = true;
+        }
+    }
+};
+
+// ---------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------
+__host__ __device__ constexpr int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+__host__ __device__ constexpr int ntri(int p) { return p * (p + 1) / 2; }
+__host__ __device__ constexpr int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// real-layout index of (n, m >= 0, part) with part 0 = Re, 1 = Im
+__host__ __device__ constexpr int ridx(int n, int m, int part) {
+    return m == 0 ? n * n : n * n + 2 * m - 1 + part;
+}
+
+// cell side and centre from the integer coordinates (FP64, no contraction so
+// that host and device agree bit for bit)
+#pragma clang fp contract(off)
+__host__ __device__ inline double cell_side(const Root& r, int level) {
+    return (2.0 * r.R) / (double)(1u << level);
+}
+__host__ __device__ inline void cell_centre(const Root& r, const Cell& c,
+                                            double out[3]) {
+    double h = cell_side(r, c.level);
+    out[0] = r.b[0] + ((double)c.ix + 0.5) * h;
+    out[1] = r.b[1] + ((double)c.iy + 0.5) * h;
+    out[2] = r.b[2] + ((double)c.iz + 0.5) * h;
+}
+#pragma clang fp contract(on)
+
+// closed boxes of two cells intersect (levels may differ)
+__device__ inline bool cells_adjacent(const Cell& a, const Cell& b) {
+    const Cell& A = a.level <= b.level ? a : b;
+    const Cell& B = a.level <= b.level ? b : a;
+    int64_t f = (int64_t)1 << (B.level - A.level);
+    int64_t ia[3] = {A.ix, A.iy, A.iz}, ib[3] = {B.ix, B.iy, B.iz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (ib[k] > (ia[k] + 1) * f) return false;
+        if (ib[k] + 1 < ia[k] * f) return false;
+    }
+    return true;
+}
+
+// Regular solid harmonics R_n^m(x, y, z), n < NP, m = 0..n (triangular).
+//   R_0^0 = 1,  R_m^m = -(x + i y) / (2m) R_{m-1}^{m-1},
+//   R_{n+1}^m = ((2n+1) z R_n^m - r^2 R_{n-1}^m) / ((n+1)^2 - m^2)
+template <typename T, int NP>
+__device__ inline void solid_regular(T x, T y, T z, T* re, T* im) {
+    const T r2 = x * x + y * y + z * z;
+    re[0] = T(1);
+    im[0] = T(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const int d = tri(m, m);
+        if (m > 0) {
+            const int s = tri(m - 1, m - 1);
+            const T c = T(-1) / T(2 * m);
+            re[d] = c * (x * re[s] - y * im[s]);
+            im[d] = c * (x * im[s] + y * re[s]);
+        }
+        if (m + 1 < NP) {
+            const int u = tri(m + 1, m);
+            const T c = T(2 * m + 1) / T((m + 1) * (m + 1) - m * m);
+            re[u] = c * z * re[d];
+            im[u] = c * z * im[d];
+        }
+#pragma unroll
+        for (int n = m + 1; n + 1 < NP; ++n) {
+            const int a = tri(n, m), b = tri(n - 1, m), u = tri(n + 1, m);
+            const T c = T(1) / T((n + 1) * (n + 1) - m * m);
+            re[u] = (T(2 * n + 1) * z * re[a] - r2 * re[b]) * c;
+            im[u] = (T(2 * n + 1) * z * im[a] - r2 * im[b]) * c;
+        }
+    }
+}
+
+// Irregular solid harmonics S_n^m(x, y, z), n < NP, m = 0..n.
+//   S_0^0 = 1/r,  S_m^m = -(2m-1)(x + i y)/r^2 S_{m-1}^{m-1},
+//   S_{n+1}^m = ((2n+1) z S_n^m - (n^2 - m^2) S_{n-1}^m) / r^2
+template <typename T, int NP>
+__device__ inline void solid_irregular(T x, T y, T z, T* re, T* im) {
+    const T r2 = x * x + y * y + z * z;
+    const T ir2 = T(1) / r2;
+    re[0] = sqrt(ir2);
+    im[0] = T(0);
+#pragma unroll
+    for (int m = 0; m < NP; ++m) {
+        const int d = tri(m, m);
+        if (m > 0) {
+            const int s = tri(m - 1, m - 1);
+            const T c = T(-(2 * m - 1)) * ir2;
+            re[d] = c * (x * re[s] - y * im[s]);
+            im[d] = c * (x * im[s] + y * re[s]);
+        }
+        if (m + 1 < NP) {
+            const int u = tri(m + 1, m);
+            const T c = T(2 * m + 1) * z * ir2;
+            re[u] = c * re[d];
+            im[u] = c * im[d];
+        }
+#pragma unroll
+        for (int n = m + 1; n + 1 < NP; ++n) {
+            const int a = tri(n, m), b = tri(n - 1, m), u = tri(n + 1, m);
+            re[u] = (T(2 * n + 1) * z * re[a] - T(n * n - m * m) * re[b]) * ir2;
+            im[u] = (T(2 * n + 1) * z * im[a] - T(n * n - m * m) * im[b]) * ir2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// host helpers (implemented in the .hip files)
+// ---------------------------------------------------------------------
+inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+// device-wide exclusive scan of int32 (returns nothing; total written to
+// out[n] when out has n+1 entries)
+void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, Arena& A,
+                        hipStream_t s);
+// stable radix sort of (key, value) pairs over bits [lo_bit, hi_bit)
+void radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int lo_bit,
+                      int hi_bit, Arena& A, hipStream_t s);
+
+void build_tree(Tree& t, const double* x, const double* y, const double* z,
+                const double* tx, const double* ty, const double* tz,
+                hipStream_t s);
+void build_fmm_lists(Tree& t, hipStream_t s);
+void build_bh_lists(Tree& t, double theta, hipStream_t s);
+void upward_pass(Tree& t, const double* m, int p, int method, int precision,
+                 hipStream_t s);
+void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi,
+                  void* ax, void* ay, void* az, hipStream_t s);
+void evaluate_treecode(Tree& t, int p, int precision, double eps2, void* phi,
+                       void* ax, void* ay, void* az, hipStream_t s);
+void direct_sum(const double* x, const double* y, const double* z,
+                const double* m, int64_t ns, const double* tx, const double* ty,
+                const double* tz, int64_t nt, int precision, double eps2,
+                Arena& A, void* phi, void* ax, void* ay, void* az,
+                hipStream_t s);
+
+// far-field and near-field kernels (launch wrappers)
+void launch_p2p(const Tree& t, int precision, double eps2, const int32_t* tgt_cells,
+                int32_t n_tgt_cells, const int32_t* src_off, const int32_t* src_items,
+                const void* far, void* phi, void* ax, void* ay, void* az,
+                hipStream_t s);
+
+}  // namespace hfmm

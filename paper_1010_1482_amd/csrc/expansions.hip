@@ -1,0 +1,841 @@
+// Expansion kernels: P2M, M2M, L2L, P2L, L2P and M2P (Sec. 2), the M2L
+// operator tables built from Eq. 4, and conversion to the paper's
+// normalisation for inspection.  See common.hpp for the basis.
+#include "common.hpp"
+#include "expansions.hpp"
+
+#include <algorithm>
+
+namespace hfmm {
+
+// ---------------------------------------------------------------------
+// streaming solid harmonics: f(n, m, re, im) for every n < ND, 0 <= m <= n,
+// column by column, so only a few values are live at a time
+// ---------------------------------------------------------------------
+template <typename T, int ND, typename F>
+__device__ __forceinline__ void stream_regular(T x, T y, T z, F&& f) {
+    const T r2 = x * x + y * y + z * z;
+    T dre = T(1), dim = T(0);
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        if (m > 0) {
+            const T c = T(-1) / T(2 * m);
+            T nr = c * (x * dre - y * dim);
+            T ni = c * (x * dim + y * dre);
+            dre = nr;
+            dim = ni;
+        }
+        f(m, m, dre, dim);
+        T pr = T(0), pi = T(0), cr = dre, ci = dim;
+#pragma unroll
+        for (int n = m; n + 1 < ND; ++n) {
+            const T c = T(1) / T((n + 1) * (n + 1) - m * m);
+            const T a = T(2 * n + 1) * z;
+            T nr = (a * cr - r2 * pr) * c;
+            T ni = (a * ci - r2 * pi) * c;
+            pr = cr;
+            pi = ci;
+            cr = nr;
+            ci = ni;
+            f(n + 1, m, cr, ci);
+        }
+    }
+}
+
+template <typename T, int ND, typename F>
+__device__ __forceinline__ void stream_irregular(T x, T y, T z, F&& f) {
+    const T r2 = x * x + y * y + z * z;
+    const T ir2 = T(1) / r2;
+    T dre = sqrt(ir2), dim = T(0);
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        if (m > 0) {
+            const T c = T(-(2 * m - 1)) * ir2;
+            T nr = c * (x * dre - y * dim);
+            T ni = c * (x * dim + y * dre);
+            dre = nr;
+            dim = ni;
+        }
+        f(m, m, dre, dim);
+        T pr = T(0), pi = T(0), cr = dre, ci = dim;
+#pragma unroll
+        for (int n = m; n + 1 < ND; ++n) {
+            const T a = T(2 * n + 1) * z;
+            const T b = T(n * n - m * m);
+            T nr = (a * cr - b * pr) * ir2;
+            T ni = (a * ci - b * pi) * ir2;
+            pr = cr;
+            pi = ci;
+            cr = nr;
+            ci = ni;
+            f(n + 1, m, cr, ci);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T cre(const double* X, int n, int m) {
+    return (T)X[ridx(n, m, 0)];
+}
+template <typename T>
+__device__ __forceinline__ T cim(const double* X, int n, int m) {
+    return m == 0 ? T(0) : (T)X[ridx(n, m, 1)];
+}
+
+// ---------------------------------------------------------------------
+// masses and centres
+// ---------------------------------------------------------------------
+__global__ void k_fill_masses(int64_t n, int64_t ns, const int32_t* __restrict__ perm,
+                              const double* __restrict__ m, const double* __restrict__ xs,
+                              const double* __restrict__ ys, const double* __restrict__ zs,
+                              float4* __restrict__ p32, double4* __restrict__ p64) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int64_t i = perm[s];
+    double q = i < ns ? m[i] : 0.0;
+    p32[s].w = (float)q;
+    p64[s] = make_double4(xs[s], ys[s], zs[s], q);
+}
+
+__global__ void k_centres_geometric(const Cell* __restrict__ cells, int nc,
+                                    const Root* __restrict__ root, double4* __restrict__ cen) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double o[3];
+    Cell cell = cells[c];
+    cell_centre(*root, cell, o);
+    cen[c] = make_double4(o[0], o[1], o[2], cell_side(*root, cell.level));
+}
+
+// centres of mass (weights |m|), leaves from particles and parents from
+// children, one level at a time (deepest first); w4 = (sum |m| x, y, z, |m|)
+__global__ void k_com_level(const Cell* __restrict__ cells, int c0, int c1,
+                            const double4* __restrict__ p64, const Root* __restrict__ root,
+                            double4* __restrict__ w4, double4* __restrict__ cen) {
+#pragma clang fp contract(off)
+    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    Cell cell = cells[c];
+    double sx = 0, sy = 0, sz = 0, sw = 0;
+    if (cell.nchild == 0) {
+        for (int s = cell.first; s < cell.first + cell.count; ++s) {
+            double4 q = p64[s];
+            double a = fabs(q.w);
+            sw += a;
+            sx += a * q.x;
+            sy += a * q.y;
+            sz += a * q.z;
+        }
+    } else {
+        for (int k = 0; k < cell.nchild; ++k) {
+            double4 q = w4[cell.child + k];
+            sx += q.x;
+            sy += q.y;
+            sz += q.z;
+            sw += q.w;
+        }
+    }
+    w4[c] = make_double4(sx, sy, sz, sw);
+    double h = cell_side(*root, cell.level);
+    if (sw > 0.0) {
+        cen[c] = make_double4(sx / sw, sy / sw, sz / sw, h);
+    } else {
+        double o[3];
+        cell_centre(*root, cell, o);
+        cen[c] = make_double4(o[0], o[1], o[2], h);
+    }
+}
+
+// ---------------------------------------------------------------------
+// shift tables: R_n^m(u) for the M2M / L2L vectors in units of the child
+// side, u = (c_child - c_parent) / h_child.  Octant table (geometric
+// centres): u = (ox - 1/2, oy - 1/2, oz - 1/2); per-child table (centres of
+// mass).  Stored as (re, im) pairs, triangular, FP64.
+// ---------------------------------------------------------------------
+template <int NP>
+__global__ void k_shift_octants(double2* __restrict__ tab) {
+    int o = threadIdx.x;
+    if (o >= 8) return;
+    double u[3] = {((o >> 2) & 1) - 0.5, ((o >> 1) & 1) - 0.5, (o & 1) - 0.5};
+    double2* out = tab + o * ntri(NP);
+    stream_regular<double, NP>(u[0], u[1], u[2], [&](int n, int m, double re, double im) {
+        out[tri(n, m)] = make_double2(re, im);
+    });
+}
+
+template <int NP>
+__global__ void k_shift_children(const Cell* __restrict__ cells, int nc,
+                                 const double4* __restrict__ cen, double2* __restrict__ tab) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    Cell cell = cells[c];
+    if (cell.parent < 0) return;
+    double4 a = cen[c], b = cen[cell.parent];
+    double ih = 1.0 / a.w;
+    double u[3] = {(a.x - b.x) * ih, (a.y - b.y) * ih, (a.z - b.z) * ih};
+    double2* out = tab + (int64_t)c * ntri(NP);
+    stream_regular<double, NP>(u[0], u[1], u[2], [&](int n, int m, double re, double im) {
+        out[tri(n, m)] = make_double2(re, im);
+    });
+}
+
+__device__ inline int octant_idx(const Cell& c) {
+    return ((c.ix & 1) << 2) | ((c.iy & 1) << 1) | (c.iz & 1);
+}
+
+// X_n^m of a stored m >= 0 triangle with X_n^{-m} = (-1)^m conj(X_n^m)
+__device__ inline double2 tri_get(const double2* X, int n, int m) {
+    if (m >= 0) return X[tri(n, m)];
+    double2 v = X[tri(n, -m)];
+    double s = (m & 1) ? -1.0 : 1.0;
+    return make_double2(s * v.x, -s * v.y);
+}
+__device__ inline double2 real_get(const double* X, int n, int m) {
+    int a = m < 0 ? -m : m;
+    double re = X[ridx(n, a, 0)], im = a == 0 ? 0.0 : X[ridx(n, a, 1)];
+    if (m >= 0) return make_double2(re, im);
+    double s = (a & 1) ? -1.0 : 1.0;
+    return make_double2(s * re, -s * im);
+}
+
+// ---------------------------------------------------------------------
+// P2M: Mt_n^m = sum_j q_j conj(R_n^m((x_j - c) / h)) (Eq. 2 in the device
+// basis).  G lanes per leaf, lanes stride over the leaf's particles, then a
+// butterfly reduction across the G lanes.
+// ---------------------------------------------------------------------
+template <typename T, int NP>
+__global__ void __launch_bounds__(256)
+k_p2m(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
+      const double4* __restrict__ cen, const double4* __restrict__ p64,
+      double* __restrict__ M) {
+    constexpr int G = 8, P = NP * NP;
+    const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int sub = threadIdx.x % G;
+    const bool active = gid < nleaves;
+    const int c = active ? leaves[gid] : 0;
+    T acc[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) acc[k] = T(0);
+    if (active) {
+        const Cell cell = cells[c];
+        const double4 q = cen[c];
+        const double ih = 1.0 / q.w;
+        for (int j = cell.first + sub; j < cell.first + cell.count; j += G) {
+            const double4 pj = p64[j];
+            const T ux = (T)((pj.x - q.x) * ih), uy = (T)((pj.y - q.y) * ih),
+                    uz = (T)((pj.z - q.z) * ih), mj = (T)pj.w;
+            stream_regular<T, NP>(ux, uy, uz, [&](int n, int m, T re, T im) {
+                acc[ridx(n, m, 0)] += mj * re;
+                if (m > 0) acc[ridx(n, m, 1)] -= mj * im;
+            });
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1)
+#pragma unroll
+        for (int k = 0; k < P; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
+    if (active && sub == 0) {
+        double* out = M + (int64_t)c * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) out[k] = (double)acc[k];
+    }
+}
+
+// ---------------------------------------------------------------------
+// M2M (FP64): Mt_p[n,m] = 2^-n sum_children sum_{k,l} conj(R_k^l(u))
+//                         Mt_c[n-k, m-l]
+// one thread per (parent, output (n, m >= 0))
+// ---------------------------------------------------------------------
+template <int NP>
+__global__ void k_m2m(const Cell* __restrict__ cells, int c0, int c1,
+                      const double2* __restrict__ shift, int per_child,
+                      double* __restrict__ M) {
+    constexpr int P = NP * NP, NT = ntri(NP);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = c0 + (int)(gid / NT);
+    if (c >= c1) return;
+    const int t = (int)(gid % NT);
+    int n = 0;
+    while (tri(n + 1, 0) <= t) ++n;
+    const int m = t - tri(n, 0);
+    const Cell cell = cells[c];
+    if (cell.nchild == 0) return;
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < cell.nchild; ++q) {
+        const int ch = cell.child + q;
+        const double2* R = per_child ? shift + (int64_t)ch * NT
+                                     : shift + octant_idx(cells[ch]) * NT;
+        const double* Mc = M + (int64_t)ch * P;
+        for (int k = 0; k <= n; ++k)
+            for (int l = -k; l <= k; ++l) {
+                const int mm = m - l;
+                if (mm > n - k || mm < -(n - k)) continue;
+                double2 r = tri_get(R, k, l);  // conj below
+                double2 x = real_get(Mc, n - k, mm);
+                sr += r.x * x.x + r.y * x.y;
+                si += r.x * x.y - r.y * x.x;
+            }
+    }
+    const double sc = ldexp(1.0, -n);
+    double* out = M + (int64_t)c * P;
+    out[ridx(n, m, 0)] = sr * sc;
+    if (m > 0) out[ridx(n, m, 1)] = si * sc;
+}
+
+// ---------------------------------------------------------------------
+// Downward pass at one level (FP64), one thread per (cell, output (j, i)):
+//   Lt_c = sum of the M2L partial results + P2L (X list, FP64)
+//          + L2L from the parent: sum_{n >= j} sum_m 2^-(n+1) Lt_p[n,m]
+//                                 R_{n-j}^{m-i}(u),  u = (c_c - c_p) / h_c
+// ---------------------------------------------------------------------
+template <int NP, typename TM>
+__global__ void k_downward(const Cell* __restrict__ cells, int c0, int c1,
+                           const TM* __restrict__ lm2l, int ldm, int nparts,
+                           int64_t part_stride, const double* __restrict__ lx,
+                           const double2* __restrict__ shift, int with_parent,
+                           double* __restrict__ L) {
+    constexpr int P = NP * NP, NT = ntri(NP);
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = c0 + (int)(gid / NT);
+    if (c >= c1) return;
+    const int t = (int)(gid % NT);
+    int j = 0;
+    while (tri(j + 1, 0) <= t) ++j;
+    const int i = t - tri(j, 0);
+    const Cell cell = cells[c];
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < nparts; ++q) {
+        const TM* src = lm2l + q * part_stride + (int64_t)c * ldm;
+        sr += (double)src[ridx(j, i, 0)];
+        if (i > 0) si += (double)src[ridx(j, i, 1)];
+    }
+    if (lx) {
+        sr += lx[(int64_t)c * P + ridx(j, i, 0)];
+        if (i > 0) si += lx[(int64_t)c * P + ridx(j, i, 1)];
+    }
+    if (with_parent && cell.parent >= 0) {
+        const double2* R = shift + octant_idx(cell) * NT;
+        const double* Lp = L + (int64_t)cell.parent * P;
+        for (int n = j; n < NP; ++n) {
+            const double sc = ldexp(1.0, -(n + 1));
+            double tr = 0.0, ti = 0.0;
+            for (int m = -n; m <= n; ++m) {
+                const int mi = m - i;
+                if (mi > n - j || mi < -(n - j)) continue;
+                double2 x = real_get(Lp, n, m);
+                double2 r = tri_get(R, n - j, mi);
+                tr += x.x * r.x - x.y * r.y;
+                ti += x.x * r.y + x.y * r.x;
+            }
+            sr += sc * tr;
+            si += sc * ti;
+        }
+    }
+    double* out = L + (int64_t)c * P;
+    out[ridx(j, i, 0)] = sr;
+    if (i > 0) out[ridx(j, i, 1)] = si;
+}
+
+// ---------------------------------------------------------------------
+// P2L for the X list (Eq. 3 in the device basis, FP64):
+//   Lt_n^m(B) += sum_j q_j conj(S_n^m((x_j - c_B) / h_B))
+// one 64-lane wave per target cell, lanes over the source particles
+// ---------------------------------------------------------------------
+template <int NP>
+__global__ void __launch_bounds__(64)
+k_p2l(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __restrict__ x_off,
+      const int32_t* __restrict__ x_items, const double4* __restrict__ cen,
+      const double4* __restrict__ p64, double* __restrict__ LX) {
+    constexpr int P = NP * NP;
+    const int b = c0 + blockIdx.x;
+    if (b >= c1) return;
+    const int lane = threadIdx.x;
+    double acc[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) acc[k] = 0.0;
+    const double4 q = cen[b];
+    const double ih = 1.0 / q.w;
+    for (int e = x_off[b]; e < x_off[b + 1]; ++e) {
+        const Cell src = cells[x_items[e]];
+        for (int s = src.first + lane; s < src.first + src.count; s += 64) {
+            const double4 pj = p64[s];
+            stream_irregular<double, NP>((pj.x - q.x) * ih, (pj.y - q.y) * ih, (pj.z - q.z) * ih,
+                                         [&](int n, int m, double re, double im) {
+                                             acc[ridx(n, m, 0)] += pj.w * re;
+                                             if (m > 0) acc[ridx(n, m, 1)] -= pj.w * im;
+                                         });
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1)
+#pragma unroll
+        for (int k = 0; k < P; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
+    if (lane == 0) {
+        double* out = LX + (int64_t)b * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) out[k] = acc[k];
+    }
+}
+
+// ---------------------------------------------------------------------
+// M2P of one expansion (Eq. 2 with its gradient) at u = (x - c) / h:
+//   phi = sum Mt S(u) / h,  grad phi from dS_n^m/dz = -S_{n+1}^m and
+//   (d/dx + i d/dy) S_n^m = S_{n+1}^{m+1}
+// ---------------------------------------------------------------------
+template <typename T, int NP>
+__device__ __forceinline__ void m2p_accumulate(const double* Mc, T ux, T uy, T uz, T ih,
+                                               T& phi, T& ax, T& ay, T& az) {
+    T f = T(0), dz = T(0), hr = T(0), hi = T(0);
+    stream_irregular<T, NP + 1>(ux, uy, uz, [&](int k, int l, T sr, T si) {
+        const T w = l == 0 ? T(1) : T(2);
+        if (k < NP) {
+            T mr = cre<T>(Mc, k, l), mi = cim<T>(Mc, k, l);
+            f += w * (mr * sr - mi * si);
+        }
+        if (k >= 1) {
+            if (l <= k - 1) {
+                T mr = cre<T>(Mc, k - 1, l), mi = cim<T>(Mc, k - 1, l);
+                dz -= w * (mr * sr - mi * si);
+            }
+            if (l >= 1) {
+                T mr = cre<T>(Mc, k - 1, l - 1), mi = cim<T>(Mc, k - 1, l - 1);
+                hr += mr * sr - mi * si;
+                hi += mr * si + mi * sr;
+            }
+            if (l + 1 <= k - 1) {
+                T mr = cre<T>(Mc, k - 1, l + 1), mi = cim<T>(Mc, k - 1, l + 1);
+                hr -= mr * sr - mi * si;
+                hi += mr * si + mi * sr;
+            }
+        }
+    });
+    const T ih2 = ih * ih;
+    phi += f * ih;
+    ax += hr * ih2;
+    ay += hi * ih2;
+    az += dz * ih2;
+}
+
+// Far field at every particle: L2P of its leaf (Eq. 3 with its gradient,
+// dR_n^m/dz = R_{n-1}^m, (d/dx + i d/dy) R_n^m = R_{n-1}^{m+1}) plus M2P over
+// the leaf's W list.  One thread per sorted particle.
+template <typename T, int NP>
+__global__ void __launch_bounds__(256)
+k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict__ cen,
+      const double4* __restrict__ p64, const double* __restrict__ L,
+      const int32_t* __restrict__ w_off, const int32_t* __restrict__ w_items,
+      const double* __restrict__ M, T* __restrict__ far) {
+    constexpr int P = NP * NP;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int b = leaf_of[s];
+    const double4 pj = p64[s];
+    const double4 q = cen[b];
+    const double ihd = 1.0 / q.w;
+    const T ux = (T)((pj.x - q.x) * ihd), uy = (T)((pj.y - q.y) * ihd),
+            uz = (T)((pj.z - q.z) * ihd);
+    const double* Lb = L + (int64_t)b * P;
+    T f = T(0), gz = T(0), gr = T(0), gi = T(0);
+    stream_regular<T, NP>(ux, uy, uz, [&](int k, int l, T rr, T ri) {
+        const T w = l == 0 ? T(1) : T(2);
+        {
+            T lr = cre<T>(Lb, k, l), li = cim<T>(Lb, k, l);
+            f += w * (lr * rr - li * ri);
+        }
+        if (k + 1 < NP) {
+            T ar = cre<T>(Lb, k + 1, l), ai = cim<T>(Lb, k + 1, l);
+            gz += w * (ar * rr - ai * ri);
+            if (l >= 1) {
+                T br = cre<T>(Lb, k + 1, l - 1), bi = cim<T>(Lb, k + 1, l - 1);
+                gr += br * rr - bi * ri;
+                gi += br * ri + bi * rr;
+            }
+            T cr = cre<T>(Lb, k + 1, l + 1), ci = cim<T>(Lb, k + 1, l + 1);
+            gr -= cr * rr - ci * ri;
+            gi += cr * ri + ci * rr;
+        }
+    });
+    const T ih = (T)ihd, ih2 = ih * ih;
+    T phi = f * ih, ax = gr * ih2, ay = gi * ih2, az = gz * ih2;
+    if (w_off) {
+        for (int e = w_off[b]; e < w_off[b + 1]; ++e) {
+            const int C = w_items[e];
+            const double4 qc = cen[C];
+            const double ic = 1.0 / qc.w;
+            m2p_accumulate<T, NP>(M + (int64_t)C * P, (T)((pj.x - qc.x) * ic),
+                                  (T)((pj.y - qc.y) * ic), (T)((pj.z - qc.z) * ic), (T)ic, phi,
+                                  ax, ay, az);
+        }
+    }
+    far[s] = phi;
+    far[n + s] = ax;
+    far[2 * n + s] = ay;
+    far[3 * n + s] = az;
+}
+
+// Treecode far field: M2P over the accepted list of the particle's leaf.
+template <typename T, int NP>
+__global__ void __launch_bounds__(256)
+k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
+               const double4* __restrict__ cen, const double4* __restrict__ p64,
+               const int32_t* __restrict__ a_off, const int32_t* __restrict__ a_items,
+               const double* __restrict__ M, T* __restrict__ far) {
+    constexpr int P = NP * NP;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int b = leaf_of[s];
+    const double4 pj = p64[s];
+    T phi = T(0), ax = T(0), ay = T(0), az = T(0);
+    for (int e = a_off[b]; e < a_off[b + 1]; ++e) {
+        const int C = a_items[e];
+        const double4 qc = cen[C];
+        const double ic = 1.0 / qc.w;
+        m2p_accumulate<T, NP>(M + (int64_t)C * P, (T)((pj.x - qc.x) * ic),
+                              (T)((pj.y - qc.y) * ic), (T)((pj.z - qc.z) * ic), (T)ic, phi, ax,
+                              ay, az);
+    }
+    far[s] = phi;
+    far[n + s] = ax;
+    far[2 * n + s] = ay;
+    far[3 * n + s] = az;
+}
+
+// ---------------------------------------------------------------------
+// M2L operator of one offset class from Eq. 4.  With the identity of Sec. 5.2,
+// Y_N^M / (A_N^M rho^{N+1}) = (N-|M|)! P_N^|M|(cos a) e^{iM b} / rho^{N+1},
+// and the change to the device basis (Lb = L / A_j^k, Mb = A_n^m M), the
+// factors A_n^m A_j^k of Eq. 4 cancel and the complex coefficient of
+// M_n^m in L_j^k becomes
+//   c(j,k,n,m) = i^{|k-m|-|k|-|m|} (-1)^j (N-|M|)! P_N^|M| e^{iM b} / rho^{N+1}
+// with N = j + n, M = m - k, (rho, a, b) the spherical coordinates of
+// c_target - c_source in cell units (offsets are source minus target, so the
+// vector is -d).  Conjugate symmetry of M folds m and -m into real entries.
+// ---------------------------------------------------------------------
+__device__ inline double factorial_d(int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= (double)i;
+    return f;
+}
+
+// (N-|M|)! P_N^|M|(x) / rho^{N+1} with e^{i M beta}: returns (re, im)
+__device__ inline double2 m2l_kernel_coeff(int N, int M, double x, double s, double rho,
+                                           double beta) {
+    const int a = M < 0 ? -M : M;
+    // P_a^a = (-1)^a (2a-1)!! s^a (Eq. 8), then Eqs. 9 and 7 up to degree N
+    double pmm = 1.0;
+    for (int i = 1; i <= a; ++i) pmm *= -(double)(2 * i - 1) * s;
+    double pn = pmm;
+    if (N > a) {
+        double p1 = pmm, p0 = 0.0, p = x * (2 * a + 1) * pmm;
+        for (int nn = a + 1; nn < N; ++nn) {
+            double pn1 = (x * (2 * nn + 1) * p - (nn + a) * p1) / (double)(nn - a + 1);
+            p1 = p;
+            p = pn1;
+        }
+        (void)p0;
+        pn = p;
+    }
+    double v = factorial_d(N - a) * pn;
+    double r = 1.0;
+    for (int i = 0; i <= N; ++i) r *= rho;
+    v /= r;
+    return make_double2(v * cos(M * beta), v * sin(M * beta));
+}
+
+__device__ inline double ipow_even_sign(int e) {  // i^e for even e
+    return ((e / 2) & 1) ? -1.0 : 1.0;
+}
+
+__device__ inline double2 m2l_c(int j, int k, int n, int m, double x, double s, double rho,
+                                double beta) {
+    const int ak = k < 0 ? -k : k, am = m < 0 ? -m : m;
+    const int e = abs(k - m) - ak - am;
+    double sg = ipow_even_sign(e) * ((j & 1) ? -1.0 : 1.0);
+    double2 y = m2l_kernel_coeff(j + n, m - k, x, s, rho, beta);
+    return make_double2(sg * y.x, sg * y.y);
+}
+
+// real-layout index -> (n, m, part)
+__device__ inline void rdecode(int r, int& n, int& m, int& part) {
+    n = 0;
+    while ((n + 1) * (n + 1) <= r) ++n;
+    int o = r - n * n;
+    if (o == 0) {
+        m = 0;
+        part = 0;
+    } else {
+        m = (o + 1) / 2;
+        part = (o + 1) % 2;
+    }
+}
+
+// one thread per (class, output row ro, input column ri); writes FP64
+// T64[cls][ri][ro] (column-major per class, for the FP64 kernel) and/or the
+// FP32 matrix-core layout Tsw[cls][rb][q][lane][4] with
+// T[16 rb + (lane & 15)][16 q + 4 (lane >> 4) + r]
+__global__ void k_m2l_ops(int p, double* __restrict__ T64, float* __restrict__ T32,
+                          int RB, int KQ) {
+    const int P = p * p;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)P * P;
+    const int cls = (int)(gid / per);
+    if (cls >= 343) return;
+    const int rem = (int)(gid % per);
+    const int ro = rem / P, ri = rem % P;
+    const int dx = cls / 49 - 3, dy = (cls / 7) % 7 - 3, dz = cls % 7 - 3;
+    double val = 0.0;
+    if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) {
+        const double vx = -dx, vy = -dy, vz = -dz;
+        const double rxy = sqrt(vx * vx + vy * vy);
+        const double rho = sqrt(vx * vx + vy * vy + vz * vz);
+        const double x = vz / rho, s = rxy / rho;
+        const double beta = (vx == 0.0 && vy == 0.0) ? 0.0 : atan2(vy, vx);
+        int j, k, po, n, m, pi;
+        rdecode(ro, j, k, po);
+        rdecode(ri, n, m, pi);
+        if (m == 0) {
+            double2 c0 = m2l_c(j, k, n, 0, x, s, rho, beta);
+            val = pi == 0 ? (po == 0 ? c0.x : c0.y) : 0.0;
+        } else {
+            double2 cp = m2l_c(j, k, n, m, x, s, rho, beta);
+            double2 cm = m2l_c(j, k, n, -m, x, s, rho, beta);
+            if (po == 0)
+                val = pi == 0 ? cp.x + cm.x : -(cp.y - cm.y);
+            else
+                val = pi == 0 ? cp.y + cm.y : cp.x - cm.x;
+        }
+    }
+    if (T64) T64[(int64_t)cls * per + (int64_t)ri * P + ro] = val;
+    if (T32) {
+        const int rb = ro / 16, il = ro % 16;
+        const int q = ri / 16, g = (ri % 16) / 4, r = ri % 4;
+        const int lane = g * 16 + il;
+        T32[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 4 + r] = (float)val;
+    }
+}
+
+// pack Mt (FP64, p*p per cell) into the M2L operand: ld = Kp (zero padded),
+// one extra zero row at index ncells for absent sources
+template <typename TO>
+__global__ void k_pack(const double* __restrict__ M, int ncells, int P, int ld,
+                       TO* __restrict__ out) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)(ncells + 1) * ld;
+    if (gid >= tot) return;
+    const int c = (int)(gid / ld), k = (int)(gid % ld);
+    double v = (c < ncells && k < P) ? M[(int64_t)c * P + k] : 0.0;
+    out[gid] = (TO)v;
+}
+
+// device basis -> the paper's normalisation:
+//   M_n^m = h^n Mt_n^m / A_n^m,  L_n^m = A_n^m Lt_n^m / h^{n+1}
+__global__ void k_export(const double* __restrict__ X, int ncells, int p,
+                         const double4* __restrict__ cen, int which,
+                         double* __restrict__ out) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int NT = p * (p + 1) / 2;
+    if (gid >= (int64_t)ncells * NT) return;
+    const int c = (int)(gid / NT), t = (int)(gid % NT);
+    int n = 0;
+    while ((n + 1) * (n + 2) / 2 <= t) ++n;
+    const int m = t - n * (n + 1) / 2;
+    const double h = cen[c].w;
+    const double A = 1.0 / sqrt(factorial_d(n - m) * factorial_d(n + m));
+    double hn = 1.0;
+    for (int i = 0; i < n; ++i) hn *= h;
+    const double f = which == 0 ? hn / A : A / (hn * h);
+    const double* Xc = X + (int64_t)c * p * p;
+    out[gid * 2] = f * Xc[ridx(n, m, 0)];
+    out[gid * 2 + 1] = m == 0 ? 0.0 : f * Xc[ridx(n, m, 1)];
+}
+
+// ---------------------------------------------------------------------
+// dispatch over p
+// ---------------------------------------------------------------------
+#define HFMM_DISPATCH_P(p, F)  \
+    switch (p) {               \
+        case 1: F(1); break;   \
+        case 2: F(2); break;   \
+        case 3: F(3); break;   \
+        case 4: F(4); break;   \
+        case 5: F(5); break;   \
+        case 6: F(6); break;   \
+        case 7: F(7); break;   \
+        case 8: F(8); break;   \
+        case 9: F(9); break;   \
+        case 10: F(10); break; \
+        case 11: F(11); break; \
+        case 12: F(12); break; \
+        case 13: F(13); break; \
+        case 14: F(14); break; \
+        case 15: F(15); break; \
+        case 16: F(16); break; \
+        default: throw Status{HFMM_E_UNSUPPORTED}; \
+    }
+
+void fill_masses(Tree& t, const double* m, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_masses, dim3(grid_for(t.n, 256)), dim3(256), 0, s, t.n, t.ns,
+                       t.perm, m, t.xs, t.ys, t.zs, t.p32, t.p64);
+    LAUNCH_CHECK();
+}
+
+void compute_centres(Tree& t, int method, hipStream_t s) {
+    double4* cen = (double4*)t.cen;
+    if (method == HFMM_TREECODE) {
+        double4* w4 = t.arena.down<double4>(t.ncells);
+        for (int l = t.depth; l >= 0; --l) {
+            int c0 = t.level_start[l], c1 = t.level_start[l + 1];
+            hipLaunchKernelGGL(k_com_level, dim3(grid_for(c1 - c0, 128)), dim3(128), 0, s,
+                               t.cells, c0, c1, t.p64, t.root, w4, cen);
+            LAUNCH_CHECK();
+        }
+    } else {
+        hipLaunchKernelGGL(k_centres_geometric, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
+                           t.cells, t.ncells, t.root, cen);
+        LAUNCH_CHECK();
+    }
+}
+
+void run_p2m(Tree& t, int p, bool fp64, hipStream_t s) {
+    const int threads = t.nleaves * 8;
+#define P2M_CASE(NP)                                                                       \
+    if (fp64)                                                                              \
+        hipLaunchKernelGGL((k_p2m<double, NP>), dim3(grid_for(threads, 256)), dim3(256), 0, \
+                           s, t.cells, t.leaves, t.nleaves, (const double4*)t.cen, t.p64,   \
+                           t.M);                                                            \
+    else                                                                                    \
+        hipLaunchKernelGGL((k_p2m<float, NP>), dim3(grid_for(threads, 256)), dim3(256), 0,  \
+                           s, t.cells, t.leaves, t.nleaves, (const double4*)t.cen, t.p64,   \
+                           t.M);
+    HFMM_DISPATCH_P(p, P2M_CASE);
+#undef P2M_CASE
+    LAUNCH_CHECK();
+}
+
+void run_m2m(Tree& t, int p, bool per_child, hipStream_t s) {
+    const int NT = p * (p + 1) / 2;
+    double2* tab;
+    if (per_child) {
+        tab = t.arena.down<double2>((size_t)t.ncells * NT);
+#define SH_CASE(NP)                                                                           \
+    hipLaunchKernelGGL((k_shift_children<NP>), dim3(grid_for(t.ncells, 128)), dim3(128), 0, s, \
+                       t.cells, t.ncells, (const double4*)t.cen, tab);
+        HFMM_DISPATCH_P(p, SH_CASE);
+#undef SH_CASE
+    } else {
+        tab = t.arena.down<double2>((size_t)8 * NT);
+#define SH_CASE(NP) hipLaunchKernelGGL((k_shift_octants<NP>), dim3(1), dim3(64), 0, s, tab);
+        HFMM_DISPATCH_P(p, SH_CASE);
+#undef SH_CASE
+    }
+    LAUNCH_CHECK();
+    for (int l = t.depth - 1; l >= 0; --l) {
+        int c0 = t.level_start[l], c1 = t.level_start[l + 1];
+        int64_t threads = (int64_t)(c1 - c0) * NT;
+#define M2M_CASE(NP)                                                                     \
+    hipLaunchKernelGGL((k_m2m<NP>), dim3(grid_for(threads, 128)), dim3(128), 0, s, t.cells, \
+                       c0, c1, tab, per_child ? 1 : 0, t.M);
+        HFMM_DISPATCH_P(p, M2M_CASE);
+#undef M2M_CASE
+        LAUNCH_CHECK();
+    }
+}
+
+void run_m2l_ops(Tree& t, int p, bool fp64, double* T64, float* T32, int RB, int KQ,
+                 hipStream_t s) {
+    const int64_t threads = (int64_t)343 * p * p * p * p;
+    hipLaunchKernelGGL(k_m2l_ops, dim3(grid_for(threads, 256)), dim3(256), 0, s, p,
+                       fp64 ? T64 : nullptr, fp64 ? nullptr : T32, RB, KQ);
+    LAUNCH_CHECK();
+}
+
+void run_pack(const double* M, int ncells, int P, int ld, void* out, bool fp64,
+              hipStream_t s) {
+    const int64_t tot = (int64_t)(ncells + 1) * ld;
+    if (fp64)
+        hipLaunchKernelGGL((k_pack<double>), dim3(grid_for(tot, 256)), dim3(256), 0, s, M,
+                           ncells, P, ld, (double*)out);
+    else
+        hipLaunchKernelGGL((k_pack<float>), dim3(grid_for(tot, 256)), dim3(256), 0, s, M,
+                           ncells, P, ld, (float*)out);
+    LAUNCH_CHECK();
+}
+
+void run_p2l(Tree& t, int p, double* LX, hipStream_t s) {
+    if (t.n_x == 0 || t.depth < 2) return;
+    int c0 = t.level_start[2], c1 = t.ncells;
+#define P2L_CASE(NP)                                                                        \
+    hipLaunchKernelGGL((k_p2l<NP>), dim3(c1 - c0), dim3(64), 0, s, t.cells, c0, c1, t.x_off, \
+                       t.x_items, (const double4*)t.cen, t.p64, LX);
+    HFMM_DISPATCH_P(p, P2L_CASE);
+#undef P2L_CASE
+    LAUNCH_CHECK();
+}
+
+void run_downward(Tree& t, int p, const void* lm2l, bool m2l_fp64, int ldm, int nparts,
+                  int64_t part_stride, const double* LX, hipStream_t s) {
+    const int NT = p * (p + 1) / 2;
+    double2* tab = t.arena.down<double2>((size_t)8 * NT);
+#define SH_CASE(NP) hipLaunchKernelGGL((k_shift_octants<NP>), dim3(1), dim3(64), 0, s, tab);
+    HFMM_DISPATCH_P(p, SH_CASE);
+#undef SH_CASE
+    LAUNCH_CHECK();
+    for (int l = 2; l <= t.depth; ++l) {
+        int c0 = t.level_start[l], c1 = t.level_start[l + 1];
+        int64_t threads = (int64_t)(c1 - c0) * NT;
+        int wp = l >= 3 ? 1 : 0;
+#define DW_CASE(NP)                                                                           \
+    if (m2l_fp64)                                                                             \
+        hipLaunchKernelGGL((k_downward<NP, double>), dim3(grid_for(threads, 128)), dim3(128),  \
+                           0, s, t.cells, c0, c1, (const double*)lm2l, ldm, nparts,            \
+                           part_stride, LX, tab, wp, t.L);                                     \
+    else                                                                                       \
+        hipLaunchKernelGGL((k_downward<NP, float>), dim3(grid_for(threads, 128)), dim3(128),   \
+                           0, s, t.cells, c0, c1, (const float*)lm2l, ldm, nparts,             \
+                           part_stride, LX, tab, wp, t.L);
+        HFMM_DISPATCH_P(p, DW_CASE);
+#undef DW_CASE
+        LAUNCH_CHECK();
+    }
+}
+
+void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
+    const bool w = t.n_w > 0;
+#define FAR_CASE(NP)                                                                       \
+    if (fp64)                                                                              \
+        hipLaunchKernelGGL((k_far<double, NP>), dim3(grid_for(t.n, 256)), dim3(256), 0, s,  \
+                           t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,               \
+                           w ? t.w_off : nullptr, t.w_items, t.M, (double*)far);            \
+    else                                                                                    \
+        hipLaunchKernelGGL((k_far<float, NP>), dim3(grid_for(t.n, 256)), dim3(256), 0, s,   \
+                           t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,               \
+                           w ? t.w_off : nullptr, t.w_items, t.M, (float*)far);
+    HFMM_DISPATCH_P(p, FAR_CASE);
+#undef FAR_CASE
+    LAUNCH_CHECK();
+}
+
+void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
+#define TF_CASE(NP)                                                                          \
+    if (fp64)                                                                                \
+        hipLaunchKernelGGL((k_treecode_far<double, NP>), dim3(grid_for(t.n, 256)), dim3(256), \
+                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,       \
+                           t.a_items, t.M, (double*)far);                                     \
+    else                                                                                      \
+        hipLaunchKernelGGL((k_treecode_far<float, NP>), dim3(grid_for(t.n, 256)), dim3(256),  \
+                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,       \
+                           t.a_items, t.M, (float*)far);
+    HFMM_DISPATCH_P(p, TF_CASE);
+#undef TF_CASE
+    LAUNCH_CHECK();
+}
+
+void run_export(const double* X, int ncells, int p, const double* cen, int which,
+                double* out, hipStream_t s) {
+    const int64_t tot = (int64_t)ncells * p * (p + 1) / 2;
+    hipLaunchKernelGGL(k_export, dim3(grid_for(tot, 256)), dim3(256), 0, s, X, ncells, p,
+                       (const double4*)cen, which, out);
+    LAUNCH_CHECK();
+}
+
+}  // namespace hfmm

@@ -1,0 +1,413 @@
+// Interaction lists on the device.
+//
+// FMM lists follow the adaptive scheme the paper cites (Cheng, Greengard and
+// Rokhlin; Sec. 6):
+//   colleagues(B)  same-level cells adjacent to B (B included): the children
+//                  of colleagues(parent(B)) adjacent to B;
+//   V(B)           children of colleagues(parent(B)) not adjacent to B (M2L);
+//   U(B leaf)      leaves adjacent to B, B included (P2P);
+//   W(B leaf)      descendants C of colleagues of B, C not adjacent to B but
+//                  parent(C) adjacent to B (M2P);
+//   X(B)           leaves C coarser than B, adjacent to parent(B) and not to
+//                  B, i.e. the cells with B in W(C) (P2L).
+// On a uniform tree these are the 27-cell P2P list of Sec. 5.1 and the
+// 189-cell M2L list of Sec. 5.2.  V is stored densely by offset slot: a
+// target in octant o of its parent sees its V cells at integer offsets
+// d in [-2-o, 3-o]^3 (per axis), 6^3 = 216 slots of which the 27 adjacent
+// ones stay empty, so slot -> offset class is the same for all targets of one
+// octant; the M2L kernel batches targets of one octant.
+//
+// Treecode lists follow the Barnes-Hut acceptance of Sec. 4 per target leaf:
+// a cell C is accepted when l_C < theta * d, d being the distance from C's
+// centre of mass to the target leaf's closed box; C is never accepted when it
+// contains the target leaf; a leaf that fails goes to P2P.
+#include "common.hpp"
+
+#include <algorithm>
+
+namespace hfmm {
+
+constexpr int kColl = 27;
+constexpr int kSlots = 216;
+
+__device__ inline int octant_of(const Cell& c) {
+    return ((c.ix & 1) << 2) | ((c.iy & 1) << 1) | (c.iz & 1);
+}
+
+// ---------------------------------------------------------------------
+// colleagues, one level at a time (parents first)
+// ---------------------------------------------------------------------
+__global__ void k_colleagues(const Cell* __restrict__ cells, int c0, int c1,
+                             int32_t* __restrict__ coll) {
+    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    int32_t* out = coll + (int64_t)c * kColl;
+    Cell B = cells[c];
+    int k = 0;
+    if (B.parent < 0) {
+        out[k++] = c;
+    } else {
+        const int32_t* pc = coll + (int64_t)B.parent * kColl;
+        for (int q = 0; q < kColl; ++q) {
+            int C = pc[q];
+            if (C < 0) break;
+            Cell cc = cells[C];
+            for (int i = 0; i < cc.nchild; ++i) {
+                int D = cc.child + i;
+                if (k < kColl && cells_adjacent(cells[D], B)) out[k++] = D;
+            }
+        }
+    }
+    for (; k < kColl; ++k) out[k] = -1;
+}
+
+// V list by slot, for every cell of level >= 2; vcount[c] = entries
+__global__ void k_vlist(const Cell* __restrict__ cells, int c0, int c1,
+                        const int32_t* __restrict__ coll, int32_t* __restrict__ vsrc,
+                        int32_t* __restrict__ vcount) {
+    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    int32_t* out = vsrc + (int64_t)c * kSlots;
+    for (int q = 0; q < kSlots; ++q) out[q] = -1;
+    Cell B = cells[c];
+    int cnt = 0;
+    if (B.level >= 2) {
+        const int ox = B.ix & 1, oy = B.iy & 1, oz = B.iz & 1;
+        const int32_t* pc = coll + (int64_t)B.parent * kColl;
+        for (int q = 0; q < kColl; ++q) {
+            int C = pc[q];
+            if (C < 0) break;
+            Cell cc = cells[C];
+            for (int i = 0; i < cc.nchild; ++i) {
+                int D = cc.child + i;
+                Cell d = cells[D];
+                int dx = d.ix - B.ix, dy = d.iy - B.iy, dz = d.iz - B.iz;
+                int ad = max(abs(dx), max(abs(dy), abs(dz)));
+                if (ad <= 1) continue;
+                int slot = ((dx + 2 + ox) * 6 + (dy + 2 + oy)) * 6 + (dz + 2 + oz);
+                out[slot] = D;
+                ++cnt;
+            }
+        }
+    }
+    vcount[c - c0] = cnt;
+}
+
+// ---------------------------------------------------------------------
+// U, W (leaves) and X (level >= 2): count pass (items == nullptr) and fill
+// pass over the same traversal
+// ---------------------------------------------------------------------
+constexpr int kStack = 8 * (HFMM_KEY_LEVELS + 1);
+
+__device__ inline bool is_ancestor_or_self(const Cell& A, const Cell& B) {
+    if (A.level > B.level) return false;
+    int s = B.level - A.level;
+    return (B.ix >> s) == A.ix && (B.iy >> s) == A.iy && (B.iz >> s) == A.iz;
+}
+
+__global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
+                      int32_t* __restrict__ cu, int32_t* __restrict__ cw,
+                      int32_t* __restrict__ cx, const int32_t* __restrict__ ou,
+                      const int32_t* __restrict__ ow, const int32_t* __restrict__ ox,
+                      int32_t* __restrict__ iu, int32_t* __restrict__ iw,
+                      int32_t* __restrict__ ix) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nc) return;
+    const bool fill = iu != nullptr;
+    Cell B = cells[b];
+    int nu = 0, nw = 0, nx = 0;
+    int32_t* pu = fill ? iu + ou[b] : nullptr;
+    int32_t* pw = fill ? iw + ow[b] : nullptr;
+    int32_t* px = fill ? ix + ox[b] : nullptr;
+    const bool leaf = B.nchild == 0;
+    // X(B): leaves C coarser than B in colleagues of ancestors, adjacent to
+    // parent(B) and not to B
+    if (B.level >= 2) {
+        Cell P = cells[B.parent];
+        for (int A = B.parent; A >= 0; A = cells[A].parent) {
+            const int32_t* ca = coll + (int64_t)A * kColl;
+            for (int q = 0; q < kColl; ++q) {
+                int C = ca[q];
+                if (C < 0) break;
+                Cell cc = cells[C];
+                if (cc.nchild != 0) continue;
+                if (cells_adjacent(cc, P) && !cells_adjacent(cc, B)) {
+                    if (fill) px[nx] = C;
+                    ++nx;
+                }
+            }
+        }
+    }
+    if (leaf) {
+        // coarser adjacent leaves: leaf colleagues of proper ancestors
+        for (int A = B.parent; A >= 0; A = cells[A].parent) {
+            const int32_t* ca = coll + (int64_t)A * kColl;
+            for (int q = 0; q < kColl; ++q) {
+                int C = ca[q];
+                if (C < 0) break;
+                Cell cc = cells[C];
+                if (cc.nchild == 0 && cells_adjacent(cc, B)) {
+                    if (fill) pu[nu] = C;
+                    ++nu;
+                }
+            }
+        }
+        // same level, then finer adjacent leaves (U) and W by descent
+        const int32_t* cb = coll + (int64_t)b * kColl;
+        int stack[kStack];
+        for (int q = 0; q < kColl; ++q) {
+            int C = cb[q];
+            if (C < 0) break;
+            Cell cc = cells[C];
+            if (cc.nchild == 0) {
+                if (fill) pu[nu] = C;
+                ++nu;
+                continue;
+            }
+            if (C == b) continue;
+            int sp = 0;
+            stack[sp++] = C;
+            while (sp > 0) {
+                Cell cur = cells[stack[--sp]];
+                for (int i = cur.nchild - 1; i >= 0; --i) {
+                    int D = cur.child + i;
+                    Cell d = cells[D];
+                    if (cells_adjacent(d, B)) {
+                        if (d.nchild == 0) {
+                            if (fill) pu[nu] = D;
+                            ++nu;
+                        } else if (sp < kStack) {
+                            stack[sp++] = D;
+                        }
+                    } else {
+                        if (fill) pw[nw] = D;
+                        ++nw;
+                    }
+                }
+            }
+        }
+    }
+    if (!fill) {
+        cu[b] = nu;
+        cw[b] = nw;
+        cx[b] = nx;
+    }
+}
+
+// ---------------------------------------------------------------------
+// M2L tiles: targets of level >= 2 ordered by (level, octant)
+// ---------------------------------------------------------------------
+__global__ void k_m2l_keys(const Cell* __restrict__ cells, int c0, int nc,
+                           uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                           int32_t* __restrict__ counts) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = c0 + i;
+    if (c >= nc) return;
+    Cell B = cells[c];
+    int k = B.level * 8 + octant_of(B);
+    keys[i] = (uint64_t)k;
+    vals[i] = c;
+    atomicAdd(&counts[k], 1);
+}
+
+void build_fmm_lists(Tree& t, hipStream_t s) {
+    if (t.fmm_lists) return;
+    Arena& A = t.arena;
+    const int nc = t.ncells;
+    t.coll = A.up<int32_t>((size_t)nc * kColl);
+    t.vsrc = A.up<int32_t>((size_t)nc * kSlots);
+    for (int l = 0; l <= t.depth; ++l) {
+        int c0 = t.level_start[l], c1 = t.level_start[l + 1];
+        hipLaunchKernelGGL(k_colleagues, dim3(grid_for(c1 - c0, 128)), dim3(128), 0, s,
+                           t.cells, c0, c1, t.coll);
+        LAUNCH_CHECK();
+    }
+    int32_t* vcount = A.down<int32_t>(nc + 1);
+    int32_t* vscan = A.down<int32_t>(nc + 1);
+    hipLaunchKernelGGL(k_vlist, dim3(grid_for(nc, 128)), dim3(128), 0, s, t.cells, 0, nc,
+                       t.coll, t.vsrc, vcount);
+    LAUNCH_CHECK();
+    scan_exclusive_i32(vcount, vscan, nc, A, s);
+    // U, W, X
+    int32_t* cnt = A.down<int32_t>(3 * (size_t)(nc + 1));
+    int32_t *cu = cnt, *cw = cnt + (nc + 1), *cx = cnt + 2 * (nc + 1);
+    hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
+                       cu, cw, cx, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    LAUNCH_CHECK();
+    t.u_off = A.up<int32_t>(nc + 1);
+    t.w_off = A.up<int32_t>(nc + 1);
+    t.x_off = A.up<int32_t>(nc + 1);
+    scan_exclusive_i32(cu, t.u_off, nc, A, s);
+    scan_exclusive_i32(cw, t.w_off, nc, A, s);
+    scan_exclusive_i32(cx, t.x_off, nc, A, s);
+    // M2L target order
+    const int c2 = t.depth >= 2 ? t.level_start[2] : nc;
+    const int nm = nc - c2;
+    uint64_t* mk = A.down<uint64_t>(std::max(nm, 1));
+    t.m2l_order = A.up<int32_t>(std::max(nm, 1));
+    int32_t* gcount = A.down<int32_t>(8 * (HFMM_KEY_LEVELS + 2));
+    HIP_TRY(hipMemsetAsync(gcount, 0, sizeof(int32_t) * 8 * (HFMM_KEY_LEVELS + 2), s));
+    if (nm > 0) {
+        hipLaunchKernelGGL(k_m2l_keys, dim3(grid_for(nm, 256)), dim3(256), 0, s, t.cells, c2,
+                           nc, mk, t.m2l_order, gcount);
+        LAUNCH_CHECK();
+        radix_sort_pairs(mk, t.m2l_order, nm, 0, 8, A, s);
+    }
+    int32_t h[4];
+    std::vector<int32_t> gc(8 * (HFMM_KEY_LEVELS + 2));
+    HIP_TRY(hipMemcpyAsync(&h[0], t.u_off + nc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h[1], t.w_off + nc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h[2], t.x_off + nc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h[3], vscan + nc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(gc.data(), gcount, sizeof(int32_t) * gc.size(),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    t.n_u = h[0];
+    t.n_w = h[1];
+    t.n_x = h[2];
+    t.n_v = h[3];
+    t.u_items = A.up<int32_t>(std::max<int64_t>(t.n_u, 1));
+    t.w_items = A.up<int32_t>(std::max<int64_t>(t.n_w, 1));
+    t.x_items = A.up<int32_t>(std::max<int64_t>(t.n_x, 1));
+    hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
+                       nullptr, nullptr, nullptr, t.u_off, t.w_off, t.x_off, t.u_items,
+                       t.w_items, t.x_items);
+    LAUNCH_CHECK();
+    // tiles of up to 256 targets that share (level, octant)
+    std::vector<int32_t> tiles;
+    int start = 0;
+    for (size_t g = 0; g < gc.size(); ++g) {
+        int cntg = gc[g];
+        for (int k = 0; k < cntg; k += 256) {
+            tiles.push_back(start + k);
+            tiles.push_back(std::min(256, cntg - k));
+            tiles.push_back((int)(g % 8));
+            tiles.push_back((int)(g / 8));
+        }
+        start += cntg;
+    }
+    t.n_m2l_tiles = (int32_t)(tiles.size() / 4);
+    t.m2l_tiles = A.up<int32_t>(std::max<size_t>(tiles.size(), 4));
+    if (!tiles.empty()) {
+        HIP_TRY(hipMemcpyAsync(t.m2l_tiles, tiles.data(), sizeof(int32_t) * tiles.size(),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // tiles lives on the host stack
+    }
+    A.release_temps();
+    t.fmm_lists = true;
+    t.mark_lists = A.lo;
+}
+
+// ---------------------------------------------------------------------
+// Barnes-Hut group lists (needs the centres of mass in t.cen)
+// ---------------------------------------------------------------------
+#pragma clang fp contract(off)
+__device__ inline double dist_point_box(const double p[3], const double lo[3], double side) {
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double hi = lo[a] + side;
+        double e = 0.0;
+        if (p[a] < lo[a]) e = lo[a] - p[a];
+        if (p[a] > hi) e = p[a] - hi;
+        d2 += e * e;
+    }
+    return sqrt(d2);
+}
+#pragma clang fp contract(on)
+
+__global__ void k_bh(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
+                     int nleaves, const Root* __restrict__ root,
+                     const double4* __restrict__ cen, double theta,
+                     int32_t* __restrict__ ca, int32_t* __restrict__ cb,
+                     const int32_t* __restrict__ oa, const int32_t* __restrict__ ob,
+                     int32_t* __restrict__ ia, int32_t* __restrict__ ib) {
+#pragma clang fp contract(off)
+    int li = blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= nleaves) return;
+    const bool fill = ia != nullptr;
+    const int b = leaves[li];
+    const Cell B = cells[b];
+    const Root r = *root;
+    const double hb = cell_side(r, B.level);
+    const double lo[3] = {r.b[0] + (double)B.ix * hb, r.b[1] + (double)B.iy * hb,
+                          r.b[2] + (double)B.iz * hb};
+    int na = 0, np = 0;
+    int32_t* pa = fill ? ia + oa[b] : nullptr;
+    int32_t* pb = fill ? ib + ob[b] : nullptr;
+    int stack[kStack];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const int C = stack[--sp];
+        const Cell cc = cells[C];
+        bool open;
+        if (is_ancestor_or_self(cc, B)) {
+            if (C == b) {
+                if (fill) pb[np] = C;
+                ++np;
+                continue;
+            }
+            open = true;
+        } else {
+            const double4 q = cen[C];
+            const double pc[3] = {q.x, q.y, q.z};
+            const double d = dist_point_box(pc, lo, hb);
+            if (cell_side(r, cc.level) < theta * d) {
+                if (fill) pa[na] = C;
+                ++na;
+                continue;
+            }
+            if (cc.nchild == 0) {
+                if (fill) pb[np] = C;
+                ++np;
+                continue;
+            }
+            open = true;
+        }
+        if (open)
+            for (int i = cc.nchild - 1; i >= 0 && sp < kStack; --i) stack[sp++] = cc.child + i;
+    }
+    if (!fill) {
+        ca[b] = na;
+        cb[b] = np;
+    }
+}
+
+void build_bh_lists(Tree& t, double theta, hipStream_t s) {
+    Arena& A = t.arena;
+    if (t.bh_theta == theta && t.a_off) {
+        A.lo = t.mark_bh;
+        return;
+    }
+    A.lo = t.mark_up;  // lists live above the upward data
+    t.fmm_lists = false;
+    const int nc = t.ncells;
+    int32_t* cnt = A.down<int32_t>(2 * (size_t)(nc + 1));
+    int32_t *ca = cnt, *cb = cnt + nc + 1;
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * (nc + 1), s));
+    hipLaunchKernelGGL(k_bh, dim3(grid_for(t.nleaves, 64)), dim3(64), 0, s, t.cells, t.leaves,
+                       t.nleaves, t.root, (const double4*)t.cen, theta, ca, cb, nullptr,
+                       nullptr, nullptr, nullptr);
+    LAUNCH_CHECK();
+    t.a_off = A.up<int32_t>(nc + 1);
+    t.b_off = A.up<int32_t>(nc + 1);
+    scan_exclusive_i32(ca, t.a_off, nc, A, s);
+    scan_exclusive_i32(cb, t.b_off, nc, A, s);
+    int32_t h[2];
+    HIP_TRY(hipMemcpyAsync(&h[0], t.a_off + nc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h[1], t.b_off + nc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    t.n_a = h[0];
+    t.n_b = h[1];
+    t.a_items = A.up<int32_t>(std::max<int64_t>(t.n_a, 1));
+    t.b_items = A.up<int32_t>(std::max<int64_t>(t.n_b, 1));
+    hipLaunchKernelGGL(k_bh, dim3(grid_for(t.nleaves, 64)), dim3(64), 0, s, t.cells, t.leaves,
+                       t.nleaves, t.root, (const double4*)t.cen, theta, nullptr, nullptr,
+                       t.a_off, t.b_off, t.a_items, t.b_items);
+    LAUNCH_CHECK();
+    A.release_temps();
+    t.bh_theta = theta;
+    t.mark_bh = A.lo;
+}
+
+}  // namespace hfmm

@@ -1,0 +1,616 @@
+// Octree construction on the device: FP64 bounding cube, 63-bit Morton keys,
+// stable LSD radix sort, and level-by-level cell splitting.
+//
+// The paper sorts particles and builds the tree and lists on the host
+// (Sec. 4, "sort" and "other" in Fig. breakdown); here every step is a
+// kernel, so the only host work is reading back the cell count per level.
+#include "common.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace hfmm {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 4;
+constexpr int kTile = kBlock * kItems;  // elements per block in scan / sort
+
+// ---------------------------------------------------------------------
+// block-level helpers
+// ---------------------------------------------------------------------
+__device__ inline int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread over a 256-thread block; returns
+// the block total in *total
+__device__ inline int block_exclusive_scan(int v, int* total) {
+    __shared__ int wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = wave_inclusive_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+        if (i < w) off += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// ---------------------------------------------------------------------
+// device-wide exclusive scan (int32): block sums, scan of sums, block scans
+// ---------------------------------------------------------------------
+__global__ void k_scan_partials(const int32_t* __restrict__ in, int64_t n,
+                                int32_t* __restrict__ part) {
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + (int64_t)threadIdx.x * kItems + k;
+        if (i < n) s += in[i];
+    }
+    int tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_sums(int32_t* part, int nparts) {
+    // single block, sequential over chunks of 256
+    int carry = 0;
+    for (int c0 = 0; c0 < nparts; c0 += kBlock) {
+        int i = c0 + threadIdx.x;
+        int v = i < nparts ? part[i] : 0;
+        int tot;
+        int ex = block_exclusive_scan(v, &tot);
+        if (i < nparts) part[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[nparts] = carry;
+}
+
+__global__ void k_scan_blocks(const int32_t* __restrict__ in, int64_t n,
+                              const int32_t* __restrict__ part,
+                              int32_t* __restrict__ out, int write_total) {
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int v[kItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + (int64_t)threadIdx.x * kItems + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int tot;
+    int ex = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + (int64_t)threadIdx.x * kItems + k;
+        if (i < n) out[i] = ex;
+        ex += v[k];
+    }
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        out[n] = part[gridDim.x];
+}
+
+void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, Arena& A,
+                        hipStream_t s) {
+    // out must hold n + 1 entries; out[n] receives the total
+    if (n <= 0) {
+        HIP_TRY(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+        return;
+    }
+    int nb = grid_for(n, kTile);
+    int32_t* part = A.down<int32_t>(nb + 1);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kBlock), 0, s, in, n, part);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, part, nb);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0, s, in, n, part, out, 1);
+    LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------
+// stable LSD radix sort of (u64 key, i32 value), 8-bit digits
+// ---------------------------------------------------------------------
+__device__ inline int key_digit(uint64_t k, int shift, int bits) {
+    return (int)((k >> shift) & ((1u << bits) - 1u));
+}
+
+__global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
+                             int shift, int bits, int32_t* __restrict__ hist,
+                             int nblocks) {
+    __shared__ int cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[key_digit(keys[i], shift, bits)], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Each wave ranks 4 consecutive runs of 64 elements in order; elements with
+// equal digits keep their input order (stable).
+__global__ void __launch_bounds__(kBlock)
+k_radix_scatter(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                uint64_t* __restrict__ kout, int32_t* __restrict__ vout,
+                int64_t n, int shift, int bits,
+                const int32_t* __restrict__ goff, int nblocks) {
+    __shared__ int wcount[kBlock / 64][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < (kBlock / 64) * 256; d += kBlock)
+        (&wcount[0][0])[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * (64 * kItems);
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    uint64_t key[kItems];
+    int32_t val[kItems];
+    int dig[kItems], rank[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + (int64_t)r * 64 + lane;
+        bool ok = i < n;
+        key[r] = ok ? kin[i] : 0ull;
+        val[r] = ok ? vin[i] : 0;
+        int d = ok ? key_digit(key[r], shift, bits) : 0;
+        dig[r] = d;
+        uint64_t mask = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bal = __ballot((d >> b) & 1);
+            mask &= ((d >> b) & 1) ? bal : ~bal;
+        }
+        int before = wcount[w][d];
+        int pre = __popcll(mask & lt);
+        rank[r] = before + pre;
+        // the lowest lane of each digit group advances the wave's counter
+        if (ok && pre == 0) wcount[w][d] = before + __popcll(mask);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // prefix over waves per digit
+    {
+        int d = threadIdx.x;  // 256 digits, 256 threads
+        int acc = 0;
+#pragma unroll
+        for (int ww = 0; ww < kBlock / 64; ++ww) {
+            int c = wcount[ww][d];
+            wcount[ww][d] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + (int64_t)r * 64 + lane;
+        if (i < n) {
+            int d = dig[r];
+            int64_t pos = (int64_t)goff[(int64_t)d * nblocks + blockIdx.x] +
+                          wcount[w][d] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
+        }
+    }
+}
+
+void radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int lo_bit,
+                      int hi_bit, Arena& A, hipStream_t s) {
+    if (n <= 1 || hi_bit <= lo_bit) return;
+    const int nb = grid_for(n, kTile);
+    uint64_t* k2 = A.down<uint64_t>(n);
+    int32_t* v2 = A.down<int32_t>(n);
+    int32_t* hist = A.down<int32_t>((int64_t)256 * nb);
+    int32_t* off = A.down<int32_t>((int64_t)256 * nb + 1);
+    uint64_t *ki = keys, *ko = k2;
+    int32_t *vi = vals, *vo = v2;
+    int passes = 0;
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
+        int bits = std::min(8, hi_bit - shift);
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kBlock), 0, s, ki, n, shift,
+                           bits, hist, nb);
+        LAUNCH_CHECK();
+        scan_exclusive_i32(hist, off, (int64_t)256 * nb, A, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko,
+                           vo, n, shift, bits, off, nb);
+        LAUNCH_CHECK();
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+        ++passes;
+    }
+    if (passes & 1) {
+        HIP_TRY(hipMemcpyAsync(keys, ki, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(vals, vi, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+// ---------------------------------------------------------------------
+// bounding cube and keys (FP64)
+// ---------------------------------------------------------------------
+__device__ inline double load_coord(const double* a, const double* ta, int64_t ns,
+                                    int64_t i) {
+    return i < ns ? a[i] : ta[i - ns];
+}
+
+__global__ void k_bbox_partial(const double* __restrict__ x, const double* __restrict__ y,
+                               const double* __restrict__ z, const double* __restrict__ tx,
+                               const double* __restrict__ ty, const double* __restrict__ tz,
+                               int64_t ns, int64_t n, double* __restrict__ part,
+                               int32_t* __restrict__ bad) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY};
+    double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int nbad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v[3] = {load_coord(x, tx, ns, i), load_coord(y, ty, ns, i),
+                       load_coord(z, tz, ns, i)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(v[a])) {
+                ++nbad;
+                continue;
+            }
+            lo[a] = fmin(lo[a], v[a]);
+            hi[a] = fmax(hi[a], v[a]);
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], d, 64));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], d, 64));
+        }
+        nbad += __shfl_xor(nbad, d, 64);
+    }
+    __shared__ double sl[4][3], sh[4][3];
+    __shared__ int sb[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 3; ++a) {
+            sl[w][a] = lo[a];
+            sh[w][a] = hi[a];
+        }
+        sb[w] = nbad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nb = 0;
+        for (int ww = 0; ww < (int)(blockDim.x >> 6); ++ww) {
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = fmin(lo[a], sl[ww][a]);
+                hi[a] = fmax(hi[a], sh[ww][a]);
+            }
+            nb += sb[ww];
+        }
+        for (int a = 0; a < 3; ++a) {
+            part[blockIdx.x * 6 + a] = lo[a];
+            part[blockIdx.x * 6 + 3 + a] = hi[a];
+        }
+        if (nb) atomicAdd(bad, nb);
+    }
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nparts, Root* root) {
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY};
+    double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nparts; ++b)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], part[b * 6 + a]);
+            hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
+        }
+    double R = 0.0, c[3];
+    for (int a = 0; a < 3; ++a) {
+        c[a] = (lo[a] + hi[a]) / 2.0;
+        double h = (hi[a] - lo[a]) / 2.0;
+        if (h > R) R = h;
+    }
+    if (!(R > 0.0)) R = 1.0;
+    for (int a = 0; a < 3; ++a) root->b[a] = c[a] - R;
+    root->R = R;
+    root->scale = 2097152.0 / (2.0 * R);
+}
+
+__device__ inline uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ inline uint32_t quantise(double v, double b, double s) {
+#pragma clang fp contract(off)
+    double f = floor((v - b) * s);
+    if (!(f >= 0.0)) return 0u;
+    if (f > 2097151.0) return 2097151u;
+    return (uint32_t)f;
+}
+
+__global__ void k_keys(const double* __restrict__ x, const double* __restrict__ y,
+                       const double* __restrict__ z, const double* __restrict__ tx,
+                       const double* __restrict__ ty, const double* __restrict__ tz,
+                       int64_t ns, int64_t n, const Root* __restrict__ root,
+                       uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = root->scale;
+    uint32_t qx = quantise(load_coord(x, tx, ns, i), root->b[0], s);
+    uint32_t qy = quantise(load_coord(y, ty, ns, i), root->b[1], s);
+    uint32_t qz = quantise(load_coord(z, tz, ns, i), root->b[2], s);
+    keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    idx[i] = (int32_t)i;
+}
+
+// Sorted FP64 positions, and FP32 positions relative to the centre of the
+// particle's leaf for the near field: a pair separation is then rounded
+// relative to the cell size instead of to |x|.
+__global__ void k_gather_positions(const double* __restrict__ x, const double* __restrict__ y,
+                                   const double* __restrict__ z, const double* __restrict__ tx,
+                                   const double* __restrict__ ty, const double* __restrict__ tz,
+                                   int64_t ns, int64_t n, const int32_t* __restrict__ perm,
+                                   const Cell* __restrict__ cells,
+                                   const int32_t* __restrict__ leaf_of,
+                                   const Root* __restrict__ root, double* __restrict__ xs,
+                                   double* __restrict__ ys, double* __restrict__ zs,
+                                   float4* __restrict__ p32) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int64_t i = perm[s];
+    double a = load_coord(x, tx, ns, i), b = load_coord(y, ty, ns, i),
+           c = load_coord(z, tz, ns, i);
+    xs[s] = a;
+    ys[s] = b;
+    zs[s] = c;
+    double o[3];
+    cell_centre(*root, cells[leaf_of[s]], o);
+    p32[s] = make_float4((float)(a - o[0]), (float)(b - o[1]), (float)(c - o[2]), 0.0f);
+}
+
+// ---------------------------------------------------------------------
+// cells, level by level
+// ---------------------------------------------------------------------
+// first index in [lo, hi) whose key digit at `shift` is >= o (keys sorted)
+__device__ inline int lower_bound_digit(const uint64_t* keys, int lo, int hi, int shift,
+                                        int o) {
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((int)((keys[mid] >> shift) & 7u) < o)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_split_count(const Cell* __restrict__ cells, int c0, int c1, int leaf_max,
+                              int sorted_levels, const uint64_t* __restrict__ keys,
+                              int32_t* __restrict__ nz, int32_t* __restrict__ flag) {
+    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    Cell cell = cells[c];
+    int nkids = 0;
+    if (cell.count > leaf_max && cell.level < HFMM_KEY_LEVELS) {
+        if (cell.level + 1 > sorted_levels) {
+            atomicOr(flag, 1);  // the sort did not order this digit: re-sort
+        } else {
+            int shift = 3 * (HFMM_KEY_LEVELS - cell.level - 1);
+            int beg = cell.first, end = cell.first + cell.count;
+            int prev = beg;
+            for (int o = 1; o <= 8; ++o) {
+                int b = o < 8 ? lower_bound_digit(keys, prev, end, shift, o) : end;
+                nkids += (b > prev);
+                prev = b;
+            }
+        }
+    }
+    nz[c - c0] = nkids;
+}
+
+__global__ void k_split_emit(Cell* __restrict__ cells, int c0, int c1, int next0,
+                             const uint64_t* __restrict__ keys,
+                             const int32_t* __restrict__ pos) {
+    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= c1) return;
+    int k = pos[c - c0];
+    int nk = pos[c - c0 + 1] - k;
+    Cell cell = cells[c];
+    if (nk == 0) {
+        cells[c].child = -1;
+        cells[c].nchild = 0;
+        return;
+    }
+    int shift = 3 * (HFMM_KEY_LEVELS - cell.level - 1);
+    int beg = cell.first, end = cell.first + cell.count;
+    int prev = beg, out = next0 + k;
+    for (int o = 0; o < 8; ++o) {
+        int b = o < 7 ? lower_bound_digit(keys, prev, end, shift, o + 1) : end;
+        if (b > prev) {
+            Cell ch;
+            ch.first = prev;
+            ch.count = b - prev;
+            ch.parent = c;
+            ch.child = -1;
+            ch.ix = 2 * cell.ix + ((o >> 2) & 1);
+            ch.iy = 2 * cell.iy + ((o >> 1) & 1);
+            ch.iz = 2 * cell.iz + (o & 1);
+            ch.level = (int16_t)(cell.level + 1);
+            ch.nchild = 0;
+            cells[out++] = ch;
+        }
+        prev = b;
+    }
+    cells[c].child = next0 + k;
+    cells[c].nchild = (int16_t)nk;
+}
+
+__global__ void k_leaf_flags(const Cell* __restrict__ cells, int nc, int32_t* __restrict__ f) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc) f[c] = cells[c].nchild == 0;
+}
+
+__global__ void k_leaf_compact(const Cell* __restrict__ cells, int nc,
+                               const int32_t* __restrict__ pos, int32_t* __restrict__ leaves,
+                               int32_t* __restrict__ leaf_of) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    Cell cell = cells[c];
+    if (cell.nchild != 0) return;
+    leaves[pos[c]] = c;
+    for (int s = cell.first; s < cell.first + cell.count; ++s) leaf_of[s] = c;
+}
+
+static int sort_levels_guess(int64_t n, int leaf_max) {
+    // levels a uniform distribution needs, plus two
+    double ratio = (double)n / (double)std::max(1, leaf_max);
+    int L = 0;
+    while (ratio > 1.0 && L < HFMM_KEY_LEVELS) {
+        ratio /= 8.0;
+        ++L;
+    }
+    return std::min(HFMM_KEY_LEVELS, L + 2);
+}
+
+void build_tree(Tree& t, const double* x, const double* y, const double* z,
+                const double* tx, const double* ty, const double* tz, hipStream_t s) {
+    Arena& A = t.arena;
+    const int64_t n = t.n;
+    t.root = A.up<Root>(1);
+    t.keys = A.up<uint64_t>(n);
+    t.perm = A.up<int32_t>(n);
+    t.xs = A.up<double>(n);
+    t.ys = A.up<double>(n);
+    t.zs = A.up<double>(n);
+    t.p32 = A.up<float4>(n);
+    t.p64 = A.up<double4>(n);
+    t.leaf_of = A.up<int32_t>(n);
+
+    // bounding cube
+    const int nbb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(n, 256)));
+    double* part = A.down<double>((size_t)nbb * 6);
+    int32_t* hbuf = A.down<int32_t>(8);
+    HIP_TRY(hipMemsetAsync(hbuf, 0, 8 * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, x, y, z, tx, ty, tz,
+                       t.ns, n, part, hbuf);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, nbb, t.root);
+    LAUNCH_CHECK();
+    int32_t nbad = 0;
+    HIP_TRY(hipMemcpyAsync(&nbad, hbuf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&t.root_h, t.root, sizeof(Root), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (nbad) throw Status{HFMM_E_DATA};
+
+    // keys, sort (top bits first; a full sort if the tree turns out deeper)
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, tx, ty,
+                       tz, t.ns, n, t.root, t.keys, t.perm);
+    LAUNCH_CHECK();
+    int sorted_levels = sort_levels_guess(n, t.leaf_max);
+    const size_t cells_lo = A.lo;
+    for (int attempt = 0;; ++attempt) {
+        int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
+        radix_sort_pairs(t.keys, t.perm, n, lo_bit, 63, A, s);
+        t.sort_bits = 63 - lo_bit;
+        // cells
+        A.lo = cells_lo;
+        t.cells = (Cell*)(A.base + A.lo);
+        auto room = [&](int64_t ncell) {
+            size_t b = Arena::align((size_t)ncell * sizeof(Cell) + 1);
+            if (cells_lo + b > A.hi) A.fail((size_t)ncell * sizeof(Cell));
+            A.lo = cells_lo + b;
+        };
+        room(1);
+        Cell root;
+        root.first = 0;
+        root.count = (int32_t)n;
+        root.parent = -1;
+        root.child = -1;
+        root.ix = root.iy = root.iz = 0;
+        root.level = 0;
+        root.nchild = 0;
+        HIP_TRY(hipMemcpyAsync(t.cells, &root, sizeof(Cell), hipMemcpyHostToDevice, s));
+        t.level_start.assign(1, 0);
+        t.level_start.push_back(1);
+        int c0 = 0, c1 = 1, level = 0;
+        bool resort = false;
+        const size_t hi_mark = A.hi;
+        while (true) {
+            int nl = c1 - c0;
+            int32_t* nz = A.down<int32_t>(nl + 1);
+            int32_t* pos = A.down<int32_t>(nl + 1);
+            int32_t* flag = A.down<int32_t>(2);
+            HIP_TRY(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), s));
+            hipLaunchKernelGGL(k_split_count, dim3(grid_for(nl, 256)), dim3(256), 0, s,
+                               t.cells, c0, c1, t.leaf_max, sorted_levels, t.keys, nz, flag);
+            LAUNCH_CHECK();
+            scan_exclusive_i32(nz, pos, nl, A, s);
+            int32_t h[2] = {0, 0};
+            HIP_TRY(hipMemcpyAsync(&h[0], pos + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(&h[1], flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (h[1]) {
+                resort = true;
+                A.hi = hi_mark;
+                break;
+            }
+            int added = h[0];
+            if (added > 0) room((int64_t)c1 + added);
+            hipLaunchKernelGGL(k_split_emit, dim3(grid_for(nl, 256)), dim3(256), 0, s,
+                               t.cells, c0, c1, c1, t.keys, pos);
+            LAUNCH_CHECK();
+            A.hi = hi_mark;
+            if (added == 0) break;
+            c0 = c1;
+            c1 += added;
+            ++level;
+            t.level_start.push_back(c1);
+        }
+        if (resort) {
+            if (sorted_levels >= HFMM_KEY_LEVELS) throw Status{HFMM_E_STATE};
+            sorted_levels = HFMM_KEY_LEVELS;
+            continue;
+        }
+        t.ncells = c1;
+        t.depth = level;
+        break;
+    }
+    // leaves
+    int32_t* f = A.down<int32_t>(t.ncells + 1);
+    int32_t* pos = A.down<int32_t>(t.ncells + 1);
+    hipLaunchKernelGGL(k_leaf_flags, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s, t.cells,
+                       t.ncells, f);
+    LAUNCH_CHECK();
+    scan_exclusive_i32(f, pos, t.ncells, A, s);
+    int32_t nleaves = 0;
+    HIP_TRY(hipMemcpyAsync(&nleaves, pos + t.ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    t.nleaves = nleaves;
+    t.leaves = A.up<int32_t>(nleaves);
+    hipLaunchKernelGGL(k_leaf_compact, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
+                       t.cells, t.ncells, pos, t.leaves, t.leaf_of);
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_gather_positions, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z,
+                       tx, ty, tz, t.ns, n, t.perm, t.cells, t.leaf_of, t.root, t.xs, t.ys,
+                       t.zs, t.p32);
+    LAUNCH_CHECK();
+    A.release_temps();
+}
+
+}  // namespace hfmm

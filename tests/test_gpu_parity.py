@@ -1,0 +1,223 @@
+"""GPU parity against the FP64 oracle: direct sum, tree and lists (exact),
+expansions (stage by stage) and the FMM / treecode results."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1010_1482_amd import workloads as W
+from tests.gpu_util import host, need_gpu, rel_err, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    from paper_1010_1482_amd import hfmm
+    hfmm.library()
+
+
+def H():
+    from paper_1010_1482_amd import hfmm
+    return hfmm
+
+
+# ---------------------------------------------------------------- direct
+@pytest.mark.parametrize("n,prec,tol", [(1000, "fp64", 1e-13), (3001, "fp32", 1e-5),
+                                        (1, "fp64", 0.0)])
+def test_direct_sum(n, prec, tol):
+    say(f"direct n={n} {prec}")
+    x, y, z, m = W.plummer(n, 31)
+    ref = O.direct(x, y, z, m)
+    out = host(H().direct(*to_dev(x, y, z, m), precision=prec))
+    torch.cuda.synchronize()
+    if n == 1:
+        assert all(float(o[0]) == 0.0 for o in out)
+        return
+    ephi, eacc = rel_err(out, ref)
+    say(f"  err phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi <= tol and eacc <= tol
+
+
+def test_direct_sum_distinct_targets_and_softening():
+    say("direct targets + eps2")
+    x, y, z, m = W.uniform(2000, 32)
+    tx, ty, tz, _ = W.uniform(333, 33)
+    ref = O.direct_points(x, y, z, m, tx, ty, tz, eps2=1e-4)
+    out = host(H().direct(*to_dev(x, y, z, m), precision="fp64", eps2=1e-4,
+                          targets=to_dev(tx, ty, tz)))
+    ephi, eacc = rel_err(out, ref)
+    assert ephi < 1e-13 and eacc < 1e-13
+
+
+# ---------------------------------------------------------------- tree
+def _cells_oracle(T):
+    c = T.cells()
+    return np.stack([c["level"], c["ix"], c["iy"], c["iz"], c["first"], c["count"],
+                     c["parent"], c["first_child"], c["nchild"]], 1)
+
+
+@pytest.mark.parametrize("dist,n,leaf", [("uniform", 16384, 64), ("plummer", 20000, 16),
+                                         ("plummer", 3000, 1), ("uniform", 70, 64)])
+def test_tree_matches_oracle_exactly(dist, n, leaf):
+    say(f"tree {dist} n={n} leaf={leaf}")
+    x, y, z, m = W.make(dist, n, 41)
+    T = O.Tree(x, y, z, leaf)
+    t = H().Tree(*to_dev(x, y, z), leaf_max=leaf)
+    st = t.stats()
+    assert st["n_cells"] == T.ncells and st["depth"] == T.depth
+    assert np.array_equal(np.array(st["root"]), T.root())
+    gc = t.cells().cpu().numpy().astype(np.int64)
+    oc = _cells_oracle(T).astype(np.int64)
+    gc[:, 7] = np.where(gc[:, 8] == 0, -1, gc[:, 7])
+    assert np.array_equal(gc, oc)
+    # particles per leaf: the same sets (order inside a leaf is free)
+    gp = t.perm().cpu().numpy()
+    op = T.perm()
+    for i in np.nonzero(oc[:, 8] == 0)[0]:
+        a, k = oc[i, 4], oc[i, 5]
+        assert np.array_equal(np.sort(gp[a:a + k]), np.sort(op[a:a + k]))
+
+
+@pytest.mark.parametrize("dist,n,leaf", [("uniform", 16384, 64), ("plummer", 20000, 16),
+                                         ("plummer", 2000, 2)])
+def test_fmm_lists_match_oracle(dist, n, leaf):
+    say(f"lists {dist} n={n} leaf={leaf}")
+    x, y, z, m = W.make(dist, n, 42)
+    T = O.Tree(x, y, z, leaf)
+    t = H().Tree(*to_dev(x, y, z), leaf_max=leaf)
+    t.upward(to_dev(m)[0], 4, H().FMM, H().FP64)
+    for w in range(4):
+        off, it = T.list(w)
+        goff, git = (a.cpu().numpy() for a in t.fmm_list(w))
+        assert len(git) == len(it), w
+        for b in range(T.ncells):
+            assert np.array_equal(np.sort(git[goff[b]:goff[b + 1]]),
+                                  np.sort(it[off[b]:off[b + 1]])), (w, b)
+
+
+# ---------------------------------------------------------------- expansions
+def _paper_half(X, p):
+    """oracle complex [nc, p*p] (all m) -> [nc, p(p+1)/2] (m >= 0)"""
+    idx = [n * n + n + m for n in range(p) for m in range(n + 1)]
+    return X[:, idx]
+
+
+@pytest.mark.parametrize("dist,n,leaf,p", [("uniform", 16384, 64, 6),
+                                           ("plummer", 6000, 16, 8)])
+def test_fmm_expansions_fp64_match_oracle(dist, n, leaf, p):
+    say(f"expansions {dist} n={n} p={p}")
+    x, y, z, m = W.make(dist, n, 43)
+    T = O.Tree(x, y, z, leaf)
+    Mo, Lo = T.fmm_expansions(m, p)
+    t = H().Tree(*to_dev(x, y, z), leaf_max=leaf)
+    xd, yd, zd, md = to_dev(x, y, z, m)
+    t.upward(md, p, H().FMM, H().FP64)
+    Mg = t.expansions(0).cpu().numpy()
+    Mr = _paper_half(Mo, p)
+    assert np.max(np.abs(Mg - Mr)) <= 1e-12 * np.max(np.abs(Mr))
+    t.evaluate()
+    Lg = t.expansions(1).cpu().numpy()
+    Lr = _paper_half(Lo, p)
+    scale = np.max(np.abs(Lr), axis=1, keepdims=True) + 1e-300
+    assert np.max(np.abs(Lg - Lr) / scale) <= 1e-11
+
+
+# ---------------------------------------------------------------- end to end
+@pytest.mark.parametrize("dist,n,leaf,p", [("uniform", 16384, 64, 6),
+                                           ("plummer", 8000, 16, 8),
+                                           ("plummer", 500, 2, 5),
+                                           ("uniform", 40, 64, 6)])
+def test_fmm_fp64_matches_oracle(dist, n, leaf, p):
+    say(f"fmm fp64 {dist} n={n} leaf={leaf} p={p}")
+    x, y, z, m = W.make(dist, n, 44)
+    ref = O.fmm(x, y, z, m, p, leaf)
+    out = host(H().solve(*to_dev(x, y, z, m), p=p, method="fmm", precision="fp64",
+                         leaf_max=leaf))
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs oracle fmm: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi <= 1e-12 and eacc <= 1e-12
+
+
+@pytest.mark.parametrize("dist,n,leaf,p", [("uniform", 16384, 64, 6),
+                                           ("uniform", 16384, 64, 10),
+                                           ("plummer", 8000, 16, 8),
+                                           ("uniform", 20000, 64, 12)])
+def test_fmm_fp32_matches_oracle(dist, n, leaf, p):
+    say(f"fmm fp32 {dist} n={n} leaf={leaf} p={p}")
+    x, y, z, m = W.make(dist, n, 45)
+    tg = W.sample_targets(n, 512, 7)
+    ref = O.fmm(x, y, z, m, p, leaf, targets=tg)
+    out = host(H().solve(*to_dev(x, y, z, m), p=p, method="fmm", precision="fp32",
+                         leaf_max=leaf))
+    out = [o[tg] for o in out]
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs oracle fmm: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi <= 1e-5 and eacc <= 1e-5
+
+
+def test_fmm_distinct_targets():
+    say("fmm distinct targets")
+    x, y, z, m = W.plummer(5000, 46)
+    tx, ty, tz, _ = W.plummer(700, 47)
+    ref = O.direct_points(x, y, z, m, tx, ty, tz)
+    out = host(H().solve(*to_dev(x, y, z, m), p=10, method="fmm", precision="fp64",
+                         leaf_max=16, targets=to_dev(tx, ty, tz)))
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs direct: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi < 1e-5 and eacc < 1e-4
+
+
+# ---------------------------------------------------------------- treecode
+@pytest.mark.parametrize("dist,n,leaf,p,theta", [("plummer", 8000, 16, 3, 0.5),
+                                                 ("uniform", 6000, 32, 4, 0.4)])
+def test_treecode_matches_oracle(dist, n, leaf, p, theta):
+    say(f"treecode {dist} n={n} p={p} theta={theta}")
+    x, y, z, m = W.make(dist, n, 48)
+    T = O.Tree(x, y, z, leaf)
+    t = H().Tree(*to_dev(x, y, z), leaf_max=leaf)
+    md = to_dev(m)[0]
+    t.upward(md, p, H().TREECODE, H().FP64)
+    out = host(t.evaluate(theta=theta))
+    # lists: identical except where l == theta d to rounding
+    for w in range(2):
+        off, it = T.bh_lists(m, theta, w)
+        goff, git = (a.cpu().numpy() for a in t.bh_list(w))
+        diff = 0
+        for b in range(T.ncells):
+            diff += len(set(git[goff[b]:goff[b + 1]]) ^ set(it[off[b]:off[b + 1]]))
+        assert diff == 0, (w, diff)
+    ref = O.treecode(x, y, z, m, p, theta, leaf)
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs oracle treecode: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi <= 1e-12 and eacc <= 1e-12
+    d = O.direct(x, y, z, m)
+    t.upward(md, p, H().TREECODE, H().FP32)
+    out32 = host(t.evaluate(theta=theta))
+    e32 = rel_err(out32, ref)
+    assert e32[0] < 1e-5 and e32[1] < 1e-5
+    assert rel_err(out, d)[1] < 5e-3
+
+
+def test_empty_and_single():
+    say("empty and single")
+    x, y, z, m = to_dev(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0))
+    out = H().solve(x, y, z, m, p=4, method="fmm", precision="fp32")
+    assert all(o.numel() == 0 for o in out)
+    x, y, z, m = to_dev([0.5], [0.25], [0.125], [2.0])
+    out = host(H().solve(x, y, z, m, p=4, method="fmm", precision="fp64"))
+    assert all(o[0] == 0.0 for o in out)
+
+
+def test_coincident_points():
+    say("coincident points")
+    x = np.zeros(300) + 0.5
+    y = np.zeros(300) + 0.5
+    z = np.zeros(300) + 0.5
+    x[:3] = [0.0, 1.0, 0.25]
+    m = np.full(300, 1.0 / 300)
+    ref = O.fmm(x, y, z, m, 6, 8)
+    out = host(H().solve(*to_dev(x, y, z, m), p=6, method="fmm", precision="fp64", leaf_max=8))
+    for a, b in zip(out, ref):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
