@@ -61,6 +61,44 @@ def cpu_baseline(p: int, leaf: int):
                       f"leaf<={leaf}, all targets; {dt:.1f} s"}
 
 
+def serving_bench(n_req: int, slots: int, budget_gb: float, plain: bool):
+    """The serving form: the seeded request trace (N log-uniform in
+    [1e3, 1e6], half uniform / half Plummer, p in {6, 8, 10}, Poisson arrivals
+    at 200 req/s), served with continuous batching on `slots` streams under an
+    HBM budget, and (plain=True) one request at a time for comparison.
+    Inputs are generated on the host before the clock starts."""
+    from paper_1010_1482_amd import serve
+    from paper_1010_1482_amd import workloads as W
+    trace = W.request_trace(n_req=n_req, seed=5)
+    data = {e["i"]: W.make(e["dist"], e["n"], e["seed"]) for e in trace}
+
+    def reqs():
+        rs = serve.trace_requests(trace)
+        for r in rs:
+            r.make_inputs = (lambda i=r.rid: data[i])
+        return rs
+
+    # warm up code objects and the allocator on a few requests
+    warm = serve.Server(int(budget_gb * 2 ** 30), slots, serve.HipExecutor(slots),
+                        serve.hip_footprint)
+    warm.run(reqs()[:2 * slots], realtime=False)
+    out = {}
+    modes = [("batched", slots)] + ([("one_at_a_time", 1)] if plain else [])
+    for name, k in modes:
+        srv = serve.Server(int(budget_gb * 2 ** 30), k, serve.HipExecutor(k),
+                           serve.hip_footprint)
+        t0 = time.perf_counter()
+        done = srv.run(reqs(), realtime=True)
+        out[name] = serve.summarize(done, time.perf_counter() - t0)
+        out[name]["slots"] = k
+    off = sum(e["n"] for e in trace) / trace[-1]["t_arrive"]
+    out["offered_particles_per_s"] = off
+    out["trace"] = (f"{n_req} requests, N log-uniform [1e3, 1e6], half uniform / half "
+                    f"Plummer, p in {{6, 8, 10}}, Poisson 200 req/s, FP32 FMM, leaf<=64, "
+                    f"HBM budget {budget_gb} GiB")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -76,6 +114,14 @@ def main() -> int:
     ap.add_argument("--accuracy-targets", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--method", default="fmm", choices=["fmm", "treecode"])
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the serving trace (0 skips the serving form)")
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-plain", action="store_true",
+                    help="also serve the trace one request at a time")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -95,15 +141,17 @@ def main() -> int:
     xd, yd, zd, md = (torch.from_numpy(a).to(dev) for a in (x, y, z, m))
     dt = hfmm.out_dtype(prec)
     out = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
-    arena = torch.empty(hfmm.arena_bytes(n, 0, leaf, p, hfmm.FMM, prec), dtype=torch.uint8,
-                        device=dev)
+    arena = torch.empty(hfmm.arena_bytes(n, 0, leaf, p, hfmm.METHODS[args.method], prec),
+                        dtype=torch.uint8, device=dev)
     hfmm.set_timing(True)
     stream = torch.cuda.current_stream()
 
+    meth = hfmm.METHODS[args.method]
+
     def step():
         t = hfmm.Tree(xd, yd, zd, leaf_max=leaf, arena=arena)
-        t.upward(md, p, hfmm.FMM, prec)
-        t.evaluate(out=out)
+        t.upward(md, p, meth, prec)
+        t.evaluate(theta=args.theta, out=out)
         return t
 
     for _ in range(args.warmup):
@@ -125,11 +173,13 @@ def main() -> int:
 
     # dominant kernel and its roofline (algorithmic work per launch / its
     # average device time over the timed steps)
-    pairs = p2p_pairs(tr)
+    pairs = p2p_pairs(tr) if args.method == "fmm" else 0
     m2l_pairs = stats["m2l_pairs"]
     m2l_flops = 2.0 * p ** 4 * m2l_pairs
+    m2l_peak = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"]}.get(
+        args.precision, PEAK["bf16_TFs"])
     cand = {
-        "m2l": (ph.get("m2l", 0.0), m2l_flops, "mfma", PEAK["fp32_TFs"]),
+        "m2l": (ph.get("m2l", 0.0), m2l_flops, "mfma", m2l_peak),
         "p2p": (ph.get("p2p", 0.0), P2P_FLOPS * pairs, "alu", PEAK["fp32_TFs"]),
     }
     dom = max(cand, key=lambda k: cand[k][0])
@@ -148,7 +198,7 @@ def main() -> int:
         "config": {"workload": f"FMM N={n} {args.dist} unit cube, masses 1/N, p={p}, "
                                f"leaf<={leaf}, {args.precision}",
                    "n": n, "p": p, "leaf_max": leaf, "dist": args.dist,
-                   "precision": args.precision, "method": "fmm"},
+                   "precision": args.precision, "method": args.method},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3)},
         "phase_ms": ph,
@@ -169,6 +219,9 @@ def main() -> int:
             "targets": len(tg), "reference": "FP64 oracle direct sum over all N",
             "rel_l2_phi": O.rel_l2(got[0], ref[0]),
             "rel_l2_acc": O.rel_l2(np.stack(got[1:]), np.stack(ref[1:]))}
+    if args.serve_requests > 0:
+        res["serving"] = serving_bench(args.serve_requests, args.serve_slots,
+                                       args.serve_budget_gb, args.serve_plain)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(p, leaf)
     print(json.dumps(res), flush=True)

@@ -81,19 +81,22 @@ void upward_pass(Tree& t, const double* m, int p, int method, int precision, hip
     const int P = p * p;
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
-    t.cen = (double*)A.up<double4>(t.ncells);
-    t.M = A.up<double>((size_t)t.ncells * P);
-    t.Mk = nullptr;
-    if (method == HFMM_FMM && m2l_uses_mfma(p, precision))
-        t.Mk = A.up<float>((size_t)(t.ncells + 1) * ld);
-    t.mark_up = A.lo;
+    t.ldm = (P + 15) / 16 * 16;
     PhaseTimer pt(t, PH_UPWARD, s);
+    if (method == HFMM_FMM) prepare_xlat_ops(t, p, s);
+    t.cen = (double*)A.up<double4>(t.ncells);
+    t.M = A.up<double>((size_t)(t.ncells + 1) * t.ldm);
+    HIP_TRY(hipMemsetAsync(t.M + (size_t)t.ncells * t.ldm, 0, sizeof(double) * t.ldm, s));
+    t.Mk = nullptr;
+    t.mark_up = A.lo;
     fill_masses(t, m, s);
     compute_centres(t, method, s);
     const bool fp64 = precision == HFMM_FP64;
     run_p2m(t, p, fp64, s);
-    run_m2m(t, p, method == HFMM_TREECODE, s);
-    if (t.Mk) run_pack(t.M, t.ncells, P, ld, t.Mk, false, s);
+    if (method == HFMM_FMM)
+        run_m2m_mfma(t, p, s);
+    else
+        run_m2m(t, p, s);
     A.release_temps();
     t.up_p = p;
     t.up_method = method;
@@ -113,34 +116,39 @@ void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi, void* a
     }
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
-    t.L = A.up<double>((size_t)t.ncells * P);
+    t.L = A.up<double>((size_t)(t.ncells + 1) * t.ldm);
+    const size_t row = sizeof(double) * t.ldm;
+    HIP_TRY(hipMemsetAsync(t.L + (size_t)t.ncells * t.ldm, 0, row, s));
     if (t.depth >= 2) {
         // M2L partial results
         const bool mf = m2l_uses_mfma(p, precision);
         int max_parts = 8;
         const size_t esz = fp64 ? 8 : 4;
         while (max_parts > 1 &&
-               (size_t)max_parts * t.ncells * ld * esz > A.free_bytes() / 2)
+               (size_t)max_parts * t.ncells * t.ldm * esz > A.free_bytes() / 2)
             max_parts /= 2;
         const int parts_cap = mf ? max_parts : 1;
-        void* lm = A.down<char>((size_t)parts_cap * t.ncells * ld * esz);
+        void* lm = A.down<char>((size_t)parts_cap * t.ncells * t.ldm * esz);
+        int32_t* levexp = A.down<int32_t>(32);
         double* LX = nullptr;
-        if (t.n_x > 0) LX = A.down<double>((size_t)t.ncells * P);
+        if (t.n_x > 0) LX = A.down<double>((size_t)t.ncells * t.ldm);
         int64_t stride = 0;
         int parts;
         {
             PhaseTimer pt(t, PH_M2L, s);
-            parts = run_m2l(t, p, precision, lm, stride, parts_cap, s);
+            parts = run_m2l(t, p, precision, lm, stride, parts_cap, levexp, s);
         }
         PhaseTimer pt(t, PH_DOWN, s);
         if (LX) {
-            HIP_TRY(hipMemsetAsync(LX, 0, sizeof(double) * t.ncells * P, s));
+            HIP_TRY(hipMemsetAsync(LX, 0, row * t.ncells, s));
             run_p2l(t, p, LX, s);
         }
-        HIP_TRY(hipMemsetAsync(t.L, 0, sizeof(double) * P * t.level_start[2], s));
-        run_downward(t, p, lm, fp64, ld, parts, stride, LX, s);
+        HIP_TRY(hipMemsetAsync(t.L, 0, row * t.level_start[2], s));
+        const bool lowp = mf && precision >= HFMM_M2L_BF16;
+        run_l2l_mfma(t, p, lm, fp64, parts, stride, LX, lowp ? t.bexp : nullptr,
+                     lowp ? levexp : nullptr, s);
     } else {
-        HIP_TRY(hipMemsetAsync(t.L, 0, sizeof(double) * P * t.ncells, s));
+        HIP_TRY(hipMemsetAsync(t.L, 0, row * t.ncells, s));
     }
     void* far = A.down<char>((size_t)4 * t.n * (fp64 ? 8 : 4));
     {
@@ -188,10 +196,11 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
     size_t per_particle = 8 + 4 + 24 + 16 + 32 + 4 + 8 + 4 + 8 + 4 * 8 + 64;
-    size_t per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)P * 8 * 3 +
+    size_t per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 * 3 +
                       (size_t)ld * 4 + (size_t)8 * ld * 4 + 64;
     if (method == HFMM_TREECODE) per_cell = 32 + 32 + 32 + (size_t)P * 8 + 512 + 64;
     size_t ops = method == HFMM_FMM ? m2l_ops_bytes(p, precision) : 0;
+    if (method == HFMM_FMM) ops += (size_t)2 * 8 * ld * ld * sizeof(double);
     if (method == HFMM_FMM && precision != HFMM_FP64 && !m2l_uses_mfma(p, precision))
         ops += (size_t)343 * P * P * 8;
     size_t tot = per_particle * (size_t)n + per_cell * (size_t)nc + ops;
@@ -500,7 +509,7 @@ int hfmm_export_expansions(hfmm_tree h, int which, double* dst, void* stream) {
     if (t.up_p == 0 || !t.M) return HFMM_E_STATE;
     if (which == 1 && (t.up_method != HFMM_FMM || !t.L || t.ev_p != t.up_p)) return HFMM_E_STATE;
     API_BEGIN
-    run_export(which == 0 ? t.M : t.L, t.ncells, t.up_p, t.cen, which, dst,
+    run_export(which == 0 ? t.M : t.L, t.ldm, t.ncells, t.up_p, t.cen, which, dst,
                (hipStream_t)stream);
     API_END
 }

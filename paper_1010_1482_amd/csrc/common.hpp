@@ -102,7 +102,9 @@ struct Cell {
     int32_t first, count;   // particle range in sorted order
     int32_t parent, child;  // parent cell, first child (-1 for a leaf)
     int32_t ix, iy, iz;     // integer coordinates at this level
-    int16_t level, nchild;
+    int16_t level;
+    int8_t nchild;
+    uint8_t mask;           // bit o set when the child of octant o exists
 };
 static_assert(sizeof(Cell) == 32, "Cell must be 32 bytes");
 
@@ -140,7 +142,8 @@ struct Tree {
     size_t mark_tree = 0;
     // upward state
     int up_p = 0, up_method = -1, up_prec = -1;
-    double* M = nullptr;             // [ncells][p*p] FP64 scaled R-basis
+    int ldm = 0;                     // row length of M and L: p*p padded to 16
+    double* M = nullptr;             // [ncells + 1][ldm] FP64 scaled R-basis, last row 0
     double* cen = nullptr;           // [ncells][4] expansion centre + side
     void* Mk = nullptr;              // M2L operand copy [(ncells+1)][Kp]
     size_t mark_up = 0;
@@ -165,9 +168,13 @@ struct Tree {
     int ops_p = 0, ops_prec = -1;
     void* T = nullptr;               // M2L matrices
     size_t mark_ops = 0;
+    int32_t* bexp = nullptr;         // low-precision M2L row exponents
     size_t mark_bh = 0;
     // last evaluation
-    double* L = nullptr;             // [ncells][p*p] FP64 local expansions
+    double* L = nullptr;             // [ncells + 1][ldm] FP64 local expansions
+    double* xl_m2m = nullptr;        // 8 octant operators, matrix-core layout
+    double* xl_l2l = nullptr;
+    std::vector<int32_t> m2l_level_start;  // host: level -> start in m2l_order
     int ev_p = 0;
     int64_t p2p_pairs = 0, m2l_pairs = 0;
     // phase timers (HIP events on the caller's stream)

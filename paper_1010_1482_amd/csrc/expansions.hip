@@ -207,7 +207,7 @@ template <typename T, int NP>
 __global__ void __launch_bounds__(256)
 k_p2m(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
       const double4* __restrict__ cen, const double4* __restrict__ p64,
-      double* __restrict__ M) {
+      double* __restrict__ M, int ld) {
     constexpr int G = 8, P = NP * NP;
     const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int sub = threadIdx.x % G;
@@ -235,9 +235,10 @@ k_p2m(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nl
 #pragma unroll
         for (int k = 0; k < P; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
     if (active && sub == 0) {
-        double* out = M + (int64_t)c * P;
+        double* out = M + (int64_t)c * ld;
 #pragma unroll
         for (int k = 0; k < P; ++k) out[k] = (double)acc[k];
+        for (int k = P; k < ld; ++k) out[k] = 0.0;
     }
 }
 
@@ -249,7 +250,7 @@ k_p2m(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nl
 template <int NP>
 __global__ void k_m2m(const Cell* __restrict__ cells, int c0, int c1,
                       const double2* __restrict__ shift, int per_child,
-                      double* __restrict__ M) {
+                      double* __restrict__ M, int ld) {
     constexpr int P = NP * NP, NT = ntri(NP);
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = c0 + (int)(gid / NT);
@@ -265,7 +266,7 @@ __global__ void k_m2m(const Cell* __restrict__ cells, int c0, int c1,
         const int ch = cell.child + q;
         const double2* R = per_child ? shift + (int64_t)ch * NT
                                      : shift + octant_idx(cells[ch]) * NT;
-        const double* Mc = M + (int64_t)ch * P;
+        const double* Mc = M + (int64_t)ch * ld;
         for (int k = 0; k <= n; ++k)
             for (int l = -k; l <= k; ++l) {
                 const int mm = m - l;
@@ -277,63 +278,9 @@ __global__ void k_m2m(const Cell* __restrict__ cells, int c0, int c1,
             }
     }
     const double sc = ldexp(1.0, -n);
-    double* out = M + (int64_t)c * P;
+    double* out = M + (int64_t)c * ld;
     out[ridx(n, m, 0)] = sr * sc;
     if (m > 0) out[ridx(n, m, 1)] = si * sc;
-}
-
-// ---------------------------------------------------------------------
-// Downward pass at one level (FP64), one thread per (cell, output (j, i)):
-//   Lt_c = sum of the M2L partial results + P2L (X list, FP64)
-//          + L2L from the parent: sum_{n >= j} sum_m 2^-(n+1) Lt_p[n,m]
-//                                 R_{n-j}^{m-i}(u),  u = (c_c - c_p) / h_c
-// ---------------------------------------------------------------------
-template <int NP, typename TM>
-__global__ void k_downward(const Cell* __restrict__ cells, int c0, int c1,
-                           const TM* __restrict__ lm2l, int ldm, int nparts,
-                           int64_t part_stride, const double* __restrict__ lx,
-                           const double2* __restrict__ shift, int with_parent,
-                           double* __restrict__ L) {
-    constexpr int P = NP * NP, NT = ntri(NP);
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int c = c0 + (int)(gid / NT);
-    if (c >= c1) return;
-    const int t = (int)(gid % NT);
-    int j = 0;
-    while (tri(j + 1, 0) <= t) ++j;
-    const int i = t - tri(j, 0);
-    const Cell cell = cells[c];
-    double sr = 0.0, si = 0.0;
-    for (int q = 0; q < nparts; ++q) {
-        const TM* src = lm2l + q * part_stride + (int64_t)c * ldm;
-        sr += (double)src[ridx(j, i, 0)];
-        if (i > 0) si += (double)src[ridx(j, i, 1)];
-    }
-    if (lx) {
-        sr += lx[(int64_t)c * P + ridx(j, i, 0)];
-        if (i > 0) si += lx[(int64_t)c * P + ridx(j, i, 1)];
-    }
-    if (with_parent && cell.parent >= 0) {
-        const double2* R = shift + octant_idx(cell) * NT;
-        const double* Lp = L + (int64_t)cell.parent * P;
-        for (int n = j; n < NP; ++n) {
-            const double sc = ldexp(1.0, -(n + 1));
-            double tr = 0.0, ti = 0.0;
-            for (int m = -n; m <= n; ++m) {
-                const int mi = m - i;
-                if (mi > n - j || mi < -(n - j)) continue;
-                double2 x = real_get(Lp, n, m);
-                double2 r = tri_get(R, n - j, mi);
-                tr += x.x * r.x - x.y * r.y;
-                ti += x.x * r.y + x.y * r.x;
-            }
-            sr += sc * tr;
-            si += sc * ti;
-        }
-    }
-    double* out = L + (int64_t)c * P;
-    out[ridx(j, i, 0)] = sr;
-    if (i > 0) out[ridx(j, i, 1)] = si;
 }
 
 // ---------------------------------------------------------------------
@@ -345,7 +292,7 @@ template <int NP>
 __global__ void __launch_bounds__(64)
 k_p2l(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __restrict__ x_off,
       const int32_t* __restrict__ x_items, const double4* __restrict__ cen,
-      const double4* __restrict__ p64, double* __restrict__ LX) {
+      const double4* __restrict__ p64, double* __restrict__ LX, int ld) {
     constexpr int P = NP * NP;
     const int b = c0 + blockIdx.x;
     if (b >= c1) return;
@@ -371,7 +318,7 @@ k_p2l(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __restrict_
 #pragma unroll
         for (int k = 0; k < P; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
     if (lane == 0) {
-        double* out = LX + (int64_t)b * P;
+        double* out = LX + (int64_t)b * ld;
 #pragma unroll
         for (int k = 0; k < P; ++k) out[k] = acc[k];
     }
@@ -424,8 +371,7 @@ __global__ void __launch_bounds__(256)
 k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict__ cen,
       const double4* __restrict__ p64, const double* __restrict__ L,
       const int32_t* __restrict__ w_off, const int32_t* __restrict__ w_items,
-      const double* __restrict__ M, T* __restrict__ far) {
-    constexpr int P = NP * NP;
+      const double* __restrict__ M, int ld, T* __restrict__ far) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int b = leaf_of[s];
@@ -434,7 +380,7 @@ k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
     const double ihd = 1.0 / q.w;
     const T ux = (T)((pj.x - q.x) * ihd), uy = (T)((pj.y - q.y) * ihd),
             uz = (T)((pj.z - q.z) * ihd);
-    const double* Lb = L + (int64_t)b * P;
+    const double* Lb = L + (int64_t)b * ld;
     T f = T(0), gz = T(0), gr = T(0), gi = T(0);
     stream_regular<T, NP>(ux, uy, uz, [&](int k, int l, T rr, T ri) {
         const T w = l == 0 ? T(1) : T(2);
@@ -462,7 +408,7 @@ k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
             const int C = w_items[e];
             const double4 qc = cen[C];
             const double ic = 1.0 / qc.w;
-            m2p_accumulate<T, NP>(M + (int64_t)C * P, (T)((pj.x - qc.x) * ic),
+            m2p_accumulate<T, NP>(M + (int64_t)C * ld, (T)((pj.x - qc.x) * ic),
                                   (T)((pj.y - qc.y) * ic), (T)((pj.z - qc.z) * ic), (T)ic, phi,
                                   ax, ay, az);
         }
@@ -479,8 +425,7 @@ __global__ void __launch_bounds__(256)
 k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
                const double4* __restrict__ cen, const double4* __restrict__ p64,
                const int32_t* __restrict__ a_off, const int32_t* __restrict__ a_items,
-               const double* __restrict__ M, T* __restrict__ far) {
-    constexpr int P = NP * NP;
+               const double* __restrict__ M, int ld, T* __restrict__ far) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int b = leaf_of[s];
@@ -490,7 +435,7 @@ k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
         const int C = a_items[e];
         const double4 qc = cen[C];
         const double ic = 1.0 / qc.w;
-        m2p_accumulate<T, NP>(M + (int64_t)C * P, (T)((pj.x - qc.x) * ic),
+        m2p_accumulate<T, NP>(M + (int64_t)C * ld, (T)((pj.x - qc.x) * ic),
                               (T)((pj.y - qc.y) * ic), (T)((pj.z - qc.z) * ic), (T)ic, phi, ax,
                               ay, az);
     }
@@ -517,44 +462,6 @@ __device__ inline double factorial_d(int n) {
     return f;
 }
 
-// (N-|M|)! P_N^|M|(x) / rho^{N+1} with e^{i M beta}: returns (re, im)
-__device__ inline double2 m2l_kernel_coeff(int N, int M, double x, double s, double rho,
-                                           double beta) {
-    const int a = M < 0 ? -M : M;
-    // P_a^a = (-1)^a (2a-1)!! s^a (Eq. 8), then Eqs. 9 and 7 up to degree N
-    double pmm = 1.0;
-    for (int i = 1; i <= a; ++i) pmm *= -(double)(2 * i - 1) * s;
-    double pn = pmm;
-    if (N > a) {
-        double p1 = pmm, p0 = 0.0, p = x * (2 * a + 1) * pmm;
-        for (int nn = a + 1; nn < N; ++nn) {
-            double pn1 = (x * (2 * nn + 1) * p - (nn + a) * p1) / (double)(nn - a + 1);
-            p1 = p;
-            p = pn1;
-        }
-        (void)p0;
-        pn = p;
-    }
-    double v = factorial_d(N - a) * pn;
-    double r = 1.0;
-    for (int i = 0; i <= N; ++i) r *= rho;
-    v /= r;
-    return make_double2(v * cos(M * beta), v * sin(M * beta));
-}
-
-__device__ inline double ipow_even_sign(int e) {  // i^e for even e
-    return ((e / 2) & 1) ? -1.0 : 1.0;
-}
-
-__device__ inline double2 m2l_c(int j, int k, int n, int m, double x, double s, double rho,
-                                double beta) {
-    const int ak = k < 0 ? -k : k, am = m < 0 ? -m : m;
-    const int e = abs(k - m) - ak - am;
-    double sg = ipow_even_sign(e) * ((j & 1) ? -1.0 : 1.0);
-    double2 y = m2l_kernel_coeff(j + n, m - k, x, s, rho, beta);
-    return make_double2(sg * y.x, sg * y.y);
-}
-
 // real-layout index -> (n, m, part)
 __device__ inline void rdecode(int r, int& n, int& m, int& part) {
     n = 0;
@@ -569,67 +476,173 @@ __device__ inline void rdecode(int r, int& n, int& m, int& part) {
     }
 }
 
-// one thread per (class, output row ro, input column ri); writes FP64
-// T64[cls][ri][ro] (column-major per class, for the FP64 kernel) and/or the
-// FP32 matrix-core layout Tsw[cls][rb][q][lane][4] with
-// T[16 rb + (lane & 15)][16 q + 4 (lane >> 4) + r]
-__global__ void k_m2l_ops(int p, double* __restrict__ T64, float* __restrict__ T32,
-                          int RB, int KQ) {
-    const int P = p * p;
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t per = (int64_t)P * P;
-    const int cls = (int)(gid / per);
-    if (cls >= 343) return;
-    const int rem = (int)(gid % per);
-    const int ro = rem / P, ri = rem % P;
+// One block per offset class (343 blocks, 27 of them adjacent offsets that
+// stay zero).  The block tabulates, for this class, the Sec. 5.2 quantity
+// (N-|M|)! P_N^|M|(cos a) / rho^{N+1} for N <= 2p-2 (Eqs. 7-9) and
+// cos(M b), sin(M b) in LDS, then threads fill the real entries.  Writes the
+// FP64 layout T64[cls][ri][ro] and/or the FP32 matrix-core layout
+// Tsw[cls][rb][q][lane][4] with T[16 rb + (lane & 15)][16 q + 4 (lane >> 4) + r].
+constexpr int kNmax = 2 * HFMM_MAX_P - 1;
+
+// LDS table of one offset class; returns false for the 27 adjacent offsets
+__device__ inline bool m2l_class_table(int p, int cls, double (*pt)[kNmax],
+                                       double (*cs)[2]) {
+    const int ND = 2 * p - 1;
     const int dx = cls / 49 - 3, dy = (cls / 7) % 7 - 3, dz = cls % 7 - 3;
-    double val = 0.0;
-    if (max(abs(dx), max(abs(dy), abs(dz))) >= 2) {
+    const bool far = max(abs(dx), max(abs(dy), abs(dz))) >= 2;
+    if (far && (int)threadIdx.x < ND) {
+        const int a = threadIdx.x;  // order |M|
         const double vx = -dx, vy = -dy, vz = -dz;
         const double rxy = sqrt(vx * vx + vy * vy);
         const double rho = sqrt(vx * vx + vy * vy + vz * vz);
-        const double x = vz / rho, s = rxy / rho;
+        const double x = vz / rho, sn = rxy / rho;
         const double beta = (vx == 0.0 && vy == 0.0) ? 0.0 : atan2(vy, vx);
-        int j, k, po, n, m, pi;
-        rdecode(ro, j, k, po);
-        rdecode(ri, n, m, pi);
-        if (m == 0) {
-            double2 c0 = m2l_c(j, k, n, 0, x, s, rho, beta);
-            val = pi == 0 ? (po == 0 ? c0.x : c0.y) : 0.0;
-        } else {
-            double2 cp = m2l_c(j, k, n, m, x, s, rho, beta);
-            double2 cm = m2l_c(j, k, n, -m, x, s, rho, beta);
-            if (po == 0)
-                val = pi == 0 ? cp.x + cm.x : -(cp.y - cm.y);
-            else
-                val = pi == 0 ? cp.y + cm.y : cp.x - cm.x;
+        cs[a][0] = cos(a * beta);
+        cs[a][1] = sin(a * beta);
+        double pmm = 1.0;  // Eq. 8
+        for (int i = 1; i <= a; ++i) pmm *= -(double)(2 * i - 1) * sn;
+        double rinv = 1.0 / rho, rpow = rinv;  // 1 / rho^{N+1}
+        for (int i = 0; i < a; ++i) rpow *= rinv;
+        double pm1 = 0.0, pc = pmm, fct = 1.0;  // P_{N-1}, P_N, (N - a)!
+        for (int N = a; N < ND; ++N) {
+            pt[N][a] = fct * pc * rpow;
+            const double pn = N == a ? x * (2 * a + 1) * pmm                                 // Eq. 9
+                                     : (x * (2 * N + 1) * pc - (N + a) * pm1) / (N - a + 1);  // Eq. 7
+            pm1 = pc;
+            pc = pn;
+            fct *= (double)(N - a + 1);
+            rpow *= rinv;
         }
     }
-    if (T64) T64[(int64_t)cls * per + (int64_t)ri * P + ro] = val;
-    if (T32) {
+    __syncthreads();
+    return far;
+}
+
+// real entry (row ro, column ri) of the class operator from its table:
+// c(j,k,n,+-m) = i^{|k-m|-|k|-|m|} (-1)^j pt[j+n][|m-k|] e^{i (m-k) b}
+__device__ inline double m2l_entry(int ro, int ri, const double (*pt)[kNmax],
+                                   const double (*cs)[2]) {
+    int j, k, po, n, m, pi;
+    rdecode(ro, j, k, po);
+    rdecode(ri, n, m, pi);
+    auto coef = [&](int mm) {
+        const int M = mm - k, aM = M < 0 ? -M : M;
+        const int ev = abs(k - mm) - abs(k) - abs(mm);
+        const double sg = (((ev / 2) & 1) ? -1.0 : 1.0) * ((j & 1) ? -1.0 : 1.0);
+        const double v = sg * pt[j + n][aM];
+        return make_double2(v * cs[aM][0], v * (M < 0 ? -cs[aM][1] : cs[aM][1]));
+    };
+    if (m == 0) {
+        double2 c0 = coef(0);
+        return pi == 0 ? (po == 0 ? c0.x : c0.y) : 0.0;
+    }
+    double2 cp = coef(m), cm = coef(-m);
+    if (po == 0) return pi == 0 ? cp.x + cm.x : -(cp.y - cm.y);
+    return pi == 0 ? cp.y + cm.y : cp.x - cm.x;
+}
+
+// One block per offset class (343 blocks, 27 of them adjacent offsets that
+// stay zero).  The block tabulates, for this class, the Sec. 5.2 quantity
+// (N-|M|)! P_N^|M|(cos a) / rho^{N+1} for N <= 2p-2 (Eqs. 7-9) and
+// cos(M b), sin(M b) in LDS, then threads fill the real entries.  Writes the
+// FP64 layout T64[cls][ri][ro] and/or the FP32 matrix-core layout
+// Tsw[cls][rb][q][lane][4] with T[16 rb + (lane & 15)][16 q + 4 (lane >> 4) + r].
+__global__ void __launch_bounds__(256)
+k_m2l_ops(int p, double* __restrict__ T64, float* __restrict__ T32, int RB, int KQ) {
+    __shared__ double pt[kNmax][kNmax];
+    __shared__ double cs[kNmax][2];
+    const int P = p * p;
+    const int cls = blockIdx.x;
+    const bool far = m2l_class_table(p, cls, pt, cs);
+    const int64_t per = (int64_t)P * P;
+    for (int64_t e = threadIdx.x; e < per; e += blockDim.x) {
+        const int ro = (int)(e / P), ri = (int)(e % P);
+        const double val = far ? m2l_entry(ro, ri, pt, cs) : 0.0;
+        if (T64) T64[(int64_t)cls * per + (int64_t)ri * P + ro] = val;
+        if (T32) {
+            const int rb = ro / 16, il = ro % 16;
+            const int q = ri / 16, g = (ri % 16) / 4, r = ri % 4;
+            const int lane = g * 16 + il;
+            T32[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 4 + r] = (float)val;
+        }
+    }
+}
+
+__device__ inline int mu_exp_d(int n) {  // floor(log2((sqrt3/2)^n / n!))
+    double v = 1.0;
+    for (int i = 1; i <= n; ++i) v *= 0.8660254037844386 / (double)i;
+    return ilogb(v);
+}
+
+// Low-precision operators.  pass 0: bexp[j] = max exponent of T_{jn} 2^{mu_n}
+// over classes and columns; pass 1: T' = T 2^{mu_n - b_j}, b_j = bexp[j] + 1,
+// split into hi and lo (lo may be null) in the layout
+// [cls][rb][q][lane][8], element (16 rb + (lane & 15), 32 q + 8 (lane >> 4) + j).
+template <typename T16>
+__global__ void __launch_bounds__(256)
+k_m2l_ops_lp(int p, int pass, int RB, int KQ, int32_t* __restrict__ bexp,
+             T16* __restrict__ hi, T16* __restrict__ lo) {
+    __shared__ double pt[kNmax][kNmax];
+    __shared__ double cs[kNmax][2];
+    const int P = p * p;
+    const int cls = blockIdx.x;
+    const bool far = m2l_class_table(p, cls, pt, cs);
+    const int R = 16 * RB, K = 32 * KQ;
+    const int64_t per = (int64_t)R * K;
+    for (int64_t e = threadIdx.x; e < per; e += blockDim.x) {
+        const int ro = (int)(e / K), ri = (int)(e % K);
+        double val = 0.0;
+        int j = 0, n = 0;
+        if (far && ro < P && ri < P) {
+            val = m2l_entry(ro, ri, pt, cs);
+            j = 0;
+            while ((j + 1) * (j + 1) <= ro) ++j;
+            while ((n + 1) * (n + 1) <= ri) ++n;
+        }
+        if (pass == 0) {
+            if (val != 0.0) atomicMax(&bexp[j], ilogb(fabs(val)) + mu_exp_d(n));
+            continue;
+        }
+        double t = val == 0.0 ? 0.0 : ldexp(val, mu_exp_d(n) - (bexp[j] + 1));
         const int rb = ro / 16, il = ro % 16;
-        const int q = ri / 16, g = (ri % 16) / 4, r = ri % 4;
-        const int lane = g * 16 + il;
-        T32[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 4 + r] = (float)val;
+        const int q = ri / 32, g = (ri % 32) / 8, jj = ri % 8;
+        const int64_t idx = ((((int64_t)cls * RB + rb) * KQ + q) * 64 + g * 16 + il) * 8 + jj;
+        const T16 h = (T16)(float)t;
+        hi[idx] = h;
+        if (lo) lo[idx] = (T16)(float)(t - (double)(float)h);
+    }
+}
+
+void run_m2l_ops_lp(int p, int precision, int RB, int KQ, int32_t* bexp, void* hi, void* lo,
+                    hipStream_t s) {
+    const bool bf = precision == HFMM_M2L_BF16 || precision == HFMM_M2L_BF16X3;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (bf)
+            hipLaunchKernelGGL((k_m2l_ops_lp<__bf16>), dim3(343), dim3(256), 0, s, p, pass, RB,
+                               KQ, bexp, (__bf16*)hi, (__bf16*)lo);
+        else
+            hipLaunchKernelGGL((k_m2l_ops_lp<_Float16>), dim3(343), dim3(256), 0, s, p, pass,
+                               RB, KQ, bexp, (_Float16*)hi, (_Float16*)lo);
+        LAUNCH_CHECK();
     }
 }
 
 // pack Mt (FP64, p*p per cell) into the M2L operand: ld = Kp (zero padded),
 // one extra zero row at index ncells for absent sources
 template <typename TO>
-__global__ void k_pack(const double* __restrict__ M, int ncells, int P, int ld,
+__global__ void k_pack(const double* __restrict__ M, int ldm, int ncells, int P, int ld,
                        TO* __restrict__ out) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)(ncells + 1) * ld;
     if (gid >= tot) return;
     const int c = (int)(gid / ld), k = (int)(gid % ld);
-    double v = (c < ncells && k < P) ? M[(int64_t)c * P + k] : 0.0;
+    double v = (c < ncells && k < P) ? M[(int64_t)c * ldm + k] : 0.0;
     out[gid] = (TO)v;
 }
 
 // device basis -> the paper's normalisation:
 //   M_n^m = h^n Mt_n^m / A_n^m,  L_n^m = A_n^m Lt_n^m / h^{n+1}
-__global__ void k_export(const double* __restrict__ X, int ncells, int p,
+__global__ void k_export(const double* __restrict__ X, int ld, int ncells, int p,
                          const double4* __restrict__ cen, int which,
                          double* __restrict__ out) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -644,7 +657,7 @@ __global__ void k_export(const double* __restrict__ X, int ncells, int p,
     double hn = 1.0;
     for (int i = 0; i < n; ++i) hn *= h;
     const double f = which == 0 ? hn / A : A / (hn * h);
-    const double* Xc = X + (int64_t)c * p * p;
+    const double* Xc = X + (int64_t)c * ld;
     out[gid * 2] = f * Xc[ridx(n, m, 0)];
     out[gid * 2 + 1] = m == 0 ? 0.0 : f * Xc[ridx(n, m, 1)];
 }
@@ -702,39 +715,39 @@ void run_p2m(Tree& t, int p, bool fp64, hipStream_t s) {
     if (fp64)                                                                              \
         hipLaunchKernelGGL((k_p2m<double, NP>), dim3(grid_for(threads, 256)), dim3(256), 0, \
                            s, t.cells, t.leaves, t.nleaves, (const double4*)t.cen, t.p64,   \
-                           t.M);                                                            \
+                           t.M, t.ldm);                                                     \
     else                                                                                    \
         hipLaunchKernelGGL((k_p2m<float, NP>), dim3(grid_for(threads, 256)), dim3(256), 0,  \
                            s, t.cells, t.leaves, t.nleaves, (const double4*)t.cen, t.p64,   \
-                           t.M);
+                           t.M, t.ldm);
     HFMM_DISPATCH_P(p, P2M_CASE);
 #undef P2M_CASE
     LAUNCH_CHECK();
 }
 
-void run_m2m(Tree& t, int p, bool per_child, hipStream_t s) {
+void run_shift_octants(int p, double2* tab, hipStream_t s) {
+#define SH_CASE(NP) hipLaunchKernelGGL((k_shift_octants<NP>), dim3(1), dim3(64), 0, s, tab);
+    HFMM_DISPATCH_P(p, SH_CASE);
+#undef SH_CASE
+    LAUNCH_CHECK();
+}
+
+// M2M with a shift vector per child (centres of mass, treecode)
+void run_m2m(Tree& t, int p, hipStream_t s) {
     const int NT = p * (p + 1) / 2;
-    double2* tab;
-    if (per_child) {
-        tab = t.arena.down<double2>((size_t)t.ncells * NT);
+    double2* tab = t.arena.down<double2>((size_t)t.ncells * NT);
 #define SH_CASE(NP)                                                                           \
     hipLaunchKernelGGL((k_shift_children<NP>), dim3(grid_for(t.ncells, 128)), dim3(128), 0, s, \
                        t.cells, t.ncells, (const double4*)t.cen, tab);
-        HFMM_DISPATCH_P(p, SH_CASE);
+    HFMM_DISPATCH_P(p, SH_CASE);
 #undef SH_CASE
-    } else {
-        tab = t.arena.down<double2>((size_t)8 * NT);
-#define SH_CASE(NP) hipLaunchKernelGGL((k_shift_octants<NP>), dim3(1), dim3(64), 0, s, tab);
-        HFMM_DISPATCH_P(p, SH_CASE);
-#undef SH_CASE
-    }
     LAUNCH_CHECK();
     for (int l = t.depth - 1; l >= 0; --l) {
         int c0 = t.level_start[l], c1 = t.level_start[l + 1];
         int64_t threads = (int64_t)(c1 - c0) * NT;
 #define M2M_CASE(NP)                                                                     \
     hipLaunchKernelGGL((k_m2m<NP>), dim3(grid_for(threads, 128)), dim3(128), 0, s, t.cells, \
-                       c0, c1, tab, per_child ? 1 : 0, t.M);
+                       c0, c1, tab, 1, t.M, t.ldm);
         HFMM_DISPATCH_P(p, M2M_CASE);
 #undef M2M_CASE
         LAUNCH_CHECK();
@@ -743,20 +756,19 @@ void run_m2m(Tree& t, int p, bool per_child, hipStream_t s) {
 
 void run_m2l_ops(Tree& t, int p, bool fp64, double* T64, float* T32, int RB, int KQ,
                  hipStream_t s) {
-    const int64_t threads = (int64_t)343 * p * p * p * p;
-    hipLaunchKernelGGL(k_m2l_ops, dim3(grid_for(threads, 256)), dim3(256), 0, s, p,
-                       fp64 ? T64 : nullptr, fp64 ? nullptr : T32, RB, KQ);
+    hipLaunchKernelGGL(k_m2l_ops, dim3(343), dim3(256), 0, s, p, fp64 ? T64 : nullptr,
+                       fp64 ? nullptr : T32, RB, KQ);
     LAUNCH_CHECK();
 }
 
-void run_pack(const double* M, int ncells, int P, int ld, void* out, bool fp64,
+void run_pack(const double* M, int ldm, int ncells, int P, int ld, void* out, bool fp64,
               hipStream_t s) {
     const int64_t tot = (int64_t)(ncells + 1) * ld;
     if (fp64)
-        hipLaunchKernelGGL((k_pack<double>), dim3(grid_for(tot, 256)), dim3(256), 0, s, M,
+        hipLaunchKernelGGL((k_pack<double>), dim3(grid_for(tot, 256)), dim3(256), 0, s, M, ldm,
                            ncells, P, ld, (double*)out);
     else
-        hipLaunchKernelGGL((k_pack<float>), dim3(grid_for(tot, 256)), dim3(256), 0, s, M,
+        hipLaunchKernelGGL((k_pack<float>), dim3(grid_for(tot, 256)), dim3(256), 0, s, M, ldm,
                            ncells, P, ld, (float*)out);
     LAUNCH_CHECK();
 }
@@ -766,37 +778,10 @@ void run_p2l(Tree& t, int p, double* LX, hipStream_t s) {
     int c0 = t.level_start[2], c1 = t.ncells;
 #define P2L_CASE(NP)                                                                        \
     hipLaunchKernelGGL((k_p2l<NP>), dim3(c1 - c0), dim3(64), 0, s, t.cells, c0, c1, t.x_off, \
-                       t.x_items, (const double4*)t.cen, t.p64, LX);
+                       t.x_items, (const double4*)t.cen, t.p64, LX, t.ldm);
     HFMM_DISPATCH_P(p, P2L_CASE);
 #undef P2L_CASE
     LAUNCH_CHECK();
-}
-
-void run_downward(Tree& t, int p, const void* lm2l, bool m2l_fp64, int ldm, int nparts,
-                  int64_t part_stride, const double* LX, hipStream_t s) {
-    const int NT = p * (p + 1) / 2;
-    double2* tab = t.arena.down<double2>((size_t)8 * NT);
-#define SH_CASE(NP) hipLaunchKernelGGL((k_shift_octants<NP>), dim3(1), dim3(64), 0, s, tab);
-    HFMM_DISPATCH_P(p, SH_CASE);
-#undef SH_CASE
-    LAUNCH_CHECK();
-    for (int l = 2; l <= t.depth; ++l) {
-        int c0 = t.level_start[l], c1 = t.level_start[l + 1];
-        int64_t threads = (int64_t)(c1 - c0) * NT;
-        int wp = l >= 3 ? 1 : 0;
-#define DW_CASE(NP)                                                                           \
-    if (m2l_fp64)                                                                             \
-        hipLaunchKernelGGL((k_downward<NP, double>), dim3(grid_for(threads, 128)), dim3(128),  \
-                           0, s, t.cells, c0, c1, (const double*)lm2l, ldm, nparts,            \
-                           part_stride, LX, tab, wp, t.L);                                     \
-    else                                                                                       \
-        hipLaunchKernelGGL((k_downward<NP, float>), dim3(grid_for(threads, 128)), dim3(128),   \
-                           0, s, t.cells, c0, c1, (const float*)lm2l, ldm, nparts,             \
-                           part_stride, LX, tab, wp, t.L);
-        HFMM_DISPATCH_P(p, DW_CASE);
-#undef DW_CASE
-        LAUNCH_CHECK();
-    }
 }
 
 void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
@@ -805,11 +790,11 @@ void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
     if (fp64)                                                                              \
         hipLaunchKernelGGL((k_far<double, NP>), dim3(grid_for(t.n, 256)), dim3(256), 0, s,  \
                            t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,               \
-                           w ? t.w_off : nullptr, t.w_items, t.M, (double*)far);            \
+                           w ? t.w_off : nullptr, t.w_items, t.M, t.ldm, (double*)far);     \
     else                                                                                    \
         hipLaunchKernelGGL((k_far<float, NP>), dim3(grid_for(t.n, 256)), dim3(256), 0, s,   \
                            t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,               \
-                           w ? t.w_off : nullptr, t.w_items, t.M, (float*)far);
+                           w ? t.w_off : nullptr, t.w_items, t.M, t.ldm, (float*)far);
     HFMM_DISPATCH_P(p, FAR_CASE);
 #undef FAR_CASE
     LAUNCH_CHECK();
@@ -820,20 +805,20 @@ void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
     if (fp64)                                                                                \
         hipLaunchKernelGGL((k_treecode_far<double, NP>), dim3(grid_for(t.n, 256)), dim3(256), \
                            0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,       \
-                           t.a_items, t.M, (double*)far);                                     \
+                           t.a_items, t.M, t.ldm, (double*)far);                              \
     else                                                                                      \
         hipLaunchKernelGGL((k_treecode_far<float, NP>), dim3(grid_for(t.n, 256)), dim3(256),  \
                            0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,       \
-                           t.a_items, t.M, (float*)far);
+                           t.a_items, t.M, t.ldm, (float*)far);
     HFMM_DISPATCH_P(p, TF_CASE);
 #undef TF_CASE
     LAUNCH_CHECK();
 }
 
-void run_export(const double* X, int ncells, int p, const double* cen, int which,
+void run_export(const double* X, int ld, int ncells, int p, const double* cen, int which,
                 double* out, hipStream_t s) {
     const int64_t tot = (int64_t)ncells * p * (p + 1) / 2;
-    hipLaunchKernelGGL(k_export, dim3(grid_for(tot, 256)), dim3(256), 0, s, X, ncells, p,
+    hipLaunchKernelGGL(k_export, dim3(grid_for(tot, 256)), dim3(256), 0, s, X, ld, ncells, p,
                        (const double4*)cen, which, out);
     LAUNCH_CHECK();
 }

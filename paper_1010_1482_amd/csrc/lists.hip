@@ -37,28 +37,39 @@ __device__ inline int octant_of(const Cell& c) {
 // ---------------------------------------------------------------------
 // colleagues, one level at a time (parents first)
 // ---------------------------------------------------------------------
+// colleagues stored by offset: slot (ex+1)*9 + (ey+1)*3 + (ez+1) holds the
+// same-level cell at B + e, or -1.  The cell at B + e is the child of octant
+// (B + e) & 1 of the parent-level cell at (B + e) >> 1, which is the parent's
+// colleague at offset ((B + e) >> 1) - parent.
 __global__ void k_colleagues(const Cell* __restrict__ cells, int c0, int c1,
                              int32_t* __restrict__ coll) {
     int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
     int32_t* out = coll + (int64_t)c * kColl;
     Cell B = cells[c];
-    int k = 0;
     if (B.parent < 0) {
-        out[k++] = c;
-    } else {
-        const int32_t* pc = coll + (int64_t)B.parent * kColl;
-        for (int q = 0; q < kColl; ++q) {
-            int C = pc[q];
-            if (C < 0) break;
-            Cell cc = cells[C];
-            for (int i = 0; i < cc.nchild; ++i) {
-                int D = cc.child + i;
-                if (k < kColl && cells_adjacent(cells[D], B)) out[k++] = D;
-            }
-        }
+        for (int q = 0; q < kColl; ++q) out[q] = q == 13 ? c : -1;
+        return;
     }
-    for (; k < kColl; ++k) out[k] = -1;
+    const int32_t* pc = coll + (int64_t)B.parent * kColl;
+    const int px = B.ix >> 1, py = B.iy >> 1, pz = B.iz >> 1;
+    for (int ex = -1; ex <= 1; ++ex)
+        for (int ey = -1; ey <= 1; ++ey)
+            for (int ez = -1; ez <= 1; ++ez) {
+                const int X = B.ix + ex, Y = B.iy + ey, Z = B.iz + ez;
+                int res = -1;
+                if (X >= 0 && Y >= 0 && Z >= 0) {
+                    const int qx = (X >> 1) - px, qy = (Y >> 1) - py, qz = (Z >> 1) - pz;
+                    const int C = pc[(qx + 1) * 9 + (qy + 1) * 3 + (qz + 1)];
+                    if (C >= 0) {
+                        const Cell cc = cells[C];
+                        const int o = ((X & 1) << 2) | ((Y & 1) << 1) | (Z & 1);
+                        if ((cc.mask >> o) & 1)
+                            res = cc.child + __popc((unsigned)cc.mask & ((1u << o) - 1u));
+                    }
+                }
+                out[(ex + 1) * 9 + (ey + 1) * 3 + (ez + 1)] = res;
+            }
 }
 
 // V list by slot, for every cell of level >= 2; vcount[c] = entries
@@ -76,7 +87,7 @@ __global__ void k_vlist(const Cell* __restrict__ cells, int c0, int c1,
         const int32_t* pc = coll + (int64_t)B.parent * kColl;
         for (int q = 0; q < kColl; ++q) {
             int C = pc[q];
-            if (C < 0) break;
+            if (C < 0) continue;
             Cell cc = cells[C];
             for (int i = 0; i < cc.nchild; ++i) {
                 int D = cc.child + i;
@@ -128,7 +139,7 @@ __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __r
             const int32_t* ca = coll + (int64_t)A * kColl;
             for (int q = 0; q < kColl; ++q) {
                 int C = ca[q];
-                if (C < 0) break;
+                if (C < 0) continue;
                 Cell cc = cells[C];
                 if (cc.nchild != 0) continue;
                 if (cells_adjacent(cc, P) && !cells_adjacent(cc, B)) {
@@ -144,7 +155,7 @@ __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __r
             const int32_t* ca = coll + (int64_t)A * kColl;
             for (int q = 0; q < kColl; ++q) {
                 int C = ca[q];
-                if (C < 0) break;
+                if (C < 0) continue;
                 Cell cc = cells[C];
                 if (cc.nchild == 0 && cells_adjacent(cc, B)) {
                     if (fill) pu[nu] = C;
@@ -157,7 +168,7 @@ __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __r
         int stack[kStack];
         for (int q = 0; q < kColl; ++q) {
             int C = cb[q];
-            if (C < 0) break;
+            if (C < 0) continue;
             Cell cc = cells[C];
             if (cc.nchild == 0) {
                 if (fill) pu[nu] = C;
@@ -197,17 +208,26 @@ __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __r
 // ---------------------------------------------------------------------
 // M2L tiles: targets of level >= 2 ordered by (level, octant)
 // ---------------------------------------------------------------------
+constexpr int kGroups = 8 * (HFMM_KEY_LEVELS + 2);
+
 __global__ void k_m2l_keys(const Cell* __restrict__ cells, int c0, int nc,
                            uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
                            int32_t* __restrict__ counts) {
+    __shared__ int hist[kGroups];
+    for (int k = threadIdx.x; k < kGroups; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     int c = c0 + i;
-    if (c >= nc) return;
-    Cell B = cells[c];
-    int k = B.level * 8 + octant_of(B);
-    keys[i] = (uint64_t)k;
-    vals[i] = c;
-    atomicAdd(&counts[k], 1);
+    if (c < nc) {
+        Cell B = cells[c];
+        int k = B.level * 8 + octant_of(B);
+        keys[i] = (uint64_t)k;
+        vals[i] = c;
+        atomicAdd(&hist[k], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kGroups; k += blockDim.x)
+        if (hist[k]) atomicAdd(&counts[k], hist[k]);
 }
 
 void build_fmm_lists(Tree& t, hipStream_t s) {
@@ -273,6 +293,12 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
                        nullptr, nullptr, nullptr, t.u_off, t.w_off, t.x_off, t.u_items,
                        t.w_items, t.x_items);
     LAUNCH_CHECK();
+    t.m2l_level_start.assign(t.depth + 2, 0);
+    for (int l = 0; l <= t.depth; ++l) {
+        int acc = t.m2l_level_start[l];
+        for (int o = 0; o < 8; ++o) acc += gc[l * 8 + o];
+        t.m2l_level_start[l + 1] = acc;
+    }
     // tiles of up to 256 targets that share (level, octant)
     std::vector<int32_t> tiles;
     int start = 0;

@@ -92,7 +92,7 @@ __global__ void k_scan_blocks(const int32_t* __restrict__ in, int64_t n,
         s += v[k];
     }
     int tot;
-    int ex = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+    int ex = block_exclusive_scan(s, &tot) + (part ? part[blockIdx.x] : 0);
 #pragma unroll
     for (int k = 0; k < kItems; ++k) {
         int64_t i = base + (int64_t)threadIdx.x * kItems + k;
@@ -100,7 +100,7 @@ __global__ void k_scan_blocks(const int32_t* __restrict__ in, int64_t n,
         ex += v[k];
     }
     if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
-        out[n] = part[gridDim.x];
+        out[n] = part ? part[gridDim.x] : tot;
 }
 
 void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, Arena& A,
@@ -111,6 +111,12 @@ void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, Arena& A,
         return;
     }
     int nb = grid_for(n, kTile);
+    if (nb == 1) {  // one block: no partial sums needed
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, in, n,
+                           (const int32_t*)nullptr, out, 1);
+        LAUNCH_CHECK();
+        return;
+    }
     int32_t* part = A.down<int32_t>(nb + 1);
     hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kBlock), 0, s, in, n, part);
     LAUNCH_CHECK();
@@ -306,14 +312,34 @@ __global__ void k_bbox_partial(const double* __restrict__ x, const double* __res
 
 __global__ void k_bbox_final(const double* __restrict__ part, int nparts, Root* root) {
 #pragma clang fp contract(off)
-    if (threadIdx.x != 0) return;
+    // 256 threads: strided partial min/max, then a tree in LDS (min and max
+    // are exact, so the order does not matter)
+    __shared__ double sm[6][256];
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nparts; ++b)
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
         for (int a = 0; a < 3; ++a) {
             lo[a] = fmin(lo[a], part[b * 6 + a]);
             hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
         }
+    for (int a = 0; a < 3; ++a) {
+        sm[a][threadIdx.x] = lo[a];
+        sm[3 + a][threadIdx.x] = hi[a];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int a = 0; a < 3; ++a) {
+                sm[a][threadIdx.x] = fmin(sm[a][threadIdx.x], sm[a][threadIdx.x + w]);
+                sm[3 + a][threadIdx.x] = fmax(sm[3 + a][threadIdx.x], sm[3 + a][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = sm[a][0];
+        hi[a] = sm[3 + a][0];
+    }
     double R = 0.0, c[3];
     for (int a = 0; a < 3; ++a) {
         c[a] = (lo[a] + hi[a]) / 2.0;
@@ -435,11 +461,13 @@ __global__ void k_split_emit(Cell* __restrict__ cells, int c0, int c1, int next0
     if (nk == 0) {
         cells[c].child = -1;
         cells[c].nchild = 0;
+        cells[c].mask = 0;
         return;
     }
     int shift = 3 * (HFMM_KEY_LEVELS - cell.level - 1);
     int beg = cell.first, end = cell.first + cell.count;
     int prev = beg, out = next0 + k;
+    unsigned mask = 0;
     for (int o = 0; o < 8; ++o) {
         int b = o < 7 ? lower_bound_digit(keys, prev, end, shift, o + 1) : end;
         if (b > prev) {
@@ -453,12 +481,15 @@ __global__ void k_split_emit(Cell* __restrict__ cells, int c0, int c1, int next0
             ch.iz = 2 * cell.iz + (o & 1);
             ch.level = (int16_t)(cell.level + 1);
             ch.nchild = 0;
+            ch.mask = 0;
             cells[out++] = ch;
+            mask |= 1u << o;
         }
         prev = b;
     }
     cells[c].child = next0 + k;
-    cells[c].nchild = (int16_t)nk;
+    cells[c].nchild = (int8_t)nk;
+    cells[c].mask = (uint8_t)mask;
 }
 
 __global__ void k_leaf_flags(const Cell* __restrict__ cells, int nc, int32_t* __restrict__ f) {
@@ -510,7 +541,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, x, y, z, tx, ty, tz,
                        t.ns, n, part, hbuf);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, part, nbb, t.root);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nbb, t.root);
     LAUNCH_CHECK();
     int32_t nbad = 0;
     HIP_TRY(hipMemcpyAsync(&nbad, hbuf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -545,6 +576,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
         root.ix = root.iy = root.iz = 0;
         root.level = 0;
         root.nchild = 0;
+        root.mask = 0;
         HIP_TRY(hipMemcpyAsync(t.cells, &root, sizeof(Cell), hipMemcpyHostToDevice, s));
         t.level_start.assign(1, 0);
         t.level_start.push_back(1);

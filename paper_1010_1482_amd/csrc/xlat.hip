@@ -1,0 +1,281 @@
+// M2M and L2L of the FMM (Sec. 2) as FP64 matrix-core products.
+//
+// With geometric centres, a child sits at u = (ox - 1/2, oy - 1/2, oz - 1/2)
+// child sides from its parent, so in the level-scaled device basis both
+// translations are one of 8 fixed real p^2 x p^2 operators:
+//   M2M  Mt_p[n,m]  = 2^-n      sum_{k,l} conj(R_k^l(u)) Mt_c[n-k, m-l]
+//   L2L  Lt_c[j,i]  = sum_{n,m} 2^-(n+1) Lt_p[n,m] R_{n-j}^{m-i}(u)
+// (R addition theorem).  The operators are built once per order from R(u)
+// and applied with v_mfma_f64_16x16x4f64: one wave takes 16 targets
+// (columns), rows are output coefficients in blocks of 16, the contraction
+// runs over input coefficients k = 16 q + 4 g + r as in the M2L kernel.
+// M2M: targets = parents, one product per child octant; L2L: targets =
+// children, one product with the operator of the child's octant, plus the
+// M2L partial sums and the X-list P2L in the epilogue.
+#include "common.hpp"
+#include "expansions.hpp"
+
+namespace hfmm {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// R_k^l from the stored m >= 0 triangle: R_k^{-l} = (-1)^l conj(R_k^l);
+// zero when |l| > k
+__device__ inline double2 rget(const double2* R, int k, int l) {
+    const int a = l < 0 ? -l : l;
+    if (k < 0 || a > k) return make_double2(0.0, 0.0);
+    double2 v = R[tri(k, a)];
+    if (l >= 0) return v;
+    const double s = (a & 1) ? -1.0 : 1.0;
+    return make_double2(s * v.x, -s * v.y);
+}
+
+__device__ inline void rdecode2(int r, int& n, int& m, int& part) {
+    n = 0;
+    while ((n + 1) * (n + 1) <= r) ++n;
+    const int o = r - n * n;
+    if (o == 0) {
+        m = 0;
+        part = 0;
+    } else {
+        m = (o + 1) / 2;
+        part = (o + 1) % 2;
+    }
+}
+
+// real entry of the map X -> c+ X + c- conj(X) for (output part, input part)
+__device__ inline double real_entry(double2 cp, double2 cm, int m_in, int po, int pi) {
+    if (m_in == 0) return pi == 0 ? (po == 0 ? cp.x : cp.y) : 0.0;
+    if (po == 0) return pi == 0 ? cp.x + cm.x : -(cp.y - cm.y);
+    return pi == 0 ? cp.y + cm.y : cp.x - cm.x;
+}
+
+// one thread per (octant, padded output row, padded input column)
+__global__ void k_xlat_ops(int p, int RB, int KQ, const double2* __restrict__ tab,
+                           double* __restrict__ m2m, double* __restrict__ l2l) {
+    const int P = p * p, NT = p * (p + 1) / 2;
+    const int R = 16 * RB, K = 16 * KQ;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)8 * R * K) return;
+    const int o = (int)(gid / ((int64_t)R * K));
+    const int rem = (int)(gid % ((int64_t)R * K));
+    const int ro = rem / K, ri = rem % K;
+    double vm = 0.0, vl = 0.0;
+    if (ro < P && ri < P) {
+        const double2* Rt = tab + o * NT;
+        int n, m, po, n2, m2, pi;
+        rdecode2(ro, n, m, po);
+        rdecode2(ri, n2, m2, pi);
+        // M2M: output (n, m), input (n2, m2), k = n - n2
+        {
+            const int k = n - n2;
+            const double sc = ldexp(1.0, -n);
+            double2 a = rget(Rt, k, m - m2);
+            double2 cp = make_double2(sc * a.x, -sc * a.y);
+            double2 cm = make_double2(0.0, 0.0);
+            if (m2 > 0) {
+                double2 b = rget(Rt, k, m + m2);
+                const double sg = (m2 & 1) ? -sc : sc;
+                cm = make_double2(sg * b.x, -sg * b.y);
+            }
+            vm = real_entry(cp, cm, m2, po, pi);
+        }
+        // L2L: output (j = n, i = m), input (n2, m2), k = n2 - j
+        {
+            const int k = n2 - n;
+            const double sc = ldexp(1.0, -(n2 + 1));
+            double2 a = rget(Rt, k, m2 - m);
+            double2 cp = make_double2(sc * a.x, sc * a.y);
+            double2 cm = make_double2(0.0, 0.0);
+            if (m2 > 0) {
+                double2 b = rget(Rt, k, -m2 - m);
+                const double sg = (m2 & 1) ? -sc : sc;
+                cm = make_double2(sg * b.x, sg * b.y);
+            }
+            vl = real_entry(cp, cm, m2, po, pi);
+        }
+    }
+    const int rb = ro / 16, il = ro % 16, q = ri / 16, g = (ri % 16) / 4, r = ri % 4;
+    const int64_t idx = ((((int64_t)o * RB + rb) * KQ + q) * 64 + (g * 16 + il)) * 4 + r;
+    m2m[idx] = vm;
+    l2l[idx] = vl;
+}
+
+__device__ inline int degree_of_row(int r) {
+    int n = 0;
+    while ((n + 1) * (n + 1) <= r) ++n;
+    return n;
+}
+
+__device__ inline int child_by_octant(const Cell& c, int o) {
+    if (!((c.mask >> o) & 1)) return -1;
+    return c.child + __popc((unsigned)c.mask & ((1u << o) - 1u));
+}
+
+__device__ inline int octant_of_cell(const Cell& c) {
+    return ((c.ix & 1) << 2) | ((c.iy & 1) << 1) | (c.iz & 1);
+}
+
+// mode 0: M2M into parents (targets = c0 + i); mode 1: L2L into children
+// (targets listed, grouped by octant), out = bias + L2L(parent)
+template <int RB, int KQ, typename TB>
+__global__ void __launch_bounds__(256)
+k_xlat_f64(const Cell* __restrict__ cells, const int32_t* __restrict__ targets, int c0,
+           int ntargets, int mode, int with_parent, const double* __restrict__ Tsw,
+           const double* __restrict__ in, double* __restrict__ out, int ld, int zero_row,
+           const TB* __restrict__ parts, int nparts, int64_t part_stride,
+           const double* __restrict__ lx, int P, const int32_t* __restrict__ bexp,
+           const int32_t* __restrict__ levexp) {
+    constexpr int NTE = RB * KQ * 64;  // 32-byte entries per operator
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, col = lane & 15;
+    const int base = (blockIdx.x * 4 + wave) * 16;
+    if (base >= ntargets) return;
+    const int ti = base + col;
+    const int tgt = ti < ntargets ? (targets ? targets[ti] : c0 + ti) : -1;
+    Cell tc;
+    if (tgt >= 0) tc = cells[tgt];
+    doublex4 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const int nslots = mode == 0 ? 8 : 1;
+    for (int s = 0; s < nslots; ++s) {
+        int src = -1, cls = 0;
+        if (tgt >= 0) {
+            if (mode == 0) {
+                cls = s;
+                src = child_by_octant(tc, s);
+            } else {
+                cls = octant_of_cell(tc);
+                src = with_parent ? tc.parent : -1;
+            }
+        }
+        uint64_t todo = __ballot(src >= 0);
+        while (todo) {
+            const int leader = __ffsll((unsigned long long)todo) - 1;
+            const int c = __shfl(cls, leader, 64);
+            const bool mine = src >= 0 && cls == c;
+            todo &= ~__ballot(mine);
+            const double* B = in + (int64_t)(mine ? src : zero_row) * ld + 4 * g;
+            const double4* A = (const double4*)Tsw + (int64_t)c * NTE;
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+                const double4 b = *(const double4*)(B + 16 * q);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const double4 a = A[(rb * KQ + q) * 64 + lane];
+                    doublex4 v = acc[rb];
+                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, v, 0, 0, 0);
+                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, v, 0, 0, 0);
+                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.z, b.z, v, 0, 0, 0);
+                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.w, b.w, v, 0, 0, 0);
+                    acc[rb] = v;
+                }
+            }
+        }
+    }
+    if (tgt < 0) return;
+    if (mode == 0 && tc.nchild == 0) return;  // leaves keep their P2M expansion
+    // v_mfma_f64_16x16x4f64 leaves row 4 r + g of column col in register r
+    double* o = out + (int64_t)tgt * ld;
+    double lfac = 0.0;
+    if (mode == 1 && levexp) lfac = (double)(levexp[tc.level] + 1);
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        doublex4 v = acc[rb];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rb + 4 * r + g;
+            double x = v[r];
+            if (mode == 1) {
+                const int64_t off = (int64_t)tgt * ld + row;
+                double ps = 0.0;
+                for (int q = 0; q < nparts; ++q) ps += (double)parts[q * part_stride + off];
+                if (bexp && row < P) ps = ldexp(ps, bexp[degree_of_row(row)] + 1 + (int)lfac);
+                x += ps;
+                if (lx) x += lx[off];
+            }
+            o[row] = x;
+        }
+    }
+}
+
+#define HFMM_DISPATCH_RB16(R, F) \
+    switch (R) {                 \
+        case 1: F(1); break;     \
+        case 2: F(2); break;     \
+        case 3: F(3); break;     \
+        case 4: F(4); break;     \
+        case 5: F(5); break;     \
+        case 6: F(6); break;     \
+        case 7: F(7); break;     \
+        case 8: F(8); break;     \
+        case 9: F(9); break;     \
+        case 10: F(10); break;   \
+        case 11: F(11); break;   \
+        case 12: F(12); break;   \
+        case 13: F(13); break;   \
+        case 14: F(14); break;   \
+        case 15: F(15); break;   \
+        case 16: F(16); break;   \
+        default: throw Status{HFMM_E_UNSUPPORTED}; \
+    }
+
+void prepare_xlat_ops(Tree& t, int p, hipStream_t s) {
+    const int RB = (p * p + 15) / 16;
+    const size_t per = (size_t)8 * RB * RB * 64 * 4;
+    t.xl_m2m = t.arena.up<double>(per);
+    t.xl_l2l = t.arena.up<double>(per);
+    double2* tab = t.arena.down<double2>((size_t)8 * p * (p + 1) / 2);
+    run_shift_octants(p, tab, s);
+    const int64_t threads = (int64_t)8 * 16 * RB * 16 * RB;
+    hipLaunchKernelGGL(k_xlat_ops, dim3(grid_for(threads, 256)), dim3(256), 0, s, p, RB, RB,
+                       (const double2*)tab, t.xl_m2m, t.xl_l2l);
+    LAUNCH_CHECK();
+}
+
+void run_m2m_mfma(Tree& t, int p, hipStream_t s) {
+    const int RB = (p * p + 15) / 16;
+    for (int l = t.depth - 1; l >= 0; --l) {
+        const int c0 = t.level_start[l], c1 = t.level_start[l + 1];
+        const int nt = c1 - c0;
+        dim3 grid((nt + 63) / 64), block(256);
+#define M2M_CASE(R)                                                                           \
+    hipLaunchKernelGGL((k_xlat_f64<R, R, double>), grid, block, 0, s, t.cells,                \
+                       (const int32_t*)nullptr, c0, nt, 0, 0, t.xl_m2m, t.M, t.M, t.ldm,     \
+                       t.ncells, (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, \
+                       p * p, (const int32_t*)nullptr, (const int32_t*)nullptr);
+        HFMM_DISPATCH_RB16(RB, M2M_CASE);
+#undef M2M_CASE
+        LAUNCH_CHECK();
+    }
+}
+
+void run_l2l_mfma(Tree& t, int p, const void* parts, bool parts_fp64, int nparts,
+                  int64_t part_stride, const double* LX, const int32_t* bexp,
+                  const int32_t* levexp, hipStream_t s) {
+    const int RB = (p * p + 15) / 16;
+    for (int l = 2; l <= t.depth; ++l) {
+        const int i0 = t.m2l_level_start[l], i1 = t.m2l_level_start[l + 1];
+        const int nt = i1 - i0;
+        if (nt == 0) continue;
+        dim3 grid((nt + 63) / 64), block(256);
+        const int wp = l >= 3 ? 1 : 0;
+#define L2L_CASE(R)                                                                         \
+    if (parts_fp64)                                                                         \
+        hipLaunchKernelGGL((k_xlat_f64<R, R, double>), grid, block, 0, s, t.cells,           \
+                           t.m2l_order + i0, 0, nt, 1, wp, t.xl_l2l, t.L, t.L, t.ldm,       \
+                           t.ncells, (const double*)parts, nparts, part_stride, LX, p * p,  \
+                           bexp, levexp);                                                  \
+    else                                                                                    \
+        hipLaunchKernelGGL((k_xlat_f64<R, R, float>), grid, block, 0, s, t.cells,            \
+                           t.m2l_order + i0, 0, nt, 1, wp, t.xl_l2l, t.L, t.L, t.ldm,       \
+                           t.ncells, (const float*)parts, nparts, part_stride, LX, p * p,   \
+                           bexp, levexp);
+        HFMM_DISPATCH_RB16(RB, L2L_CASE);
+#undef L2L_CASE
+        LAUNCH_CHECK();
+    }
+}
+
+}  // namespace hfmm

@@ -221,3 +221,30 @@ def test_coincident_points():
     out = host(H().solve(*to_dev(x, y, z, m), p=6, method="fmm", precision="fp64", leaf_max=8))
     for a, b in zip(out, ref):
         assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
+
+
+# ---------------------------------------------------------------- precision form
+# Tolerances from the arithmetic: an M2L product with both operands rounded to
+# a format of unit roundoff u is off by at most ~2u relative; the hi/lo split
+# leaves the dropped lo*lo term and the two representation errors, ~3u^2.
+# BF16: u = 2^-8, FP16: u = 2^-11 (after the power-of-two range scaling).
+_U = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11}
+_TOL = {"bf16": 2 * _U["bf16"], "fp16": 2 * _U["fp16"],
+        "bf16x3": 3 * _U["bf16"] ** 2, "fp16x3": max(3 * _U["fp16"] ** 2, 1e-5)}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "bf16x3", "fp16", "fp16x3"])
+@pytest.mark.parametrize("dist,n,leaf,p", [("uniform", 16384, 64, 8),
+                                           ("uniform", 20000, 64, 12),
+                                           ("plummer", 8000, 16, 8)])
+def test_fmm_low_precision_m2l(prec, dist, n, leaf, p):
+    say(f"fmm {prec} {dist} n={n} leaf={leaf} p={p}")
+    x, y, z, m = W.make(dist, n, 49)
+    tg = W.sample_targets(n, 512, 8)
+    ref = O.fmm(x, y, z, m, p, leaf, targets=tg)
+    out = host(H().solve(*to_dev(x, y, z, m), p=p, method="fmm", precision=prec,
+                         leaf_max=leaf))
+    out = [o[tg] for o in out]
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs oracle fmm: phi {ephi:.2e} acc {eacc:.2e} (tol {_TOL[prec]:.1e})")
+    assert ephi <= _TOL[prec] and eacc <= _TOL[prec]
