@@ -128,15 +128,21 @@ k_m2l_mfma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const float4 a4 = sT[(rb * KQ + q) * 64 + lane];
+                // the four column blocks are independent accumulators:
+                // interleave them so no instruction waits on the previous one
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    if (!act[cb]) continue;
-                    floatx4 c = acc[cb][rb];
-                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4[cb].x, c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4[cb].y, c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4[cb].z, c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4[cb].w, c, 0, 0, 0);
-                    acc[cb][rb] = c;
+                for (int r = 0; r < 4; ++r) {
+                    const float av = r == 0 ? a4.x : r == 1 ? a4.y : r == 2 ? a4.z : a4.w;
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb) {
+                        if (!act[cb]) continue;
+                        const float bv = r == 0   ? b4[cb].x
+                                         : r == 1 ? b4[cb].y
+                                         : r == 2 ? b4[cb].z
+                                                  : b4[cb].w;
+                        acc[cb][rb] =
+                            __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[cb][rb], 0, 0, 0);
+                    }
                 }
             }
         }
@@ -297,15 +303,15 @@ k_m2l_mfma_lp(const int32_t* __restrict__ tiles, const int32_t* __restrict__ ord
                 V al;
                 if (X3) al = sT[NT + (rb * KQ + q) * 64 + lane];
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    if (!act[cb]) continue;
-                    floatx4 c = acc[cb][rb];
-                    c = LowP<T16>::mma(ah, bh[cb], c);
-                    if (X3) {
-                        c = LowP<T16>::mma(ah, bl[cb], c);
-                        c = LowP<T16>::mma(al, bh[cb], c);
-                    }
-                    acc[cb][rb] = c;
+                for (int cb = 0; cb < 4; ++cb)
+                    if (act[cb]) acc[cb][rb] = LowP<T16>::mma(ah, bh[cb], acc[cb][rb]);
+                if (X3) {
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        if (act[cb]) acc[cb][rb] = LowP<T16>::mma(ah, bl[cb], acc[cb][rb]);
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        if (act[cb]) acc[cb][rb] = LowP<T16>::mma(al, bh[cb], acc[cb][rb]);
                 }
             }
         }

@@ -116,87 +116,154 @@ __device__ inline int octant_of_cell(const Cell& c) {
     return ((c.ix & 1) << 2) | ((c.iy & 1) << 1) | (c.iz & 1);
 }
 
-// mode 0: M2M into parents (targets = c0 + i); mode 1: L2L into children
-// (targets listed, grouped by octant), out = bias + L2L(parent)
-template <int RB, int KQ, typename TB>
-__global__ void __launch_bounds__(256)
-k_xlat_f64(const Cell* __restrict__ cells, const int32_t* __restrict__ targets, int c0,
-           int ntargets, int mode, int with_parent, const double* __restrict__ Tsw,
-           const double* __restrict__ in, double* __restrict__ out, int ld, int zero_row,
-           const TB* __restrict__ parts, int nparts, int64_t part_stride,
-           const double* __restrict__ lx, int P, const int32_t* __restrict__ bexp,
-           const int32_t* __restrict__ levexp) {
-    constexpr int NTE = RB * KQ * 64;  // 32-byte entries per operator
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = lane >> 4, col = lane & 15;
-    const int base = (blockIdx.x * 4 + wave) * 16;
-    if (base >= ntargets) return;
-    const int ti = base + col;
-    const int tgt = ti < ntargets ? (targets ? targets[ti] : c0 + ti) : -1;
-    Cell tc;
-    if (tgt >= 0) tc = cells[tgt];
-    doublex4 acc[RB];
+__host__ __device__ constexpr int isqrt_c(int r) {
+    int n = 0;
+    while ((n + 1) * (n + 1) <= r) ++n;
+    return n;
+}
+
+// Block (rb, q) of an operator is structurally zero when no output degree of
+// rows 16 rb .. 16 rb + 15 can draw on an input degree of columns
+// 16 q .. 16 q + 15: M2M maps degree n2 into degrees n >= n2, L2L degree n2
+// into degrees j <= n2.
+template <int MODE>
+__host__ __device__ constexpr bool block_live(int rb, int q) {
+    return MODE == 0 ? isqrt_c(16 * q) <= isqrt_c(16 * rb + 15)
+                     : isqrt_c(16 * q + 15) >= isqrt_c(16 * rb);
+}
+
+// acc[rb] += A(cls) * B over the live blocks; independent accumulators are
+// interleaved so that consecutive matrix-core instructions do not depend on
+// each other.
+template <int RB, int KQ, int MODE>
+__device__ __forceinline__ void xlat_accumulate(doublex4 (&acc)[RB], const double4* A,
+                                                const double* B, int lane) {
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) acc[rb] = doublex4{0.0, 0.0, 0.0, 0.0};
-    const int nslots = mode == 0 ? 8 : 1;
-    for (int s = 0; s < nslots; ++s) {
-        int src = -1, cls = 0;
-        if (tgt >= 0) {
-            if (mode == 0) {
-                cls = s;
-                src = child_by_octant(tc, s);
-            } else {
-                cls = octant_of_cell(tc);
-                src = with_parent ? tc.parent : -1;
-            }
-        }
-        uint64_t todo = __ballot(src >= 0);
-        while (todo) {
-            const int leader = __ffsll((unsigned long long)todo) - 1;
-            const int c = __shfl(cls, leader, 64);
-            const bool mine = src >= 0 && cls == c;
-            todo &= ~__ballot(mine);
-            const double* B = in + (int64_t)(mine ? src : zero_row) * ld + 4 * g;
-            const double4* A = (const double4*)Tsw + (int64_t)c * NTE;
+    for (int q = 0; q < KQ; ++q) {
+        const double4 b = *(const double4*)(B + 16 * q);
+        double4 a[RB];
 #pragma unroll
-            for (int q = 0; q < KQ; ++q) {
-                const double4 b = *(const double4*)(B + 16 * q);
+        for (int rb = 0; rb < RB; ++rb)
+            if (block_live<MODE>(rb, q)) a[rb] = A[(rb * KQ + q) * 64 + lane];
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const double4 a = A[(rb * KQ + q) * 64 + lane];
-                    doublex4 v = acc[rb];
-                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, v, 0, 0, 0);
-                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, v, 0, 0, 0);
-                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.z, b.z, v, 0, 0, 0);
-                    v = __builtin_amdgcn_mfma_f64_16x16x4f64(a.w, b.w, v, 0, 0, 0);
-                    acc[rb] = v;
-                }
+        for (int r = 0; r < 4; ++r) {
+            const double bv = r == 0 ? b.x : r == 1 ? b.y : r == 2 ? b.z : b.w;
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                if (!block_live<MODE>(rb, q)) continue;
+                const double av = r == 0 ? a[rb].x : r == 1 ? a[rb].y : r == 2 ? a[rb].z : a[rb].w;
+                acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rb], 0, 0, 0);
             }
         }
     }
-    if (tgt < 0) return;
-    if (mode == 0 && tc.nchild == 0) return;  // leaves keep their P2M expansion
-    // v_mfma_f64_16x16x4f64 leaves row 4 r + g of column col in register r
-    double* o = out + (int64_t)tgt * ld;
-    double lfac = 0.0;
-    if (mode == 1 && levexp) lfac = (double)(levexp[tc.level] + 1);
+}
+
+// M2M: a block of 8 waves takes 16 parents of one level; wave w applies the
+// operator of child octant w, the 8 results are summed in LDS in a fixed
+// order and written as whole rows.  Leaves keep their P2M expansion.
+template <int RB, int KQ>
+__global__ void __launch_bounds__(512)
+k_m2m_f64(const Cell* __restrict__ cells, int c0, int ntargets,
+          const double* __restrict__ Tsw, double* __restrict__ M, int ld, int zero_row) {
+    constexpr int NTE = RB * KQ * 64;
+    constexpr int LDR = 16 * RB + 1;  // padded LDS row
+    __shared__ double red[16 * LDR];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, col = lane & 15;
+    const int ti = blockIdx.x * 16 + col;
+    const int tgt = ti < ntargets ? c0 + ti : -1;
+    int src = -1;
+    if (tgt >= 0) src = child_by_octant(cells[tgt], wave);
+    doublex4 acc[RB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        doublex4 v = acc[rb];
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = doublex4{0.0, 0.0, 0.0, 0.0};
+    if (__ballot(src >= 0))
+        xlat_accumulate<RB, KQ, 0>(acc, (const double4*)Tsw + (int64_t)wave * NTE,
+                                   M + (int64_t)(src >= 0 ? src : zero_row) * ld + 4 * g, lane);
+    for (int w = 0; w < 8; ++w) {
+        if (wave == w) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * rb + 4 * r + g;
-            double x = v[r];
-            if (mode == 1) {
-                const int64_t off = (int64_t)tgt * ld + row;
-                double ps = 0.0;
-                for (int q = 0; q < nparts; ++q) ps += (double)parts[q * part_stride + off];
-                if (bexp && row < P) ps = ldexp(ps, bexp[degree_of_row(row)] + 1 + (int)lfac);
-                x += ps;
-                if (lx) x += lx[off];
-            }
-            o[row] = x;
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * rb + 4 * r + g;  // f64 16x16x4 output layout
+                    double* d = &red[col * LDR + row];
+                    *d = (w == 0 ? 0.0 : *d) + acc[rb][r];
+                }
         }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < 16 * 16 * RB; e += blockDim.x) {
+        const int c = e / (16 * RB), row = e % (16 * RB);
+        const int t = blockIdx.x * 16 + c;
+        if (t >= ntargets) continue;
+        const int cell = c0 + t;
+        if (cells[cell].nchild == 0) continue;
+        M[(int64_t)cell * ld + row] = red[c * LDR + row];
+    }
+}
+
+// L2L: a block of 4 waves takes 64 children (16 per wave, listed grouped by
+// octant); out = L2L(parent) + sum of the M2L partial results (+ P2L),
+// combined through LDS so that the partials are read along whole rows.
+// Low-precision M2L partials are rescaled by 2^(b_j + e_level + 1).
+template <int RB, int KQ, typename TB>
+__global__ void __launch_bounds__(256)
+k_l2l_f64(const Cell* __restrict__ cells, const int32_t* __restrict__ targets, int ntargets,
+          int with_parent, const double* __restrict__ Tsw, double* __restrict__ L, int ld,
+          int zero_row, const TB* __restrict__ parts, int nparts, int64_t part_stride,
+          const double* __restrict__ lx, int P, const int32_t* __restrict__ bexp,
+          const int32_t* __restrict__ levexp) {
+    constexpr int NTE = RB * KQ * 64;
+    constexpr int LDR = 16 * RB + 1;
+    __shared__ double red[64 * LDR];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, col = lane & 15;
+    const int ti = blockIdx.x * 64 + wave * 16 + col;
+    const int tgt = ti < ntargets ? targets[ti] : -1;
+    int src = -1, cls = 0;
+    if (tgt >= 0 && with_parent) {
+        const Cell tc = cells[tgt];
+        cls = octant_of_cell(tc);
+        src = tc.parent;
+    }
+    doublex4 acc[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[rb] = doublex4{0.0, 0.0, 0.0, 0.0};
+    uint64_t todo = __ballot(src >= 0);
+    while (todo) {  // one product per distinct child octant in the wave
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int c = __shfl(cls, leader, 64);
+        const bool mine = src >= 0 && cls == c;
+        todo &= ~__ballot(mine);
+        doublex4 part[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) part[rb] = doublex4{0.0, 0.0, 0.0, 0.0};
+        xlat_accumulate<RB, KQ, 1>(part, (const double4*)Tsw + (int64_t)c * NTE,
+                                   L + (int64_t)(mine ? src : zero_row) * ld + 4 * g, lane);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+            if (mine) acc[rb] += part[rb];
+    }
+    const int lc = wave * 16 + col;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[lc * LDR + 16 * rb + 4 * r + g] = acc[rb][r];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 16 * RB; e += blockDim.x) {
+        const int c = e / (16 * RB), row = e % (16 * RB);
+        const int t = blockIdx.x * 64 + c;
+        if (t >= ntargets) continue;
+        const int cell = targets[t];
+        const int64_t off = (int64_t)cell * ld + row;
+        double ps = 0.0;
+        for (int q = 0; q < nparts; ++q) ps += (double)parts[q * part_stride + off];
+        if (bexp && row < P)
+            ps = ldexp(ps, bexp[isqrt_c(row)] + 1 + levexp[cells[cell].level] + 1);
+        double v = red[c * LDR + row] + ps;
+        if (lx) v += lx[off];
+        L[off] = v;
     }
 }
 
@@ -239,12 +306,10 @@ void run_m2m_mfma(Tree& t, int p, hipStream_t s) {
     for (int l = t.depth - 1; l >= 0; --l) {
         const int c0 = t.level_start[l], c1 = t.level_start[l + 1];
         const int nt = c1 - c0;
-        dim3 grid((nt + 63) / 64), block(256);
-#define M2M_CASE(R)                                                                           \
-    hipLaunchKernelGGL((k_xlat_f64<R, R, double>), grid, block, 0, s, t.cells,                \
-                       (const int32_t*)nullptr, c0, nt, 0, 0, t.xl_m2m, t.M, t.M, t.ldm,     \
-                       t.ncells, (const double*)nullptr, 0, (int64_t)0, (const double*)nullptr, \
-                       p * p, (const int32_t*)nullptr, (const int32_t*)nullptr);
+        dim3 grid((nt + 15) / 16), block(512);
+#define M2M_CASE(R)                                                                        \
+    hipLaunchKernelGGL((k_m2m_f64<R, R>), grid, block, 0, s, t.cells, c0, nt, t.xl_m2m, t.M, \
+                       t.ldm, t.ncells);
         HFMM_DISPATCH_RB16(RB, M2M_CASE);
 #undef M2M_CASE
         LAUNCH_CHECK();
@@ -263,15 +328,14 @@ void run_l2l_mfma(Tree& t, int p, const void* parts, bool parts_fp64, int nparts
         const int wp = l >= 3 ? 1 : 0;
 #define L2L_CASE(R)                                                                         \
     if (parts_fp64)                                                                         \
-        hipLaunchKernelGGL((k_xlat_f64<R, R, double>), grid, block, 0, s, t.cells,           \
-                           t.m2l_order + i0, 0, nt, 1, wp, t.xl_l2l, t.L, t.L, t.ldm,       \
-                           t.ncells, (const double*)parts, nparts, part_stride, LX, p * p,  \
-                           bexp, levexp);                                                  \
+        hipLaunchKernelGGL((k_l2l_f64<R, R, double>), grid, block, 0, s, t.cells,            \
+                           t.m2l_order + i0, nt, wp, t.xl_l2l, t.L, t.ldm, t.ncells,         \
+                           (const double*)parts, nparts, part_stride, LX, p * p, bexp,      \
+                           levexp);                                                         \
     else                                                                                    \
-        hipLaunchKernelGGL((k_xlat_f64<R, R, float>), grid, block, 0, s, t.cells,            \
-                           t.m2l_order + i0, 0, nt, 1, wp, t.xl_l2l, t.L, t.L, t.ldm,       \
-                           t.ncells, (const float*)parts, nparts, part_stride, LX, p * p,   \
-                           bexp, levexp);
+        hipLaunchKernelGGL((k_l2l_f64<R, R, float>), grid, block, 0, s, t.cells,             \
+                           t.m2l_order + i0, nt, wp, t.xl_l2l, t.L, t.ldm, t.ncells,         \
+                           (const float*)parts, nparts, part_stride, LX, p * p, bexp, levexp);
         HFMM_DISPATCH_RB16(RB, L2L_CASE);
 #undef L2L_CASE
         LAUNCH_CHECK();
