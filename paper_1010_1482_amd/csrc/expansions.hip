@@ -584,8 +584,10 @@ k_m2l_ops_lp(int p, int pass, int RB, int KQ, int32_t* __restrict__ bexp,
              T16* __restrict__ hi, T16* __restrict__ lo) {
     __shared__ double pt[kNmax][kNmax];
     __shared__ double cs[kNmax][2];
+    __shared__ int bmax[kNmax];  // pass 0: block maximum per output degree
     const int P = p * p;
     const int cls = blockIdx.x;
+    if (threadIdx.x < kNmax) bmax[threadIdx.x] = INT_MIN;
     const bool far = m2l_class_table(p, cls, pt, cs);
     const int R = 16 * RB, K = 32 * KQ;
     const int64_t per = (int64_t)R * K;
@@ -600,7 +602,7 @@ k_m2l_ops_lp(int p, int pass, int RB, int KQ, int32_t* __restrict__ bexp,
             while ((n + 1) * (n + 1) <= ri) ++n;
         }
         if (pass == 0) {
-            if (val != 0.0) atomicMax(&bexp[j], ilogb(fabs(val)) + mu_exp_d(n));
+            if (val != 0.0) atomicMax(&bmax[j], ilogb(fabs(val)) + mu_exp_d(n));
             continue;
         }
         double t = val == 0.0 ? 0.0 : ldexp(val, mu_exp_d(n) - (bexp[j] + 1));
@@ -610,6 +612,11 @@ k_m2l_ops_lp(int p, int pass, int RB, int KQ, int32_t* __restrict__ bexp,
         const T16 h = (T16)(float)t;
         hi[idx] = h;
         if (lo) lo[idx] = (T16)(float)(t - (double)(float)h);
+    }
+    if (pass == 0) {
+        __syncthreads();
+        if ((int)threadIdx.x < p && bmax[threadIdx.x] != INT_MIN)
+            atomicMax(&bexp[threadIdx.x], bmax[threadIdx.x]);
     }
 }
 

@@ -299,18 +299,25 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
         for (int o = 0; o < 8; ++o) acc += gc[l * 8 + o];
         t.m2l_level_start[l + 1] = acc;
     }
-    // tiles of up to 256 targets that share (level, octant)
+    // tiles of up to 256 targets that share (level, octant), listed as
+    // (level, k, octant) for the k-th tile of each octant: the eight tiles
+    // of one k cover the same stretch of Morton order, so they read nearly
+    // the same source expansions
     std::vector<int32_t> tiles;
-    int start = 0;
-    for (size_t g = 0; g < gc.size(); ++g) {
-        int cntg = gc[g];
-        for (int k = 0; k < cntg; k += 256) {
-            tiles.push_back(start + k);
-            tiles.push_back(std::min(256, cntg - k));
-            tiles.push_back((int)(g % 8));
-            tiles.push_back((int)(g / 8));
-        }
-        start += cntg;
+    std::vector<int> gstart(gc.size() + 1, 0);
+    for (size_t g = 0; g < gc.size(); ++g) gstart[g + 1] = gstart[g] + gc[g];
+    for (int l = 0; l <= HFMM_KEY_LEVELS + 1; ++l) {
+        int kmax = 0;
+        for (int o = 0; o < 8; ++o) kmax = std::max(kmax, gc[l * 8 + o]);
+        for (int k = 0; k < kmax; k += 256)
+            for (int o = 0; o < 8; ++o) {
+                const int g = l * 8 + o;
+                if (k >= gc[g]) continue;
+                tiles.push_back(gstart[g] + k);
+                tiles.push_back(std::min(256, gc[g] - k));
+                tiles.push_back(o);
+                tiles.push_back(l);
+            }
     }
     t.n_m2l_tiles = (int32_t)(tiles.size() / 4);
     t.m2l_tiles = A.up<int32_t>(std::max<size_t>(tiles.size(), 4));

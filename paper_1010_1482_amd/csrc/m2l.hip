@@ -66,100 +66,6 @@ k_m2l_valu(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __rest
     }
 }
 
-// ---------------------------------------------------------------------
-// FP32 matrix-core M2L.  Block = 4 waves, tile = up to 256 targets of one
-// (level, octant), 64 per wave (4 column blocks of 16).  blockIdx.y selects a
-// contiguous range of slots; each range writes its own partial result,
-// summed later in the downward pass (deterministic, no atomics).
-// ---------------------------------------------------------------------
-template <int RB, int KQ>
-__global__ void __launch_bounds__(256)
-k_m2l_mfma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
-           const int32_t* __restrict__ vsrc, const float* __restrict__ Mk, int ncells,
-           const float* __restrict__ Tsw, float* __restrict__ out, int64_t part_stride,
-           int slots_per_part) {
-    constexpr int KP = 16 * KQ;
-    constexpr int NT = RB * KQ * 64;  // float4 entries of one T_d
-    __shared__ float4 sT[NT];
-    const int tile = blockIdx.x, part = blockIdx.y;
-    const int start = tiles[4 * tile], count = tiles[4 * tile + 1], oct = tiles[4 * tile + 2];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = lane >> 4, col = lane & 15;
-    int tgt[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        const int i = wave * 64 + cb * 16 + col;
-        tgt[cb] = i < count ? order[start + i] : -1;
-    }
-    floatx4 acc[4][RB];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int ox = (oct >> 2) & 1, oy = (oct >> 1) & 1, oz = oct & 1;
-    const int s0 = part * slots_per_part, s1 = min(216, s0 + slots_per_part);
-    for (int slot = s0; slot < s1; ++slot) {
-        const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
-        if (max(abs(dx), max(abs(dy), abs(dz))) <= 1) continue;  // adjacent: never in V
-        const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
-        int src[4];
-        bool any = false;
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            src[cb] = tgt[cb] >= 0 ? vsrc[(int64_t)tgt[cb] * 216 + slot] : -1;
-            any |= src[cb] >= 0;
-        }
-        if (!__syncthreads_or(any)) continue;
-        const float4* Tg = (const float4*)Tsw + (int64_t)cls * NT;
-        for (int i = threadIdx.x; i < NT; i += 256) sT[i] = Tg[i];
-        __syncthreads();
-        bool act[4];
-        const float* Bp[4];
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            act[cb] = __ballot(src[cb] >= 0) != 0;
-            Bp[cb] = Mk + (int64_t)(src[cb] >= 0 ? src[cb] : ncells) * KP + 4 * g;
-        }
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            float4 b4[4];
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb) b4[cb] = *(const float4*)(Bp[cb] + 16 * q);
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const float4 a4 = sT[(rb * KQ + q) * 64 + lane];
-                // the four column blocks are independent accumulators:
-                // interleave them so no instruction waits on the previous one
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float av = r == 0 ? a4.x : r == 1 ? a4.y : r == 2 ? a4.z : a4.w;
-#pragma unroll
-                    for (int cb = 0; cb < 4; ++cb) {
-                        if (!act[cb]) continue;
-                        const float bv = r == 0   ? b4[cb].x
-                                         : r == 1 ? b4[cb].y
-                                         : r == 2 ? b4[cb].z
-                                                  : b4[cb].w;
-                        acc[cb][rb] =
-                            __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[cb][rb], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // output block (rb): lane holds rows 16 rb + 4 g + (0..3) of column col
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        if (tgt[cb] < 0) continue;
-        float* o = out + part * part_stride + (int64_t)tgt[cb] * KP + 4 * g;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            floatx4 c = acc[cb][rb];
-            *(float4*)(o + 16 * rb) = make_float4(c[0], c[1], c[2], c[3]);
-        }
-    }
-}
 
 
 // ---------------------------------------------------------------------
@@ -232,93 +138,205 @@ __global__ void k_pack_lp(const Cell* __restrict__ cells, const double* __restri
     if (lo) lo[gid] = (T16)(float)(v - (double)(float)h);
 }
 
-template <int RB, int KQ, typename T16, bool X3>
-__global__ void __launch_bounds__(256)
-k_m2l_mfma_lp(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
-              const int32_t* __restrict__ vsrc, const T16* __restrict__ Mhi,
-              const T16* __restrict__ Mlo, int ncells, const T16* __restrict__ Thi,
-              const T16* __restrict__ Tlo, float* __restrict__ out, int64_t part_stride,
-              int slots_per_part) {
-    using V = typename LowP<T16>::vec;
-    constexpr int KP = 32 * KQ;        // padded contraction length of the operand
-    constexpr int LDO = 16 * RB;       // output row length
-    constexpr int NT = RB * KQ * 64;   // 16-byte entries of one operator
-    __shared__ V sT[(X3 ? 2 : 1) * NT];
-    const int tile = blockIdx.x, part = blockIdx.y;
+// ---------------------------------------------------------------------
+// Matrix-core M2L.  Block = 4 waves, tile = up to 256 targets of one
+// (level, octant), 64 per wave (4 column blocks of 16).  blockIdx.y selects a
+// contiguous range of slots; each range writes its own partial result,
+// summed later in the downward pass (deterministic, no atomics).
+//
+// Both operands travel in 16-byte chunks: chunk 4 q + g of a row holds the
+// contraction elements that lane group g feeds to step q.  For FP32 a chunk
+// is 4 floats (four 16x16x4 products), for BF16/FP16 8 halves (one 16x16x32
+// product).  Per slot the operator T_d is copied to LDS with direct
+// global-to-LDS loads, the next active slot's source indices and the first
+// source chunks are requested before the barrier, and the source chunks of
+// step q + 1 are in flight while step q runs on the matrix cores.
+// ---------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct OpF32 {
+    using E = float;
+    static constexpr bool X3 = false;
+    static constexpr int S = 4;  // products per (q, rb, cb)
+    template <int s>
+    static __device__ __forceinline__ floatx4 mma(u32x4 ah, u32x4, u32x4 bh, u32x4,
+                                                  floatx4 c) {
+        // whole-vector casts: a bit_cast of one vector element loses its
+        // index with this compiler (every s would read element 0)
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(floatx4, ah)[s],
+                                                    __builtin_bit_cast(floatx4, bh)[s], c, 0, 0,
+                                                    0);
+    }
+};
+
+template <typename T16, bool SPLIT>
+struct OpLow {
+    using E = T16;
+    static constexpr bool X3 = SPLIT;
+    static constexpr int S = SPLIT ? 3 : 1;  // hi*hi (+ hi*lo + lo*hi)
+    template <int s>
+    static __device__ __forceinline__ floatx4 mma(u32x4 ah, u32x4 al, u32x4 bh, u32x4 bl,
+                                                  floatx4 c) {
+        using V = typename LowP<T16>::vec;
+        const u32x4 a = s == 2 ? al : ah;
+        const u32x4 b = s == 1 ? bl : bh;
+        return LowP<T16>::mma(__builtin_bit_cast(V, a), __builtin_bit_cast(V, b), c);
+    }
+};
+
+// column blocks of 16 targets per wave (8 waves per 256-target tile)
+constexpr int kM2LCB = 2;
+typedef __attribute__((address_space(3))) void* lds_ptr;
+typedef const __attribute__((address_space(1))) void* gbl_ptr;
+
+template <int RB, int KQ, int CB, class Op>
+__global__ void __launch_bounds__(1024 / CB)
+k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
+          const int32_t* __restrict__ vsrc, const typename Op::E* __restrict__ Mhi,
+          const typename Op::E* __restrict__ Mlo, int ncells,
+          const typename Op::E* __restrict__ Thi, const typename Op::E* __restrict__ Tlo,
+          float* __restrict__ out, int64_t part_stride, int slots_per_part) {
+    constexpr int NT = RB * KQ * 64;  // 16-byte chunks of one operator
+    constexpr int CPR = 4 * KQ;       // 16-byte chunks per operand row
+    constexpr int LDO = 16 * RB;      // output row length (floats)
+    constexpr int NS = Op::X3 ? 2 : 1;
+    constexpr int NW = 16 / CB;       // waves per block (CB column blocks each)
+    __shared__ u32x4 sT[NS * NT];
+    __shared__ uint32_t smask[8];
+    // Workgroups are handed to the 8 XCDs round-robin; renumber them so that
+    // each XCD (own L2) runs one contiguous range of (tile, part), parts
+    // fastest: the blocks resident on an XCD then share source expansions.
+    const int nparts = gridDim.y, nb = gridDim.x * nparts;
+    const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+    const int xcd = lin & 7, q8 = nb >> 3, r8 = nb & 7;
+    const int logical = xcd * q8 + min(xcd, r8) + (lin >> 3);
+    const int tile = logical / nparts, part = logical % nparts;
     const int start = tiles[4 * tile], count = tiles[4 * tile + 1], oct = tiles[4 * tile + 2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, col = lane & 15;
-    int tgt[4];
+    const int s0 = part * slots_per_part, ns = min(216, s0 + slots_per_part) - s0;
+    const int ox = (oct >> 2) & 1, oy = (oct >> 1) & 1, oz = oct & 1;
+
+    // slots of this range in which some target of the tile has a source
+    if (threadIdx.x < 8) smask[threadIdx.x] = 0u;
+    __syncthreads();
+    if ((int)threadIdx.x < count) {
+        const int32_t* row = vsrc + (int64_t)order[start + threadIdx.x] * 216 + s0;
+        for (int w = 0; w * 32 < ns; ++w) {
+            uint32_t bits = 0u;
+            const int nb = min(32, ns - 32 * w);
+            for (int j = 0; j < nb; ++j) bits |= (row[32 * w + j] >= 0 ? 1u : 0u) << j;
+            if (bits) atomicOr(&smask[w], bits);
+        }
+    }
+    __syncthreads();
+    // kept in registers: LDS reads would have to wait for the operator copies
+    uint32_t mw[7];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        const int i = wave * 64 + cb * 16 + col;
+    for (int w = 0; w < 7; ++w) mw[w] = __builtin_amdgcn_readfirstlane(smask[w]);
+    auto next_slot = [&](int j) -> int {  // first active slot >= j, else ns
+#pragma unroll
+        for (int w = 0; w < 7; ++w) {
+            if (j < 32 * w + 32) {
+                const uint32_t b = j > 32 * w ? mw[w] & (~0u << (j - 32 * w)) : mw[w];
+                if (b) return 32 * w + __builtin_ctz(b);
+            }
+        }
+        return ns;
+    };
+
+    int tgt[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int i = (wave * CB + cb) * 16 + col;
         tgt[cb] = i < count ? order[start + i] : -1;
     }
-    floatx4 acc[4][RB];
+    floatx4 acc[CB][RB];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int ox = (oct >> 2) & 1, oy = (oct >> 1) & 1, oz = oct & 1;
-    const int s0 = part * slots_per_part, s1 = min(216, s0 + slots_per_part);
-    for (int slot = s0; slot < s1; ++slot) {
+
+    const u32x4* Mh = (const u32x4*)Mhi;
+    const u32x4* Ml = (const u32x4*)Mlo;
+    int j = next_slot(0);
+    int src[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+        src[cb] = (j < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + j] : -1;
+    while (j < ns) {
+        const int slot = s0 + j;
         const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
-        if (max(abs(dx), max(abs(dy), abs(dz))) <= 1) continue;
         const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
-        int src[4];
-        bool any = false;
-#pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            src[cb] = tgt[cb] >= 0 ? vsrc[(int64_t)tgt[cb] * 216 + slot] : -1;
-            any |= src[cb] >= 0;
-        }
-        if (!__syncthreads_or(any)) continue;
+        // operator of this slot -> LDS (each wave copies every 4th 1-KiB chunk)
         {
-            const V* th = (const V*)Thi + (int64_t)cls * NT;
-            for (int i = threadIdx.x; i < NT; i += 256) sT[i] = th[i];
-            if (X3) {
-                const V* tl = (const V*)Tlo + (int64_t)cls * NT;
-                for (int i = threadIdx.x; i < NT; i += 256) sT[NT + i] = tl[i];
+            const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
+            for (int k = wave; k < RB * KQ; k += NW)
+                __builtin_amdgcn_global_load_lds((gbl_ptr)(th + k * 64 + lane),
+                                                 (lds_ptr)(sT + k * 64), 16, 0, 0);
+            if (Op::X3) {
+                const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
+                for (int k = wave; k < RB * KQ; k += NW)
+                    __builtin_amdgcn_global_load_lds((gbl_ptr)(tl + k * 64 + lane),
+                                                     (lds_ptr)(sT + NT + k * 64), 16, 0, 0);
             }
         }
-        __syncthreads();
-        bool act[4];
-        int64_t boff[4];
+        int64_t boff[CB];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            act[cb] = __ballot(src[cb] >= 0) != 0;
-            boff[cb] = (int64_t)(src[cb] >= 0 ? src[cb] : ncells) * KP + 8 * g;
+        for (int cb = 0; cb < CB; ++cb) boff[cb] = (int64_t)(src[cb] >= 0 ? src[cb] : ncells) * CPR + g;
+        u32x4 bh[CB], bl[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            bh[cb] = Mh[boff[cb]];
+            if (Op::X3) bl[cb] = Ml[boff[cb]];
         }
+        const int jn = next_slot(j + 1);
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            V bh[4], bl[4];
+        for (int cb = 0; cb < CB; ++cb)
+            src[cb] = (jn < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + jn] : -1;
+        __syncthreads();  // operator in LDS
+        {
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                bh[cb] = *(const V*)(Mhi + boff[cb] + 32 * q);
-                if (X3) bl[cb] = *(const V*)(Mlo + boff[cb] + 32 * q);
-            }
+            for (int q = 0; q < KQ; ++q) {
+                u32x4 nh[CB], nl[CB];
+                if (q + 1 < KQ) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const V ah = sT[(rb * KQ + q) * 64 + lane];
-                V al;
-                if (X3) al = sT[NT + (rb * KQ + q) * 64 + lane];
+                    for (int cb = 0; cb < CB; ++cb) {
+                        nh[cb] = Mh[boff[cb] + 4 * (q + 1)];
+                        if (Op::X3) nl[cb] = Ml[boff[cb] + 4 * (q + 1)];
+                    }
+                }
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb)
-                    if (act[cb]) acc[cb][rb] = LowP<T16>::mma(ah, bh[cb], acc[cb][rb]);
-                if (X3) {
+                for (int rb = 0; rb < RB; ++rb) {
+                    const u32x4 ah = sT[(rb * KQ + q) * 64 + lane];
+                    u32x4 al = ah;
+                    if (Op::X3) al = sT[NT + (rb * KQ + q) * 64 + lane];
+#define M2L_STEP(s)                                                                      \
+    if (s < Op::S) {                                                                     \
+        _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                   \
+            Op::template mma<(s < Op::S ? s : 0)>(ah, al, bh[cb], bl[cb], acc[cb][rb]); \
+    }
+                    M2L_STEP(0)
+                    M2L_STEP(1)
+                    M2L_STEP(2)
+                    M2L_STEP(3)
+#undef M2L_STEP
+                }
+                if (q + 1 < KQ) {
 #pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        if (act[cb]) acc[cb][rb] = LowP<T16>::mma(ah, bl[cb], acc[cb][rb]);
-#pragma unroll
-                    for (int cb = 0; cb < 4; ++cb)
-                        if (act[cb]) acc[cb][rb] = LowP<T16>::mma(al, bh[cb], acc[cb][rb]);
+                    for (int cb = 0; cb < CB; ++cb) {
+                        bh[cb] = nh[cb];
+                        if (Op::X3) bl[cb] = nl[cb];
+                    }
                 }
             }
         }
-        __syncthreads();
+        __syncthreads();  // LDS free for the next operator
+        j = jn;
     }
+    // output block (rb): lane holds rows 16 rb + 4 g + (0..3) of column col
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
+    for (int cb = 0; cb < CB; ++cb) {
         if (tgt[cb] < 0) continue;
         float* o = out + part * part_stride + (int64_t)tgt[cb] * LDO + 4 * g;
 #pragma unroll
@@ -459,14 +477,14 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     const int spp = (216 + parts - 1) / parts;
     parts = (216 + spp - 1) / spp;
     part_stride = (int64_t)t.ncells * t.ldm;
-    dim3 grid(ntiles, parts), block(256);
+    dim3 grid(ntiles, parts), block(1024 / kM2LCB);
     if (!is_lowp(precision)) {
         float* Mk = A.down<float>((size_t)(t.ncells + 1) * ld);
         run_pack(t.M, t.ldm, t.ncells, P, ld, Mk, false, s);
-#define MFMA_CASE(R)                                                                          \
-    hipLaunchKernelGGL((k_m2l_mfma<R, R>), grid, block, 0, s, t.m2l_tiles, t.m2l_order, t.vsrc, \
-                       (const float*)Mk, t.ncells, (const float*)t.T, (float*)out, part_stride, \
-                       spp);
+#define MFMA_CASE(R)                                                                         \
+    hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, OpF32>), grid, block, 0, s, t.m2l_tiles, t.m2l_order,  \
+                       t.vsrc, (const float*)Mk, (const float*)nullptr, t.ncells,              \
+                       (const float*)t.T, (const float*)nullptr, (float*)out, part_stride, spp);
         HFMM_DISPATCH_RB(RB, MFMA_CASE);
 #undef MFMA_CASE
         LAUNCH_CHECK();
@@ -491,11 +509,11 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         const __bf16* tl = x3 ? th + half : nullptr;
 #define LP_CASE(R)                                                                             \
     if (x3)                                                                                    \
-        hipLaunchKernelGGL((k_m2l_mfma_lp<R, (R + 1) / 2, __bf16, true>), grid, block, 0, s,    \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<__bf16, true>>), grid, block, 0, s,    \
                            t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);                                      \
     else                                                                                       \
-        hipLaunchKernelGGL((k_m2l_mfma_lp<R, (R + 1) / 2, __bf16, false>), grid, block, 0, s,   \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<__bf16, false>>), grid, block, 0, s,   \
                            t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);
         HFMM_DISPATCH_RB(RB, LP_CASE);
@@ -510,11 +528,11 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         const _Float16* tl = x3 ? th + half : nullptr;
 #define LP_CASE(R)                                                                             \
     if (x3)                                                                                    \
-        hipLaunchKernelGGL((k_m2l_mfma_lp<R, (R + 1) / 2, _Float16, true>), grid, block, 0, s,  \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<_Float16, true>>), grid, block, 0, s,  \
                            t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);                                      \
     else                                                                                       \
-        hipLaunchKernelGGL((k_m2l_mfma_lp<R, (R + 1) / 2, _Float16, false>), grid, block, 0, s, \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<_Float16, false>>), grid, block, 0, s, \
                            t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);
         HFMM_DISPATCH_RB(RB, LP_CASE);

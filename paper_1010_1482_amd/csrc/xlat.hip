@@ -213,10 +213,11 @@ k_l2l_f64(const Cell* __restrict__ cells, const int32_t* __restrict__ targets, i
           int with_parent, const double* __restrict__ Tsw, double* __restrict__ L, int ld,
           int zero_row, const TB* __restrict__ parts, int nparts, int64_t part_stride,
           const double* __restrict__ lx, int P, const int32_t* __restrict__ bexp,
-          const int32_t* __restrict__ levexp) {
+          const int32_t* __restrict__ levexp, int level) {
     constexpr int NTE = RB * KQ * 64;
     constexpr int LDR = 16 * RB + 1;
     __shared__ double red[64 * LDR];
+    __shared__ int scell[64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, col = lane & 15;
     const int ti = blockIdx.x * 64 + wave * 16 + col;
@@ -250,20 +251,49 @@ k_l2l_f64(const Cell* __restrict__ cells, const int32_t* __restrict__ targets, i
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) red[lc * LDR + 16 * rb + 4 * r + g] = acc[rb][r];
+    if (g == 0) scell[lc] = tgt;
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 16 * RB; e += blockDim.x) {
-        const int c = e / (16 * RB), row = e % (16 * RB);
-        const int t = blockIdx.x * 64 + c;
-        if (t >= ntargets) continue;
-        const int cell = targets[t];
-        const int64_t off = (int64_t)cell * ld + row;
-        double ps = 0.0;
-        for (int q = 0; q < nparts; ++q) ps += (double)parts[q * part_stride + off];
-        if (bexp && row < P)
-            ps = ldexp(ps, bexp[isqrt_c(row)] + 1 + levexp[cells[cell].level] + 1);
-        double v = red[c * LDR + row] + ps;
-        if (lx) v += lx[off];
-        L[off] = v;
+    // epilogue: thread -> elements threadIdx.x + 256 k of the 64 x (16 RB)
+    // block, in 4 chunks of RB; the partial results are read four parts at
+    // a time with every load of a batch in flight (the loads are not
+    // predicated: a missing part or element re-reads a valid address)
+    const int sc_lev = bexp ? levexp[level] + 2 : 0;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        int64_t off[RB];
+        double ps[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int e = (ch * RB + k) * 256 + threadIdx.x;
+            const int cell = scell[e / (16 * RB)];
+            off[k] = cell >= 0 ? (int64_t)cell * ld + e % (16 * RB) : -1;
+            ps[k] = 0.0;
+        }
+        for (int q0 = 0; q0 < nparts; q0 += 4) {
+            TB v[4][RB];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const TB* pp = parts + (int64_t)min(q0 + u, nparts - 1) * part_stride;
+#pragma unroll
+                for (int k = 0; k < RB; ++k) v[u][k] = pp[off[k] >= 0 ? off[k] : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < RB; ++k)
+                    if (q0 + u < nparts) ps[k] += (double)v[u][k];
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            if (off[k] < 0) continue;
+            const int e = (ch * RB + k) * 256 + threadIdx.x;
+            const int c = e / (16 * RB), row = e % (16 * RB);
+            double v = ps[k];
+            if (bexp && row < P) v = ldexp(v, bexp[isqrt_c(row)] + sc_lev);
+            v += red[c * LDR + row];
+            if (lx) v += lx[off[k]];
+            L[off[k]] = v;
+        }
     }
 }
 
@@ -331,11 +361,12 @@ void run_l2l_mfma(Tree& t, int p, const void* parts, bool parts_fp64, int nparts
         hipLaunchKernelGGL((k_l2l_f64<R, R, double>), grid, block, 0, s, t.cells,            \
                            t.m2l_order + i0, nt, wp, t.xl_l2l, t.L, t.ldm, t.ncells,         \
                            (const double*)parts, nparts, part_stride, LX, p * p, bexp,      \
-                           levexp);                                                         \
+                           levexp, l);                                                      \
     else                                                                                    \
         hipLaunchKernelGGL((k_l2l_f64<R, R, float>), grid, block, 0, s, t.cells,             \
                            t.m2l_order + i0, nt, wp, t.xl_l2l, t.L, t.ldm, t.ncells,         \
-                           (const float*)parts, nparts, part_stride, LX, p * p, bexp, levexp);
+                           (const float*)parts, nparts, part_stride, LX, p * p, bexp, levexp,  \
+                           l);
         HFMM_DISPATCH_RB16(RB, L2L_CASE);
 #undef L2L_CASE
         LAUNCH_CHECK();
