@@ -48,6 +48,12 @@ __global__ void k_v_fill(const int32_t* __restrict__ vsrc, int nc, const int32_t
     }
 }
 
+__global__ void k_offsets_minus(const int32_t* __restrict__ in, int64_t n, int32_t base,
+                                int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i] - base;
+}
+
 static void check_p(int p) {
     if (p < 1 || p > HFMM_MAX_P) throw Status{HFMM_E_UNSUPPORTED};
 }
@@ -478,12 +484,18 @@ int hfmm_export_list(hfmm_tree h, int which, int32_t* off, int32_t* items, void*
         HIP_TRY(hipStreamSynchronize(s));
         t.arena.release_temps();
     } else {
+        // U, W and X share one item array with absolute offsets: export the
+        // list's own slice with offsets starting at 0
         const int32_t* o = which == 0 ? t.u_off : which == 2 ? t.w_off : t.x_off;
         const int32_t* it = which == 0 ? t.u_items : which == 2 ? t.w_items : t.x_items;
         const int64_t nn = which == 0 ? t.n_u : which == 2 ? t.n_w : t.n_x;
-        HIP_TRY(hipMemcpyAsync(off, o, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToDevice, s));
+        const int64_t base = which == 0 ? 0 : which == 2 ? t.n_u : t.n_u + t.n_w;
+        hipLaunchKernelGGL(k_offsets_minus, dim3(grid_for(nc + 1, 256)), dim3(256), 0, s, o,
+                           (int64_t)nc + 1, (int32_t)base, off);
+        LAUNCH_CHECK();
         if (nn > 0)
-            HIP_TRY(hipMemcpyAsync(items, it, sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(items, it + base, sizeof(int32_t) * nn,
+                                   hipMemcpyDeviceToDevice, s));
     }
     API_END
 }

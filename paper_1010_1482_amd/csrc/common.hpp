@@ -112,7 +112,9 @@ struct Root {
     double b[3];   // lower corner of the root cube
     double R;      // half width
     double scale;  // 2^21 / (2R)
-    double pad[3];
+    int32_t nbad;  // non-finite input coordinates
+    int32_t pad_i;
+    double pad[2];
 };
 
 // per-call timing of the phases (host wall clock around synchronised steps
@@ -151,6 +153,9 @@ struct Tree {
     bool fmm_lists = false;
     int32_t* coll = nullptr;         // [ncells][27] colleagues, -1 padded
     int32_t* vsrc = nullptr;         // [ncells][216] V list by slot, -1 empty
+    uint8_t* cflag = nullptr;        // [ncells] bit 0: a colleague is a leaf;
+                                     // bit 1: so is one of a proper ancestor
+    // U, W, X share one item array; offsets are absolute into it
     int32_t *u_off = nullptr, *u_items = nullptr;
     int32_t *w_off = nullptr, *w_items = nullptr;
     int32_t *x_off = nullptr, *x_items = nullptr;
@@ -315,10 +320,12 @@ inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block
 // device-wide exclusive scan of int32 (returns nothing; total written to
 // out[n] when out has n+1 entries)
 void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, Arena& A,
-                        hipStream_t s);
-// stable radix sort of (key, value) pairs over bits [lo_bit, hi_bit)
-void radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int lo_bit,
-                      int hi_bit, Arena& A, hipStream_t s);
+                        hipStream_t s, int32_t* total2 = nullptr);
+// stable LSD radix sort of key bits [lo_bit, hi_bit); the input pairs are
+// only read, the sorted pairs land in (keys_out, vals_out)
+void radix_sort_pairs(const uint64_t* keys, const int32_t* vals, uint64_t* keys_out,
+                      int32_t* vals_out, int64_t n, int lo_bit, int hi_bit, Arena& A,
+                      hipStream_t s);
 
 void build_tree(Tree& t, const double* x, const double* y, const double* z,
                 const double* tx, const double* ty, const double* tz,

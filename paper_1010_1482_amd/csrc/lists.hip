@@ -41,67 +41,99 @@ __device__ inline int octant_of(const Cell& c) {
 // same-level cell at B + e, or -1.  The cell at B + e is the child of octant
 // (B + e) & 1 of the parent-level cell at (B + e) >> 1, which is the parent's
 // colleague at offset ((B + e) >> 1) - parent.
-__global__ void k_colleagues(const Cell* __restrict__ cells, int c0, int c1,
-                             int32_t* __restrict__ coll) {
-    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c1) return;
-    int32_t* out = coll + (int64_t)c * kColl;
-    Cell B = cells[c];
-    if (B.parent < 0) {
-        for (int q = 0; q < kColl; ++q) out[q] = q == 13 ? c : -1;
-        return;
-    }
-    const int32_t* pc = coll + (int64_t)B.parent * kColl;
-    const int px = B.ix >> 1, py = B.iy >> 1, pz = B.iz >> 1;
-    for (int ex = -1; ex <= 1; ++ex)
-        for (int ey = -1; ey <= 1; ++ey)
-            for (int ez = -1; ez <= 1; ++ez) {
-                const int X = B.ix + ex, Y = B.iy + ey, Z = B.iz + ez;
-                int res = -1;
-                if (X >= 0 && Y >= 0 && Z >= 0) {
-                    const int qx = (X >> 1) - px, qy = (Y >> 1) - py, qz = (Z >> 1) - pz;
-                    const int C = pc[(qx + 1) * 9 + (qy + 1) * 3 + (qz + 1)];
-                    if (C >= 0) {
-                        const Cell cc = cells[C];
-                        const int o = ((X & 1) << 2) | ((Y & 1) << 1) | (Z & 1);
-                        if ((cc.mask >> o) & 1)
-                            res = cc.child + __popc((unsigned)cc.mask & ((1u << o) - 1u));
-                    }
-                }
-                out[(ex + 1) * 9 + (ey + 1) * 3 + (ez + 1)] = res;
-            }
+// The same rule locates any cell at offset d in [-2, 3]^3 of a child of the
+// parent's colleagues (d per axis within [-2 - o, 3 - o], o the octant).
+__device__ inline int cell_at_offset(const Cell* __restrict__ cells,
+                                     const int32_t* __restrict__ pc, const Cell& B, int dx,
+                                     int dy, int dz) {
+    const int X = B.ix + dx, Y = B.iy + dy, Z = B.iz + dz;
+    if (X < 0 || Y < 0 || Z < 0) return -1;
+    const int qx = (X >> 1) - (B.ix >> 1), qy = (Y >> 1) - (B.iy >> 1),
+              qz = (Z >> 1) - (B.iz >> 1);
+    const int C = pc[(qx + 1) * 9 + (qy + 1) * 3 + (qz + 1)];
+    if (C < 0) return -1;
+    const Cell cc = cells[C];
+    const int o = ((X & 1) << 2) | ((Y & 1) << 1) | (Z & 1);
+    if (!((cc.mask >> o) & 1)) return -1;
+    return cc.child + __popc((unsigned)cc.mask & ((1u << o) - 1u));
 }
 
-// V list by slot, for every cell of level >= 2; vcount[c] = entries
-__global__ void k_vlist(const Cell* __restrict__ cells, int c0, int c1,
-                        const int32_t* __restrict__ coll, int32_t* __restrict__ vsrc,
-                        int32_t* __restrict__ vcount) {
-    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c1) return;
+// 32 lanes per cell (27 used), cells of one level (parents done before)
+__global__ void k_colleagues(const Cell* __restrict__ cells, int c0, int c1,
+                             int32_t* __restrict__ coll, uint8_t* __restrict__ cflag) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = c0 + (e >> 5), q = e & 31;
+    const bool ok = c < c1 && q < kColl;
+    int res = -1;
+    bool leafc = false;
+    Cell B;
+    if (c < c1) B = cells[c];
+    if (ok) {
+        const int ex = q / 9 - 1, ey = (q / 3) % 3 - 1, ez = q % 3 - 1;
+        if (B.parent < 0)
+            res = q == 13 ? c : -1;
+        else
+            res = cell_at_offset(cells, coll + (int64_t)B.parent * kColl, B, ex, ey, ez);
+        coll[(int64_t)c * kColl + q] = res;
+        leafc = res >= 0 && cells[res].nchild == 0;
+    }
+    const uint64_t bl = __ballot(leafc);
+    if (c < c1 && q == 0) {
+        const uint32_t mine = (uint32_t)(bl >> (threadIdx.x & 32));
+        uint8_t f = mine ? 1 : 0;
+        if (B.parent >= 0) {
+            const uint8_t pf = cflag[B.parent];
+            if (pf & 3) f |= 2;
+        }
+        cflag[c] = f;
+    }
+}
+
+// V list by slot, one wave per cell.  Lanes 0..26 fetch the parent's
+// colleagues (child mask and first child) once; each slot then takes the
+// entry of its parent-level offset from the owning lane with a shuffle.
+// Rows of levels 0 and 1 stay empty; cv[c] = number of entries.
+__global__ void __launch_bounds__(256)
+k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
+        int32_t* __restrict__ vsrc, int32_t* __restrict__ cv) {
+    const int lane = threadIdx.x & 63;
+    const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (c >= nc) return;  // uniform per wave
+    const Cell B = cells[c];
     int32_t* out = vsrc + (int64_t)c * kSlots;
-    for (int q = 0; q < kSlots; ++q) out[q] = -1;
-    Cell B = cells[c];
-    int cnt = 0;
-    if (B.level >= 2) {
-        const int ox = B.ix & 1, oy = B.iy & 1, oz = B.iz & 1;
-        const int32_t* pc = coll + (int64_t)B.parent * kColl;
-        for (int q = 0; q < kColl; ++q) {
-            int C = pc[q];
-            if (C < 0) continue;
-            Cell cc = cells[C];
-            for (int i = 0; i < cc.nchild; ++i) {
-                int D = cc.child + i;
-                Cell d = cells[D];
-                int dx = d.ix - B.ix, dy = d.iy - B.iy, dz = d.iz - B.iz;
-                int ad = max(abs(dx), max(abs(dy), abs(dz)));
-                if (ad <= 1) continue;
-                int slot = ((dx + 2 + ox) * 6 + (dy + 2 + oy)) * 6 + (dz + 2 + oz);
-                out[slot] = D;
-                ++cnt;
-            }
+    if (B.level < 2) {
+        for (int q = lane; q < kSlots; q += 64) out[q] = -1;
+        if (lane == 0) cv[c] = 0;
+        return;
+    }
+    int cm = 0, cch = 0;
+    if (lane < kColl) {
+        const int C = coll[(int64_t)B.parent * kColl + lane];
+        if (C >= 0) {
+            const Cell cc = cells[C];
+            cm = cc.mask;
+            cch = cc.child;
         }
     }
-    vcount[c - c0] = cnt;
+    const int ox = B.ix & 1, oy = B.iy & 1, oz = B.iz & 1;
+    int cnt = 0;
+#pragma unroll
+    for (int s0 = 0; s0 < kSlots; s0 += 64) {
+        const int slot = s0 + lane;
+        const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
+        const int X = B.ix + dx, Y = B.iy + dy, Z = B.iz + dz;
+        const bool ok = slot < kSlots && max(abs(dx), max(abs(dy), abs(dz))) > 1 && X >= 0 &&
+                        Y >= 0 && Z >= 0;
+        const int q = ok ? ((X >> 1) - (B.ix >> 1) + 1) * 9 + ((Y >> 1) - (B.iy >> 1) + 1) * 3 +
+                               ((Z >> 1) - (B.iz >> 1) + 1)
+                         : 0;
+        const int m = __shfl(cm, q, 64), ch = __shfl(cch, q, 64);
+        const int o = ((X & 1) << 2) | ((Y & 1) << 1) | (Z & 1);
+        const int res = ok && ((m >> o) & 1) ? ch + __popc((unsigned)m & ((1u << o) - 1u)) : -1;
+        if (slot < kSlots) out[slot] = res;
+        cnt += __popcll(__ballot(res >= 0));
+    }
+    if (lane == 0) cv[c] = cnt;
 }
 
 // ---------------------------------------------------------------------
@@ -116,24 +148,25 @@ __device__ inline bool is_ancestor_or_self(const Cell& A, const Cell& B) {
     return (B.ix >> s) == A.ix && (B.iy >> s) == A.iy && (B.iz >> s) == A.iz;
 }
 
-__global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
-                      int32_t* __restrict__ cu, int32_t* __restrict__ cw,
-                      int32_t* __restrict__ cx, const int32_t* __restrict__ ou,
-                      const int32_t* __restrict__ ow, const int32_t* __restrict__ ox,
-                      int32_t* __restrict__ iu, int32_t* __restrict__ iw,
-                      int32_t* __restrict__ ix) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nc) return;
-    const bool fill = iu != nullptr;
+// U, W, X of cell b: counted (items == nullptr) or written at the offsets.
+// Ancestor chains are walked only when some ancestor has a leaf colleague
+// (cflag bit 1).
+__device__ inline void uwx_cell(const Cell* __restrict__ cells, int b,
+                                const int32_t* __restrict__ coll,
+                                const uint8_t* __restrict__ cflag, bool fill,
+                                const int32_t* __restrict__ ou, const int32_t* __restrict__ ow,
+                                const int32_t* __restrict__ ox, int32_t* __restrict__ iu,
+                                int32_t* __restrict__ iw, int32_t* __restrict__ ix, int& nu,
+                                int& nw, int& nx) {
     Cell B = cells[b];
-    int nu = 0, nw = 0, nx = 0;
+    const bool walk = (cflag[b] & 2) != 0;
     int32_t* pu = fill ? iu + ou[b] : nullptr;
     int32_t* pw = fill ? iw + ow[b] : nullptr;
     int32_t* px = fill ? ix + ox[b] : nullptr;
     const bool leaf = B.nchild == 0;
     // X(B): leaves C coarser than B in colleagues of ancestors, adjacent to
     // parent(B) and not to B
-    if (B.level >= 2) {
+    if (B.level >= 2 && walk) {
         Cell P = cells[B.parent];
         for (int A = B.parent; A >= 0; A = cells[A].parent) {
             const int32_t* ca = coll + (int64_t)A * kColl;
@@ -151,7 +184,7 @@ __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __r
     }
     if (leaf) {
         // coarser adjacent leaves: leaf colleagues of proper ancestors
-        for (int A = B.parent; A >= 0; A = cells[A].parent) {
+        for (int A = walk ? B.parent : -1; A >= 0; A = cells[A].parent) {
             const int32_t* ca = coll + (int64_t)A * kColl;
             for (int q = 0; q < kColl; ++q) {
                 int C = ca[q];
@@ -198,10 +231,35 @@ __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __r
             }
         }
     }
-    if (!fill) {
+}
+
+// Count pass (iu == nullptr): cu, cw, cx per cell (entry nc of these and
+// of cv set to 0); fill pass: the items.
+__global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
+                      const uint8_t* __restrict__ cflag, int32_t* __restrict__ cu,
+                      int32_t* __restrict__ cw, int32_t* __restrict__ cx,
+                      int32_t* __restrict__ cv, const int32_t* __restrict__ ou,
+                      const int32_t* __restrict__ ow, const int32_t* __restrict__ ox,
+                      int32_t* __restrict__ iu, int32_t* __restrict__ iw,
+                      int32_t* __restrict__ ix) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool fill = iu != nullptr;
+    int nu = 0, nw = 0, nx = 0;
+    if (b < nc) uwx_cell(cells, b, coll, cflag, fill, ou, ow, ox, iu, iw, ix, nu, nw, nx);
+    if (fill) return;
+    if (b <= nc) {  // entry nc is 0: the four arrays are scanned as one
         cu[b] = nu;
         cw[b] = nw;
         cx[b] = nx;
+        if (b == nc) cv[b] = 0;
+    }
+}
+
+// list totals from the joint offsets [U | W | X | V], each nc + 1 long
+__global__ void k_list_totals(const int32_t* __restrict__ off, int nc, int32_t* __restrict__ tot) {
+    if (threadIdx.x < 4) {
+        const int64_t a = (int64_t)threadIdx.x * (nc + 1);
+        tot[threadIdx.x] = off[a + nc] - off[a];
     }
 }
 
@@ -236,62 +294,62 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     const int nc = t.ncells;
     t.coll = A.up<int32_t>((size_t)nc * kColl);
     t.vsrc = A.up<int32_t>((size_t)nc * kSlots);
+    t.cflag = A.up<uint8_t>(nc);
+    // read back once: [0..3] U, W, X, V totals, [4..) group counts
+    int32_t* hr = A.down<int32_t>(4 + kGroups);
+    HIP_TRY(hipMemsetAsync(hr, 0, sizeof(int32_t) * (4 + kGroups), s));
     for (int l = 0; l <= t.depth; ++l) {
-        int c0 = t.level_start[l], c1 = t.level_start[l + 1];
-        hipLaunchKernelGGL(k_colleagues, dim3(grid_for(c1 - c0, 128)), dim3(128), 0, s,
-                           t.cells, c0, c1, t.coll);
+        const int c0 = t.level_start[l], c1 = t.level_start[l + 1];
+        hipLaunchKernelGGL(k_colleagues, dim3(grid_for((int64_t)(c1 - c0) * 32, 256)),
+                           dim3(256), 0, s, t.cells, c0, c1, t.coll, t.cflag);
         LAUNCH_CHECK();
     }
-    int32_t* vcount = A.down<int32_t>(nc + 1);
-    int32_t* vscan = A.down<int32_t>(nc + 1);
-    hipLaunchKernelGGL(k_vlist, dim3(grid_for(nc, 128)), dim3(128), 0, s, t.cells, 0, nc,
-                       t.coll, t.vsrc, vcount);
+    // per-cell counts as one array [U | W | X | V] of 4 (nc + 1), one scan:
+    // the offsets of U, W and X index one shared item array (V is stored
+    // densely by slot, only its total is used)
+    const int64_t n4 = 4 * (int64_t)(nc + 1);
+    int32_t* cnt = A.down<int32_t>(n4);
+    int32_t *cu = cnt, *cw = cnt + (nc + 1), *cx = cnt + 2 * (nc + 1), *cv = cnt + 3 * (nc + 1);
+    hipLaunchKernelGGL(k_vlist, dim3(grid_for((int64_t)nc * 64, 256)), dim3(256), 0, s,
+                       t.cells, nc, t.coll, t.vsrc, cv);
     LAUNCH_CHECK();
-    scan_exclusive_i32(vcount, vscan, nc, A, s);
-    // U, W, X
-    int32_t* cnt = A.down<int32_t>(3 * (size_t)(nc + 1));
-    int32_t *cu = cnt, *cw = cnt + (nc + 1), *cx = cnt + 2 * (nc + 1);
-    hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
-                       cu, cw, cx, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc + 1, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
+                       t.cflag, cu, cw, cx, cv, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       nullptr);
     LAUNCH_CHECK();
-    t.u_off = A.up<int32_t>(nc + 1);
-    t.w_off = A.up<int32_t>(nc + 1);
-    t.x_off = A.up<int32_t>(nc + 1);
-    scan_exclusive_i32(cu, t.u_off, nc, A, s);
-    scan_exclusive_i32(cw, t.w_off, nc, A, s);
-    scan_exclusive_i32(cx, t.x_off, nc, A, s);
+    int32_t* off = A.up<int32_t>(n4 + 1);
+    scan_exclusive_i32(cnt, off, n4, A, s);
+    hipLaunchKernelGGL(k_list_totals, dim3(1), dim3(64), 0, s, off, nc, hr);
+    LAUNCH_CHECK();
+    t.u_off = off;
+    t.w_off = off + (nc + 1);
+    t.x_off = off + 2 * (nc + 1);
     // M2L target order
     const int c2 = t.depth >= 2 ? t.level_start[2] : nc;
     const int nm = nc - c2;
     uint64_t* mk = A.down<uint64_t>(std::max(nm, 1));
+    uint64_t* mk2 = A.down<uint64_t>(std::max(nm, 1));
+    int32_t* mv = A.down<int32_t>(std::max(nm, 1));
     t.m2l_order = A.up<int32_t>(std::max(nm, 1));
-    int32_t* gcount = A.down<int32_t>(8 * (HFMM_KEY_LEVELS + 2));
-    HIP_TRY(hipMemsetAsync(gcount, 0, sizeof(int32_t) * 8 * (HFMM_KEY_LEVELS + 2), s));
     if (nm > 0) {
         hipLaunchKernelGGL(k_m2l_keys, dim3(grid_for(nm, 256)), dim3(256), 0, s, t.cells, c2,
-                           nc, mk, t.m2l_order, gcount);
+                           nc, mk, mv, hr + 4);
         LAUNCH_CHECK();
-        radix_sort_pairs(mk, t.m2l_order, nm, 0, 8, A, s);
+        radix_sort_pairs(mk, mv, mk2, t.m2l_order, nm, 0, 8, A, s);
     }
-    int32_t h[4];
-    std::vector<int32_t> gc(8 * (HFMM_KEY_LEVELS + 2));
-    HIP_TRY(hipMemcpyAsync(&h[0], t.u_off + nc, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&h[1], t.w_off + nc, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&h[2], t.x_off + nc, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&h[3], vscan + nc, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(gc.data(), gcount, sizeof(int32_t) * gc.size(),
-                           hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> h(4 + kGroups);
+    HIP_TRY(hipMemcpyAsync(h.data(), hr, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     t.n_u = h[0];
     t.n_w = h[1];
     t.n_x = h[2];
     t.n_v = h[3];
-    t.u_items = A.up<int32_t>(std::max<int64_t>(t.n_u, 1));
-    t.w_items = A.up<int32_t>(std::max<int64_t>(t.n_w, 1));
-    t.x_items = A.up<int32_t>(std::max<int64_t>(t.n_x, 1));
+    std::vector<int32_t> gc(h.begin() + 4, h.end());
+    int32_t* items = A.up<int32_t>(std::max<int64_t>(t.n_u + t.n_w + t.n_x, 1));
+    t.u_items = t.w_items = t.x_items = items;
     hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
-                       nullptr, nullptr, nullptr, t.u_off, t.w_off, t.x_off, t.u_items,
-                       t.w_items, t.x_items);
+                       t.cflag, nullptr, nullptr, nullptr, nullptr, t.u_off, t.w_off, t.x_off,
+                       items, items, items);
     LAUNCH_CHECK();
     t.m2l_level_start.assign(t.depth + 2, 0);
     for (int l = 0; l <= t.depth; ++l) {

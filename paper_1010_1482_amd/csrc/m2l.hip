@@ -113,12 +113,20 @@ __device__ inline int degree_of(int r) {
 }
 
 // largest monopole exponent per level
+// (block maxima in LDS first: one global atomic per block and level)
 __global__ void k_level_exp(const Cell* __restrict__ cells, int nc, const double* __restrict__ M,
                             int ldm, int32_t* __restrict__ levexp) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    double v = fabs(M[(int64_t)c * ldm]);
-    if (v > 0.0) atomicMax(&levexp[cells[c].level], ilogb(v));
+    __shared__ int bmax[32];
+    if (threadIdx.x < 32) bmax[threadIdx.x] = INT_MIN;
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc) {
+        const double v = fabs(M[(int64_t)c * ldm]);
+        if (v > 0.0) atomicMax(&bmax[cells[c].level], ilogb(v));
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && bmax[threadIdx.x] != INT_MIN)
+        atomicMax(&levexp[threadIdx.x], bmax[threadIdx.x]);
 }
 
 template <typename T16>

@@ -34,13 +34,19 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, bool SOFT>
+// ZERO: the pair may coincide (r^2 == 0, skipped).  Coincident points share
+// a key, hence a leaf, so only a leaf with itself needs the test.  Across
+// leaves FP64 separations are never 0; FP32 ones can round to 0 for points
+// closer than FP32 resolves at the leaf size, and r^2 is clamped there so
+// that the (then meaningless) pair stays finite.
+template <typename T, bool SOFT, bool ZERO>
 __device__ __forceinline__ void pair(T xi, T yi, T zi, const typename Vec4<T>::type& s,
                                      T eps2, T& phi, T& ax, T& ay, T& az) {
     const T dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-    const T r2 = dx * dx + dy * dy + dz * dz;
+    T r2 = dx * dx + dy * dy + dz * dz;
+    if (!ZERO && sizeof(T) == 4) r2 = fmaxf(r2, 1e-24f);
     T rinv = rsqrt_fast(SOFT ? r2 + eps2 : r2);
-    rinv = r2 > T(0) ? rinv : T(0);
+    if (ZERO) rinv = r2 > T(0) ? rinv : T(0);
     const T mr = s.w * rinv;
     phi += mr;
     const T sc = mr * rinv * rinv;
@@ -54,7 +60,7 @@ __device__ __forceinline__ void pair(T xi, T yi, T zi, const typename Vec4<T>::t
 // leaf centre; the offset between the source and target leaf centres is
 // formed in FP64 once per source cell and added while staging.
 template <typename T, int G, bool SOFT>
-__device__ __forceinline__ void p2p_chunk(const Cell* __restrict__ cells,
+__device__ __forceinline__ void p2p_chunk(const Cell* __restrict__ cells, int self,
                                           const int32_t* __restrict__ items, int e0, int e1,
                                           const typename Vec4<T>::type* __restrict__ P,
                                           typename Vec4<T>::type* sh, const Root& root,
@@ -66,8 +72,13 @@ __device__ __forceinline__ void p2p_chunk(const Cell* __restrict__ cells,
     const int lane = threadIdx.x & 63;
     const int g = lane / TW;
     for (int e = e0; e < e1; ++e) {
-        const Cell c = cells[items[e]];
+        const int ci = items[e];
+        const Cell c = cells[ci];
         const int end = c.first + c.count;
+        // coincident points can only meet within one leaf; with softening
+        // every pair is finite except the excluded r^2 == 0 ones, which
+        // again need the same leaf
+        const bool zero = ci == self;
         T ox = T(0), oy = T(0), oz = T(0);
         if (REL) {
             double cc[3];
@@ -94,17 +105,25 @@ __device__ __forceinline__ void p2p_chunk(const Cell* __restrict__ cells,
             wave_lds_sync();
             const int nl = min(64, end - base);
             const int steps = (nl + G - 1) / G;
+            if (zero) {
 #pragma unroll 8
-            for (int q = 0; q < steps; ++q) {
-                const V s = sh[q * G + g];
-                pair<T, SOFT>(xi, yi, zi, s, eps2, phi, ax, ay, az);
+                for (int q = 0; q < steps; ++q) {
+                    const V s = sh[q * G + g];
+                    pair<T, SOFT, true>(xi, yi, zi, s, eps2, phi, ax, ay, az);
+                }
+            } else {
+#pragma unroll 8
+                for (int q = 0; q < steps; ++q) {
+                    const V s = sh[q * G + g];
+                    pair<T, SOFT, false>(xi, yi, zi, s, eps2, phi, ax, ay, az);
+                }
             }
         }
     }
 }
 
 template <typename T, typename O, int G, bool SOFT>
-__device__ __forceinline__ void p2p_leaf(const Cell& leaf, const Root& root,
+__device__ __forceinline__ void p2p_leaf(const Cell& leaf, int self, const Root& root,
                                          const Cell* __restrict__ cells,
                                          const int32_t* __restrict__ items, int e0, int e1,
                                          const typename Vec4<T>::type* __restrict__ P,
@@ -124,8 +143,8 @@ __device__ __forceinline__ void p2p_leaf(const Cell& leaf, const Root& root,
         const bool ok = c0 + t < leaf.count;
         V me = ok ? P[s] : V{T(0), T(0), T(0), T(0)};
         T phi = T(0), ax = T(0), ay = T(0), az = T(0);
-        p2p_chunk<T, G, SOFT>(cells, items, e0, e1, P, sh, root, cb, me.x, me.y, me.z, eps2, phi,
-                              ax, ay, az);
+        p2p_chunk<T, G, SOFT>(cells, self, items, e0, e1, P, sh, root, cb, me.x, me.y, me.z, eps2,
+                              phi, ax, ay, az);
 #pragma unroll
         for (int d = TW; d < 64; d <<= 1) {
             phi += __shfl_xor(phi, d, 64);
@@ -172,13 +191,13 @@ k_p2p(const Cell* __restrict__ cells, const Root* __restrict__ rootp,
     const int e0 = off[b], e1 = off[b + 1];
     V* sh = shm[w];
     if (leaf.count <= 16)
-        p2p_leaf<T, O, 4, SOFT>(leaf, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
+        p2p_leaf<T, O, 4, SOFT>(leaf, b, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
                                 eps2, phi_o, ax_o, ay_o, az_o);
     else if (leaf.count <= 32)
-        p2p_leaf<T, O, 2, SOFT>(leaf, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
+        p2p_leaf<T, O, 2, SOFT>(leaf, b, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
                                 eps2, phi_o, ax_o, ay_o, az_o);
     else
-        p2p_leaf<T, O, 1, SOFT>(leaf, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
+        p2p_leaf<T, O, 1, SOFT>(leaf, b, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
                                 eps2, phi_o, ax_o, ay_o, az_o);
 }
 
@@ -249,7 +268,8 @@ k_direct(const typename Vec4<T>::type* __restrict__ src, int64_t ns,
         wave_lds_sync();
         const int nl = (int)min((int64_t)64, ns - base);
 #pragma unroll 8
-        for (int q = 0; q < nl; ++q) pair<T, SOFT>(me.x, me.y, me.z, sh[q], eps2, phi, ax, ay, az);
+        for (int q = 0; q < nl; ++q)
+            pair<T, SOFT, true>(me.x, me.y, me.z, sh[q], eps2, phi, ax, ay, az);
     }
     if (i < nt) {
         phi_o[i] = phi;

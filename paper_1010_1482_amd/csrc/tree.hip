@@ -81,7 +81,8 @@ __global__ void k_scan_sums(int32_t* part, int nparts) {
 
 __global__ void k_scan_blocks(const int32_t* __restrict__ in, int64_t n,
                               const int32_t* __restrict__ part,
-                              int32_t* __restrict__ out, int write_total) {
+                              int32_t* __restrict__ out, int write_total,
+                              int32_t* __restrict__ total2) {
     const int64_t base = (int64_t)blockIdx.x * kTile;
     int v[kItems];
     int s = 0;
@@ -99,21 +100,25 @@ __global__ void k_scan_blocks(const int32_t* __restrict__ in, int64_t n,
         if (i < n) out[i] = ex;
         ex += v[k];
     }
-    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+    if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
         out[n] = part ? part[gridDim.x] : tot;
+        if (total2) *total2 = out[n];
+    }
 }
 
 void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, Arena& A,
-                        hipStream_t s) {
-    // out must hold n + 1 entries; out[n] receives the total
+                        hipStream_t s, int32_t* total2) {
+    // out must hold n + 1 entries; out[n] (and *total2 if given) receives
+    // the total
     if (n <= 0) {
         HIP_TRY(hipMemsetAsync(out, 0, sizeof(int32_t), s));
+        if (total2) HIP_TRY(hipMemsetAsync(total2, 0, sizeof(int32_t), s));
         return;
     }
     int nb = grid_for(n, kTile);
     if (nb == 1) {  // one block: no partial sums needed
         hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, in, n,
-                           (const int32_t*)nullptr, out, 1);
+                           (const int32_t*)nullptr, out, 1, total2);
         LAUNCH_CHECK();
         return;
     }
@@ -122,7 +127,8 @@ void scan_exclusive_i32(const int32_t* in, int32_t* out, int64_t n, Arena& A,
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, part, nb);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0, s, in, n, part, out, 1);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0, s, in, n, part, out, 1,
+                       total2);
     LAUNCH_CHECK();
 }
 
@@ -213,19 +219,34 @@ k_radix_scatter(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vi
     }
 }
 
-void radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int lo_bit,
-                      int hi_bit, Arena& A, hipStream_t s) {
-    if (n <= 1 || hi_bit <= lo_bit) return;
+void radix_sort_pairs(const uint64_t* keys, const int32_t* vals, uint64_t* keys_out,
+                      int32_t* vals_out, int64_t n, int lo_bit, int hi_bit, Arena& A,
+                      hipStream_t s) {
+    const int passes = hi_bit > lo_bit ? (hi_bit - lo_bit + 7) / 8 : 0;
+    if (n <= 1 || passes == 0) {
+        if (n > 0 && keys != keys_out) {
+            HIP_TRY(hipMemcpyAsync(keys_out, keys, sizeof(uint64_t) * n,
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(vals_out, vals, sizeof(int32_t) * n,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        return;
+    }
     const int nb = grid_for(n, kTile);
     uint64_t* k2 = A.down<uint64_t>(n);
     int32_t* v2 = A.down<int32_t>(n);
     int32_t* hist = A.down<int32_t>((int64_t)256 * nb);
     int32_t* off = A.down<int32_t>((int64_t)256 * nb + 1);
-    uint64_t *ki = keys, *ko = k2;
-    int32_t *vi = vals, *vo = v2;
-    int passes = 0;
-    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
-        int bits = std::min(8, hi_bit - shift);
+    // ping-pong between the temporary and the output so that the last pass
+    // writes the output
+    const uint64_t* ki = keys;
+    const int32_t* vi = vals;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = lo_bit + 8 * pass;
+        const int bits = std::min(8, hi_bit - shift);
+        const bool to_out = ((passes - 1 - pass) & 1) == 0;
+        uint64_t* ko = to_out ? keys_out : k2;
+        int32_t* vo = to_out ? vals_out : v2;
         hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kBlock), 0, s, ki, n, shift,
                            bits, hist, nb);
         LAUNCH_CHECK();
@@ -233,13 +254,8 @@ void radix_sort_pairs(uint64_t* keys, int32_t* vals, int64_t n, int lo_bit,
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kBlock), 0, s, ki, vi, ko,
                            vo, n, shift, bits, off, nb);
         LAUNCH_CHECK();
-        std::swap(ki, ko);
-        std::swap(vi, vo);
-        ++passes;
-    }
-    if (passes & 1) {
-        HIP_TRY(hipMemcpyAsync(keys, ki, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(vals, vi, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        ki = ko;
+        vi = vo;
     }
 }
 
@@ -254,8 +270,7 @@ __device__ inline double load_coord(const double* a, const double* ta, int64_t n
 __global__ void k_bbox_partial(const double* __restrict__ x, const double* __restrict__ y,
                                const double* __restrict__ z, const double* __restrict__ tx,
                                const double* __restrict__ ty, const double* __restrict__ tz,
-                               int64_t ns, int64_t n, double* __restrict__ part,
-                               int32_t* __restrict__ bad) {
+                               int64_t ns, int64_t n, double* __restrict__ part) {
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int nbad = 0;
@@ -303,39 +318,58 @@ __global__ void k_bbox_partial(const double* __restrict__ x, const double* __res
             nb += sb[ww];
         }
         for (int a = 0; a < 3; ++a) {
-            part[blockIdx.x * 6 + a] = lo[a];
-            part[blockIdx.x * 6 + 3 + a] = hi[a];
+            part[blockIdx.x * 8 + a] = lo[a];
+            part[blockIdx.x * 8 + 3 + a] = hi[a];
         }
-        if (nb) atomicAdd(bad, nb);
+        part[blockIdx.x * 8 + 6] = (double)nb;
     }
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nparts, Root* root) {
+// Also writes the root cell (all n particles) as cells[0].
+__global__ void k_bbox_final(const double* __restrict__ part, int nparts, int64_t n, Root* root,
+                             Cell* __restrict__ cells) {
 #pragma clang fp contract(off)
     // 256 threads: strided partial min/max, then a tree in LDS (min and max
     // are exact, so the order does not matter)
-    __shared__ double sm[6][256];
+    __shared__ double sm[7][256];
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = threadIdx.x; b < nparts; b += blockDim.x)
+    double nbad = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
         for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(lo[a], part[b * 6 + a]);
-            hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
+            lo[a] = fmin(lo[a], part[b * 8 + a]);
+            hi[a] = fmax(hi[a], part[b * 8 + 3 + a]);
         }
+        nbad += part[b * 8 + 6];
+    }
     for (int a = 0; a < 3; ++a) {
         sm[a][threadIdx.x] = lo[a];
         sm[3 + a][threadIdx.x] = hi[a];
     }
+    sm[6][threadIdx.x] = nbad;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
+        if ((int)threadIdx.x < w) {
             for (int a = 0; a < 3; ++a) {
                 sm[a][threadIdx.x] = fmin(sm[a][threadIdx.x], sm[a][threadIdx.x + w]);
                 sm[3 + a][threadIdx.x] = fmax(sm[3 + a][threadIdx.x], sm[3 + a][threadIdx.x + w]);
             }
+            sm[6][threadIdx.x] += sm[6][threadIdx.x + w];
+        }
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
+    root->nbad = (int32_t)sm[6][0];
+    Cell rc;
+    rc.first = 0;
+    rc.count = (int32_t)n;
+    rc.parent = -1;
+    rc.child = -1;
+    rc.ix = rc.iy = rc.iz = 0;
+    rc.level = 0;
+    rc.nchild = 0;
+    rc.mask = 0;
+    cells[0] = rc;
     for (int a = 0; a < 3; ++a) {
         lo[a] = sm[a][0];
         hi[a] = sm[3 + a][0];
@@ -413,63 +447,101 @@ __global__ void k_gather_positions(const double* __restrict__ x, const double* _
 // ---------------------------------------------------------------------
 // cells, level by level
 // ---------------------------------------------------------------------
-// first index in [lo, hi) whose key digit at `shift` is >= o (keys sorted)
-__device__ inline int lower_bound_digit(const uint64_t* keys, int lo, int hi, int shift,
-                                        int o) {
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if ((int)((keys[mid] >> shift) & 7u) < o)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-__global__ void k_split_count(const Cell* __restrict__ cells, int c0, int c1, int leaf_max,
-                              int sorted_levels, const uint64_t* __restrict__ keys,
-                              int32_t* __restrict__ nz, int32_t* __restrict__ flag) {
-    int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= c1) return;
-    Cell cell = cells[c];
-    int nkids = 0;
-    if (cell.count > leaf_max && cell.level < HFMM_KEY_LEVELS) {
+// Child ranges of the splitting cells of one level, one wave per cell.  The
+// seven octant boundaries (first index whose digit is >= o) are narrowed
+// together: each round every lane samples one key per boundary inside the
+// current bracket, and the ballot of "digit < o" (a prefix, the keys being
+// sorted) shrinks the bracket 65-fold; a bracket of <= 64 keys is resolved
+// exactly.  bnd[8 c + o - 1] = boundary o, nz[c] = number of nonempty
+// children; info[0] |= 1 when the sort did not order the next digit,
+// info[1] counts the splitting cells.
+__global__ void __launch_bounds__(1024)
+k_split_find(const Cell* __restrict__ cells, int c0, int c1, int leaf_max, int sorted_levels,
+             const uint64_t* __restrict__ keys, int32_t* __restrict__ nz,
+             int32_t* __restrict__ bnd, int32_t* __restrict__ info) {
+    const int lane = threadIdx.x & 63;
+    const int c = c0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    int nk = 0;
+    Cell cell;
+    cell.count = 0;
+    cell.level = 0;
+    if (c < c1) cell = cells[c];
+    if (c < c1 && cell.count > leaf_max && cell.level < HFMM_KEY_LEVELS) {
         if (cell.level + 1 > sorted_levels) {
-            atomicOr(flag, 1);  // the sort did not order this digit: re-sort
+            if (lane == 0) atomicOr(&info[0], 1);
         } else {
-            int shift = 3 * (HFMM_KEY_LEVELS - cell.level - 1);
-            int beg = cell.first, end = cell.first + cell.count;
-            int prev = beg;
-            for (int o = 1; o <= 8; ++o) {
-                int b = o < 8 ? lower_bound_digit(keys, prev, end, shift, o) : end;
-                nkids += (b > prev);
-                prev = b;
+            const int shift = 3 * (HFMM_KEY_LEVELS - cell.level - 1);
+            const int beg = cell.first, end = cell.first + cell.count;
+            int lo[7], hi[7];
+#pragma unroll
+            for (int o = 0; o < 7; ++o) {
+                lo[o] = beg;
+                hi[o] = end;
             }
+            for (;;) {
+                int widest = 0;
+#pragma unroll
+                for (int o = 0; o < 7; ++o) widest = max(widest, hi[o] - lo[o]);
+                if (widest <= 64) break;
+                uint32_t dg[7];
+#pragma unroll
+                for (int o = 0; o < 7; ++o) {
+                    const int64_t len = hi[o] - lo[o];
+                    const int at = lo[o] + (int)(((int64_t)(lane + 1) * len) / 65);
+                    dg[o] = len > 64 ? (uint32_t)(keys[at] >> shift) & 7u : 0u;
+                }
+#pragma unroll
+                for (int o = 0; o < 7; ++o) {
+                    const int64_t len = hi[o] - lo[o];
+                    if (len <= 64) continue;
+                    const int k = __popcll(__ballot(dg[o] < (uint32_t)(o + 1)));
+                    const int below = k == 0 ? lo[o] - 1 : lo[o] + (int)(((int64_t)k * len) / 65);
+                    const int above = k == 64 ? hi[o] : lo[o] + (int)(((int64_t)(k + 1) * len) / 65);
+                    lo[o] = below + 1;
+                    hi[o] = above;
+                }
+            }
+            int b[9];
+            b[0] = beg;
+            b[8] = end;
+#pragma unroll
+            for (int o = 0; o < 7; ++o) {
+                const int at = lo[o] + lane;
+                const bool less = at < hi[o] && ((uint32_t)(keys[at] >> shift) & 7u) < (uint32_t)(o + 1);
+                b[o + 1] = lo[o] + __popcll(__ballot(less));
+            }
+#pragma unroll
+            for (int o = 0; o < 8; ++o) nk += b[o + 1] > b[o];
+#pragma unroll
+            for (int o = 0; o < 7; ++o)
+                if (lane == o) bnd[(int64_t)(c - c0) * 8 + o] = b[o + 1];
         }
     }
-    nz[c - c0] = nkids;
+    if (c < c1 && lane == 0) nz[c - c0] = nk;
+    // one atomic per block for the count of splitting cells
+    const int k = __syncthreads_count(c < c1 && lane == 0 && nk > 0);
+    if (threadIdx.x == 0 && k) atomicAdd(&info[1], k);
 }
 
 __global__ void k_split_emit(Cell* __restrict__ cells, int c0, int c1, int next0,
-                             const uint64_t* __restrict__ keys,
+                             const int32_t* __restrict__ bnd,
                              const int32_t* __restrict__ pos) {
     int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
     int k = pos[c - c0];
     int nk = pos[c - c0 + 1] - k;
-    Cell cell = cells[c];
     if (nk == 0) {
         cells[c].child = -1;
         cells[c].nchild = 0;
         cells[c].mask = 0;
         return;
     }
-    int shift = 3 * (HFMM_KEY_LEVELS - cell.level - 1);
-    int beg = cell.first, end = cell.first + cell.count;
-    int prev = beg, out = next0 + k;
+    const Cell cell = cells[c];
+    const int32_t* bc = bnd + (int64_t)(c - c0) * 8;
+    int prev = cell.first, out = next0 + k;
     unsigned mask = 0;
     for (int o = 0; o < 8; ++o) {
-        int b = o < 7 ? lower_bound_digit(keys, prev, end, shift, o + 1) : end;
+        const int b = o < 7 ? bc[o] : cell.first + cell.count;
         if (b > prev) {
             Cell ch;
             ch.first = prev;
@@ -532,80 +604,74 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
     t.p32 = A.up<float4>(n);
     t.p64 = A.up<double4>(n);
     t.leaf_of = A.up<int32_t>(n);
+    const size_t cells_lo = A.lo;
+    t.cells = (Cell*)(A.base + A.lo);
+    auto room = [&](int64_t ncell) {
+        size_t b = Arena::align((size_t)ncell * sizeof(Cell) + 1);
+        if (cells_lo + b > A.hi) A.fail((size_t)ncell * sizeof(Cell));
+        A.lo = cells_lo + b;
+    };
+    room(1);
 
-    // bounding cube
+    // bounding cube (and the root cell)
     const int nbb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(n, 256)));
-    double* part = A.down<double>((size_t)nbb * 6);
-    int32_t* hbuf = A.down<int32_t>(8);
-    HIP_TRY(hipMemsetAsync(hbuf, 0, 8 * sizeof(int32_t), s));
+    double* part = A.down<double>((size_t)nbb * 8);
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, x, y, z, tx, ty, tz,
-                       t.ns, n, part, hbuf);
+                       t.ns, n, part);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nbb, t.root);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nbb, n, t.root, t.cells);
     LAUNCH_CHECK();
-    int32_t nbad = 0;
-    HIP_TRY(hipMemcpyAsync(&nbad, hbuf, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&t.root_h, t.root, sizeof(Root), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (nbad) throw Status{HFMM_E_DATA};
+    if (t.root_h.nbad) throw Status{HFMM_E_DATA};
 
     // keys, sort (top bits first; a full sort if the tree turns out deeper)
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, tx, ty,
-                       tz, t.ns, n, t.root, t.keys, t.perm);
-    LAUNCH_CHECK();
+    uint64_t* k0 = A.down<uint64_t>(n);
+    int32_t* i0 = A.down<int32_t>(n);
+    // per level and attempt: [children added, re-sort needed, cells split]
+    int32_t* info = A.down<int32_t>(3 * 2 * (HFMM_KEY_LEVELS + 1));
+    HIP_TRY(hipMemsetAsync(info, 0, sizeof(int32_t) * 3 * 2 * (HFMM_KEY_LEVELS + 1), s));
     int sorted_levels = sort_levels_guess(n, t.leaf_max);
-    const size_t cells_lo = A.lo;
-    for (int attempt = 0;; ++attempt) {
-        int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
-        radix_sort_pairs(t.keys, t.perm, n, lo_bit, 63, A, s);
+    const size_t hi_mark = A.hi;
+    int nsplit_total = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, tx, ty,
+                           tz, t.ns, n, t.root, k0, i0);
+        LAUNCH_CHECK();
+        const int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
+        radix_sort_pairs(k0, i0, t.keys, t.perm, n, lo_bit, 63, A, s);
+        A.hi = hi_mark;
         t.sort_bits = 63 - lo_bit;
-        // cells
-        A.lo = cells_lo;
-        t.cells = (Cell*)(A.base + A.lo);
-        auto room = [&](int64_t ncell) {
-            size_t b = Arena::align((size_t)ncell * sizeof(Cell) + 1);
-            if (cells_lo + b > A.hi) A.fail((size_t)ncell * sizeof(Cell));
-            A.lo = cells_lo + b;
-        };
         room(1);
-        Cell root;
-        root.first = 0;
-        root.count = (int32_t)n;
-        root.parent = -1;
-        root.child = -1;
-        root.ix = root.iy = root.iz = 0;
-        root.level = 0;
-        root.nchild = 0;
-        root.mask = 0;
-        HIP_TRY(hipMemcpyAsync(t.cells, &root, sizeof(Cell), hipMemcpyHostToDevice, s));
         t.level_start.assign(1, 0);
         t.level_start.push_back(1);
         int c0 = 0, c1 = 1, level = 0;
         bool resort = false;
-        const size_t hi_mark = A.hi;
+        nsplit_total = 0;
         while (true) {
-            int nl = c1 - c0;
+            const int nl = c1 - c0;
+            int32_t* in = info + 3 * (attempt * (HFMM_KEY_LEVELS + 1) + level);
             int32_t* nz = A.down<int32_t>(nl + 1);
             int32_t* pos = A.down<int32_t>(nl + 1);
-            int32_t* flag = A.down<int32_t>(2);
-            HIP_TRY(hipMemsetAsync(flag, 0, 2 * sizeof(int32_t), s));
-            hipLaunchKernelGGL(k_split_count, dim3(grid_for(nl, 256)), dim3(256), 0, s,
-                               t.cells, c0, c1, t.leaf_max, sorted_levels, t.keys, nz, flag);
+            int32_t* bnd = A.down<int32_t>((size_t)nl * 8);
+            hipLaunchKernelGGL(k_split_find, dim3(grid_for((int64_t)nl * 64, 1024)), dim3(1024),
+                               0, s, t.cells, c0, c1, t.leaf_max, sorted_levels, t.keys, nz,
+                               bnd, in + 1);
             LAUNCH_CHECK();
-            scan_exclusive_i32(nz, pos, nl, A, s);
-            int32_t h[2] = {0, 0};
-            HIP_TRY(hipMemcpyAsync(&h[0], pos + nl, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipMemcpyAsync(&h[1], flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            scan_exclusive_i32(nz, pos, nl, A, s, in);
+            int32_t h[3] = {0, 0, 0};
+            HIP_TRY(hipMemcpyAsync(h, in, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (h[1]) {
                 resort = true;
                 A.hi = hi_mark;
                 break;
             }
-            int added = h[0];
+            const int added = h[0];
+            nsplit_total += h[2];
             if (added > 0) room((int64_t)c1 + added);
             hipLaunchKernelGGL(k_split_emit, dim3(grid_for(nl, 256)), dim3(256), 0, s,
-                               t.cells, c0, c1, c1, t.keys, pos);
+                               t.cells, c0, c1, c1, bnd, pos);
             LAUNCH_CHECK();
             A.hi = hi_mark;
             if (added == 0) break;
@@ -623,18 +689,15 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
         t.depth = level;
         break;
     }
-    // leaves
+    // leaves (cells that did not split), in cell order
+    t.nleaves = t.ncells - nsplit_total;
     int32_t* f = A.down<int32_t>(t.ncells + 1);
     int32_t* pos = A.down<int32_t>(t.ncells + 1);
     hipLaunchKernelGGL(k_leaf_flags, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s, t.cells,
                        t.ncells, f);
     LAUNCH_CHECK();
     scan_exclusive_i32(f, pos, t.ncells, A, s);
-    int32_t nleaves = 0;
-    HIP_TRY(hipMemcpyAsync(&nleaves, pos + t.ncells, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    t.nleaves = nleaves;
-    t.leaves = A.up<int32_t>(nleaves);
+    t.leaves = A.up<int32_t>(t.nleaves);
     hipLaunchKernelGGL(k_leaf_compact, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
                        t.cells, t.ncells, pos, t.leaves, t.leaf_of);
     LAUNCH_CHECK();
