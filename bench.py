@@ -45,20 +45,24 @@ def p2p_pairs(tree) -> int:
     return int(np.sum(cnt[leaf] * src[leaf]))
 
 
-def cpu_baseline(p: int, leaf: int):
-    """The FP64 oracle FMM, as it stands, on a bounded sample of the workload."""
+def cpu_baseline(x, y, z, m, p: int, leaf: int, dist: str, ntarget: int = 2048):
+    """The FP64 oracle FMM, as it stands, on a bounded sample of the same
+    workload: the whole tree and upward pass for all N particles, then the
+    far and near field for `ntarget` seeded target particles.  The rate is
+    target particles per second, setup included."""
     from oracle import oracle as O
     from paper_1010_1482_amd import workloads as W
-    n = 16384  # 8^3 leaves of mean 32 particles: the 1M tree's leaf occupancy
-    x, y, z, m = W.uniform(n, 2)
+    n = len(x)
+    tg = W.sample_targets(n, ntarget, 7)
     t0 = time.perf_counter()
-    O.fmm(x, y, z, m, p, leaf)
+    O.fmm(x, y, z, m, p, leaf, targets=tg)
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "particles/s", "cores": O.num_threads(),
+    return {"value": ntarget / dt, "unit": "particles/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": f"oracle FMM (FP64, Eq. 4 M2L as complex sums) on N={n} uniform "
-                      f"particles (mean 32 per leaf like the 1M workload), p={p}, "
-                      f"leaf<={leaf}, all targets; {dt:.1f} s"}
+            "sample": f"oracle FMM (FP64, Eq. 4 M2L as complex sums) on the same N={n} "
+                      f"{dist} particles, p={p}, leaf<={leaf}: full tree and upward pass, "
+                      f"far and near field for {ntarget} seeded targets; {dt:.1f} s; "
+                      f"value = targets / time"}
 
 
 def serving_bench(n_req: int, slots: int, budget_gb: float, plain: bool):
@@ -99,6 +103,114 @@ def serving_bench(n_req: int, slots: int, budget_gb: float, plain: bool):
     return out
 
 
+def source_digest(path: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, config: str):
+    """HBM bytes per launch of `kernel` on `config` from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    plain copy), or None when the kernel's source changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{config}_counters.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-json:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec.get("source_sha") != source_digest(rec["source"]):
+                    return None
+                return rec
+    return None
+
+
+def copy_probe(mib: int = 1024) -> int:
+    """A plain device copy of known size, for calibrating the FETCH_SIZE and
+    WRITE_SIZE counters (rocprofv3 --pmc ... -- python3 bench.py --copy-probe)."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
+    return 0
+
+
+def measure(args, prec_name, x, y, z, m, dev, steps, warmup, accuracy):
+    """Time `steps` whole steps (after `warmup`) of one configuration."""
+    import torch
+    from paper_1010_1482_amd import hfmm
+    from paper_1010_1482_amd import workloads as W
+    n, p, leaf = len(x), args.p, args.leaf
+    prec = hfmm.PRECISIONS[prec_name]
+    meth = hfmm.METHODS[args.method]
+    xd, yd, zd, md = (torch.from_numpy(a).to(dev) for a in (x, y, z, m))
+    dt = hfmm.out_dtype(prec)
+    out = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    hold = {"arena": torch.empty(hfmm.arena_bytes(n, 0, leaf, p, meth, prec),
+                                 dtype=torch.uint8, device=dev)}
+    hfmm.set_timing(True)
+
+    def step(sizing=False):
+        try:
+            t = hfmm.Tree(xd, yd, zd, leaf_max=leaf, arena=hold["arena"])
+        except hfmm.HfmmError as e:
+            if sizing and e.code == hfmm.E_NOMEM:
+                return hfmm._lib().hfmm_last_required_bytes()
+            raise
+        try:
+            t.upward(md, p, meth, prec)
+            t.evaluate(theta=args.theta, out=out)
+        except hfmm.HfmmError as e:
+            if sizing and e.code == hfmm.E_NOMEM:
+                return t.required_bytes()
+            raise
+        return t
+
+    # sizing pass, outside the clock: the arena estimate can fall short for
+    # clustered data (long treecode lists); grow it to what the call needed
+    for _ in range(4):
+        need = step(sizing=True)
+        if not isinstance(need, int):
+            break
+        hold["arena"] = None
+        torch.cuda.synchronize()
+        hold["arena"] = torch.empty(int(need * 1.25) + (64 << 20), dtype=torch.uint8,
+                                    device=dev)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    lat, phases = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        tr = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+        phases.append(tr.stats()["phase_ms"])
+    t1 = time.perf_counter()
+    ms = (t1 - t0) / steps * 1e3
+    res = {"ms_per_step": ms, "value": n / (ms * 1e-3),
+           "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                          "p99": float(np.percentile(lat, 99) * 1e3)},
+           "phase_ms": {k: float(np.mean([d[k] for d in phases])) for k in phases[-1]},
+           "stats": tr.stats(), "tree": tr}
+    if accuracy:
+        from oracle import oracle as O
+        tg = W.sample_targets(n, args.accuracy_targets, 100 + args.seed)
+        ref = O.direct(x, y, z, m, targets=tg)
+        got = [o.double().cpu().numpy()[tg] for o in out]
+        res["accuracy"] = {
+            "targets": len(tg), "reference": "FP64 oracle direct sum over all N",
+            "rel_l2_phi": O.rel_l2(got[0], ref[0]),
+            "rel_l2_acc": O.rel_l2(np.stack(got[1:]), np.stack(ref[1:]))}
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -116,114 +228,103 @@ def main() -> int:
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--method", default="fmm", choices=["fmm", "treecode"])
     ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--forms", default="bf16x3,fp16x3,bf16,fp16",
+                    help="M2L precision forms measured beside the headline one "
+                         "('' for none)")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving trace (0 skips the serving form)")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-plain", action="store_true",
                     help="also serve the trace one request at a time")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         return 2
+    if args.copy_probe:
+        return copy_probe()
 
     import torch
-    from paper_1010_1482_amd import hfmm
     from paper_1010_1482_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
     n, p, leaf = args.n, args.p, args.leaf
-    prec = hfmm.PRECISIONS[args.precision]
     x, y, z, m = W.make(args.dist, n, args.seed)
-    xd, yd, zd, md = (torch.from_numpy(a).to(dev) for a in (x, y, z, m))
-    dt = hfmm.out_dtype(prec)
-    out = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
-    arena = torch.empty(hfmm.arena_bytes(n, 0, leaf, p, hfmm.METHODS[args.method], prec),
-                        dtype=torch.uint8, device=dev)
-    hfmm.set_timing(True)
-    stream = torch.cuda.current_stream()
+    r = measure(args, args.precision, x, y, z, m, dev, args.steps, args.warmup,
+                not args.no_accuracy)
+    tr, stats, ph = r["tree"], r["stats"], r["phase_ms"]
+    workload = (f"FMM N={n} {args.dist} unit cube, masses 1/N, p={p}, leaf<={leaf}, "
+                f"{args.precision}") if args.method == "fmm" else (
+                f"treecode N={n} {args.dist}, p={p}, theta={args.theta}, leaf<={leaf}, "
+                f"{args.precision}")
 
-    meth = hfmm.METHODS[args.method]
-
-    def step():
-        t = hfmm.Tree(xd, yd, zd, leaf_max=leaf, arena=arena)
-        t.upward(md, p, meth, prec)
-        t.evaluate(theta=args.theta, out=out)
-        return t
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    lat = []
-    phases = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        s0 = time.perf_counter()
-        tr = step()
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - s0)
-        phases.append(tr.stats()["phase_ms"])
-    t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
-    stats = tr.stats()
-    ph = {k: float(np.mean([d[k] for d in phases])) for k in phases[-1]}
-
-    # dominant kernel and its roofline (algorithmic work per launch / its
-    # average device time over the timed steps)
+    # Roofline of the dominant kernel: algorithmic work per launch over the
+    # kernel's own device time (HIP events on its stream, averaged over the
+    # timed steps).  M2L: 2 p^4 flops per V pair (the real p^2 x p^2
+    # operator), on the matrix cores of its operand type.  P2P: 21 flops per
+    # pair (the paper's count plus the potential) on the FP32 vector units.
     pairs = p2p_pairs(tr) if args.method == "fmm" else 0
     m2l_pairs = stats["m2l_pairs"]
-    m2l_flops = 2.0 * p ** 4 * m2l_pairs
     m2l_peak = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"]}.get(
         args.precision, PEAK["bf16_TFs"])
     cand = {
-        "m2l": (ph.get("m2l", 0.0), m2l_flops, "mfma", m2l_peak),
+        "m2l": (ph.get("m2l", 0.0), 2.0 * p ** 4 * m2l_pairs, "mfma", m2l_peak),
         "p2p": (ph.get("p2p", 0.0), P2P_FLOPS * pairs, "alu", PEAK["fp32_TFs"]),
     }
     dom = max(cand, key=lambda k: cand[k][0])
     dms, dwork, dbound, dpeak = cand[dom]
     ach = dwork / (dms * 1e-3) / 1e12
+    m2l_kernel = "k_m2l_valu" if (args.precision == "fp64" or p > 13) else "k_m2l_mma"
+    kname = {"m2l": m2l_kernel, "p2p": "k_p2p"}[dom]
+    cfg = f"{args.dist}_{n >> 20}M_p{p}_{args.precision}" if n >= 1 << 20 else \
+        f"{args.dist}_{n}_p{p}_{args.precision}"
+    rec = recorded_traffic(kname, cfg)
     roof = {"bound": dbound, "achieved": ach, "peak": dpeak, "unit": "TFLOP/s",
-            "frac": ach / dpeak, "traffic": None, "kernel": dom,
-            "work_per_launch": dwork, "launch_ms": dms}
+            "frac": ach / dpeak, "traffic": rec["bytes_per_launch"] if rec else None,
+            "kernel": kname, "work_per_launch": dwork, "launch_ms": dms}
+    if rec:
+        roof["traffic_note"] = rec["note"]
 
     res = {
         "metric": "particles/s, FMM N=1M at rel err<=1e-4 vs FP64; p50/p99 request latency",
-        "value": n / (ms * 1e-3), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "value": r["value"], "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec != hfmm.FP64 else "f64", "data": "synthetic",
-        "config": {"workload": f"FMM N={n} {args.dist} unit cube, masses 1/N, p={p}, "
-                               f"leaf<={leaf}, {args.precision}",
-                   "n": n, "p": p, "leaf_max": leaf, "dist": args.dist,
-                   "precision": args.precision, "method": args.method},
-        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                       "p99": float(np.percentile(lat, 99) * 1e3)},
+        "dtype": "f32" if args.precision != "fp64" else "f64", "data": "synthetic",
+        "config": {"workload": workload, "n": n, "p": p, "leaf_max": leaf,
+                   "dist": args.dist, "precision": args.precision, "method": args.method},
+        "latency_ms": r["latency_ms"],
         "phase_ms": ph,
         "tree": {"cells": stats["n_cells"], "leaves": stats["n_leaves"],
                  "depth": stats["depth"], "list_u": stats["list_u"],
                  "list_v": stats["list_v"]},
-        "p2p_interactions_per_s": pairs / (ph.get("p2p", 1.0) * 1e-3),
-        "m2l_pairs_per_s": m2l_pairs / (ph.get("m2l", 1.0) * 1e-3),
+        "p2p_interactions_per_s": pairs / (ph.get("p2p", 1.0) * 1e-3) if pairs else None,
+        "m2l_pairs_per_s": m2l_pairs / (ph.get("m2l", 1.0) * 1e-3) if m2l_pairs else None,
         "roofline": roof,
     }
-
-    if not args.no_accuracy:
-        from oracle import oracle as O
-        tg = W.sample_targets(n, args.accuracy_targets, 100 + args.seed)
-        ref = O.direct(x, y, z, m, targets=tg)
-        got = [o.double().cpu().numpy()[tg] for o in out]
-        res["accuracy"] = {
-            "targets": len(tg), "reference": "FP64 oracle direct sum over all N",
-            "rel_l2_phi": O.rel_l2(got[0], ref[0]),
-            "rel_l2_acc": O.rel_l2(np.stack(got[1:]), np.stack(ref[1:]))}
+    if "accuracy" in r:
+        res["accuracy"] = r["accuracy"]
+    forms = [f for f in args.forms.split(",") if f and f != args.precision]
+    if forms and args.method == "fmm":
+        res["precision_forms"] = {}
+        for f in forms:
+            rf = measure(args, f, x, y, z, m, dev, args.steps, args.warmup,
+                         not args.no_accuracy)
+            res["precision_forms"][f] = {
+                "value": rf["value"], "ms_per_step": rf["ms_per_step"],
+                "m2l_ms": rf["phase_ms"].get("m2l"),
+                "rel_l2_acc": rf.get("accuracy", {}).get("rel_l2_acc"),
+                "rel_l2_phi": rf.get("accuracy", {}).get("rel_l2_phi")}
     if args.serve_requests > 0:
         res["serving"] = serving_bench(args.serve_requests, args.serve_slots,
                                        args.serve_budget_gb, args.serve_plain)
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(p, leaf)
+        res["cpu_baseline"] = cpu_baseline(x, y, z, m, p, leaf, args.dist)
     print(json.dumps(res), flush=True)
     return 0
 

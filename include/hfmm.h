@@ -83,7 +83,7 @@ enum hfmm_status {
 
 #define HFMM_MAX_P 16
 #define HFMM_KEY_LEVELS 21   /* octree depth limit: 21 bits per axis */
-#define HFMM_PHASES 9
+#define HFMM_PHASES 10
 
 /* Upper estimate of the arena bytes for one tree over n_src sources and
  * n_tgt distinct targets (0 for self-evaluation) at order p.  Host only.  The
@@ -161,8 +161,9 @@ typedef struct {
     size_t arena_used;
     /* device time of the phases of the last calls, in ms (-1 when not timed):
      * 0 tree build, 1 FMM lists, 2 upward (P2M, M2M), 3 M2L operator tables,
-     * 4 M2L kernel, 5 downward (P2L, L2L), 6 far field (L2P, M2P),
-     * 7 P2P (+ output scatter), 8 treecode lists */
+     * 4 M2L kernel (the matrix products alone), 5 downward (P2L, L2L),
+     * 6 far field (L2P, M2P), 7 P2P (+ output scatter), 8 treecode lists,
+     * 9 M2L operand preparation (packing, low-precision scaling) */
     double phase_ms[HFMM_PHASES];
 } hfmm_stats;
 

@@ -140,10 +140,7 @@ void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi, void* a
         if (t.n_x > 0) LX = A.down<double>((size_t)t.ncells * t.ldm);
         int64_t stride = 0;
         int parts;
-        {
-            PhaseTimer pt(t, PH_M2L, s);
-            parts = run_m2l(t, p, precision, lm, stride, parts_cap, levexp, s);
-        }
+        parts = run_m2l(t, p, precision, lm, stride, parts_cap, levexp, s);
         PhaseTimer pt(t, PH_DOWN, s);
         if (LX) {
             HIP_TRY(hipMemsetAsync(LX, 0, row * t.ncells, s));

@@ -161,7 +161,8 @@ struct Tree {
     int32_t *x_off = nullptr, *x_items = nullptr;
     int64_t n_u = 0, n_v = 0, n_w = 0, n_x = 0;
     int32_t* m2l_order = nullptr;    // targets (level >= 2) by (level, octant)
-    int32_t* m2l_tiles = nullptr;    // per tile: start into m2l_order, count, octant
+    int32_t* m2l_torder = nullptr;   // the same targets by (octant, level)
+    int32_t* m2l_tiles = nullptr;    // per tile: start into m2l_torder, count, octant
     int32_t n_m2l_tiles = 0;
     size_t mark_lists = 0;
     // treecode lists
@@ -188,7 +189,9 @@ struct Tree {
     bool ev_used[HFMM_PHASES] = {};
 };
 
-enum Phase { PH_BUILD = 0, PH_LISTS, PH_UPWARD, PH_OPS, PH_M2L, PH_DOWN, PH_FAR, PH_P2P, PH_BH };
+enum Phase {
+    PH_BUILD = 0, PH_LISTS, PH_UPWARD, PH_OPS, PH_M2L, PH_DOWN, PH_FAR, PH_P2P, PH_BH, PH_M2L_PREP
+};
 
 // records an event pair around a scope when the tree is timed
 struct PhaseTimer {

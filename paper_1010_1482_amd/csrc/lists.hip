@@ -268,9 +268,11 @@ __global__ void k_list_totals(const int32_t* __restrict__ off, int nc, int32_t* 
 // ---------------------------------------------------------------------
 constexpr int kGroups = 8 * (HFMM_KEY_LEVELS + 2);
 
+// keys (level, octant) for the L2L order and (octant, level) for the M2L
+// tiles, with the counts per (level, octant)
 __global__ void k_m2l_keys(const Cell* __restrict__ cells, int c0, int nc,
-                           uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
-                           int32_t* __restrict__ counts) {
+                           uint64_t* __restrict__ keys, uint64_t* __restrict__ keys2,
+                           int32_t* __restrict__ vals, int32_t* __restrict__ counts) {
     __shared__ int hist[kGroups];
     for (int k = threadIdx.x; k < kGroups; k += blockDim.x) hist[k] = 0;
     __syncthreads();
@@ -280,6 +282,7 @@ __global__ void k_m2l_keys(const Cell* __restrict__ cells, int c0, int nc,
         Cell B = cells[c];
         int k = B.level * 8 + octant_of(B);
         keys[i] = (uint64_t)k;
+        keys2[i] = (uint64_t)(octant_of(B) * 32 + B.level);
         vals[i] = c;
         atomicAdd(&hist[k], 1);
     }
@@ -329,13 +332,16 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     const int nm = nc - c2;
     uint64_t* mk = A.down<uint64_t>(std::max(nm, 1));
     uint64_t* mk2 = A.down<uint64_t>(std::max(nm, 1));
+    uint64_t* mk3 = A.down<uint64_t>(std::max(nm, 1));
     int32_t* mv = A.down<int32_t>(std::max(nm, 1));
     t.m2l_order = A.up<int32_t>(std::max(nm, 1));
+    t.m2l_torder = A.up<int32_t>(std::max(nm, 1));
     if (nm > 0) {
         hipLaunchKernelGGL(k_m2l_keys, dim3(grid_for(nm, 256)), dim3(256), 0, s, t.cells, c2,
-                           nc, mk, mv, hr + 4);
+                           nc, mk, mk3, mv, hr + 4);
         LAUNCH_CHECK();
         radix_sort_pairs(mk, mv, mk2, t.m2l_order, nm, 0, 8, A, s);
+        radix_sort_pairs(mk3, mv, mk2, t.m2l_torder, nm, 0, 8, A, s);
     }
     std::vector<int32_t> h(4 + kGroups);
     HIP_TRY(hipMemcpyAsync(h.data(), hr, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, s));
@@ -357,26 +363,26 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
         for (int o = 0; o < 8; ++o) acc += gc[l * 8 + o];
         t.m2l_level_start[l + 1] = acc;
     }
-    // tiles of up to 256 targets that share (level, octant), listed as
-    // (level, k, octant) for the k-th tile of each octant: the eight tiles
-    // of one k cover the same stretch of Morton order, so they read nearly
-    // the same source expansions
+    // M2L tiles: runs of up to 256 targets of one octant, levels mixed (the
+    // scaled operators do not depend on the level and every source is read
+    // by index), so only the last tile of an octant is partly filled.  Tiles
+    // are listed as (k, octant) for the k-th tile of each octant: the eight
+    // tiles of one k cover about the same stretch of Morton order and read
+    // nearly the same source expansions.
     std::vector<int32_t> tiles;
-    std::vector<int> gstart(gc.size() + 1, 0);
-    for (size_t g = 0; g < gc.size(); ++g) gstart[g + 1] = gstart[g] + gc[g];
-    for (int l = 0; l <= HFMM_KEY_LEVELS + 1; ++l) {
-        int kmax = 0;
-        for (int o = 0; o < 8; ++o) kmax = std::max(kmax, gc[l * 8 + o]);
-        for (int k = 0; k < kmax; k += 256)
-            for (int o = 0; o < 8; ++o) {
-                const int g = l * 8 + o;
-                if (k >= gc[g]) continue;
-                tiles.push_back(gstart[g] + k);
-                tiles.push_back(std::min(256, gc[g] - k));
-                tiles.push_back(o);
-                tiles.push_back(l);
-            }
-    }
+    int ocount[8] = {0}, ostart[9] = {0};
+    for (int o = 0; o < 8; ++o)
+        for (int l = 0; l <= HFMM_KEY_LEVELS + 1; ++l) ocount[o] += gc[l * 8 + o];
+    for (int o = 0; o < 8; ++o) ostart[o + 1] = ostart[o] + ocount[o];
+    const int kmax = *std::max_element(ocount, ocount + 8);
+    for (int k = 0; k < kmax; k += 256)
+        for (int o = 0; o < 8; ++o) {
+            if (k >= ocount[o]) continue;
+            tiles.push_back(ostart[o] + k);
+            tiles.push_back(std::min(256, ocount[o] - k));
+            tiles.push_back(o);
+            tiles.push_back(0);
+        }
     t.n_m2l_tiles = (int32_t)(tiles.size() / 4);
     t.m2l_tiles = A.up<int32_t>(std::max<size_t>(tiles.size(), 4));
     if (!tiles.empty()) {

@@ -19,6 +19,7 @@
 #include "expansions.hpp"
 
 #include <algorithm>
+#include <optional>
 
 namespace hfmm {
 
@@ -194,10 +195,18 @@ struct OpLow {
 
 // column blocks of 16 targets per wave (8 waves per 256-target tile)
 constexpr int kM2LCB = 2;
+// contraction steps whose source chunks are loaded ahead of use
+constexpr int kM2LAhead = 2;
+// Two operator buffers (the next slot's operator streams in during the
+// products) pay off for the split forms, whose slots are short relative to
+// the operator copy; they are used when both copies fit in 144 KiB of LDS.
+constexpr bool m2l_double_buffer(int rb, int kq, int ns) {
+    return ns == 2 && 2 * ns * rb * kq * 64 * 16 <= 144 * 1024;
+}
 typedef __attribute__((address_space(3))) void* lds_ptr;
 typedef const __attribute__((address_space(1))) void* gbl_ptr;
 
-template <int RB, int KQ, int CB, class Op>
+template <int RB, int KQ, int CB, bool DB, class Op>
 __global__ void __launch_bounds__(1024 / CB)
 k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
           const int32_t* __restrict__ vsrc, const typename Op::E* __restrict__ Mhi,
@@ -210,6 +219,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
     constexpr int NS = Op::X3 ? 2 : 1;
     constexpr int NW = 16 / CB;       // waves per block (CB column blocks each)
     __shared__ u32x4 sT[NS * NT];
+    __shared__ u32x4 sT2[DB ? NS * NT : 1];
     __shared__ uint32_t smask[8];
     // Workgroups are handed to the 8 XCDs round-robin; renumber them so that
     // each XCD (own L2) runs one contiguous range of (tile, part), parts
@@ -267,80 +277,119 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
 
     const u32x4* Mh = (const u32x4*)Mhi;
     const u32x4* Ml = (const u32x4*)Mlo;
-    int j = next_slot(0);
-    int src[CB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-        src[cb] = (j < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + j] : -1;
-    while (j < ns) {
-        const int slot = s0 + j;
+    // operator of relative slot jj -> LDS buffer (each wave copies every
+    // NW-th 1-KiB chunk with direct global-to-LDS loads)
+    auto stage = [&](u32x4* buf, int jj) {
+        const int slot = s0 + jj;
         const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
         const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
-        // operator of this slot -> LDS (each wave copies every 4th 1-KiB chunk)
-        {
-            const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
+        const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
+        for (int k = wave; k < RB * KQ; k += NW)
+            __builtin_amdgcn_global_load_lds((gbl_ptr)(th + k * 64 + lane),
+                                             (lds_ptr)(buf + k * 64), 16, 0, 0);
+        if (Op::X3) {
+            const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
             for (int k = wave; k < RB * KQ; k += NW)
-                __builtin_amdgcn_global_load_lds((gbl_ptr)(th + k * 64 + lane),
-                                                 (lds_ptr)(sT + k * 64), 16, 0, 0);
-            if (Op::X3) {
-                const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
-                for (int k = wave; k < RB * KQ; k += NW)
-                    __builtin_amdgcn_global_load_lds((gbl_ptr)(tl + k * 64 + lane),
-                                                     (lds_ptr)(sT + NT + k * 64), 16, 0, 0);
-            }
+                __builtin_amdgcn_global_load_lds((gbl_ptr)(tl + k * 64 + lane),
+                                                 (lds_ptr)(buf + NT + k * 64), 16, 0, 0);
         }
-        int64_t boff[CB];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) boff[cb] = (int64_t)(src[cb] >= 0 ? src[cb] : ncells) * CPR + g;
-        u32x4 bh[CB], bl[CB];
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            bh[cb] = Mh[boff[cb]];
-            if (Op::X3) bl[cb] = Ml[boff[cb]];
-        }
-        const int jn = next_slot(j + 1);
+    };
+    auto load_src = [&](int jj, int (&sv)[CB]) {
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-            src[cb] = (jn < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + jn] : -1;
-        __syncthreads();  // operator in LDS
-        {
+            sv[cb] = (jj < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + jj] : -1;
+    };
+    // source chunks of step q live in bh[q]; kM2LAhead steps are in flight
+    // ahead of the matrix cores (registers are only allocated for the live
+    // ones, every index being a constant after unrolling)
+    auto first_chunks = [&](const int (&sv)[CB], int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
+                            u32x4 (&bl)[KQ][CB]) {
 #pragma unroll
-            for (int q = 0; q < KQ; ++q) {
-                u32x4 nh[CB], nl[CB];
-                if (q + 1 < KQ) {
+        for (int cb = 0; cb < CB; ++cb)
+            boff[cb] = (int64_t)(sv[cb] >= 0 ? sv[cb] : ncells) * CPR + g;
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) {
-                        nh[cb] = Mh[boff[cb] + 4 * (q + 1)];
-                        if (Op::X3) nl[cb] = Ml[boff[cb] + 4 * (q + 1)];
-                    }
-                }
+        for (int q = 0; q < KQ && q < kM2LAhead; ++q)
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const u32x4 ah = sT[(rb * KQ + q) * 64 + lane];
-                    u32x4 al = ah;
-                    if (Op::X3) al = sT[NT + (rb * KQ + q) * 64 + lane];
-#define M2L_STEP(s)                                                                      \
-    if (s < Op::S) {                                                                     \
-        _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                   \
-            Op::template mma<(s < Op::S ? s : 0)>(ah, al, bh[cb], bl[cb], acc[cb][rb]); \
-    }
-                    M2L_STEP(0)
-                    M2L_STEP(1)
-                    M2L_STEP(2)
-                    M2L_STEP(3)
-#undef M2L_STEP
-                }
-                if (q + 1 < KQ) {
+            for (int cb = 0; cb < CB; ++cb) {
+                bh[q][cb] = Mh[boff[cb] + 4 * q];
+                if (Op::X3) bl[q][cb] = Ml[boff[cb] + 4 * q];
+            }
+    };
+    auto products = [&](const u32x4* buf, const int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
+                        u32x4 (&bl)[KQ][CB]) {
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) {
-                        bh[cb] = nh[cb];
-                        if (Op::X3) bl[cb] = nl[cb];
-                    }
+        for (int q = 0; q < KQ; ++q) {
+            if (q + kM2LAhead < KQ) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    bh[q + kM2LAhead][cb] = Mh[boff[cb] + 4 * (q + kM2LAhead)];
+                    if (Op::X3) bl[q + kM2LAhead][cb] = Ml[boff[cb] + 4 * (q + kM2LAhead)];
                 }
             }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const u32x4 ah = buf[(rb * KQ + q) * 64 + lane];
+                u32x4 al = ah;
+                if (Op::X3) al = buf[NT + (rb * KQ + q) * 64 + lane];
+#define M2L_STEP(s)                                                                         \
+    if (s < Op::S) {                                                                        \
+        _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                      \
+            Op::template mma<(s < Op::S ? s : 0)>(ah, al, bh[q][cb], bl[q][cb], acc[cb][rb]); \
+    }
+                M2L_STEP(0)
+                M2L_STEP(1)
+                M2L_STEP(2)
+                M2L_STEP(3)
+#undef M2L_STEP
+            }
         }
-        __syncthreads();  // LDS free for the next operator
-        j = jn;
+    };
+
+    int j = next_slot(0);
+    int src[CB];
+    load_src(j, src);
+    if (DB) {
+        // two operator buffers: the next active slot's operator streams in
+        // while this one is on the matrix cores; one barrier per slot
+        if (j < ns) stage(sT, j);
+        while (j < ns) {
+            {
+                int64_t boff[CB];
+                u32x4 bh[KQ][CB], bl[KQ][CB];
+                first_chunks(src, boff, bh, bl);
+                const int jn = next_slot(j + 1);
+                load_src(jn, src);
+                __syncthreads();  // sT holds slot j, sT2 is no longer read
+                if (jn < ns) stage(sT2, jn);
+                products(sT, boff, bh, bl);
+                j = jn;
+            }
+            if (j >= ns) break;
+            {
+                int64_t boff[CB];
+                u32x4 bh[KQ][CB], bl[KQ][CB];
+                first_chunks(src, boff, bh, bl);
+                const int jn = next_slot(j + 1);
+                load_src(jn, src);
+                __syncthreads();  // sT2 holds slot j, sT is no longer read
+                if (jn < ns) stage(sT, jn);
+                products(sT2, boff, bh, bl);
+                j = jn;
+            }
+        }
+    } else {
+        while (j < ns) {
+            stage(sT, j);
+            int64_t boff[CB];
+            u32x4 bh[KQ][CB], bl[KQ][CB];
+            first_chunks(src, boff, bh, bl);
+            const int jn = next_slot(j + 1);
+            load_src(jn, src);
+            __syncthreads();  // operator in LDS
+            products(sT, boff, bh, bl);
+            __syncthreads();  // LDS free for the next operator
+            j = jn;
+        }
     }
     // output block (rb): lane holds rows 16 rb + 4 g + (0..3) of column col
 #pragma unroll
@@ -467,6 +516,7 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     Arena& A = t.arena;
     const int c0 = t.level_start[2], c1 = t.ncells;
     if (!m2l_uses_mfma(p, precision)) {
+        PhaseTimer pt(t, PH_M2L, s);
         const size_t sm = (size_t)P * (precision == HFMM_FP64 ? 8 : 4);
         if (precision == HFMM_FP64)
             hipLaunchKernelGGL((k_m2l_valu<double>), dim3(c1 - c0), dim3(64), sm, s, t.cells, c0,
@@ -488,9 +538,13 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     dim3 grid(ntiles, parts), block(1024 / kM2LCB);
     if (!is_lowp(precision)) {
         float* Mk = A.down<float>((size_t)(t.ncells + 1) * ld);
-        run_pack(t.M, t.ldm, t.ncells, P, ld, Mk, false, s);
+        {
+            PhaseTimer pp(t, PH_M2L_PREP, s);
+            run_pack(t.M, t.ldm, t.ncells, P, ld, Mk, false, s);
+        }
+        PhaseTimer pt(t, PH_M2L, s);
 #define MFMA_CASE(R)                                                                         \
-    hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, OpF32>), grid, block, 0, s, t.m2l_tiles, t.m2l_order,  \
+    hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, m2l_double_buffer(R, R, 1), OpF32>), grid, block, 0, s, t.m2l_tiles, t.m2l_torder,  \
                        t.vsrc, (const float*)Mk, (const float*)nullptr, t.ncells,              \
                        (const float*)t.T, (const float*)nullptr, (float*)out, part_stride, spp);
         HFMM_DISPATCH_RB(RB, MFMA_CASE);
@@ -500,6 +554,8 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     }
     // low precision: per-level scale, packed hi/lo operand, matrix cores
     const bool x3 = is_x3(precision);
+    std::optional<PhaseTimer> tm;  // operand preparation, then the products
+    tm.emplace(t, PH_M2L_PREP, s);
     HIP_TRY(hipMemsetAsync(levexp, 0x80, 32 * sizeof(int32_t), s));
     hipLaunchKernelGGL(k_level_exp, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s, t.cells,
                        t.ncells, t.M, t.ldm, levexp);
@@ -513,16 +569,18 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         hipLaunchKernelGGL((k_pack_lp<__bf16>), dim3(grid_for(tot, 256)), dim3(256), 0, s,
                            t.cells, t.M, t.ldm, t.ncells, P, ld, levexp, mh, ml);
         LAUNCH_CHECK();
+        tm.reset();
+        tm.emplace(t, PH_M2L, s);
         const __bf16* th = (const __bf16*)t.T;
         const __bf16* tl = x3 ? th + half : nullptr;
 #define LP_CASE(R)                                                                             \
     if (x3)                                                                                    \
-        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<__bf16, true>>), grid, block, 0, s,    \
-                           t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 2), OpLow<__bf16, true>>), grid, block, 0, s,    \
+                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);                                      \
     else                                                                                       \
-        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<__bf16, false>>), grid, block, 0, s,   \
-                           t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 1), OpLow<__bf16, false>>), grid, block, 0, s,   \
+                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);
         HFMM_DISPATCH_RB(RB, LP_CASE);
 #undef LP_CASE
@@ -532,16 +590,18 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         hipLaunchKernelGGL((k_pack_lp<_Float16>), dim3(grid_for(tot, 256)), dim3(256), 0, s,
                            t.cells, t.M, t.ldm, t.ncells, P, ld, levexp, mh, ml);
         LAUNCH_CHECK();
+        tm.reset();
+        tm.emplace(t, PH_M2L, s);
         const _Float16* th = (const _Float16*)t.T;
         const _Float16* tl = x3 ? th + half : nullptr;
 #define LP_CASE(R)                                                                             \
     if (x3)                                                                                    \
-        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<_Float16, true>>), grid, block, 0, s,  \
-                           t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 2), OpLow<_Float16, true>>), grid, block, 0, s,  \
+                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);                                      \
     else                                                                                       \
-        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, OpLow<_Float16, false>>), grid, block, 0, s, \
-                           t.m2l_tiles, t.m2l_order, t.vsrc, mh, ml, t.ncells, th, tl,          \
+        hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 1), OpLow<_Float16, false>>), grid, block, 0, s, \
+                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
                            (float*)out, part_stride, spp);
         HFMM_DISPATCH_RB(RB, LP_CASE);
 #undef LP_CASE

@@ -45,10 +45,10 @@ class Stats(C.Structure):
                 ("root", C.c_double * 4), ("list_u", C.c_int64), ("list_v", C.c_int64),
                 ("list_w", C.c_int64), ("list_x", C.c_int64), ("list_m2p", C.c_int64),
                 ("list_p2p", C.c_int64), ("p2p_pairs", C.c_int64), ("m2l_pairs", C.c_int64),
-                ("arena_used", C.c_size_t), ("phase_ms", C.c_double * 9)]
+                ("arena_used", C.c_size_t), ("phase_ms", C.c_double * 10)]
 
     PHASES = ("build", "lists", "upward", "m2l_ops", "m2l", "downward", "far", "p2p",
-              "bh_lists")
+              "bh_lists", "m2l_prep")
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
