@@ -279,7 +279,7 @@ def main() -> int:
     dom = max(cand, key=lambda k: cand[k][0])
     dms, dwork, dbound, dpeak = cand[dom]
     ach = dwork / (dms * 1e-3) / 1e12
-    m2l_kernel = "k_m2l_valu" if (args.precision == "fp64" or p > 13) else "k_m2l_mma"
+    m2l_kernel = "k_m2l_valu" if p > (11 if args.precision == "fp64" else 13) else "k_m2l_mma"
     kname = {"m2l": m2l_kernel, "p2p": "k_p2p"}[dom]
     cfg = f"{args.dist}_{n >> 20}M_p{p}_{args.precision}" if n >= 1 << 20 else \
         f"{args.dist}_{n}_p{p}_{args.precision}"

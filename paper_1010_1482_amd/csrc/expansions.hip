@@ -548,7 +548,12 @@ __device__ inline double m2l_entry(int ro, int ri, const double (*pt)[kNmax],
 // FP64 layout T64[cls][ri][ro] and/or the FP32 matrix-core layout
 // Tsw[cls][rb][q][lane][4] with T[16 rb + (lane & 15)][16 q + 4 (lane >> 4) + r].
 __global__ void __launch_bounds__(256)
-k_m2l_ops(int p, double* __restrict__ T64, float* __restrict__ T32, int RB, int KQ) {
+k_m2l_ops(int p, int layout, void* __restrict__ T, int RB, int KQ) {
+    // layout 0: FP64 [class][ri][ro] (vector units); 1: FP32 matrix-core
+    // chunks, contraction element ri = 16 q + 4 r + g at lane group g,
+    // product r; 2: FP64 matrix-core chunks, ri = 8 q + 4 r + g.  The r-major
+    // order puts the padding of the last block into whole products, which
+    // the kernel skips.
     __shared__ double pt[kNmax][kNmax];
     __shared__ double cs[kNmax][2];
     const int P = p * p;
@@ -558,12 +563,17 @@ k_m2l_ops(int p, double* __restrict__ T64, float* __restrict__ T32, int RB, int 
     for (int64_t e = threadIdx.x; e < per; e += blockDim.x) {
         const int ro = (int)(e / P), ri = (int)(e % P);
         const double val = far ? m2l_entry(ro, ri, pt, cs) : 0.0;
-        if (T64) T64[(int64_t)cls * per + (int64_t)ri * P + ro] = val;
-        if (T32) {
-            const int rb = ro / 16, il = ro % 16;
-            const int q = ri / 16, g = (ri % 16) / 4, r = ri % 4;
+        const int rb = ro / 16, il = ro % 16;
+        if (layout == 0) {
+            ((double*)T)[(int64_t)cls * per + (int64_t)ri * P + ro] = val;
+        } else if (layout == 1) {
+            const int q = ri / 16, g = (ri % 16) % 4, r = (ri % 16) / 4;
             const int lane = g * 16 + il;
-            T32[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 4 + r] = (float)val;
+            ((float*)T)[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 4 + r] = (float)val;
+        } else {
+            const int q = ri / 8, g = (ri % 8) % 4, r = (ri % 8) / 4;
+            const int lane = g * 16 + il;
+            ((double*)T)[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 2 + r] = val;
         }
     }
 }
@@ -637,12 +647,20 @@ void run_m2l_ops_lp(int p, int precision, int RB, int KQ, int32_t* bexp, void* h
 // pack Mt (FP64, p*p per cell) into the M2L operand: ld = Kp (zero padded),
 // one extra zero row at index ncells for absent sources
 template <typename TO>
+// Rows of the matrix-core M2L operand.  Within each block of 4 NR (NR = 4
+// floats or 2 doubles per 16-byte chunk), position NR g + r holds element
+// 4 NR q + 4 r + g (the operator's r-major contraction order); the zero row
+// ncells stands for an absent source.
 __global__ void k_pack(const double* __restrict__ M, int ldm, int ncells, int P, int ld,
                        TO* __restrict__ out) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)(ncells + 1) * ld;
     if (gid >= tot) return;
-    const int c = (int)(gid / ld), k = (int)(gid % ld);
+    const int c = (int)(gid / ld), pos = (int)(gid % ld);
+    // blocks of 16 floats (4 lane groups x 4 products) or 8 doubles (x 2)
+    constexpr int NR = 16 / sizeof(TO);
+    const int blk = pos / (4 * NR), w = pos % (4 * NR);
+    const int k = blk * 4 * NR + 4 * (w % NR) + w / NR;
     double v = (c < ncells && k < P) ? M[(int64_t)c * ldm + k] : 0.0;
     out[gid] = (TO)v;
 }
@@ -761,10 +779,8 @@ void run_m2m(Tree& t, int p, hipStream_t s) {
     }
 }
 
-void run_m2l_ops(Tree& t, int p, bool fp64, double* T64, float* T32, int RB, int KQ,
-                 hipStream_t s) {
-    hipLaunchKernelGGL(k_m2l_ops, dim3(343), dim3(256), 0, s, p, fp64 ? T64 : nullptr,
-                       fp64 ? nullptr : T32, RB, KQ);
+void run_m2l_ops(Tree& t, int p, int layout, void* T, int RB, int KQ, hipStream_t s) {
+    hipLaunchKernelGGL(k_m2l_ops, dim3(343), dim3(256), 0, s, p, layout, T, RB, KQ);
     LAUNCH_CHECK();
 }
 

@@ -14,8 +14,7 @@ void run_m2m_mfma(Tree& t, int p, hipStream_t s);
 void run_l2l_mfma(Tree& t, int p, const void* parts, bool parts_fp64, int nparts,
                   int64_t part_stride, const double* LX, const int32_t* bexp,
                   const int32_t* levexp, hipStream_t s);
-void run_m2l_ops(Tree& t, int p, bool fp64, double* T64, float* T32, int RB, int KQ,
-                 hipStream_t s);
+void run_m2l_ops(Tree& t, int p, int layout, void* T, int RB, int KQ, hipStream_t s);
 void run_m2l_ops_lp(int p, int precision, int RB, int KQ, int32_t* bexp, void* hi, void* lo,
                     hipStream_t s);
 void run_pack(const double* M, int ldm, int ncells, int P, int ld, void* out, bool fp64,

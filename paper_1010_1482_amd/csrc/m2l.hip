@@ -165,8 +165,15 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct OpF32 {
     using E = float;
+    using O = float;  // partial results
+    using Acc = floatx4;
     static constexpr bool X3 = false;
     static constexpr int S = 4;  // products per (q, rb, cb)
+    static __device__ __forceinline__ Acc zero() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
+    // output block rb of one target row: rows 16 rb + 4 g + (0..3)
+    static __device__ __forceinline__ void store(O* o, int rb, int g, Acc c) {
+        *(float4*)(o + 16 * rb + 4 * g) = make_float4(c[0], c[1], c[2], c[3]);
+    }
     template <int s>
     static __device__ __forceinline__ floatx4 mma(u32x4 ah, u32x4, u32x4 bh, u32x4,
                                                   floatx4 c) {
@@ -181,8 +188,14 @@ struct OpF32 {
 template <typename T16, bool SPLIT>
 struct OpLow {
     using E = T16;
+    using O = float;
+    using Acc = floatx4;
     static constexpr bool X3 = SPLIT;
     static constexpr int S = SPLIT ? 3 : 1;  // hi*hi (+ hi*lo + lo*hi)
+    static __device__ __forceinline__ Acc zero() { return floatx4{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ __forceinline__ void store(O* o, int rb, int g, Acc c) {
+        *(float4*)(o + 16 * rb + 4 * g) = make_float4(c[0], c[1], c[2], c[3]);
+    }
     template <int s>
     static __device__ __forceinline__ floatx4 mma(u32x4 ah, u32x4 al, u32x4 bh, u32x4 bl,
                                                   floatx4 c) {
@@ -203,16 +216,41 @@ constexpr int kM2LAhead = 2;
 constexpr bool m2l_double_buffer(int rb, int kq, int ns) {
     return ns == 2 && 2 * ns * rb * kq * 64 * 16 <= 144 * 1024;
 }
+// FP64: a 16-byte chunk holds 2 doubles (two 16x16x4 FP64 products); the
+// output rows of a block are 16 rb + 4 r + g (the FP64 product's layout)
+typedef double doublex2 __attribute__((ext_vector_type(2)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+struct OpF64 {
+    using E = double;
+    using O = double;
+    using Acc = doublex4;
+    static constexpr bool X3 = false;
+    static constexpr int S = 2;
+    static __device__ __forceinline__ Acc zero() { return doublex4{0.0, 0.0, 0.0, 0.0}; }
+    template <int s>
+    static __device__ __forceinline__ Acc mma(u32x4 ah, u32x4, u32x4 bh, u32x4, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(__builtin_bit_cast(doublex2, ah)[s],
+                                                    __builtin_bit_cast(doublex2, bh)[s], c, 0,
+                                                    0, 0);
+    }
+    static __device__ __forceinline__ void store(O* o, int rb, int g, Acc c) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[16 * rb + 4 * r + g] = c[r];
+    }
+};
+
 typedef __attribute__((address_space(3))) void* lds_ptr;
 typedef const __attribute__((address_space(1))) void* gbl_ptr;
 
-template <int RB, int KQ, int CB, bool DB, class Op>
+// LASTS: products of the last contraction step that carry data (FP32:
+// ceil((p^2 - 16 (KQ - 1)) / 4), the rest are padding and skipped)
+template <int RB, int KQ, int CB, bool DB, class Op, int LASTS = Op::S>
 __global__ void __launch_bounds__(1024 / CB)
 k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
           const int32_t* __restrict__ vsrc, const typename Op::E* __restrict__ Mhi,
           const typename Op::E* __restrict__ Mlo, int ncells,
           const typename Op::E* __restrict__ Thi, const typename Op::E* __restrict__ Tlo,
-          float* __restrict__ out, int64_t part_stride, int slots_per_part) {
+          typename Op::O* __restrict__ out, int64_t part_stride, int slots_per_part) {
     constexpr int NT = RB * KQ * 64;  // 16-byte chunks of one operator
     constexpr int CPR = 4 * KQ;       // 16-byte chunks per operand row
     constexpr int LDO = 16 * RB;      // output row length (floats)
@@ -269,11 +307,11 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
         const int i = (wave * CB + cb) * 16 + col;
         tgt[cb] = i < count ? order[start + i] : -1;
     }
-    floatx4 acc[CB][RB];
+    typename Op::Acc acc[CB][RB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = Op::zero();
 
     const u32x4* Mh = (const u32x4*)Mhi;
     const u32x4* Ml = (const u32x4*)Mlo;
@@ -332,7 +370,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
                 u32x4 al = ah;
                 if (Op::X3) al = buf[NT + (rb * KQ + q) * 64 + lane];
 #define M2L_STEP(s)                                                                         \
-    if (s < Op::S) {                                                                        \
+    if (s < Op::S && (q + 1 < KQ || s < LASTS)) {                                           \
         _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                      \
             Op::template mma<(s < Op::S ? s : 0)>(ah, al, bh[q][cb], bl[q][cb], acc[cb][rb]); \
     }
@@ -391,16 +429,13 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
             j = jn;
         }
     }
-    // output block (rb): lane holds rows 16 rb + 4 g + (0..3) of column col
+    // output block (rb) of column col: the rows this lane holds
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
         if (tgt[cb] < 0) continue;
-        float* o = out + part * part_stride + (int64_t)tgt[cb] * LDO + 4 * g;
+        typename Op::O* o = out + part * part_stride + (int64_t)tgt[cb] * LDO;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            floatx4 c = acc[cb][rb];
-            *(float4*)(o + 16 * rb) = make_float4(c[0], c[1], c[2], c[3]);
-        }
+        for (int rb = 0; rb < RB; ++rb) Op::store(o, rb, g, acc[cb][rb]);
     }
 }
 
@@ -415,7 +450,11 @@ static bool is_bf16(int precision) {
     return precision == HFMM_M2L_BF16 || precision == HFMM_M2L_BF16X3;
 }
 
-bool m2l_uses_mfma(int p, int precision) { return precision != HFMM_FP64 && p <= 13; }
+// matrix cores for p <= 13 (FP32, BF16, FP16) and p <= 11 (FP64, whose
+// operator must fit in LDS: 16 ceil(p^2/16) x 8 ceil(p^2/8) doubles)
+bool m2l_uses_mfma(int p, int precision) {
+    return precision == HFMM_FP64 ? p <= 11 : p <= 13;
+}
 
 // RB: output row blocks of 16; KQ: contraction blocks (16 for FP32, 32 for
 // BF16/FP16); ld: row length of the packed operand
@@ -428,6 +467,9 @@ void m2l_layout(int p, int precision, int& RB, int& KQ, int& ld) {
     } else if (is_lowp(precision)) {
         KQ = (P + 31) / 32;
         ld = 32 * KQ;
+    } else if (precision == HFMM_FP64) {
+        KQ = (P + 7) / 8;
+        ld = 8 * KQ;
     } else {
         KQ = RB;
         ld = 16 * KQ;
@@ -438,12 +480,31 @@ size_t m2l_ops_bytes(int p, int precision) {
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
     const int P = p * p;
-    if (precision == HFMM_FP64) return (size_t)343 * P * P * sizeof(double);
-    if (!m2l_uses_mfma(p, precision)) return (size_t)343 * P * P * sizeof(float);
+    if (!m2l_uses_mfma(p, precision))
+        return (size_t)343 * P * P * (precision == HFMM_FP64 ? sizeof(double) : sizeof(float));
+    if (precision == HFMM_FP64) return (size_t)343 * RB * KQ * 64 * 16;
     if (is_lowp(precision))
         return (size_t)343 * RB * KQ * 64 * 16 * (is_x3(precision) ? 2 : 1) + 256;
     return (size_t)343 * RB * KQ * 64 * 4 * sizeof(float);
 }
+
+#define HFMM_DISPATCH_P13(P_, F) \
+    switch (P_) {                \
+        case 1: F(1); break;     \
+        case 2: F(2); break;     \
+        case 3: F(3); break;     \
+        case 4: F(4); break;     \
+        case 5: F(5); break;     \
+        case 6: F(6); break;     \
+        case 7: F(7); break;     \
+        case 8: F(8); break;     \
+        case 9: F(9); break;     \
+        case 10: F(10); break;   \
+        case 11: F(11); break;   \
+        case 12: F(12); break;   \
+        case 13: F(13); break;   \
+        default: throw Status{HFMM_E_UNSUPPORTED}; \
+    }
 
 #define HFMM_DISPATCH_RB(R, F) \
     switch (R) {               \
@@ -477,12 +538,16 @@ void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s) {
     const size_t bytes = m2l_ops_bytes(p, precision);
     t.T = t.arena.up<char>(bytes);
     t.bexp = nullptr;
-    if (precision == HFMM_FP64) {
-        run_m2l_ops(t, p, true, (double*)t.T, nullptr, 0, 0, s);
+    if (precision == HFMM_FP64 && !m2l_uses_mfma(p, precision)) {
+        run_m2l_ops(t, p, 0, t.T, 0, 0, s);
+    } else if (precision == HFMM_FP64) {
+        // the kernel fills the p^2 x p^2 block; the padding must read as zero
+        HIP_TRY(hipMemsetAsync(t.T, 0, bytes, s));
+        run_m2l_ops(t, p, 2, t.T, RB, KQ, s);
     } else if (!m2l_uses_mfma(p, precision)) {
         const int64_t nn = (int64_t)343 * p * p * p * p;
         double* tmp = t.arena.down<double>(nn);
-        run_m2l_ops(t, p, true, tmp, nullptr, 0, 0, s);
+        run_m2l_ops(t, p, 0, tmp, 0, 0, s);
         hipLaunchKernelGGL((k_cast_ops<float>), dim3(grid_for(nn, 256)), dim3(256), 0, s, tmp,
                            nn, (float*)t.T);
         LAUNCH_CHECK();
@@ -496,7 +561,7 @@ void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s) {
     } else {
         // the kernel fills the p^2 x p^2 block; the padding must read as zero
         HIP_TRY(hipMemsetAsync(t.T, 0, bytes, s));
-        run_m2l_ops(t, p, false, nullptr, (float*)t.T, RB, KQ, s);
+        run_m2l_ops(t, p, 1, t.T, RB, KQ, s);
     }
     t.ops_p = p;
     t.ops_prec = precision;
@@ -536,6 +601,41 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     parts = (216 + spp - 1) / spp;
     part_stride = (int64_t)t.ncells * t.ldm;
     dim3 grid(ntiles, parts), block(1024 / kM2LCB);
+    if (precision == HFMM_FP64) {
+        double* Mk = A.down<double>((size_t)(t.ncells + 1) * ld);
+        {
+            PhaseTimer pp(t, PH_M2L_PREP, s);
+            run_pack(t.M, t.ldm, t.ncells, P, ld, Mk, true, s);
+        }
+        PhaseTimer pt(t, PH_M2L, s);
+#define MFMA64_CASE(PP)                                                                       \
+    {                                                                                         \
+        constexpr int R = ((PP) * (PP) + 15) / 16;                                            \
+        constexpr int K = ((PP) * (PP) + 7) / 8;                                              \
+        constexpr int LS = ((PP) * (PP) - 8 * (K - 1) + 3) / 4;                               \
+        hipLaunchKernelGGL((k_m2l_mma<R, K, kM2LCB, false, OpF64, LS>), grid, block, 0, s,    \
+                           t.m2l_tiles, t.m2l_torder, t.vsrc, (const double*)Mk,              \
+                           (const double*)nullptr, t.ncells, (const double*)t.T,              \
+                           (const double*)nullptr, (double*)out, part_stride, spp);           \
+    }
+        switch (p) {
+            case 1: MFMA64_CASE(1); break;
+            case 2: MFMA64_CASE(2); break;
+            case 3: MFMA64_CASE(3); break;
+            case 4: MFMA64_CASE(4); break;
+            case 5: MFMA64_CASE(5); break;
+            case 6: MFMA64_CASE(6); break;
+            case 7: MFMA64_CASE(7); break;
+            case 8: MFMA64_CASE(8); break;
+            case 9: MFMA64_CASE(9); break;
+            case 10: MFMA64_CASE(10); break;
+            case 11: MFMA64_CASE(11); break;
+            default: throw Status{HFMM_E_UNSUPPORTED};
+        }
+#undef MFMA64_CASE
+        LAUNCH_CHECK();
+        return parts;
+    }
     if (!is_lowp(precision)) {
         float* Mk = A.down<float>((size_t)(t.ncells + 1) * ld);
         {
@@ -543,11 +643,17 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
             run_pack(t.M, t.ldm, t.ncells, P, ld, Mk, false, s);
         }
         PhaseTimer pt(t, PH_M2L, s);
-#define MFMA_CASE(R)                                                                         \
-    hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, m2l_double_buffer(R, R, 1), OpF32>), grid, block, 0, s, t.m2l_tiles, t.m2l_torder,  \
-                       t.vsrc, (const float*)Mk, (const float*)nullptr, t.ncells,              \
-                       (const float*)t.T, (const float*)nullptr, (float*)out, part_stride, spp);
-        HFMM_DISPATCH_RB(RB, MFMA_CASE);
+#define MFMA_CASE(PP)                                                                        \
+    {                                                                                        \
+        constexpr int R = ((PP) * (PP) + 15) / 16;                                           \
+        constexpr int LS = ((PP) * (PP) - 16 * (R - 1) + 3) / 4;                             \
+        hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, m2l_double_buffer(R, R, 1), OpF32, LS>), \
+                           grid, block, 0, s, t.m2l_tiles, t.m2l_torder, t.vsrc,             \
+                           (const float*)Mk, (const float*)nullptr, t.ncells,                \
+                           (const float*)t.T, (const float*)nullptr, (float*)out,            \
+                           part_stride, spp);                                                \
+    }
+        HFMM_DISPATCH_P13(p, MFMA_CASE);
 #undef MFMA_CASE
         LAUNCH_CHECK();
         return parts;
