@@ -146,7 +146,7 @@ struct Tree {
     int up_p = 0, up_method = -1, up_prec = -1;
     int ldm = 0;                     // row length of M and L: p*p padded to 16
     double* M = nullptr;             // [ncells + 1][ldm] FP64 scaled R-basis, last row 0
-    double* cen = nullptr;           // [ncells][4] expansion centre + side
+    double* cen = nullptr;           // [ncells][4] expansion centre, 1 / side
     void* Mk = nullptr;              // M2L operand copy [(ncells+1)][Kp]
     size_t mark_up = 0;
     // FMM lists (independent of p and masses)

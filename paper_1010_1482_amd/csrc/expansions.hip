@@ -104,7 +104,7 @@ __global__ void k_centres_geometric(const Cell* __restrict__ cells, int nc,
     double o[3];
     Cell cell = cells[c];
     cell_centre(*root, cell, o);
-    cen[c] = make_double4(o[0], o[1], o[2], cell_side(*root, cell.level));
+    cen[c] = make_double4(o[0], o[1], o[2], 1.0 / cell_side(*root, cell.level));
 }
 
 // centres of mass (weights |m|), leaves from particles and parents from
@@ -138,11 +138,11 @@ __global__ void k_com_level(const Cell* __restrict__ cells, int c0, int c1,
     w4[c] = make_double4(sx, sy, sz, sw);
     double h = cell_side(*root, cell.level);
     if (sw > 0.0) {
-        cen[c] = make_double4(sx / sw, sy / sw, sz / sw, h);
+        cen[c] = make_double4(sx / sw, sy / sw, sz / sw, 1.0 / h);
     } else {
         double o[3];
         cell_centre(*root, cell, o);
-        cen[c] = make_double4(o[0], o[1], o[2], h);
+        cen[c] = make_double4(o[0], o[1], o[2], 1.0 / h);
     }
 }
 
@@ -171,7 +171,7 @@ __global__ void k_shift_children(const Cell* __restrict__ cells, int nc,
     Cell cell = cells[c];
     if (cell.parent < 0) return;
     double4 a = cen[c], b = cen[cell.parent];
-    double ih = 1.0 / a.w;
+    double ih = a.w;
     double u[3] = {(a.x - b.x) * ih, (a.y - b.y) * ih, (a.z - b.z) * ih};
     double2* out = tab + (int64_t)c * ntri(NP);
     stream_regular<double, NP>(u[0], u[1], u[2], [&](int n, int m, double re, double im) {
@@ -219,7 +219,7 @@ k_p2m(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nl
     if (active) {
         const Cell cell = cells[c];
         const double4 q = cen[c];
-        const double ih = 1.0 / q.w;
+        const double ih = q.w;
         for (int j = cell.first + sub; j < cell.first + cell.count; j += G) {
             const double4 pj = p64[j];
             const T ux = (T)((pj.x - q.x) * ih), uy = (T)((pj.y - q.y) * ih),
@@ -301,7 +301,7 @@ k_p2l(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __restrict_
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k] = 0.0;
     const double4 q = cen[b];
-    const double ih = 1.0 / q.w;
+    const double ih = q.w;
     for (int e = x_off[b]; e < x_off[b + 1]; ++e) {
         const Cell src = cells[x_items[e]];
         for (int s = src.first + lane; s < src.first + src.count; s += 64) {
@@ -377,7 +377,7 @@ k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
     const int b = leaf_of[s];
     const double4 pj = p64[s];
     const double4 q = cen[b];
-    const double ihd = 1.0 / q.w;
+    const double ihd = q.w;
     const T ux = (T)((pj.x - q.x) * ihd), uy = (T)((pj.y - q.y) * ihd),
             uz = (T)((pj.z - q.z) * ihd);
     const double* Lb = L + (int64_t)b * ld;
@@ -407,7 +407,7 @@ k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
         for (int e = w_off[b]; e < w_off[b + 1]; ++e) {
             const int C = w_items[e];
             const double4 qc = cen[C];
-            const double ic = 1.0 / qc.w;
+            const double ic = qc.w;
             m2p_accumulate<T, NP>(M + (int64_t)C * ld, (T)((pj.x - qc.x) * ic),
                                   (T)((pj.y - qc.y) * ic), (T)((pj.z - qc.z) * ic), (T)ic, phi,
                                   ax, ay, az);
@@ -434,7 +434,7 @@ k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
     for (int e = a_off[b]; e < a_off[b + 1]; ++e) {
         const int C = a_items[e];
         const double4 qc = cen[C];
-        const double ic = 1.0 / qc.w;
+        const double ic = qc.w;
         m2p_accumulate<T, NP>(M + (int64_t)C * ld, (T)((pj.x - qc.x) * ic),
                               (T)((pj.y - qc.y) * ic), (T)((pj.z - qc.z) * ic), (T)ic, phi, ax,
                               ay, az);
@@ -677,7 +677,7 @@ __global__ void k_export(const double* __restrict__ X, int ld, int ncells, int p
     int n = 0;
     while ((n + 1) * (n + 2) / 2 <= t) ++n;
     const int m = t - n * (n + 1) / 2;
-    const double h = cen[c].w;
+    const double h = 1.0 / cen[c].w;
     const double A = 1.0 / sqrt(factorial_d(n - m) * factorial_d(n + m));
     double hn = 1.0;
     for (int i = 0; i < n; ++i) hn *= h;
