@@ -220,6 +220,22 @@ __host__ __device__ constexpr int ridx(int n, int m, int part) {
     return m == 0 ? n * n : n * n + 2 * m - 1 + part;
 }
 
+// Reciprocal square root: FP32 from the hardware estimate (1 ulp); FP64 from
+// the estimate refined by two Newton steps y <- y + y (1 - x y^2) / 2 (each
+// squares the relative error), full double precision at a fraction of a
+// correctly rounded sqrt and divide.  x = 0 gives inf (FP32) or NaN (FP64);
+// callers mask such pairs.
+__device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_fast(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x, y * y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 // cell side and centre from the integer coordinates (FP64, no contraction so
 // that host and device agree bit for bit)
 #pragma clang fp contract(off)

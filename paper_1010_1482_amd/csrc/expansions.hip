@@ -45,8 +45,9 @@ __device__ __forceinline__ void stream_regular(T x, T y, T z, F&& f) {
 template <typename T, int ND, typename F>
 __device__ __forceinline__ void stream_irregular(T x, T y, T z, F&& f) {
     const T r2 = x * x + y * y + z * z;
-    const T ir2 = T(1) / r2;
-    T dre = sqrt(ir2), dim = T(0);
+    const T ir = rsqrt_fast(r2);
+    const T ir2 = ir * ir;
+    T dre = ir, dim = T(0);
 #pragma unroll
     for (int m = 0; m < ND; ++m) {
         if (m > 0) {
@@ -79,6 +80,14 @@ __device__ __forceinline__ T cre(const double* X, int n, int m) {
 }
 template <typename T>
 __device__ __forceinline__ T cim(const double* X, int n, int m) {
+    return m == 0 ? T(0) : (T)X[ridx(n, m, 1)];
+}
+template <typename T>
+__device__ __forceinline__ T cre(const float* X, int n, int m) {
+    return (T)X[ridx(n, m, 0)];
+}
+template <typename T>
+__device__ __forceinline__ T cim(const float* X, int n, int m) {
     return m == 0 ? T(0) : (T)X[ridx(n, m, 1)];
 }
 
@@ -329,8 +338,8 @@ k_p2l(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __restrict_
 //   phi = sum Mt S(u) / h,  grad phi from dS_n^m/dz = -S_{n+1}^m and
 //   (d/dx + i d/dy) S_n^m = S_{n+1}^{m+1}
 // ---------------------------------------------------------------------
-template <typename T, int NP>
-__device__ __forceinline__ void m2p_accumulate(const double* Mc, T ux, T uy, T uz, T ih,
+template <typename T, int NP, typename MT>
+__device__ __forceinline__ void m2p_accumulate(const MT* Mc, T ux, T uy, T uz, T ih,
                                                T& phi, T& ax, T& ay, T& az) {
     T f = T(0), dz = T(0), hr = T(0), hi = T(0);
     stream_irregular<T, NP + 1>(ux, uy, uz, [&](int k, int l, T sr, T si) {
@@ -419,13 +428,15 @@ k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
     far[3 * n + s] = az;
 }
 
-// Treecode far field: M2P over the accepted list of the particle's leaf.
-template <typename T, int NP>
+// Treecode far field: M2P over the accepted list of the particle's leaf, one
+// thread per sorted particle (neighbouring threads share a leaf and read the
+// same cells); MT: FP32 copy of the multipoles for the FP32 path.
+template <typename T, int NP, typename MT>
 __global__ void __launch_bounds__(256)
 k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
                const double4* __restrict__ cen, const double4* __restrict__ p64,
                const int32_t* __restrict__ a_off, const int32_t* __restrict__ a_items,
-               const double* __restrict__ M, int ld, T* __restrict__ far) {
+               const MT* __restrict__ M, int ld, T* __restrict__ far) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int b = leaf_of[s];
@@ -443,6 +454,11 @@ k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
     far[n + s] = ax;
     far[2 * n + s] = ay;
     far[3 * n + s] = az;
+}
+
+__global__ void k_to_float(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
 }
 
 // ---------------------------------------------------------------------
@@ -824,15 +840,24 @@ void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
 }
 
 void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
-#define TF_CASE(NP)                                                                          \
-    if (fp64)                                                                                \
-        hipLaunchKernelGGL((k_treecode_far<double, NP>), dim3(grid_for(t.n, 256)), dim3(256), \
-                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,       \
-                           t.a_items, t.M, t.ldm, (double*)far);                              \
+    if (t.n == 0) return;
+    const float* M32 = nullptr;
+    if (!fp64) {  // FP32 copy of the multipoles (same layout)
+        const int64_t nel = (int64_t)t.ncells * t.ldm;
+        float* m = t.arena.down<float>(nel);
+        hipLaunchKernelGGL(k_to_float, dim3(grid_for(nel, 256)), dim3(256), 0, s, t.M, nel, m);
+        LAUNCH_CHECK();
+        M32 = m;
+    }
+#define TF_CASE(NP)                                                                           \
+    if (fp64)                                                                                 \
+        hipLaunchKernelGGL((k_treecode_far<double, NP, double>), dim3(grid_for(t.n, 256)),     \
+                           dim3(256), 0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64,     \
+                           t.a_off, t.a_items, t.M, t.ldm, (double*)far);                     \
     else                                                                                      \
-        hipLaunchKernelGGL((k_treecode_far<float, NP>), dim3(grid_for(t.n, 256)), dim3(256),  \
-                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,       \
-                           t.a_items, t.M, t.ldm, (float*)far);
+        hipLaunchKernelGGL((k_treecode_far<float, NP, float>), dim3(grid_for(t.n, 256)),       \
+                           dim3(256), 0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64,     \
+                           t.a_off, t.a_items, M32, t.ldm, (float*)far);
     HFMM_DISPATCH_P(p, TF_CASE);
 #undef TF_CASE
     LAUNCH_CHECK();

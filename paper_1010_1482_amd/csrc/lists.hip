@@ -412,15 +412,86 @@ __device__ inline double dist_point_box(const double p[3], const double lo[3], d
 }
 #pragma clang fp contract(on)
 
-__global__ void k_bh(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
-                     int nleaves, const Root* __restrict__ root,
-                     const double4* __restrict__ cen, double theta,
-                     int32_t* __restrict__ ca, int32_t* __restrict__ cb,
-                     const int32_t* __restrict__ oa, const int32_t* __restrict__ ob,
-                     int32_t* __restrict__ ia, int32_t* __restrict__ ib) {
+// Barnes-Hut lists, one wave per target leaf: a depth-first traversal from
+// the root with the stack shared by the wave in LDS (up to 64 nodes are
+// tested per step, opened nodes push their children).  A node containing the
+// target leaf is opened (the leaf itself goes to P2P); otherwise it is
+// accepted (M2P) when side < theta * distance(centre of mass, leaf box),
+// else a leaf goes to P2P and an inner node is opened.  Item order within a list is
+// free (sums over a list are order-insensitive up to rounding).  When a push
+// would overflow the LDS stack, each lane finishes its own node's subtree
+// with a private stack (counted, then written at scanned offsets).
+constexpr int kBhCap = 2048;
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(x, d, 64);
+        if (lane >= d) x += u;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 0: open, 1: accept (M2P), 2: P2P
+__device__ __forceinline__ int bh_class(const Cell& cc, int C, const Cell& B, int b,
+                                        const Root& r, const double4* __restrict__ cen,
+                                        const double lo[3], double hb, double theta) {
 #pragma clang fp contract(off)
-    int li = blockIdx.x * blockDim.x + threadIdx.x;
-    if (li >= nleaves) return;
+    if (is_ancestor_or_self(cc, B)) return C == b ? 2 : 0;
+    const double4 q = cen[C];
+    const double pc[3] = {q.x, q.y, q.z};
+    const double d = dist_point_box(pc, lo, hb);
+    if (cell_side(r, cc.level) < theta * d) return 1;
+    return cc.nchild == 0 ? 2 : 0;
+}
+
+// subtree of an opened node C0 with a private stack: counts (or writes)
+__device__ inline void bh_subtree(const Cell* __restrict__ cells, int C0, const Cell& B, int b,
+                                  const Root& r, const double4* __restrict__ cen,
+                                  const double lo[3], double hb, double theta, int32_t* pa,
+                                  int32_t* pb, int& na, int& np) {
+    int stack[kStack];
+    int sp = 0;
+    const Cell c0 = cells[C0];
+    for (int i = c0.nchild - 1; i >= 0 && sp < kStack; --i) stack[sp++] = c0.child + i;
+    while (sp > 0) {
+        const int C = stack[--sp];
+        const Cell cc = cells[C];
+        const int k = bh_class(cc, C, B, b, r, cen, lo, hb, theta);
+        if (k == 1) {
+            if (pa) pa[na] = C;
+            ++na;
+        } else if (k == 2) {
+            if (pb) pb[np] = C;
+            ++np;
+        } else {
+            for (int i = cc.nchild - 1; i >= 0 && sp < kStack; --i) stack[sp++] = cc.child + i;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_bh_wave(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
+          const Root* __restrict__ root, const double4* __restrict__ cen, double theta,
+          int32_t* __restrict__ ca, int32_t* __restrict__ cb, const int32_t* __restrict__ oa,
+          const int32_t* __restrict__ ob, int32_t* __restrict__ ia, int32_t* __restrict__ ib) {
+#pragma clang fp contract(off)
+    __shared__ int stk[4][kBhCap];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = blockIdx.x * 4 + w;
+    if (li >= nleaves) return;  // uniform per wave; no block-wide barrier below
     const bool fill = ia != nullptr;
     const int b = leaves[li];
     const Cell B = cells[b];
@@ -428,43 +499,56 @@ __global__ void k_bh(const Cell* __restrict__ cells, const int32_t* __restrict__
     const double hb = cell_side(r, B.level);
     const double lo[3] = {r.b[0] + (double)B.ix * hb, r.b[1] + (double)B.iy * hb,
                           r.b[2] + (double)B.iz * hb};
-    int na = 0, np = 0;
     int32_t* pa = fill ? ia + oa[b] : nullptr;
     int32_t* pb = fill ? ib + ob[b] : nullptr;
-    int stack[kStack];
-    int sp = 0;
-    stack[sp++] = 0;
+    int* st = stk[w];
+    int na = 0, np = 0, sp = 1;
+    if (lane == 0) st[0] = 0;
+    wave_lds_fence();
     while (sp > 0) {
-        const int C = stack[--sp];
-        const Cell cc = cells[C];
-        bool open;
-        if (is_ancestor_or_self(cc, B)) {
-            if (C == b) {
-                if (fill) pb[np] = C;
-                ++np;
-                continue;
+        const int k = min(sp, 64), base = sp - k;
+        const int C = lane < k ? st[base + lane] : -1;
+        wave_lds_fence();
+        sp = base;
+        int cls = -1, nch = 0, child = 0;
+        if (C >= 0) {
+            const Cell cc = cells[C];
+            cls = bh_class(cc, C, B, b, r, cen, lo, hb, theta);
+            if (cls == 0) {
+                nch = cc.nchild;
+                child = cc.child;
             }
-            open = true;
-        } else {
-            const double4 q = cen[C];
-            const double pc[3] = {q.x, q.y, q.z};
-            const double d = dist_point_box(pc, lo, hb);
-            if (cell_side(r, cc.level) < theta * d) {
-                if (fill) pa[na] = C;
-                ++na;
-                continue;
-            }
-            if (cc.nchild == 0) {
-                if (fill) pb[np] = C;
-                ++np;
-                continue;
-            }
-            open = true;
         }
-        if (open)
-            for (int i = cc.nchild - 1; i >= 0 && sp < kStack; --i) stack[sp++] = cc.child + i;
+        const uint64_t am = __ballot(cls == 1), pm = __ballot(cls == 2);
+        const uint64_t lt = lanes_below(lane);
+        if (fill && cls == 1) pa[na + __popcll(am & lt)] = C;
+        if (fill && cls == 2) pb[np + __popcll(pm & lt)] = C;
+        na += __popcll(am);
+        np += __popcll(pm);
+        int total;
+        const int off = wave_excl_scan(nch, lane, total);
+        if (sp + total <= kBhCap) {
+            for (int i = 0; i < nch; ++i) st[sp + off + i] = child + i;
+            sp += total;
+        } else {
+            // stack full: every lane finishes the subtree of its opened node
+            int ka = 0, kp = 0;
+            if (cls == 0)
+                bh_subtree(cells, C, B, b, r, cen, lo, hb, theta, nullptr, nullptr, ka, kp);
+            int ta, tp;
+            const int oa_l = wave_excl_scan(ka, lane, ta);
+            const int ob_l = wave_excl_scan(kp, lane, tp);
+            if (fill && cls == 0) {
+                int xa = 0, xp = 0;
+                bh_subtree(cells, C, B, b, r, cen, lo, hb, theta, pa + na + oa_l, pb + np + ob_l,
+                           xa, xp);
+            }
+            na += ta;
+            np += tp;
+        }
+        wave_lds_fence();
     }
-    if (!fill) {
+    if (!fill && lane == 0) {
         ca[b] = na;
         cb[b] = np;
     }
@@ -482,9 +566,9 @@ void build_bh_lists(Tree& t, double theta, hipStream_t s) {
     int32_t* cnt = A.down<int32_t>(2 * (size_t)(nc + 1));
     int32_t *ca = cnt, *cb = cnt + nc + 1;
     HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * (nc + 1), s));
-    hipLaunchKernelGGL(k_bh, dim3(grid_for(t.nleaves, 64)), dim3(64), 0, s, t.cells, t.leaves,
-                       t.nleaves, t.root, (const double4*)t.cen, theta, ca, cb, nullptr,
-                       nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_bh_wave, dim3(grid_for(t.nleaves, 4)), dim3(256), 0, s, t.cells,
+                       t.leaves, t.nleaves, t.root, (const double4*)t.cen, theta, ca, cb,
+                       nullptr, nullptr, nullptr, nullptr);
     LAUNCH_CHECK();
     t.a_off = A.up<int32_t>(nc + 1);
     t.b_off = A.up<int32_t>(nc + 1);
@@ -498,9 +582,9 @@ void build_bh_lists(Tree& t, double theta, hipStream_t s) {
     t.n_b = h[1];
     t.a_items = A.up<int32_t>(std::max<int64_t>(t.n_a, 1));
     t.b_items = A.up<int32_t>(std::max<int64_t>(t.n_b, 1));
-    hipLaunchKernelGGL(k_bh, dim3(grid_for(t.nleaves, 64)), dim3(64), 0, s, t.cells, t.leaves,
-                       t.nleaves, t.root, (const double4*)t.cen, theta, nullptr, nullptr,
-                       t.a_off, t.b_off, t.a_items, t.b_items);
+    hipLaunchKernelGGL(k_bh_wave, dim3(grid_for(t.nleaves, 4)), dim3(256), 0, s, t.cells,
+                       t.leaves, t.nleaves, t.root, (const double4*)t.cen, theta, nullptr,
+                       nullptr, t.a_off, t.b_off, t.a_items, t.b_items);
     LAUNCH_CHECK();
     A.release_temps();
     t.bh_theta = theta;

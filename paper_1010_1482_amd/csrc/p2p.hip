@@ -25,21 +25,6 @@ struct Vec4<double> {
     using type = double4;
 };
 
-__device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
-// FP64: hardware reciprocal square-root estimate refined by two Newton steps
-// y <- y + y (1 - x y^2) / 2 (each squares the relative error), full double
-// precision at a fraction of a correctly rounded sqrt and divide.  x = 0
-// gives NaN here; such pairs are masked by the caller.
-__device__ __forceinline__ double rsqrt_fast(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-x, y * y, 1.0);
-        y = fma(0.5 * y, e, y);
-    }
-    return y;
-}
-
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
