@@ -305,13 +305,15 @@ k_p2l(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __restrict_
     constexpr int P = NP * NP;
     const int b = c0 + blockIdx.x;
     if (b >= c1) return;
+    const int e0 = x_off[b], e1 = x_off[b + 1];
+    if (e0 == e1) return;  // no X list: LX stays zero
     const int lane = threadIdx.x;
     double acc[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) acc[k] = 0.0;
     const double4 q = cen[b];
     const double ih = q.w;
-    for (int e = x_off[b]; e < x_off[b + 1]; ++e) {
+    for (int e = e0; e < e1; ++e) {
         const Cell src = cells[x_items[e]];
         for (int s = src.first + lane; s < src.first + src.count; s += 64) {
             const double4 pj = p64[s];
