@@ -211,10 +211,10 @@ constexpr int kM2LCB = 2;
 // contraction steps whose source chunks are loaded ahead of use
 constexpr int kM2LAhead = 2;
 // Two operator buffers (the next slot's operator streams in during the
-// products) pay off for the split forms, whose slots are short relative to
-// the operator copy; they are used when both copies fit in 144 KiB of LDS.
+// products, one barrier per slot), used when both copies fit in 144 KiB of
+// LDS.
 constexpr bool m2l_double_buffer(int rb, int kq, int ns) {
-    return ns == 2 && 2 * ns * rb * kq * 64 * 16 <= 144 * 1024;
+    return 2 * ns * rb * kq * 64 * 16 <= 144 * 1024;
 }
 // FP64: a 16-byte chunk holds 2 doubles (two 16x16x4 FP64 products); the
 // output rows of a block are 16 rb + 4 r + g (the FP64 product's layout)
