@@ -353,10 +353,24 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
                 if (Op::X3) bl[q][cb] = Ml[boff[cb] + 4 * q];
             }
     };
+    // The single-product forms (BF16/FP16 x1) and FP32 with one operator
+    // buffer read the A chunks of step q + 1 from LDS while step q runs (kept
+    // there by a scheduling barrier); the other forms load A where it is
+    // used, which schedules better for them (measured on the device).
+    constexpr bool kPinA = Op::S == 1 || (Op::S == 4 && !DB);
     auto products = [&](const u32x4* buf, const int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
                         u32x4 (&bl)[KQ][CB]) {
+        u32x4 ah[2][RB], al[2][RB];
+        if (kPinA) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                ah[0][rb] = buf[rb * KQ * 64 + lane];
+                al[0][rb] = Op::X3 ? buf[NT + rb * KQ * 64 + lane] : ah[0][rb];
+            }
+        }
 #pragma unroll
         for (int q = 0; q < KQ; ++q) {
+            const int cur = q & 1, nxt = cur ^ 1;
             if (q + kM2LAhead < KQ) {
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
@@ -364,15 +378,28 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
                     if (Op::X3) bl[q + kM2LAhead][cb] = Ml[boff[cb] + 4 * (q + kM2LAhead)];
                 }
             }
+            if (kPinA) {
+                if (q + 1 < KQ) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        ah[nxt][rb] = buf[(rb * KQ + q + 1) * 64 + lane];
+                        al[nxt][rb] =
+                            Op::X3 ? buf[NT + (rb * KQ + q + 1) * 64 + lane] : ah[nxt][rb];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                const u32x4 ah = buf[(rb * KQ + q) * 64 + lane];
-                u32x4 al = ah;
-                if (Op::X3) al = buf[NT + (rb * KQ + q) * 64 + lane];
-#define M2L_STEP(s)                                                                         \
-    if (s < Op::S && (q + 1 < KQ || s < LASTS)) {                                           \
-        _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                      \
-            Op::template mma<(s < Op::S ? s : 0)>(ah, al, bh[q][cb], bl[q][cb], acc[cb][rb]); \
+                if (!kPinA) {
+                    ah[cur][rb] = buf[(rb * KQ + q) * 64 + lane];
+                    al[cur][rb] = Op::X3 ? buf[NT + (rb * KQ + q) * 64 + lane] : ah[cur][rb];
+                }
+#define M2L_STEP(s)                                                                        \
+    if (s < Op::S && (q + 1 < KQ || s < LASTS)) {                                          \
+        _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                     \
+            Op::template mma<(s < Op::S ? s : 0)>(ah[cur][rb], al[cur][rb], bh[q][cb],      \
+                                                  bl[q][cb], acc[cb][rb]);                  \
     }
                 M2L_STEP(0)
                 M2L_STEP(1)
