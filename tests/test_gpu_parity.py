@@ -157,6 +157,32 @@ def test_fmm_fp32_matches_oracle(dist, n, leaf, p):
     assert ephi <= 1e-5 and eacc <= 1e-5
 
 
+# the orders where the M2L path changes: FP64 on the matrix cores up to
+# p = 11 and on the vector units above; FP32 on the matrix cores up to
+# p = 13; the extremes p = 1 and p = HFMM_MAX_P
+_ORDER_CASES = [("fp64", 1), ("fp64", 11), ("fp64", 12), ("fp64", 16),
+                ("fp32", 1), ("fp32", 13), ("fp32", 14)]
+
+
+@pytest.fixture(scope="module")
+def order_inputs():
+    x, y, z, m = W.make("uniform", 3000, 46)
+    return x, y, z, m, W.sample_targets(3000, 64, 9)
+
+
+@pytest.mark.parametrize("prec,p", _ORDER_CASES)
+def test_fmm_order_boundaries(order_inputs, prec, p):
+    x, y, z, m, tg = order_inputs
+    say(f"fmm {prec} uniform n=3000 leaf=32 p={p}")
+    ref = O.fmm(x, y, z, m, p, 32, targets=tg)
+    out = [o[tg] for o in host(H().solve(*to_dev(x, y, z, m), p=p, method="fmm",
+                                         precision=prec, leaf_max=32))]
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs oracle fmm: phi {ephi:.2e} acc {eacc:.2e}")
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    assert ephi <= tol and eacc <= tol
+
+
 def test_fmm_distinct_targets():
     say("fmm distinct targets")
     x, y, z, m = W.plummer(5000, 46)
