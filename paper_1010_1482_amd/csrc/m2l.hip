@@ -307,6 +307,9 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
         const int i = (wave * CB + cb) * 16 + col;
         tgt[cb] = i < count ? order[start + i] : -1;
     }
+    // waves past the tile's last target skip the products (small tiles:
+    // edges and corners of the box, the last tile of a group)
+    const bool busy = wave * CB * 16 < count;
     typename Op::Acc acc[CB][RB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
@@ -426,7 +429,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
                 load_src(jn, src);
                 __syncthreads();  // sT holds slot j, sT2 is no longer read
                 if (jn < ns) stage(sT2, jn);
-                products(sT, boff, bh, bl);
+                if (busy) products(sT, boff, bh, bl);
                 j = jn;
             }
             if (j >= ns) break;
@@ -438,7 +441,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
                 load_src(jn, src);
                 __syncthreads();  // sT2 holds slot j, sT is no longer read
                 if (jn < ns) stage(sT, jn);
-                products(sT2, boff, bh, bl);
+                if (busy) products(sT2, boff, bh, bl);
                 j = jn;
             }
         }
@@ -451,7 +454,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
             const int jn = next_slot(j + 1);
             load_src(jn, src);
             __syncthreads();  // operator in LDS
-            products(sT, boff, bh, bl);
+            if (busy) products(sT, boff, bh, bl);
             __syncthreads();  // LDS free for the next operator
             j = jn;
         }
