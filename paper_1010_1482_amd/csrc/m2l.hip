@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <optional>
+#include <type_traits>
 
 namespace hfmm {
 
@@ -208,8 +209,11 @@ struct OpLow {
 
 // column blocks of 16 targets per wave (8 waves per 256-target tile)
 constexpr int kM2LCB = 2;
-// contraction steps whose source chunks are loaded ahead of use
+// contraction steps whose source chunks are loaded ahead of use (with
+// register-staged operators: across slot boundaries, 3 for the split forms'
+// shorter steps; measured on the device)
 constexpr int kM2LAhead = 2;
+constexpr int m2l_ahead_staged(bool x3) { return x3 ? 3 : 2; }
 // Two operator buffers (the next slot's operator streams in during the
 // products, one barrier per slot), used when both copies fit in 144 KiB of
 // LDS.
@@ -340,14 +344,28 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
         for (int cb = 0; cb < CB; ++cb)
             sv[cb] = (jj < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + jj] : -1;
     };
+    // the same, issued unconditionally (a valid row stands in), so that every
+    // call issues CB loads
+    auto load_src_u = [&](int jj, int (&sv)[CB]) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const bool ok = jj < ns && tgt[cb] >= 0;
+            const int v = vsrc[(int64_t)(tgt[cb] >= 0 ? tgt[cb] : 0) * 216 + s0 +
+                               (jj < ns ? jj : 0)];
+            sv[cb] = ok ? v : -1;
+        }
+    };
+    auto set_boff = [&](const int (&sv)[CB], int64_t (&boff)[CB]) {
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+            boff[cb] = (int64_t)(sv[cb] >= 0 ? sv[cb] : ncells) * CPR + g;
+    };
     // source chunks of step q live in bh[q]; kM2LAhead steps are in flight
     // ahead of the matrix cores (registers are only allocated for the live
     // ones, every index being a constant after unrolling)
     auto first_chunks = [&](const int (&sv)[CB], int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
                             u32x4 (&bl)[KQ][CB]) {
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-            boff[cb] = (int64_t)(sv[cb] >= 0 ? sv[cb] : ncells) * CPR + g;
+        set_boff(sv, boff);
 #pragma unroll
         for (int q = 0; q < KQ && q < kM2LAhead; ++q)
 #pragma unroll
@@ -413,12 +431,153 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
         }
     };
 
+    // Register-staged double buffering (FP32 and the split forms).  The
+    // operator of the next active slot is read
+    // into registers (each wave its NPW chunks) while this slot runs, and
+    // written to the other LDS buffer before the slot's barrier: the
+    // compiler then tracks every wait itself.  (A direct global-to-LDS copy
+    // would make it wait for the copy before the first LDS read of the
+    // products, since it cannot tell the two buffers apart.)  The source
+    // chunks run kAhead contraction steps ahead across slot boundaries: the
+    // last steps of a slot request the first chunks of the next one.
+    constexpr int kAhead = KQ < m2l_ahead_staged(Op::X3) ? KQ : m2l_ahead_staged(Op::X3);
+    constexpr int NCH = RB * KQ, NPW = (NCH + NW - 1) / NW;
+    constexpr bool kStaged = DB && Op::S != 1;
+    auto load_op = [&](int jj, u32x4 (&r)[NPW][NS]) {
+        const int slot = s0 + jj;
+        const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
+        const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
+        const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
+        const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+            const int k = min(wave + NW * i, NCH - 1);
+            r[i][0] = th[k * 64 + lane];
+            if (Op::X3) r[i][NS - 1] = tl[k * 64 + lane];
+        }
+    };
+    // (no branches: the loads would be sunk into a conditional store's
+    // block, i.e. issued just before the store; the waves past the last
+    // chunk write that chunk's bytes again)
+    auto store_op = [&](u32x4* buf, const u32x4 (&r)[NPW][NS]) {
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+            const int k = min(wave + NW * i, NCH - 1);
+            buf[k * 64 + lane] = r[i][0];
+            if (Op::X3) buf[NT + k * 64 + lane] = r[i][NS - 1];
+        }
+    };
+    // products of one slot from operator `buf` and source offsets boff; the
+    // first kAhead chunks arrive in bf, which on return holds the first
+    // chunks of the slot at offsets boffn
+    auto products_db = [&](const u32x4* buf, const int64_t (&boff)[CB],
+                           const int64_t (&boffn)[CB], u32x4 (&bfh)[kAhead][CB],
+                           u32x4 (&bfl)[kAhead][CB]) {
+        u32x4 bh[KQ][CB], bl[KQ][CB];
+#pragma unroll
+        for (int q = 0; q < kAhead; ++q)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                bh[q][cb] = bfh[q][cb];
+                bl[q][cb] = bfl[q][cb];
+            }
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                if (q + kAhead < KQ) {
+                    bh[q + kAhead][cb] = Mh[boff[cb] + 4 * (q + kAhead)];
+                    if (Op::X3) bl[q + kAhead][cb] = Ml[boff[cb] + 4 * (q + kAhead)];
+                } else {
+                    const int qn = q + kAhead - KQ;
+                    bfh[qn][cb] = Mh[boffn[cb] + 4 * qn];
+                    if (Op::X3) bfl[qn][cb] = Ml[boffn[cb] + 4 * qn];
+                }
+            }
+            // keeps the optimiser from sinking the next slot's loads to
+            // their use after the barrier (an empty statement, no wait)
+            if (q + kAhead >= KQ) asm volatile("" ::: "memory");
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const u32x4 ah = buf[(rb * KQ + q) * 64 + lane];
+                const u32x4 al = Op::X3 ? buf[NT + (rb * KQ + q) * 64 + lane] : ah;
+#define M2L_STEP(s)                                                                        \
+    if (s < Op::S && (q + 1 < KQ || s < LASTS)) {                                          \
+        _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                     \
+            Op::template mma<(s < Op::S ? s : 0)>(ah, al, bh[q][cb], bl[q][cb], acc[cb][rb]); \
+    }
+                M2L_STEP(0)
+                M2L_STEP(1)
+                M2L_STEP(2)
+                M2L_STEP(3)
+#undef M2L_STEP
+            }
+            // the step's loads stay in the step (the scheduler would move
+            // them down to their use, shortening the distance ahead)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
     int j = next_slot(0);
     int src[CB];
     load_src(j, src);
-    if (DB) {
-        // two operator buffers: the next active slot's operator streams in
-        // while this one is on the matrix cores; one barrier per slot
+    if (kStaged) {
+        // state at the top of a slot j: its operator in `cur`, its source
+        // offsets in boff and first chunks in flight (bfh/bfl), the source
+        // indices of the next active slot jn in srcn
+        int64_t boff[CB];
+        u32x4 bfh[kAhead][CB], bfl[kAhead][CB];
+        u32x4 opr[NPW][NS];
+        int srcn[CB];
+        int jn = next_slot(j + 1);
+        load_src_u(jn, srcn);
+        set_boff(src, boff);
+#pragma unroll
+        for (int q = 0; q < kAhead; ++q)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                bfh[q][cb] = Mh[boff[cb] + 4 * q];
+                bfl[q][cb] = Op::X3 ? Ml[boff[cb] + 4 * q] : bfh[q][cb];
+            }
+        if (j < ns) {
+            load_op(j, opr);
+            store_op(sT, opr);
+        }
+        __syncthreads();
+        auto body = [&](const u32x4* cur, u32x4* nxt) {
+            const int jnn = jn < ns ? next_slot(jn + 1) : ns;
+            int srcnn[CB];
+            load_src_u(jnn, srcnn);
+            // unconditional loads (past the last slot, the last slot's
+            // operator again), and every wave runs the products, so that
+            // the number of loads in flight is the same on every path and
+            // each wait covers only the load it is for
+            load_op(jn < ns ? jn : j, opr);
+            __builtin_amdgcn_sched_barrier(0);  // issued here, not at their use
+            int64_t boffn[CB];
+            set_boff(srcn, boffn);
+            products_db(cur, boff, boffn, bfh, bfl);
+            store_op(nxt, opr);
+            __syncthreads();  // nxt holds slot jn; cur is no longer read
+            j = jn;
+            jn = jnn;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                boff[cb] = boffn[cb];
+                srcn[cb] = srcnn[cb];
+            }
+        };
+        // one body per iteration, the buffers swapped by parity (with the
+        // loop unrolled by two, the next slot's first loads would be sunk
+        // past the barrier into the second half)
+        for (int par = 0; j < ns; par ^= 1) body(par ? sT2 : sT, par ? sT : sT2);
+    } else if (DB) {
+        // single-product forms (short slots): two operator buffers filled
+        // by direct global-to-LDS copies, the next active slot's operator
+        // streaming in while this one is on the matrix cores (the compiler
+        // waits for the copy before the first LDS read, which costs less
+        // here than the register staging's shorter reach ahead); one
+        // barrier per slot
         if (j < ns) stage(sT, j);
         while (j < ns) {
             {
