@@ -220,6 +220,14 @@ constexpr int m2l_ahead_staged(bool x3) { return x3 ? 3 : 2; }
 constexpr bool m2l_double_buffer(int rb, int kq, int ns) {
     return 2 * ns * rb * kq * 64 * 16 <= 144 * 1024;
 }
+// Registers (per lane) of a register-staged operator pipeline: the wave's
+// share of the next operator, the accumulators and the source chunks in
+// flight.  With one LDS buffer the staging is used when this stays within
+// 160 of the 256 a wave has at two waves per SIMD (beyond, the compiler
+// spills); otherwise the operator is copied straight to LDS.
+constexpr int m2l_staged_regs(int rb, int npw, int ns, int cb, int acc_regs, int ahead) {
+    return 4 * npw * ns + cb * rb * acc_regs + 4 * (ahead + 1) * cb * ns;
+}
 // FP64: a 16-byte chunk holds 2 doubles (two 16x16x4 FP64 products); the
 // output rows of a block are 16 rb + 4 r + g (the FP64 product's layout)
 typedef double doublex2 __attribute__((ext_vector_type(2)));
@@ -431,18 +439,20 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
         }
     };
 
-    // Register-staged double buffering (FP32 and the split forms).  The
-    // operator of the next active slot is read
-    // into registers (each wave its NPW chunks) while this slot runs, and
-    // written to the other LDS buffer before the slot's barrier: the
-    // compiler then tracks every wait itself.  (A direct global-to-LDS copy
+    // Register-staged operators (FP32, FP64 and the split forms).  The
+    // operator of the next active slot is read into registers (each wave its
+    // NPW chunks) while this slot runs, and written to the other LDS buffer
+    // before the slot's barrier (with one buffer: between two barriers after
+    // the products): the compiler then tracks every wait itself.  (A direct global-to-LDS copy
     // would make it wait for the copy before the first LDS read of the
     // products, since it cannot tell the two buffers apart.)  The source
     // chunks run kAhead contraction steps ahead across slot boundaries: the
     // last steps of a slot request the first chunks of the next one.
     constexpr int kAhead = KQ < m2l_ahead_staged(Op::X3) ? KQ : m2l_ahead_staged(Op::X3);
     constexpr int NCH = RB * KQ, NPW = (NCH + NW - 1) / NW;
-    constexpr bool kStaged = DB && Op::S != 1;
+    constexpr bool kStaged =
+        Op::S != 1 && (DB || m2l_staged_regs(RB, NPW, NS, CB, sizeof(typename Op::Acc) / 4,
+                                             kAhead) <= 160);
     auto load_op = [&](int jj, u32x4 (&r)[NPW][NS]) {
         const int slot = s0 + jj;
         const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
@@ -521,7 +531,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
     int j = next_slot(0);
     int src[CB];
     load_src(j, src);
-    if (kStaged) {
+    if constexpr (kStaged) {
         // state at the top of a slot j: its operator in `cur`, its source
         // offsets in boff and first chunks in flight (bfh/bfl), the source
         // indices of the next active slot jn in srcn
@@ -557,6 +567,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
             int64_t boffn[CB];
             set_boff(srcn, boffn);
             products_db(cur, boff, boffn, bfh, bfl);
+            if (!DB) __syncthreads();  // the one buffer is no longer read
             store_op(nxt, opr);
             __syncthreads();  // nxt holds slot jn; cur is no longer read
             j = jn;
@@ -570,8 +581,12 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
         // one body per iteration, the buffers swapped by parity (with the
         // loop unrolled by two, the next slot's first loads would be sunk
         // past the barrier into the second half)
-        for (int par = 0; j < ns; par ^= 1) body(par ? sT2 : sT, par ? sT : sT2);
-    } else if (DB) {
+        if (DB) {
+            for (int par = 0; j < ns; par ^= 1) body(par ? sT2 : sT, par ? sT : sT2);
+        } else {
+            for (; j < ns;) body(sT, sT);
+        }
+    } else if constexpr (DB) {
         // single-product forms (short slots): two operator buffers filled
         // by direct global-to-LDS copies, the next active slot's operator
         // streaming in while this one is on the matrix cores (the compiler
@@ -802,7 +817,8 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         constexpr int R = ((PP) * (PP) + 15) / 16;                                            \
         constexpr int K = ((PP) * (PP) + 7) / 8;                                              \
         constexpr int LS = ((PP) * (PP) - 8 * (K - 1) + 3) / 4;                               \
-        hipLaunchKernelGGL((k_m2l_mma<R, K, kM2LCB, false, OpF64, LS>), grid, block, 0, s,    \
+        hipLaunchKernelGGL((k_m2l_mma<R, K, kM2LCB, m2l_double_buffer(R, K, 1), OpF64, LS>),  \
+                           grid, block, 0, s,                                                 \
                            t.m2l_tiles, t.m2l_torder, t.vsrc, (const double*)Mk,              \
                            (const double*)nullptr, t.ncells, (const double*)t.T,              \
                            (const double*)nullptr, (double*)out, part_stride, spp);           \
