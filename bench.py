@@ -45,6 +45,28 @@ def p2p_pairs(tree) -> int:
     return int(np.sum(cnt[leaf] * src[leaf]))
 
 
+# FP32 flops one M2P evaluation executes (FMA = 2), by expansion order p,
+# counted from the instruction mix of the treecode far-field kernel's inner
+# loop (irregular solid harmonics to degree p by recurrence, the potential
+# and the three gradient contractions, the scaled offset and rsqrt)
+M2P_FLOPS = {1: 48, 2: 106, 3: 203, 4: 334, 5: 499, 6: 698, 7: 931, 8: 1198}
+
+
+def treecode_work(tree):
+    """(M2P evaluations, P2P pairs) of the Barnes-Hut group lists: per leaf,
+    (its particles) x (accepted cells), and (its particles) x (particles of
+    the leaves in its near list)."""
+    cells = tree.cells().cpu().numpy()
+    cnt = cells[:, 5].astype(np.int64)
+    leaf = cells[:, 8] == 0
+    aoff, _ = (a.cpu().numpy() for a in tree.bh_list(0))
+    boff, bitems = (a.cpu().numpy() for a in tree.bh_list(1))
+    alen = (aoff[1:] - aoff[:-1]).astype(np.int64)
+    cs = np.concatenate([[0], np.cumsum(cnt[bitems])])
+    src = cs[boff[1:]] - cs[boff[:-1]]
+    return int(np.sum(cnt[leaf] * alen[leaf])), int(np.sum(cnt[leaf] * src[leaf]))
+
+
 def cpu_baseline(x, y, z, m, p: int, leaf: int, dist: str, ntarget: int = 2048):
     """The FP64 oracle FMM, as it stands, on a bounded sample of the same
     workload: the whole tree and upward pass for all N particles, then the
@@ -268,19 +290,26 @@ def main() -> int:
     # timed steps).  M2L: 2 p^4 flops per V pair (the real p^2 x p^2
     # operator), on the matrix cores of its operand type.  P2P: 21 flops per
     # pair (the paper's count plus the potential) on the FP32 vector units.
-    pairs = p2p_pairs(tr) if args.method == "fmm" else 0
+    alu_peak = PEAK["fp64_TFs"] if args.precision == "fp64" else PEAK["fp32_TFs"]
+    m2p_evals = 0
+    if args.method == "fmm":
+        pairs = p2p_pairs(tr)
+    else:
+        m2p_evals, pairs = treecode_work(tr)
     m2l_pairs = stats["m2l_pairs"]
     m2l_peak = {"fp32": PEAK["fp32_TFs"], "fp64": PEAK["fp64_TFs"]}.get(
         args.precision, PEAK["bf16_TFs"])
     cand = {
         "m2l": (ph.get("m2l", 0.0), 2.0 * p ** 4 * m2l_pairs, "mfma", m2l_peak),
-        "p2p": (ph.get("p2p", 0.0), P2P_FLOPS * pairs, "alu", PEAK["fp32_TFs"]),
+        "p2p": (ph.get("p2p", 0.0), P2P_FLOPS * pairs, "alu", alu_peak),
     }
+    if args.method != "fmm" and p in M2P_FLOPS:
+        cand["far"] = (ph.get("far", 0.0), M2P_FLOPS[p] * m2p_evals, "alu", alu_peak)
     dom = max(cand, key=lambda k: cand[k][0])
     dms, dwork, dbound, dpeak = cand[dom]
     ach = dwork / (dms * 1e-3) / 1e12
     m2l_kernel = "k_m2l_valu" if p > (11 if args.precision == "fp64" else 13) else "k_m2l_mma"
-    kname = {"m2l": m2l_kernel, "p2p": "k_p2p"}[dom]
+    kname = {"m2l": m2l_kernel, "p2p": "k_p2p", "far": "k_treecode_far"}[dom]
     cfg = f"{args.dist}_{n >> 20}M_p{p}_{args.precision}" if n >= 1 << 20 else \
         f"{args.dist}_{n}_p{p}_{args.precision}"
     rec = recorded_traffic(kname, cfg)
@@ -302,9 +331,13 @@ def main() -> int:
         "phase_ms": ph,
         "tree": {"cells": stats["n_cells"], "leaves": stats["n_leaves"],
                  "depth": stats["depth"], "list_u": stats["list_u"],
-                 "list_v": stats["list_v"]},
+                 "list_v": stats["list_v"], "list_m2p": stats["list_m2p"],
+                 "list_p2p": stats["list_p2p"], "p2p_pairs": pairs,
+                 "m2p_evaluations": m2p_evals},
         "p2p_interactions_per_s": pairs / (ph.get("p2p", 1.0) * 1e-3) if pairs else None,
         "m2l_pairs_per_s": m2l_pairs / (ph.get("m2l", 1.0) * 1e-3) if m2l_pairs else None,
+        "m2p_evaluations_per_s": (m2p_evals / (ph.get("far", 1.0) * 1e-3)
+                                  if m2p_evals else None),
         "roofline": roof,
     }
     if "accuracy" in r:

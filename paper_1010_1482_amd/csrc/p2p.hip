@@ -3,11 +3,14 @@
 // Per pair: a_i += m_j (x_j - x_i) / r^3 and phi_i += m_j / r with one
 // reciprocal square root (Listing 1 of Sec. 5.1 plus the potential), pairs
 // at r^2 == 0 skipped.  The paper gives each target cell a thread block and
-// pads the targets to the block size (Secs. 3 and 5.1); leaves here hold ~32
-// particles, so one 64-lane wave takes one target leaf and, when the leaf has
-// at most 32 (16) targets, splits the sources over 2 (4) lane groups that
-// are summed with cross-lane shuffles at the end.  Sources of each list cell
-// are staged through LDS in chunks of 64 as (x, y, z, m) records; each wave
+// pads the targets to the block size (Secs. 3 and 5.1); leaves here hold up
+// to ~32 particles (clustered data: ~10 on average), so one 64-lane wave
+// takes one target leaf and, when the leaf has at most 32 (16, 8) targets,
+// splits the sources over 2 (4, 8) lane groups that are summed with
+// cross-lane shuffles at the end.  The sources of consecutive list cells are
+// packed into chunks of 64 (x, y, z, m) records in LDS, so a chunk is full
+// however few particles each cell holds; the target leaf itself, whose
+// coincident points need the r^2 == 0 test, is taken on its own.  Each wave
 // owns its LDS slice, so there is no block-wide barrier.
 #include "common.hpp"
 #include "expansions.hpp"
@@ -52,79 +55,139 @@ __device__ __forceinline__ void pair(T xi, T yi, T zi, const typename Vec4<T>::t
     az += dz * sc;
 }
 
-// Sum over the source cells of one target chunk.  Lane layout: TW = 64 / G
-// targets, lane = g * TW + t.  In FP32 the positions are relative to their
-// leaf centre; the offset between the source and target leaf centres is
-// formed in FP64 once per source cell and added while staging.
+__device__ __forceinline__ int wave_excl_scan_p2p(int v, int lane, int& total) {
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(x, d, 64);
+        if (lane >= d) x += u;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// Sum over the sources staged in sh[0, nl): lane layout TW = 64 / G
+// targets, lane = g * TW + t, group g takes sources g, g + G, ...  Entries
+// past nl up to the next multiple of G are padding (mass 0, far away).
+template <typename T, int G, bool SOFT, bool ZERO>
+__device__ __forceinline__ void p2p_staged(const typename Vec4<T>::type* sh, int nl, int g,
+                                           T xi, T yi, T zi, T eps2, T& phi, T& ax, T& ay,
+                                           T& az) {
+    const int steps = (nl + G - 1) / G;
+#pragma unroll 8
+    for (int q = 0; q < steps; ++q) {
+        const typename Vec4<T>::type s = sh[q * G + g];
+        pair<T, SOFT, ZERO>(xi, yi, zi, s, eps2, phi, ax, ay, az);
+    }
+}
+
+// Padding record: zero mass far from every target (its terms are exactly 0).
+template <typename T>
+__device__ __forceinline__ typename Vec4<T>::type p2p_pad() {
+    return typename Vec4<T>::type{T(1e18), T(1e18), T(1e18), T(0)};
+}
+
+// The target leaf as its own source (coincident points possible).  In FP32
+// positions are relative to the leaf centre, so no offset is added.
 template <typename T, int G, bool SOFT>
-__device__ __forceinline__ void p2p_chunk(const Cell* __restrict__ cells, int self,
-                                          const int32_t* __restrict__ items, int e0, int e1,
-                                          const typename Vec4<T>::type* __restrict__ P,
-                                          typename Vec4<T>::type* sh, const Root& root,
-                                          const double cb[3], T xi, T yi, T zi, T eps2,
-                                          T& phi, T& ax, T& ay, T& az) {
+__device__ __forceinline__ void p2p_self(const Cell& c, const typename Vec4<T>::type* __restrict__ P,
+                                         typename Vec4<T>::type* sh, T xi, T yi, T zi, T eps2,
+                                         T& phi, T& ax, T& ay, T& az) {
+    constexpr int TW = 64 / G;
+    const int lane = threadIdx.x & 63, g = lane / TW;
+    const int end = c.first + c.count;
+    for (int base = c.first; base < end; base += 64) {
+        const int k = base + lane;
+        const typename Vec4<T>::type v = k < end ? P[k] : p2p_pad<T>();
+        wave_lds_sync();
+        sh[lane] = v;
+        wave_lds_sync();
+        p2p_staged<T, G, SOFT, true>(sh, min(64, end - base), g, xi, yi, zi, eps2, phi, ax, ay,
+                                     az);
+    }
+}
+
+// Sum over the list cells items[e0, e1) other than the target leaf `self`.
+// Per batch of 64 cells, lane j holds cell j's range and (FP32) the offset
+// between its centre and the target leaf's centre, formed in FP64; a scan
+// over the counts places the batch's particles in one sequence, which is
+// staged 64 at a time.
+template <typename T, int G, bool SOFT>
+__device__ __forceinline__ void p2p_packed(const Cell* __restrict__ cells, int self,
+                                           const int32_t* __restrict__ items, int e0, int e1,
+                                           const typename Vec4<T>::type* __restrict__ P,
+                                           typename Vec4<T>::type* sh, int* own,
+                                           const Root& root, const double cb[3], T xi, T yi,
+                                           T zi, T eps2, T& phi, T& ax, T& ay, T& az) {
     using V = typename Vec4<T>::type;
     constexpr int TW = 64 / G;
     constexpr bool REL = sizeof(T) == 4;
-    const int lane = threadIdx.x & 63;
-    const int g = lane / TW;
-    for (int e = e0; e < e1; ++e) {
-        const int ci = items[e];
-        const Cell c = cells[ci];
-        const int end = c.first + c.count;
-        // coincident points can only meet within one leaf; with softening
-        // every pair is finite except the excluded r^2 == 0 ones, which
-        // again need the same leaf
-        const bool zero = ci == self;
+    const int lane = threadIdx.x & 63, g = lane / TW;
+    for (int eb = e0; eb < e1; eb += 64) {
+        int first = 0, cnt = 0;
         T ox = T(0), oy = T(0), oz = T(0);
-        if (REL) {
-            double cc[3];
-            cell_centre(root, c, cc);
-            ox = (T)(cc[0] - cb[0]);
-            oy = (T)(cc[1] - cb[1]);
-            oz = (T)(cc[2] - cb[2]);
-        }
-        for (int base = c.first; base < end; base += 64) {
-            const int k = base + lane;
-            V v;
-            if (k < end) {
-                v = P[k];
+        if (eb + lane < e1) {
+            const int ci = items[eb + lane];
+            if (ci != self) {
+                const Cell c = cells[ci];
+                first = c.first;
+                cnt = c.count;
                 if (REL) {
-                    v.x += ox;
-                    v.y += oy;
-                    v.z += oz;
+                    double cc[3];
+                    cell_centre(root, c, cc);
+                    ox = (T)(cc[0] - cb[0]);
+                    oy = (T)(cc[1] - cb[1]);
+                    oz = (T)(cc[2] - cb[2]);
                 }
-            } else {
-                v = V{T(0), T(0), T(0), T(0)};
+            }
+        }
+        int tot;
+        const int off = wave_excl_scan_p2p(cnt, lane, tot);
+        for (int pb = 0; pb < tot; pb += 64) {
+            // owner of each slot: the cell lane whose range starts there (or
+            // covers slot 0) marks it, then a running maximum over the slots
+            wave_lds_sync();
+            own[lane] = -1;
+            if (cnt > 0 && off < pb + 64 && off + cnt > pb) own[max(off - pb, 0)] = lane;
+            wave_lds_sync();
+            int o = own[lane];
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int u = __shfl_up(o, d, 64);
+                if (lane >= d) o = max(o, u);
+            }
+            const bool ok = pb + lane < tot;
+            o = ok ? o : 0;
+            const int f = __shfl(first, o, 64), fo = __shfl(off, o, 64);
+            V v = p2p_pad<T>();
+            if (REL) {
+                const T sx = __shfl(ox, o, 64), sy = __shfl(oy, o, 64), sz = __shfl(oz, o, 64);
+                if (ok) {
+                    v = P[f + (pb + lane - fo)];
+                    v.x += sx;
+                    v.y += sy;
+                    v.z += sz;
+                }
+            } else if (ok) {
+                v = P[f + (pb + lane - fo)];
             }
             wave_lds_sync();
             sh[lane] = v;
             wave_lds_sync();
-            const int nl = min(64, end - base);
-            const int steps = (nl + G - 1) / G;
-            if (zero) {
-#pragma unroll 8
-                for (int q = 0; q < steps; ++q) {
-                    const V s = sh[q * G + g];
-                    pair<T, SOFT, true>(xi, yi, zi, s, eps2, phi, ax, ay, az);
-                }
-            } else {
-#pragma unroll 8
-                for (int q = 0; q < steps; ++q) {
-                    const V s = sh[q * G + g];
-                    pair<T, SOFT, false>(xi, yi, zi, s, eps2, phi, ax, ay, az);
-                }
-            }
+            p2p_staged<T, G, SOFT, false>(sh, min(64, tot - pb), g, xi, yi, zi, eps2, phi, ax,
+                                          ay, az);
         }
     }
 }
 
 template <typename T, typename O, int G, bool SOFT>
-__device__ __forceinline__ void p2p_leaf(const Cell& leaf, int self, const Root& root,
+__device__ __forceinline__ void p2p_leaf(const Cell& leaf, int self, bool in_list,
+                                         const Root& root,
                                          const Cell* __restrict__ cells,
                                          const int32_t* __restrict__ items, int e0, int e1,
                                          const typename Vec4<T>::type* __restrict__ P,
-                                         typename Vec4<T>::type* sh, const T* __restrict__ far,
+                                         typename Vec4<T>::type* sh, int* own,
+                                         const T* __restrict__ far,
                                          int64_t n, const int32_t* __restrict__ perm,
                                          int64_t out_shift, T eps2, O* __restrict__ phi_o,
                                          O* __restrict__ ax_o, O* __restrict__ ay_o,
@@ -140,8 +203,10 @@ __device__ __forceinline__ void p2p_leaf(const Cell& leaf, int self, const Root&
         const bool ok = c0 + t < leaf.count;
         V me = ok ? P[s] : V{T(0), T(0), T(0), T(0)};
         T phi = T(0), ax = T(0), ay = T(0), az = T(0);
-        p2p_chunk<T, G, SOFT>(cells, self, items, e0, e1, P, sh, root, cb, me.x, me.y, me.z, eps2,
-                              phi, ax, ay, az);
+        if (in_list)
+            p2p_self<T, G, SOFT>(leaf, P, sh, me.x, me.y, me.z, eps2, phi, ax, ay, az);
+        p2p_packed<T, G, SOFT>(cells, self, items, e0, e1, P, sh, own, root, cb, me.x, me.y, me.z,
+                               eps2, phi, ax, ay, az);
 #pragma unroll
         for (int d = TW; d < 64; d <<= 1) {
             phi += __shfl_xor(phi, d, 64);
@@ -179,7 +244,8 @@ k_p2p(const Cell* __restrict__ cells, const Root* __restrict__ rootp,
       O* __restrict__ ax_o, O* __restrict__ ay_o, O* __restrict__ az_o) {
     using V = typename Vec4<T>::type;
     __shared__ V shm[4][64];
-    const int w = threadIdx.x >> 6;
+    __shared__ int owm[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = blockIdx.x * 4 + w;
     if (li >= ntgt) return;
     const int b = tgt[li];
@@ -187,15 +253,23 @@ k_p2p(const Cell* __restrict__ cells, const Root* __restrict__ rootp,
     const Root root = *rootp;
     const int e0 = off[b], e1 = off[b + 1];
     V* sh = shm[w];
-    if (leaf.count <= 16)
-        p2p_leaf<T, O, 4, SOFT>(leaf, b, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
-                                eps2, phi_o, ax_o, ay_o, az_o);
+    int* own = owm[w];
+    // is the target leaf in its own list (then it is summed on its own)
+    bool mine = false;
+    for (int e = e0 + lane; e < e1; e += 64) mine |= items[e] == b;
+    const bool in_list = __ballot(mine) != 0ull;
+#define P2P_LEAF(G)                                                                            \
+    p2p_leaf<T, O, G, SOFT>(leaf, b, in_list, root, cells, items, e0, e1, P, sh, own, far, n, \
+                            perm, out_shift, eps2, phi_o, ax_o, ay_o, az_o)
+    if (leaf.count <= 8)
+        P2P_LEAF(8);
+    else if (leaf.count <= 16)
+        P2P_LEAF(4);
     else if (leaf.count <= 32)
-        p2p_leaf<T, O, 2, SOFT>(leaf, b, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
-                                eps2, phi_o, ax_o, ay_o, az_o);
+        P2P_LEAF(2);
     else
-        p2p_leaf<T, O, 1, SOFT>(leaf, b, root, cells, items, e0, e1, P, sh, far, n, perm, out_shift,
-                                eps2, phi_o, ax_o, ay_o, az_o);
+        P2P_LEAF(1);
+#undef P2P_LEAF
 }
 
 void launch_p2p(const Tree& t, int precision, double eps2, const int32_t* tgt_cells,
