@@ -412,9 +412,9 @@ __device__ inline double dist_point_box(const double p[3], const double lo[3], d
 }
 #pragma clang fp contract(on)
 
-// Barnes-Hut lists, one wave per target leaf: a depth-first traversal from
-// the root with the stack shared by the wave in LDS (up to 64 nodes are
-// tested per step, opened nodes push their children).  A node containing the
+// Barnes-Hut lists, one wave per group of target leaves: a depth-first
+// traversal from the root with the stack shared by the wave in LDS (up to 64
+// nodes are tested per step, opened nodes push their children).  A node containing the
 // target leaf is opened (the leaf itself goes to P2P); otherwise it is
 // accepted (M2P) when side < theta * distance(centre of mass, leaf box),
 // else a leaf goes to P2P and an inner node is opened.  Item order within a list is
@@ -482,76 +482,166 @@ __device__ inline void bh_subtree(const Cell* __restrict__ cells, int C0, const 
     }
 }
 
+// Sibling leaves (the leaf children of one cell, at most 8) are traversed
+// together by one wave: a stack entry carries a node and the set of the
+// group's leaves for which it is visited (all its ancestors opened for
+// them).  Each leaf's lists are exactly those of its own traversal; the
+// tree is read once per group instead of once per leaf.
+constexpr int kBhGroup = 8;
+
 __global__ void __launch_bounds__(256)
-k_bh_wave(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
-          const Root* __restrict__ root, const double4* __restrict__ cen, double theta,
-          int32_t* __restrict__ ca, int32_t* __restrict__ cb, const int32_t* __restrict__ oa,
-          const int32_t* __restrict__ ob, int32_t* __restrict__ ia, int32_t* __restrict__ ib) {
+k_bh_group(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
+           const int32_t* __restrict__ gstart, const int32_t* __restrict__ ngroups,
+           const Root* __restrict__ root, const double4* __restrict__ cen, double theta,
+           int32_t* __restrict__ ca, int32_t* __restrict__ cb, const int32_t* __restrict__ oa,
+           const int32_t* __restrict__ ob, int32_t* __restrict__ ia, int32_t* __restrict__ ib) {
 #pragma clang fp contract(off)
     __shared__ int stk[4][kBhCap];
+    __shared__ uint8_t msk[4][kBhCap];
+    // per wave: the group's leaves, their box corners and list offsets
+    __shared__ double glo[4][kBhGroup][3];
+    __shared__ int gbl[4][kBhGroup], goa[4][kBhGroup], gob[4][kBhGroup];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = blockIdx.x * 4 + w;
-    if (li >= nleaves) return;  // uniform per wave; no block-wide barrier below
+    const int gi = blockIdx.x * 4 + w;
+    if (gi >= *ngroups) return;  // uniform per wave; no block-wide barrier below
     const bool fill = ia != nullptr;
-    const int b = leaves[li];
-    const Cell B = cells[b];
+    const int l0 = gstart[gi], nl = gstart[gi + 1] - l0;
     const Root r = *root;
-    const double hb = cell_side(r, B.level);
-    const double lo[3] = {r.b[0] + (double)B.ix * hb, r.b[1] + (double)B.iy * hb,
-                          r.b[2] + (double)B.iz * hb};
-    int32_t* pa = fill ? ia + oa[b] : nullptr;
-    int32_t* pb = fill ? ib + ob[b] : nullptr;
+    const Cell B0 = cells[leaves[l0]];
+    const int lv = B0.level;
+    const double hb = cell_side(r, lv);
+    if (lane < nl) {
+        const int b = leaves[l0 + lane];
+        const Cell Bi = cells[b];
+        gbl[w][lane] = b;
+        glo[w][lane][0] = r.b[0] + (double)Bi.ix * hb;
+        glo[w][lane][1] = r.b[1] + (double)Bi.iy * hb;
+        glo[w][lane][2] = r.b[2] + (double)Bi.iz * hb;
+        goa[w][lane] = fill ? oa[b] : 0;
+        gob[w][lane] = fill ? ob[b] : 0;
+    }
+    int na[kBhGroup], np[kBhGroup];
+#pragma unroll
+    for (int i = 0; i < kBhGroup; ++i) na[i] = np[i] = 0;
+    // the common parent (the root for a lone root leaf)
+    const Cell P = B0.parent >= 0 ? cells[B0.parent] : B0;
+    const uint32_t all = (1u << nl) - 1u;
     int* st = stk[w];
-    int na = 0, np = 0, sp = 1;
-    if (lane == 0) st[0] = 0;
+    uint8_t* sm = msk[w];
+    int sp = 1;
+    if (lane == 0) {
+        st[0] = 0;
+        sm[0] = (uint8_t)all;
+    }
     wave_lds_fence();
     while (sp > 0) {
         const int k = min(sp, 64), base = sp - k;
         const int C = lane < k ? st[base + lane] : -1;
+        const uint32_t m = lane < k ? sm[base + lane] : 0u;
         wave_lds_fence();
         sp = base;
-        int cls = -1, nch = 0, child = 0;
+        uint32_t am = 0u, pm = 0u, om = 0u;
+        int nch = 0, child = 0;
         if (C >= 0) {
             const Cell cc = cells[C];
-            cls = bh_class(cc, C, B, b, r, cen, lo, hb, theta);
-            if (cls == 0) {
+            if (cc.level < lv && is_ancestor_or_self(cc, P)) {
+                om = m;  // contains every leaf of the group
+            } else {
+                const double4 q = cen[C];
+                const double pc[3] = {q.x, q.y, q.z};
+                const double side = cell_side(r, cc.level);
+#pragma unroll 1
+                for (int i = 0; i < nl; ++i) {
+                    if (!((m >> i) & 1u)) continue;
+                    if (C == gbl[w][i]) {
+                        pm |= 1u << i;  // the leaf itself
+                    } else if (side < theta * dist_point_box(pc, glo[w][i], hb)) {
+                        am |= 1u << i;
+                    } else if (cc.nchild == 0) {
+                        pm |= 1u << i;
+                    } else {
+                        om |= 1u << i;
+                    }
+                }
+            }
+            if (om) {
                 nch = cc.nchild;
                 child = cc.child;
             }
         }
-        const uint64_t am = __ballot(cls == 1), pm = __ballot(cls == 2);
         const uint64_t lt = lanes_below(lane);
-        if (fill && cls == 1) pa[na + __popcll(am & lt)] = C;
-        if (fill && cls == 2) pb[np + __popcll(pm & lt)] = C;
-        na += __popcll(am);
-        np += __popcll(pm);
+#pragma unroll
+        for (int i = 0; i < kBhGroup; ++i) {
+            if (i >= nl) break;
+            const bool a = (am >> i) & 1u, pp = (pm >> i) & 1u;
+            const uint64_t ab = __ballot(a), pb = __ballot(pp);
+            if (fill && a) ia[goa[w][i] + na[i] + __popcll(ab & lt)] = C;
+            if (fill && pp) ib[gob[w][i] + np[i] + __popcll(pb & lt)] = C;
+            na[i] += __popcll(ab);
+            np[i] += __popcll(pb);
+        }
         int total;
         const int off = wave_excl_scan(nch, lane, total);
         if (sp + total <= kBhCap) {
-            for (int i = 0; i < nch; ++i) st[sp + off + i] = child + i;
+            for (int c = 0; c < nch; ++c) {
+                st[sp + off + c] = child + c;
+                sm[sp + off + c] = (uint8_t)om;
+            }
             sp += total;
         } else {
-            // stack full: every lane finishes the subtree of its opened node
-            int ka = 0, kp = 0;
-            if (cls == 0)
-                bh_subtree(cells, C, B, b, r, cen, lo, hb, theta, nullptr, nullptr, ka, kp);
-            int ta, tp;
-            const int oa_l = wave_excl_scan(ka, lane, ta);
-            const int ob_l = wave_excl_scan(kp, lane, tp);
-            if (fill && cls == 0) {
-                int xa = 0, xp = 0;
-                bh_subtree(cells, C, B, b, r, cen, lo, hb, theta, pa + na + oa_l, pb + np + ob_l,
-                           xa, xp);
+            // stack full: every lane finishes the subtree of its opened node,
+            // leaf by leaf, with a private stack
+#pragma unroll
+            for (int i = 0; i < kBhGroup; ++i) {
+                if (i >= nl) break;
+                const int b = gbl[w][i];
+                const Cell Bi = cells[b];
+                int ka = 0, kp = 0;
+                const bool mine = (om >> i) & 1u;
+                if (mine)
+                    bh_subtree(cells, C, Bi, b, r, cen, glo[w][i], hb, theta, nullptr, nullptr,
+                               ka, kp);
+                int ta, tp;
+                const int oa_l = wave_excl_scan(ka, lane, ta);
+                const int ob_l = wave_excl_scan(kp, lane, tp);
+                if (fill && mine) {
+                    int xa = 0, xp = 0;
+                    bh_subtree(cells, C, Bi, b, r, cen, glo[w][i], hb, theta,
+                               ia + goa[w][i] + na[i] + oa_l, ib + gob[w][i] + np[i] + ob_l, xa,
+                               xp);
+                }
+                na[i] += ta;
+                np[i] += tp;
             }
-            na += ta;
-            np += tp;
         }
         wave_lds_fence();
     }
-    if (!fill && lane == 0) {
-        ca[b] = na;
-        cb[b] = np;
+    if (!fill) {
+#pragma unroll
+        for (int i = 0; i < kBhGroup; ++i)
+            if (i < nl && lane == i) {
+                ca[gbl[w][i]] = na[i];
+                cb[gbl[w][i]] = np[i];
+            }
     }
+}
+
+// groups of sibling leaves: a flag where a leaf's parent differs from the
+// previous leaf's (sibling leaves are adjacent in the leaf array)
+__global__ void k_bh_group_flags(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
+                                 int nleaves, int32_t* __restrict__ flag) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaves) return;
+    flag[i] = (i == 0 || cells[leaves[i]].parent != cells[leaves[i - 1]].parent) ? 1 : 0;
+}
+
+__global__ void k_bh_group_starts(const int32_t* __restrict__ flag,
+                                  const int32_t* __restrict__ gidx, int nleaves,
+                                  int32_t* __restrict__ gstart) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nleaves) return;
+    if (flag[i]) gstart[gidx[i]] = i;
+    if (i == nleaves - 1) gstart[gidx[nleaves]] = nleaves;
 }
 
 void build_bh_lists(Tree& t, double theta, hipStream_t s) {
@@ -566,9 +656,23 @@ void build_bh_lists(Tree& t, double theta, hipStream_t s) {
     int32_t* cnt = A.down<int32_t>(2 * (size_t)(nc + 1));
     int32_t *ca = cnt, *cb = cnt + nc + 1;
     HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * (nc + 1), s));
-    hipLaunchKernelGGL(k_bh_wave, dim3(grid_for(t.nleaves, 4)), dim3(256), 0, s, t.cells,
-                       t.leaves, t.nleaves, t.root, (const double4*)t.cen, theta, ca, cb,
-                       nullptr, nullptr, nullptr, nullptr);
+    // sibling groups (at most 8 leaves each); the launches cover one wave
+    // per leaf, the waves past the group count exit
+    const int nlv = t.nleaves;
+    int32_t* gflag = A.down<int32_t>(nlv);
+    int32_t* gidx = A.down<int32_t>(nlv + 1);
+    int32_t* gstart = A.down<int32_t>(nlv + 1);
+    hipLaunchKernelGGL(k_bh_group_flags, dim3(grid_for(nlv, 256)), dim3(256), 0, s, t.cells,
+                       t.leaves, nlv, gflag);
+    LAUNCH_CHECK();
+    scan_exclusive_i32(gflag, gidx, nlv, A, s);
+    hipLaunchKernelGGL(k_bh_group_starts, dim3(grid_for(nlv, 256)), dim3(256), 0, s, gflag,
+                       gidx, nlv, gstart);
+    LAUNCH_CHECK();
+    const int32_t* ngroups = gidx + nlv;
+    hipLaunchKernelGGL(k_bh_group, dim3(grid_for(nlv, 4)), dim3(256), 0, s, t.cells, t.leaves,
+                       gstart, ngroups, t.root, (const double4*)t.cen, theta, ca, cb, nullptr,
+                       nullptr, nullptr, nullptr);
     LAUNCH_CHECK();
     t.a_off = A.up<int32_t>(nc + 1);
     t.b_off = A.up<int32_t>(nc + 1);
@@ -582,9 +686,9 @@ void build_bh_lists(Tree& t, double theta, hipStream_t s) {
     t.n_b = h[1];
     t.a_items = A.up<int32_t>(std::max<int64_t>(t.n_a, 1));
     t.b_items = A.up<int32_t>(std::max<int64_t>(t.n_b, 1));
-    hipLaunchKernelGGL(k_bh_wave, dim3(grid_for(t.nleaves, 4)), dim3(256), 0, s, t.cells,
-                       t.leaves, t.nleaves, t.root, (const double4*)t.cen, theta, nullptr,
-                       nullptr, t.a_off, t.b_off, t.a_items, t.b_items);
+    hipLaunchKernelGGL(k_bh_group, dim3(grid_for(nlv, 4)), dim3(256), 0, s, t.cells, t.leaves,
+                       gstart, ngroups, t.root, (const double4*)t.cen, theta, nullptr, nullptr,
+                       t.a_off, t.b_off, t.a_items, t.b_items);
     LAUNCH_CHECK();
     A.release_temps();
     t.bh_theta = theta;
