@@ -255,8 +255,9 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 typedef const __attribute__((address_space(1))) void* gbl_ptr;
 
 // LASTS: products of the last contraction step that carry data (FP32:
-// ceil((p^2 - 16 (KQ - 1)) / 4), the rest are padding and skipped)
-template <int RB, int KQ, int CB, bool DB, class Op, int LASTS = Op::S>
+// ceil((p^2 - 16 (KQ - 1)) / 4), the rest are padding and skipped).
+// LASTR: rows of the last output block that carry data (p^2 - 16 (RB - 1)).
+template <int RB, int KQ, int CB, bool DB, class Op, int LASTS = Op::S, int LASTR = 16>
 __global__ void __launch_bounds__(1024 / CB)
 k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
           const int32_t* __restrict__ vsrc, const typename Op::E* __restrict__ Mhi,
@@ -453,6 +454,21 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
     constexpr bool kStaged =
         Op::S != 1 && (DB || m2l_staged_regs(RB, NPW, NS, CB, sizeof(typename Op::Acc) / 4,
                                              kAhead) <= 160);
+    // FP32: a last output block with at most 12 rows of data runs as
+    // 4-row products (v_mfma_f32_4x4x1f32, 16 blocks of 4 x 4: a quarter of
+    // a 16 x 16 x 4 product's cycles) instead of a padded 16-row block.
+    // Lane (g, col) feeds row 4 u + (col & 3) of the operator and element
+    // 16 q + 4 r + g of target col; each block (4 lanes of one g) sums over
+    // its own contraction elements, and the four lane groups are added at
+    // the end.
+    constexpr int NQ = (kStaged && std::is_same<Op, OpF32>::value && LASTR <= 12)
+                           ? (LASTR + 3) / 4 : 0;
+    constexpr int RBM = NQ > 0 ? RB - 1 : RB;  // row blocks on 16 x 16 products
+    floatx4 accq[CB][NQ > 0 ? NQ : 1];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int u = 0; u < (NQ > 0 ? NQ : 1); ++u) accq[cb][u] = floatx4{0.f, 0.f, 0.f, 0.f};
     auto load_op = [&](int jj, u32x4 (&r)[NPW][NS]) {
         const int slot = s0 + jj;
         const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
@@ -507,8 +523,25 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
             // keeps the optimiser from sinking the next slot's loads to
             // their use after the barrier (an empty statement, no wait)
             if (q + kAhead >= KQ) asm volatile("" ::: "memory");
+            if constexpr (NQ > 0) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
+                for (int u = 0; u < NQ; ++u) {
+                    const floatx4 aq = __builtin_bit_cast(
+                        floatx4, buf[(RBM * KQ + q) * 64 + 16 * g + 4 * u + (lane & 3)]);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (q + 1 < KQ || r < LASTS) {
+#pragma unroll
+                            for (int cb = 0; cb < CB; ++cb)
+                                accq[cb][u] = __builtin_amdgcn_mfma_f32_4x4x1f32(
+                                    aq[r], __builtin_bit_cast(floatx4, bh[q][cb])[r],
+                                    accq[cb][u], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < RBM; ++rb) {
                 const u32x4 ah = buf[(rb * KQ + q) * 64 + lane];
                 const u32x4 al = Op::X3 ? buf[NT + (rb * KQ + q) * 64 + lane] : ah;
 #define M2L_STEP(s)                                                                        \
@@ -631,6 +664,25 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
             if (busy) products(sT, boff, bh, bl);
             __syncthreads();  // LDS free for the next operator
             j = jn;
+        }
+    }
+    if constexpr (NQ > 0) {
+        // sum the four lane groups; lane group g keeps rows 4 g .. 4 g + 3
+        // of the last block (the 16 x 16 layout the store expects)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                floatx4 t = accq[cb][u];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    t[i] += __shfl_xor(t[i], 16, 64);
+                    t[i] += __shfl_xor(t[i], 32, 64);
+                }
+                if (g == u) v = t;
+            }
+            acc[cb][RB - 1] = v;
         }
     }
     // output block (rb) of column col: the rows this lane holds
@@ -852,7 +904,9 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     {                                                                                        \
         constexpr int R = ((PP) * (PP) + 15) / 16;                                           \
         constexpr int LS = ((PP) * (PP) - 16 * (R - 1) + 3) / 4;                             \
-        hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, m2l_double_buffer(R, R, 1), OpF32, LS>), \
+        constexpr int LR = (PP) * (PP) - 16 * (R - 1);                                       \
+        hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, m2l_double_buffer(R, R, 1), OpF32, LS,   \
+                                      LR>),                                                  \
                            grid, block, 0, s, t.m2l_tiles, t.m2l_torder, t.vsrc,             \
                            (const float*)Mk, (const float*)nullptr, t.ncells,                \
                            (const float*)t.T, (const float*)nullptr, (float*)out,            \

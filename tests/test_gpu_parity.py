@@ -159,9 +159,12 @@ def test_fmm_fp32_matches_oracle(dist, n, leaf, p):
 
 # the orders where the M2L path changes: FP64 on the matrix cores up to
 # p = 11 and on the vector units above; FP32 on the matrix cores up to
-# p = 13; the extremes p = 1 and p = HFMM_MAX_P
+# p = 13, with the last output block of p^2 mod 16 in {1, 4, 9} rows on
+# 4 x 4 products (p = 3: every row; p = 5, 11: three 4-row groups; p = 9:
+# one row); the extremes p = 1 and p = HFMM_MAX_P
 _ORDER_CASES = [("fp64", 1), ("fp64", 11), ("fp64", 12), ("fp64", 16),
-                ("fp32", 1), ("fp32", 13), ("fp32", 14)]
+                ("fp32", 1), ("fp32", 3), ("fp32", 5), ("fp32", 9), ("fp32", 11),
+                ("fp32", 13), ("fp32", 14)]
 
 
 @pytest.fixture(scope="module")
