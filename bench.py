@@ -59,7 +59,7 @@ def treecode_work(tree):
     cells = tree.cells().cpu().numpy()
     cnt = cells[:, 5].astype(np.int64)
     leaf = cells[:, 8] == 0
-    aoff, _ = (a.cpu().numpy() for a in tree.bh_list(0))
+    aoff = tree.bh_list(0, offsets_only=True).cpu().numpy()
     boff, bitems = (a.cpu().numpy() for a in tree.bh_list(1))
     alen = (aoff[1:] - aoff[:-1]).astype(np.int64)
     cs = np.concatenate([[0], np.cumsum(cnt[bitems])])

@@ -190,7 +190,8 @@ int hfmm_export_cells(hfmm_tree t, int32_t* dst, void* stream);
  * items (hfmm_stats.list_* int32), rows in cell order. */
 int hfmm_export_list(hfmm_tree t, int which, int32_t* off, int32_t* items,
                      void* stream);
-/* Treecode lists (0 accepted/M2P, 1 P2P) per cell as CSR, like above. */
+/* Treecode lists (0 accepted/M2P, 1 P2P) per cell as CSR, like above;
+ * items may be NULL to export the offsets only. */
 int hfmm_export_bh_list(hfmm_tree t, int which, int32_t* off, int32_t* items,
                         void* stream);
 /* Expansions in the paper's normalisation (Eqs. 2 and 3): which 0 = M

@@ -498,7 +498,7 @@ int hfmm_export_list(hfmm_tree h, int which, int32_t* off, int32_t* items, void*
 }
 
 int hfmm_export_bh_list(hfmm_tree h, int which, int32_t* off, int32_t* items, void* stream) {
-    if (!h || !off || !items || which < 0 || which > 1) return HFMM_E_INVAL;
+    if (!h || !off || which < 0 || which > 1) return HFMM_E_INVAL;
     Tree& t = h->t;
     if (!t.a_off) return HFMM_E_STATE;
     API_BEGIN
@@ -507,7 +507,7 @@ int hfmm_export_bh_list(hfmm_tree h, int which, int32_t* off, int32_t* items, vo
     const int32_t* it = which == 0 ? t.a_items : t.b_items;
     const int64_t nn = which == 0 ? t.n_a : t.n_b;
     HIP_TRY(hipMemcpyAsync(off, o, sizeof(int32_t) * (t.ncells + 1), hipMemcpyDeviceToDevice, s));
-    if (nn > 0)
+    if (nn > 0 && items)
         HIP_TRY(hipMemcpyAsync(items, it, sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s));
     API_END
 }

@@ -245,10 +245,14 @@ class Tree:
                "export_list")
         return off, items[:nn]
 
-    def bh_list(self, which, stream=None):
+    def bh_list(self, which, stream=None, offsets_only=False):
         st = self.stats()
         nn = [st["list_m2p"], st["list_p2p"]][which]
         off = torch.empty(st["n_cells"] + 1, dtype=torch.int32, device=self.arena.device)
+        if offsets_only:
+            _check(_lib().hfmm_export_bh_list(self.h, which, _ptr(off), None, _stream(stream)),
+                   "export_bh_list")
+            return off
         items = torch.empty(max(nn, 1), dtype=torch.int32, device=self.arena.device)
         _check(_lib().hfmm_export_bh_list(self.h, which, _ptr(off), _ptr(items),
                                           _stream(stream)), "export_bh_list")
