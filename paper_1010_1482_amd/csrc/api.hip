@@ -199,8 +199,10 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
     size_t per_particle = 8 + 4 + 24 + 16 + 32 + 4 + 8 + 4 + 8 + 4 * 8 + 64;
+    // M, L, LX (FP64), the M2L operand and the FP32 copy of M for the
+    // far field (FP32), eight M2L partial results
     size_t per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 * 3 +
-                      (size_t)ld * 4 + (size_t)8 * ld * 4 + 64;
+                      (size_t)ld * 4 * 2 + (size_t)8 * ld * 4 + 64;
     if (method == HFMM_TREECODE) per_cell = 32 + 32 + 32 + (size_t)P * 8 + 512 + 64;
     size_t ops = method == HFMM_FMM ? m2l_ops_bytes(p, precision) : 0;
     if (method == HFMM_FMM) ops += (size_t)2 * 8 * ld * ld * sizeof(double);

@@ -159,6 +159,8 @@ struct Tree {
     int32_t *u_off = nullptr, *u_items = nullptr;
     int32_t *w_off = nullptr, *w_items = nullptr;
     int32_t *x_off = nullptr, *x_items = nullptr;
+    int32_t* x_cells = nullptr;  // cells with an X list (P2L targets)
+    int32_t n_xcells = 0;
     int64_t n_u = 0, n_v = 0, n_w = 0, n_x = 0;
     int32_t* m2l_order = nullptr;    // targets (level >= 2) by (level, octant)
     int32_t* m2l_torder = nullptr;   // the same targets by (octant, level)
@@ -234,6 +236,46 @@ __device__ __forceinline__ double rsqrt_fast(double x) {
         y = fma(0.5 * y, e, y);
     }
     return y;
+}
+
+// wave-level helpers (64 lanes): lanes below this one, an exclusive scan
+// over the wave, and an LDS fence between lanes of one wave
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(x, d, 64);
+        if (lane >= d) x += u;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// The owner lane of each of `width` consecutive slots of a packed sequence:
+// lane j holds a run [off, off + cnt) of it; the runs are in lane order.  The
+// lane whose run starts in the window (or covers its first slot) marks that
+// slot in own[], then a running maximum over the lanes fills the rest.
+// Returns the owner of slot pb + lane (meaningful for slots < total).
+__device__ __forceinline__ int wave_run_owner(int* own, int off, int cnt, int pb, int width,
+                                              int lane) {
+    wave_lds_fence();
+    own[lane] = -1;
+    if (cnt > 0 && off < pb + width && off + cnt > pb) own[max(off - pb, 0)] = lane;
+    wave_lds_fence();
+    int o = own[lane];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(o, d, 64);
+        if (lane >= d) o = max(o, u);
+    }
+    return o;
 }
 
 // cell side and centre from the integer coordinates (FP64, no contraction so

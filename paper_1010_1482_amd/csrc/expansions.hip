@@ -295,45 +295,94 @@ __global__ void k_m2m(const Cell* __restrict__ cells, int c0, int c1,
 // ---------------------------------------------------------------------
 // P2L for the X list (Eq. 3 in the device basis, FP64):
 //   Lt_n^m(B) += sum_j q_j conj(S_n^m((x_j - c_B) / h_B))
-// one 64-lane wave per target cell, lanes over the source particles
+// One 64-lane wave per target cell with an X list (from the compact array
+// of such cells; the others keep LX = 0).  The particles
+// of the cell's X-list leaves are packed into chunks of CH (a lane per list
+// leaf, a scan of the counts, the owner of each slot from wave_run_owner);
+// lane j evaluates
+// particle j of the chunk and stores its P weighted terms in LDS
+// (coefficient-major, so the stores of one term are consecutive), then lane
+// k adds coefficient k (and k + 64, ...) over the chunk: no cross-lane
+// reduction, and every lane is busy however few particles a leaf holds.
 // ---------------------------------------------------------------------
-template <int NP>
-__global__ void __launch_bounds__(64)
-k_p2l(const Cell* __restrict__ cells, int c0, int c1, const int32_t* __restrict__ x_off,
-      const int32_t* __restrict__ x_items, const double4* __restrict__ cen,
-      const double4* __restrict__ p64, double* __restrict__ LX, int ld) {
+template <int NP, int CH, int RS, int KPL>
+__device__ __forceinline__ void p2l_cell(const Cell* __restrict__ cells, int b,
+                                         const int32_t* __restrict__ x_off,
+                                         const int32_t* __restrict__ x_items,
+                                         const double4* __restrict__ cen,
+                                         const double4* __restrict__ p64,
+                                         double* __restrict__ LX, int ld, double* sh, int* own,
+                                         int lane) {
     constexpr int P = NP * NP;
-    const int b = c0 + blockIdx.x;
-    if (b >= c1) return;
     const int e0 = x_off[b], e1 = x_off[b + 1];
-    if (e0 == e1) return;  // no X list: LX stays zero
-    const int lane = threadIdx.x;
-    double acc[P];
+    double acc[KPL];
 #pragma unroll
-    for (int k = 0; k < P; ++k) acc[k] = 0.0;
+    for (int k = 0; k < KPL; ++k) acc[k] = 0.0;
     const double4 q = cen[b];
     const double ih = q.w;
-    for (int e = e0; e < e1; ++e) {
-        const Cell src = cells[x_items[e]];
-        for (int s = src.first + lane; s < src.first + src.count; s += 64) {
-            const double4 pj = p64[s];
-            stream_irregular<double, NP>((pj.x - q.x) * ih, (pj.y - q.y) * ih, (pj.z - q.z) * ih,
-                                         [&](int n, int m, double re, double im) {
-                                             acc[ridx(n, m, 0)] += pj.w * re;
-                                             if (m > 0) acc[ridx(n, m, 1)] -= pj.w * im;
-                                         });
+    for (int eb = e0; eb < e1; eb += 64) {
+        int first = 0, cnt = 0;
+        if (eb + lane < e1) {
+            const Cell src = cells[x_items[eb + lane]];
+            first = src.first;
+            cnt = src.count;
+        }
+        int tot;
+        const int off = wave_excl_scan(cnt, lane, tot);
+        for (int pb = 0; pb < tot; pb += CH) {
+            int o = wave_run_owner(own, off, cnt, pb, CH, lane);
+            const bool ok = lane < CH && pb + lane < tot;
+            o = ok ? o : 0;
+            const int f = __shfl(first, o, 64), fo = __shfl(off, o, 64);
+            const int nv = min(CH, tot - pb);
+            wave_lds_fence();
+            if (ok) {
+                const double4 pj = p64[f + (pb + lane - fo)];
+                stream_irregular<double, NP>((pj.x - q.x) * ih, (pj.y - q.y) * ih,
+                                             (pj.z - q.z) * ih,
+                                             [&](int n, int m, double re, double im) {
+                                                 sh[ridx(n, m, 0) * RS + lane] = pj.w * re;
+                                                 if (m > 0)
+                                                     sh[ridx(n, m, 1) * RS + lane] = -pj.w * im;
+                                             });
+            }
+            wave_lds_fence();
+#pragma unroll
+            for (int kk = 0; kk < KPL; ++kk) {
+                const int k = lane + 64 * kk;
+                if (k < P) {
+                    double a = 0.0;
+                    for (int j = 0; j < nv; ++j) a += sh[k * RS + j];
+                    acc[kk] += a;
+                }
+            }
         }
     }
+    double* out = LX + (int64_t)b * ld;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1)
-#pragma unroll
-        for (int k = 0; k < P; ++k) acc[k] += __shfl_xor(acc[k], d, 64);
-    if (lane == 0) {
-        double* out = LX + (int64_t)b * ld;
-#pragma unroll
-        for (int k = 0; k < P; ++k) out[k] = acc[k];
+    for (int kk = 0; kk < KPL; ++kk) {
+        const int k = lane + 64 * kk;
+        if (k < P) out[k] = acc[kk];
     }
+    wave_lds_fence();  // the next cell reuses sh and own
 }
+
+template <int NP>
+__global__ void __launch_bounds__(64)
+k_p2l(const Cell* __restrict__ cells, const int32_t* __restrict__ x_cells,
+      const int32_t* __restrict__ x_off, const int32_t* __restrict__ x_items,
+      const double4* __restrict__ cen, const double4* __restrict__ p64,
+      double* __restrict__ LX, int ld) {
+    constexpr int P = NP * NP;
+    constexpr int CH = 2048 / P < 64 ? 2048 / P : 64;  // particles per chunk (<= 17 KB)
+    constexpr int RS = CH + 1;                         // LDS row stride (bank spread)
+    constexpr int KPL = (P + 63) / 64;                 // coefficients per lane
+    __shared__ double sh[P * RS];
+    __shared__ int own[64];
+    p2l_cell<NP, CH, RS, KPL>(cells, x_cells[blockIdx.x], x_off, x_items, cen, p64, LX, ld, sh,
+                              own, threadIdx.x);
+}
+
 
 // ---------------------------------------------------------------------
 // M2P of one expansion (Eq. 2 with its gradient) at u = (x - c) / h:
@@ -376,13 +425,14 @@ __device__ __forceinline__ void m2p_accumulate(const MT* Mc, T ux, T uy, T uz, T
 
 // Far field at every particle: L2P of its leaf (Eq. 3 with its gradient,
 // dR_n^m/dz = R_{n-1}^m, (d/dx + i d/dy) R_n^m = R_{n-1}^{m+1}) plus M2P over
-// the leaf's W list.  One thread per sorted particle.
-template <typename T, int NP>
+// the leaf's W list.  One thread per sorted particle; MT: FP32 copy of the
+// multipoles for the FP32 path.
+template <typename T, int NP, typename MT>
 __global__ void __launch_bounds__(256)
 k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict__ cen,
       const double4* __restrict__ p64, const double* __restrict__ L,
       const int32_t* __restrict__ w_off, const int32_t* __restrict__ w_items,
-      const double* __restrict__ M, int ld, T* __restrict__ far) {
+      const MT* __restrict__ M, int ld, T* __restrict__ far) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int b = leaf_of[s];
@@ -815,11 +865,10 @@ void run_pack(const double* M, int ldm, int ncells, int P, int ld, void* out, bo
 }
 
 void run_p2l(Tree& t, int p, double* LX, hipStream_t s) {
-    if (t.n_x == 0 || t.depth < 2) return;
-    int c0 = t.level_start[2], c1 = t.ncells;
+    if (t.n_x == 0 || t.n_xcells == 0) return;
 #define P2L_CASE(NP)                                                                        \
-    hipLaunchKernelGGL((k_p2l<NP>), dim3(c1 - c0), dim3(64), 0, s, t.cells, c0, c1, t.x_off, \
-                       t.x_items, (const double4*)t.cen, t.p64, LX, t.ldm);
+    hipLaunchKernelGGL((k_p2l<NP>), dim3(t.n_xcells), dim3(64), 0, s, t.cells, t.x_cells,  \
+                       t.x_off, t.x_items, (const double4*)t.cen, t.p64, LX, t.ldm);
     HFMM_DISPATCH_P(p, P2L_CASE);
 #undef P2L_CASE
     LAUNCH_CHECK();
@@ -827,15 +876,23 @@ void run_p2l(Tree& t, int p, double* LX, hipStream_t s) {
 
 void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
     const bool w = t.n_w > 0;
+    const float* M32 = nullptr;
+    if (!fp64 && w) {  // FP32 copy of the multipoles for the W-list M2P
+        const int64_t nel = (int64_t)t.ncells * t.ldm;
+        float* m = t.arena.down<float>(nel);
+        hipLaunchKernelGGL(k_to_float, dim3(grid_for(nel, 256)), dim3(256), 0, s, t.M, nel, m);
+        LAUNCH_CHECK();
+        M32 = m;
+    }
 #define FAR_CASE(NP)                                                                       \
     if (fp64)                                                                              \
-        hipLaunchKernelGGL((k_far<double, NP>), dim3(grid_for(t.n, 256)), dim3(256), 0, s,  \
-                           t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,               \
+        hipLaunchKernelGGL((k_far<double, NP, double>), dim3(grid_for(t.n, 256)), dim3(256), \
+                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,         \
                            w ? t.w_off : nullptr, t.w_items, t.M, t.ldm, (double*)far);     \
     else                                                                                    \
-        hipLaunchKernelGGL((k_far<float, NP>), dim3(grid_for(t.n, 256)), dim3(256), 0, s,   \
-                           t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,               \
-                           w ? t.w_off : nullptr, t.w_items, t.M, t.ldm, (float*)far);
+        hipLaunchKernelGGL((k_far<float, NP, float>), dim3(grid_for(t.n, 256)), dim3(256),  \
+                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,         \
+                           w ? t.w_off : nullptr, t.w_items, M32, t.ldm, (float*)far);
     HFMM_DISPATCH_P(p, FAR_CASE);
 #undef FAR_CASE
     LAUNCH_CHECK();

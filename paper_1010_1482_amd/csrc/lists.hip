@@ -238,7 +238,8 @@ __device__ inline void uwx_cell(const Cell* __restrict__ cells, int b,
 __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
                       const uint8_t* __restrict__ cflag, int32_t* __restrict__ cu,
                       int32_t* __restrict__ cw, int32_t* __restrict__ cx,
-                      int32_t* __restrict__ cv, const int32_t* __restrict__ ou,
+                      int32_t* __restrict__ cv, int32_t* __restrict__ cf,
+                      const int32_t* __restrict__ ou,
                       const int32_t* __restrict__ ow, const int32_t* __restrict__ ox,
                       int32_t* __restrict__ iu, int32_t* __restrict__ iw,
                       int32_t* __restrict__ ix) {
@@ -247,20 +248,28 @@ __global__ void k_uwx(const Cell* __restrict__ cells, int nc, const int32_t* __r
     int nu = 0, nw = 0, nx = 0;
     if (b < nc) uwx_cell(cells, b, coll, cflag, fill, ou, ow, ox, iu, iw, ix, nu, nw, nx);
     if (fill) return;
-    if (b <= nc) {  // entry nc is 0: the four arrays are scanned as one
+    if (b <= nc) {  // entry nc is 0: the five arrays are scanned as one
         cu[b] = nu;
         cw[b] = nw;
         cx[b] = nx;
+        cf[b] = nx > 0 ? 1 : 0;  // cells with an X list (P2L targets)
         if (b == nc) cv[b] = 0;
     }
 }
 
-// list totals from the joint offsets [U | W | X | V], each nc + 1 long
+// list totals from the joint offsets [U | W | X | V | X flags], each nc + 1
+// long (the last total: cells with an X list)
 __global__ void k_list_totals(const int32_t* __restrict__ off, int nc, int32_t* __restrict__ tot) {
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < 5) {
         const int64_t a = (int64_t)threadIdx.x * (nc + 1);
         tot[threadIdx.x] = off[a + nc] - off[a];
     }
+}
+
+// compact array of the cells with an X list, from the scanned flags
+__global__ void k_x_cells(const int32_t* __restrict__ foff, int nc, int32_t* __restrict__ xc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < nc && foff[c + 1] > foff[c]) xc[foff[c] - foff[0]] = c;
 }
 
 // ---------------------------------------------------------------------
@@ -298,27 +307,30 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     t.coll = A.up<int32_t>((size_t)nc * kColl);
     t.vsrc = A.up<int32_t>((size_t)nc * kSlots);
     t.cflag = A.up<uint8_t>(nc);
-    // read back once: [0..3] U, W, X, V totals, [4..) group counts
-    int32_t* hr = A.down<int32_t>(4 + kGroups);
-    HIP_TRY(hipMemsetAsync(hr, 0, sizeof(int32_t) * (4 + kGroups), s));
+    // read back once: [0..3] U, W, X, V totals, [4] cells with an X list,
+    // [5..) group counts
+    int32_t* hr = A.down<int32_t>(5 + kGroups);
+    HIP_TRY(hipMemsetAsync(hr, 0, sizeof(int32_t) * (5 + kGroups), s));
     for (int l = 0; l <= t.depth; ++l) {
         const int c0 = t.level_start[l], c1 = t.level_start[l + 1];
         hipLaunchKernelGGL(k_colleagues, dim3(grid_for((int64_t)(c1 - c0) * 32, 256)),
                            dim3(256), 0, s, t.cells, c0, c1, t.coll, t.cflag);
         LAUNCH_CHECK();
     }
-    // per-cell counts as one array [U | W | X | V] of 4 (nc + 1), one scan:
-    // the offsets of U, W and X index one shared item array (V is stored
-    // densely by slot, only its total is used)
-    const int64_t n4 = 4 * (int64_t)(nc + 1);
+    // per-cell counts as one array [U | W | X | V | X flag] of 5 (nc + 1),
+    // one scan: the offsets of U, W and X index one shared item array (V is
+    // stored densely by slot, only its total is used); the flags place the
+    // cells with an X list in a compact array
+    const int64_t n4 = 5 * (int64_t)(nc + 1);
     int32_t* cnt = A.down<int32_t>(n4);
-    int32_t *cu = cnt, *cw = cnt + (nc + 1), *cx = cnt + 2 * (nc + 1), *cv = cnt + 3 * (nc + 1);
+    int32_t *cu = cnt, *cw = cnt + (nc + 1), *cx = cnt + 2 * (nc + 1), *cv = cnt + 3 * (nc + 1),
+            *cf = cnt + 4 * (nc + 1);
     hipLaunchKernelGGL(k_vlist, dim3(grid_for((int64_t)nc * 64, 256)), dim3(256), 0, s,
                        t.cells, nc, t.coll, t.vsrc, cv);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc + 1, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
-                       t.cflag, cu, cw, cx, cv, nullptr, nullptr, nullptr, nullptr, nullptr,
-                       nullptr);
+                       t.cflag, cu, cw, cx, cv, cf, nullptr, nullptr, nullptr, nullptr,
+                       nullptr, nullptr);
     LAUNCH_CHECK();
     int32_t* off = A.up<int32_t>(n4 + 1);
     scan_exclusive_i32(cnt, off, n4, A, s);
@@ -338,25 +350,32 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     t.m2l_torder = A.up<int32_t>(std::max(nm, 1));
     if (nm > 0) {
         hipLaunchKernelGGL(k_m2l_keys, dim3(grid_for(nm, 256)), dim3(256), 0, s, t.cells, c2,
-                           nc, mk, mk3, mv, hr + 4);
+                           nc, mk, mk3, mv, hr + 5);
         LAUNCH_CHECK();
         radix_sort_pairs(mk, mv, mk2, t.m2l_order, nm, 0, 8, A, s);
         radix_sort_pairs(mk3, mv, mk2, t.m2l_torder, nm, 0, 8, A, s);
     }
-    std::vector<int32_t> h(4 + kGroups);
+    std::vector<int32_t> h(5 + kGroups);
     HIP_TRY(hipMemcpyAsync(h.data(), hr, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     t.n_u = h[0];
     t.n_w = h[1];
     t.n_x = h[2];
     t.n_v = h[3];
-    std::vector<int32_t> gc(h.begin() + 4, h.end());
+    t.n_xcells = h[4];
+    std::vector<int32_t> gc(h.begin() + 5, h.end());
     int32_t* items = A.up<int32_t>(std::max<int64_t>(t.n_u + t.n_w + t.n_x, 1));
     t.u_items = t.w_items = t.x_items = items;
     hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
-                       t.cflag, nullptr, nullptr, nullptr, nullptr, t.u_off, t.w_off, t.x_off,
-                       items, items, items);
+                       t.cflag, nullptr, nullptr, nullptr, nullptr, nullptr, t.u_off, t.w_off,
+                       t.x_off, items, items, items);
     LAUNCH_CHECK();
+    t.x_cells = A.up<int32_t>(std::max(t.n_xcells, 1));
+    if (t.n_xcells > 0) {
+        hipLaunchKernelGGL(k_x_cells, dim3(grid_for(nc, 256)), dim3(256), 0, s, off + 4 * (nc + 1),
+                           nc, t.x_cells);
+        LAUNCH_CHECK();
+    }
     t.m2l_level_start.assign(t.depth + 2, 0);
     for (int l = 0; l <= t.depth; ++l) {
         int acc = t.m2l_level_start[l];
@@ -422,27 +441,6 @@ __device__ inline double dist_point_box(const double p[3], const double lo[3], d
 // would overflow the LDS stack, each lane finishes its own node's subtree
 // with a private stack (counted, then written at scanned offsets).
 constexpr int kBhCap = 2048;
-
-__device__ __forceinline__ uint64_t lanes_below(int lane) {
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-__device__ __forceinline__ int wave_excl_scan(int v, int lane, int& total) {
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(x, d, 64);
-        if (lane >= d) x += u;
-    }
-    total = __shfl(x, 63, 64);
-    return x - v;
-}
-
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // 0: open, 1: accept (M2P), 2: P2P
 __device__ __forceinline__ int bh_class(const Cell& cc, int C, const Cell& B, int b,

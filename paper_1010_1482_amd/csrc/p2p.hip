@@ -28,11 +28,6 @@ struct Vec4<double> {
     using type = double4;
 };
 
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // ZERO: the pair may coincide (r^2 == 0, skipped).  Coincident points share
 // a key, hence a leaf, so only a leaf with itself needs the test.  Across
@@ -53,17 +48,6 @@ __device__ __forceinline__ void pair(T xi, T yi, T zi, const typename Vec4<T>::t
     ax += dx * sc;
     ay += dy * sc;
     az += dz * sc;
-}
-
-__device__ __forceinline__ int wave_excl_scan_p2p(int v, int lane, int& total) {
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int u = __shfl_up(x, d, 64);
-        if (lane >= d) x += u;
-    }
-    total = __shfl(x, 63, 64);
-    return x - v;
 }
 
 // Sum over the sources staged in sh[0, nl): lane layout TW = 64 / G
@@ -99,9 +83,9 @@ __device__ __forceinline__ void p2p_self(const Cell& c, const typename Vec4<T>::
     for (int base = c.first; base < end; base += 64) {
         const int k = base + lane;
         const typename Vec4<T>::type v = k < end ? P[k] : p2p_pad<T>();
-        wave_lds_sync();
+        wave_lds_fence();
         sh[lane] = v;
-        wave_lds_sync();
+        wave_lds_fence();
         p2p_staged<T, G, SOFT, true>(sh, min(64, end - base), g, xi, yi, zi, eps2, phi, ax, ay,
                                      az);
     }
@@ -142,20 +126,9 @@ __device__ __forceinline__ void p2p_packed(const Cell* __restrict__ cells, int s
             }
         }
         int tot;
-        const int off = wave_excl_scan_p2p(cnt, lane, tot);
+        const int off = wave_excl_scan(cnt, lane, tot);
         for (int pb = 0; pb < tot; pb += 64) {
-            // owner of each slot: the cell lane whose range starts there (or
-            // covers slot 0) marks it, then a running maximum over the slots
-            wave_lds_sync();
-            own[lane] = -1;
-            if (cnt > 0 && off < pb + 64 && off + cnt > pb) own[max(off - pb, 0)] = lane;
-            wave_lds_sync();
-            int o = own[lane];
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int u = __shfl_up(o, d, 64);
-                if (lane >= d) o = max(o, u);
-            }
+            int o = wave_run_owner(own, off, cnt, pb, 64, lane);
             const bool ok = pb + lane < tot;
             o = ok ? o : 0;
             const int f = __shfl(first, o, 64), fo = __shfl(off, o, 64);
@@ -171,9 +144,9 @@ __device__ __forceinline__ void p2p_packed(const Cell* __restrict__ cells, int s
             } else if (ok) {
                 v = P[f + (pb + lane - fo)];
             }
-            wave_lds_sync();
+            wave_lds_fence();
             sh[lane] = v;
-            wave_lds_sync();
+            wave_lds_fence();
             p2p_staged<T, G, SOFT, false>(sh, min(64, tot - pb), g, xi, yi, zi, eps2, phi, ax,
                                           ay, az);
         }
@@ -334,9 +307,9 @@ k_direct(const typename Vec4<T>::type* __restrict__ src, int64_t ns,
     for (int64_t base = 0; base < ns; base += 64) {
         const int64_t k = base + lane;
         V v = k < ns ? src[k] : V{T(0), T(0), T(0), T(0)};
-        wave_lds_sync();
+        wave_lds_fence();
         sh[lane] = v;
-        wave_lds_sync();
+        wave_lds_fence();
         const int nl = (int)min((int64_t)64, ns - base);
 #pragma unroll 8
         for (int q = 0; q < nl; ++q)
