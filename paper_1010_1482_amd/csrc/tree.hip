@@ -580,6 +580,19 @@ __global__ void k_leaf_compact(const Cell* __restrict__ cells, int nc,
     for (int s = cell.first; s < cell.first + cell.count; ++s) leaf_of[s] = c;
 }
 
+// After a sort of the top `sorted_levels` levels: a run of more than
+// leaf_max keys with one prefix at that level is a cell that must split
+// below the sorted bits (its ancestors all split), so the tree needs a
+// deeper sort.  Flags it in info[1] before the level loop starts, instead
+// of at the level where the split finds it (any thread may store the 1).
+__global__ void k_sort_check(const uint64_t* __restrict__ keys, int64_t n, int leaf_max,
+                             int sorted_levels, int32_t* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i + leaf_max >= n) return;
+    const int sh = 3 * (HFMM_KEY_LEVELS - sorted_levels);
+    if ((keys[i] >> sh) == (keys[i + leaf_max] >> sh)) *flag = 1;
+}
+
 static int sort_levels_guess(int64_t n, int leaf_max) {
     // levels a uniform distribution needs, plus two
     double ratio = (double)n / (double)std::max(1, leaf_max);
@@ -621,9 +634,9 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nbb, n, t.root, t.cells);
     LAUNCH_CHECK();
+    // the root is read back with the level-0 counts (non-finite inputs only
+    // make meaningless keys until then)
     HIP_TRY(hipMemcpyAsync(&t.root_h, t.root, sizeof(Root), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (t.root_h.nbad) throw Status{HFMM_E_DATA};
 
     // keys, sort (top bits first; a full sort if the tree turns out deeper)
     uint64_t* k0 = A.down<uint64_t>(n);
@@ -640,6 +653,14 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
         LAUNCH_CHECK();
         const int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
         radix_sort_pairs(k0, i0, t.keys, t.perm, n, lo_bit, 63, A, s);
+        if (sorted_levels < HFMM_KEY_LEVELS) {
+            // read back with the level-0 counts: a deeper tree than sorted
+            // restarts there
+            int32_t* in0 = info + 3 * (attempt * (HFMM_KEY_LEVELS + 1));
+            hipLaunchKernelGGL(k_sort_check, dim3(grid_for(n, 256)), dim3(256), 0, s, t.keys,
+                               n, t.leaf_max, sorted_levels, in0 + 1);
+            LAUNCH_CHECK();
+        }
         A.hi = hi_mark;
         t.sort_bits = 63 - lo_bit;
         room(1);
@@ -662,6 +683,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
             int32_t h[3] = {0, 0, 0};
             HIP_TRY(hipMemcpyAsync(h, in, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            if (t.root_h.nbad) throw Status{HFMM_E_DATA};
             if (h[1]) {
                 resort = true;
                 A.hi = hi_mark;
