@@ -47,9 +47,11 @@ def p2p_pairs(tree) -> int:
 
 # FP32 flops one M2P evaluation executes (FMA = 2), by expansion order p,
 # counted from the instruction mix of the treecode far-field kernel's inner
-# loop (irregular solid harmonics to degree p by recurrence, the potential
-# and the three gradient contractions, the scaled offset and rsqrt)
-M2P_FLOPS = {1: 48, 2: 106, 3: 203, 4: 334, 5: 499, 6: 698, 7: 931, 8: 1198}
+# loop: irregular solid harmonics to degree p by recurrence, the potential
+# and the three gradient contractions, the scaled offset and rsqrt; at p = 3
+# the Cartesian quadrupole form (monopole, dipole and traceless quadrupole
+# with their analytic gradient)
+M2P_FLOPS = {1: 48, 2: 106, 3: 80, 4: 334, 5: 499, 6: 698, 7: 931, 8: 1198}
 
 
 def treecode_work(tree):

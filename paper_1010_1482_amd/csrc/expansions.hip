@@ -508,6 +508,91 @@ k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
     far[3 * n + s] = az;
 }
 
+// ---------------------------------------------------------------------
+// M2P at p = 3 (monopole, dipole, quadrupole: the treecode's quadrupole
+// moments) in Cartesian form.  With the irregular harmonics of degree <= 2
+// written out, S_0^0 = 1/r, S_1^0 = z/r^3, S_1^1 = -(x + iy)/r^3,
+// S_2^0 = (3z^2 - r^2)/r^5, S_2^1 = -3z(x + iy)/r^5, S_2^2 = 3(x + iy)^2/r^5,
+// the truncated expansion of a cell is
+//   f(u) = q/r + (D.u)/r^3 + (u.Q.u)/r^5,
+// q = M00, D = (-2 Re M11, 2 Im M11, M10) and the traceless symmetric
+//   Q = [[6 Re M22 - M20, -6 Im M22, -3 Re M21],
+//        [-6 Im M22, -6 Re M22 - M20, 3 Im M21],
+//        [-3 Re M21, 3 Im M21, 2 M20]],
+// the same function the degree-by-degree sum evaluates, and its gradient is
+//   D/r^3 + 2 Q.u/r^5 - u (q/r^3 + 3 (D.u)/r^5 + 5 (u.Q.u)/r^7).
+// Per cell: (q, Dx, Dy, Dz), (Qxx, Qyy, Qzz, Qxy), (Qxz, Qyz, 0, 0).
+// ---------------------------------------------------------------------
+template <typename TC>
+__global__ void k_cart3(const double* __restrict__ M, int ld, int ncells, TC* __restrict__ C) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const double* X = M + (int64_t)c * ld;
+    const double m00 = X[ridx(0, 0, 0)], m10 = X[ridx(1, 0, 0)];
+    const double m11r = X[ridx(1, 1, 0)], m11i = X[ridx(1, 1, 1)];
+    const double m20 = X[ridx(2, 0, 0)], m21r = X[ridx(2, 1, 0)], m21i = X[ridx(2, 1, 1)];
+    const double m22r = X[ridx(2, 2, 0)], m22i = X[ridx(2, 2, 1)];
+    TC* o = C + (int64_t)c * 12;
+    o[0] = (TC)m00;
+    o[1] = (TC)(-2.0 * m11r);
+    o[2] = (TC)(2.0 * m11i);
+    o[3] = (TC)m10;
+    o[4] = (TC)(6.0 * m22r - m20);
+    o[5] = (TC)(-6.0 * m22r - m20);
+    o[6] = (TC)(2.0 * m20);
+    o[7] = (TC)(-6.0 * m22i);
+    o[8] = (TC)(-3.0 * m21r);
+    o[9] = (TC)(3.0 * m21i);
+    o[10] = TC(0);
+    o[11] = TC(0);
+}
+
+template <typename T>
+__device__ __forceinline__ void m2p_cart3(const T* __restrict__ c, T ux, T uy, T uz, T ih,
+                                          T& phi, T& ax, T& ay, T& az) {
+    const T q = c[0], dx = c[1], dy = c[2], dz = c[3];
+    const T qxx = c[4], qyy = c[5], qzz = c[6], qxy = c[7], qxz = c[8], qyz = c[9];
+    const T r2 = ux * ux + uy * uy + uz * uz;
+    const T ir = rsqrt_fast(r2), ir2 = ir * ir;
+    const T ir3 = ir * ir2, ir5 = ir3 * ir2, ir7 = ir5 * ir2;
+    const T du = dx * ux + dy * uy + dz * uz;
+    const T qx = qxx * ux + qxy * uy + qxz * uz;
+    const T qy = qxy * ux + qyy * uy + qyz * uz;
+    const T qz = qxz * ux + qyz * uy + qzz * uz;
+    const T uqu = ux * qx + uy * qy + uz * qz;
+    phi += (q * ir + du * ir3 + uqu * ir5) * ih;
+    const T sc = q * ir3 + T(3) * du * ir5 + T(5) * uqu * ir7;
+    const T ih2 = ih * ih;
+    ax += (dx * ir3 + T(2) * qx * ir5 - ux * sc) * ih2;
+    ay += (dy * ir3 + T(2) * qy * ir5 - uy * sc) * ih2;
+    az += (dz * ir3 + T(2) * qz * ir5 - uz * sc) * ih2;
+}
+
+// Treecode far field at p = 3 from the Cartesian moments (k_cart3).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_treecode_far3(int64_t n, const int32_t* __restrict__ leaf_of,
+                const double4* __restrict__ cen, const double4* __restrict__ p64,
+                const int32_t* __restrict__ a_off, const int32_t* __restrict__ a_items,
+                const T* __restrict__ C, T* __restrict__ far) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int b = leaf_of[s];
+    const double4 pj = p64[s];
+    T phi = T(0), ax = T(0), ay = T(0), az = T(0);
+    for (int e = a_off[b]; e < a_off[b + 1]; ++e) {
+        const int k = a_items[e];
+        const double4 qc = cen[k];
+        const double ic = qc.w;
+        m2p_cart3<T>(C + (int64_t)k * 12, (T)((pj.x - qc.x) * ic), (T)((pj.y - qc.y) * ic),
+                     (T)((pj.z - qc.z) * ic), (T)ic, phi, ax, ay, az);
+    }
+    far[s] = phi;
+    far[n + s] = ax;
+    far[2 * n + s] = ay;
+    far[3 * n + s] = az;
+}
+
 __global__ void k_to_float(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) b[i] = (float)a[i];
@@ -900,6 +985,28 @@ void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
 
 void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
     if (t.n == 0) return;
+    if (p == 3) {  // quadrupole moments: the Cartesian form
+        const int64_t nel = (int64_t)t.ncells * 12;
+        if (fp64) {
+            double* c = t.arena.down<double>(nel);
+            hipLaunchKernelGGL(k_cart3<double>, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
+                               t.M, t.ldm, t.ncells, c);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_treecode_far3<double>, dim3(grid_for(t.n, 256)), dim3(256), 0,
+                               s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,
+                               t.a_items, c, (double*)far);
+        } else {
+            float* c = t.arena.down<float>(nel);
+            hipLaunchKernelGGL(k_cart3<float>, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
+                               t.M, t.ldm, t.ncells, c);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_treecode_far3<float>, dim3(grid_for(t.n, 256)), dim3(256), 0,
+                               s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,
+                               t.a_items, c, (float*)far);
+        }
+        LAUNCH_CHECK();
+        return;
+    }
     const float* M32 = nullptr;
     if (!fp64) {  // FP32 copy of the multipoles (same layout)
         const int64_t nel = (int64_t)t.ncells * t.ldm;
