@@ -128,11 +128,11 @@ void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi, void* a
     if (t.depth >= 2) {
         // M2L partial results
         const bool mf = m2l_uses_mfma(p, precision);
-        int max_parts = 8;
+        int max_parts = 12;
         const size_t esz = fp64 ? 8 : 4;
         while (max_parts > 1 &&
                (size_t)max_parts * t.ncells * t.ldm * esz > A.free_bytes() / 2)
-            max_parts /= 2;
+            --max_parts;
         const int parts_cap = mf ? max_parts : 1;
         void* lm = A.down<char>((size_t)parts_cap * t.ncells * t.ldm * esz);
         int32_t* levexp = A.down<int32_t>(32);
@@ -200,9 +200,9 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
     m2l_layout(p, precision, RB, KQ, ld);
     size_t per_particle = 8 + 4 + 24 + 16 + 32 + 4 + 8 + 4 + 8 + 4 * 8 + 64;
     // M, L, LX (FP64), the M2L operand and the FP32 copy of M for the
-    // far field (FP32), eight M2L partial results
+    // far field (FP32), up to twelve M2L partial results
     size_t per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 * 3 +
-                      (size_t)ld * 4 * 2 + (size_t)8 * ld * 4 + 64;
+                      (size_t)ld * 4 * 2 + (size_t)12 * ld * 4 + 64;
     if (method == HFMM_TREECODE) per_cell = 32 + 32 + 32 + (size_t)P * 8 + 512 + 64;
     size_t ops = method == HFMM_FMM ? m2l_ops_bytes(p, precision) : 0;
     if (method == HFMM_FMM) ops += (size_t)2 * 8 * ld * ld * sizeof(double);

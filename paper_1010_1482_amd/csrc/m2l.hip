@@ -19,6 +19,8 @@
 #include "expansions.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <cmath>
 #include <optional>
 #include <type_traits>
 
@@ -708,6 +710,22 @@ static bool is_bf16(int precision) {
 
 // matrix cores for p <= 13 (FP32, BF16, FP16) and p <= 11 (FP64, whose
 // operator must fit in LDS: 16 ceil(p^2/16) x 8 ceil(p^2/8) doubles)
+// compute units of a device (cached per device; calls from several host
+// threads store the same value)
+static int m2l_cus(int device) {
+    static std::atomic<int> cached[64];
+    if (device < 0 || device >= 64) return 256;
+    int n = cached[device].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) !=
+                hipSuccess ||
+            n <= 0)
+            n = 256;
+        cached[device].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 bool m2l_uses_mfma(int p, int precision) {
     return precision == HFMM_FP64 ? p <= 11 : p <= 13;
 }
@@ -853,6 +871,26 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     m2l_layout(p, precision, RB, KQ, ld);
     const int ntiles = t.n_m2l_tiles;
     int parts = std::max(1, std::min(max_parts, (2048 + ntiles - 1) / std::max(ntiles, 1)));
+    {
+        // Blocks run one (two when the operator buffers take at most 80 KiB
+        // of LDS) per CU; among parts .. parts + 4 take the count whose last
+        // round of blocks is the fullest (the tail leaves CUs idle).
+        const int lds_kb = (m2l_double_buffer(RB, KQ, is_x3(precision) ? 2 : 1) ? 2 : 1) *
+                           (is_x3(precision) ? 2 : 1) * RB * KQ;
+        const int slots = m2l_cus(t.device) * (lds_kb <= 80 ? 2 : 1);
+        double best = -1.0;
+        int bp = parts;
+        for (int q = parts; q <= std::min(max_parts, parts + 4); ++q) {
+            const int sq = (216 + q - 1) / q, qq = (216 + sq - 1) / sq;
+            const double rounds = (double)ntiles * qq / slots;
+            const double fill = rounds / std::ceil(rounds);
+            if (fill > best + 1e-9) {
+                best = fill;
+                bp = qq;
+            }
+        }
+        parts = bp;
+    }
     const int spp = (216 + parts - 1) / parts;
     parts = (216 + spp - 1) / spp;
     part_stride = (int64_t)t.ncells * t.ldm;
