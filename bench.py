@@ -329,7 +329,8 @@ def main() -> int:
     dms, dwork, dbound, dpeak = cand[dom]
     ach = dwork / (dms * 1e-3) / 1e12
     m2l_kernel = "k_m2l_valu" if p > (11 if args.precision == "fp64" else 13) else "k_m2l_mma"
-    kname = {"m2l": m2l_kernel, "p2p": "k_p2p", "far": "k_treecode_far"}[dom]
+    far_kernel = "k_treecode_far3" if p == 3 else "k_treecode_far"
+    kname = {"m2l": m2l_kernel, "p2p": "k_p2p", "far": far_kernel}[dom]
     cfg = f"{args.dist}_{n >> 20}M_p{p}_{args.precision}" if n >= 1 << 20 else \
         f"{args.dist}_{n}_p{p}_{args.precision}"
     rec = recorded_traffic(kname, cfg)
