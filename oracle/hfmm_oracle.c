@@ -1148,6 +1148,43 @@ static void bh_point(const otree* t, const double* com, const cplx* M, int p,
     }
 }
 
+/* The treecode of Sec. 4: the FMM's interaction lists with every M2L + L2L +
+ * L2P replaced by one M2P at the target.  For a target in leaf B the far
+ * field is M2P from the V lists of B and of each ancestor of B and from the
+ * W list of B; the near field is P2P with the U list of B and the X lists of
+ * B and of each ancestor of B (X sources are leaves too close to B's
+ * particles for their multipole expansions, which the FMM reaches through
+ * P2L).  Together these cover every source particle once. */
+static void fmm_list_point(const otree* t, const double* cen, const cplx* M,
+                           int p, const double* ms, double eps2, int64_t s,
+                           double acc[4]) {
+    const int64_t pp = (int64_t)p * p;
+    const int B = t->leaf_of[s];
+    double xt[3] = {t->xs[s], t->ys[s], t->zs[s]}, o[4];
+    for (int a = B; a >= 0; a = t->c[a].parent) {
+        for (int64_t q = t->loff[1][a]; q < t->loff[1][a + 1]; q++) {
+            int C = t->litem[1][q];
+            oracle_m2p(p, &cen[3 * C], (const double*)(M + C * pp), xt, o);
+            for (int i = 0; i < 4; i++) acc[i] += o[i];
+        }
+        for (int64_t q = t->loff[3][a]; q < t->loff[3][a + 1]; q++) {
+            const ocell* c = &t->c[t->litem[3][q]];
+            p2p_point(xt, c->first, c->first + c->count, t->xs, t->ys, t->zs,
+                      ms, eps2, acc);
+        }
+    }
+    for (int64_t q = t->loff[2][B]; q < t->loff[2][B + 1]; q++) {
+        int C = t->litem[2][q];
+        oracle_m2p(p, &cen[3 * C], (const double*)(M + C * pp), xt, o);
+        for (int i = 0; i < 4; i++) acc[i] += o[i];
+    }
+    for (int64_t q = t->loff[0][B]; q < t->loff[0][B + 1]; q++) {
+        const ocell* c = &t->c[t->litem[0][q]];
+        p2p_point(xt, c->first, c->first + c->count, t->xs, t->ys, t->zs, ms,
+                  eps2, acc);
+    }
+}
+
 int oracle_treecode(int64_t n, const double* x, const double* y,
                     const double* z, const double* m, int leaf_max, int p,
                     double theta, int mode, double eps2, int64_t nt,
@@ -1158,15 +1195,19 @@ int oracle_treecode(int64_t n, const double* x, const double* y,
     otree* t = oracle_tree_build(n, x, y, z, leaf_max);
     const int64_t nc = t->ncells, pp = (int64_t)p * p;
     double* ms = sorted_masses(t, m);
-    double* com = com_array(t, m);
+    /* mode 2 expands about the geometric centres, as the FMM does */
+    double* com = mode == 2 ? geometric_centres(t) : com_array(t, m);
     int64_t* inv = inverse_perm(t);
     cplx* M = (cplx*)malloc(sizeof(cplx) * nc * pp);
+    if (mode == 2) build_lists(t);
     upward(t, ms, p, com, M);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; k++) {
         int64_t s = inv[tidx ? tidx[k] : k];
         double acc[4] = {0, 0, 0, 0};
-        if (mode == 1) {
+        if (mode == 2) {
+            fmm_list_point(t, com, M, p, ms, eps2, s, acc);
+        } else if (mode == 1) {
             bh_point(t, com, M, p, theta, ms, eps2, s, 0, acc);
         } else {
             int b = t->leaf_of[s];

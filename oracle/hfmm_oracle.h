@@ -118,7 +118,10 @@ int oracle_fmm(int64_t n, const double* x, const double* y, const double* z,
                const int64_t* tidx, double* phi, double* ax, double* ay,
                double* az);
 /* Treecode. mode 0: group acceptance per target leaf; mode 1: per target
- * particle. Expansions are centred at centres of mass. */
+ * particle; expansions centred at centres of mass.  mode 2: the treecode of
+ * Sec. 4, M2P over the FMM's V lists (leaf and ancestors) and W list, P2P
+ * over its U list and X lists (leaf and ancestors), expansions about the
+ * geometric centres; theta is not used. */
 int oracle_treecode(int64_t n, const double* x, const double* y,
                     const double* z, const double* m, int leaf_max, int p,
                     double theta, int mode, double eps2, int64_t nt,

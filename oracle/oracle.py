@@ -316,7 +316,11 @@ def fmm(x, y, z, m, p, leaf_max, targets=None, eps2=0.0):
 
 
 def treecode(x, y, z, m, p, theta, leaf_max, targets=None, mode=0, eps2=0.0):
-    """Oracle Barnes-Hut treecode; mode 0 per target leaf, 1 per particle."""
+    """Oracle treecode.  Barnes-Hut acceptance l < theta d about centres of
+    mass: mode 0 per target leaf, 1 per particle.  Mode 2: the treecode of
+    Sec. 4 over the FMM lists (M2P from the V lists of the leaf and its
+    ancestors and the leaf's W list, P2P over U and the X lists, expansions
+    about geometric centres; theta unused)."""
     x, y, z, m = map(_f64, (x, y, z, m))
     nt, tg = _targets(targets, len(x))
     out = [np.zeros(nt) for _ in range(4)]

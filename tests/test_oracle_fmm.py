@@ -123,3 +123,105 @@ def test_treecode_per_particle_mode():
     d = O.direct(x, y, z, m)
     e = _err(O.treecode(x, y, z, m, p=4, theta=0.4, leaf_max=16, mode=1), d)[1]
     assert e < 1e-3
+
+
+# ---- the treecode of Sec. 4 (mode 2: FMM lists, geometric centres) ----------
+
+def _fmm_list_sets(T, leaf):
+    """Far cells (V of the leaf and its ancestors, W of the leaf) and near
+    leaves (U of the leaf, X of the leaf and its ancestors) of a target leaf,
+    from the oracle's lists (pinned against their brute-force definitions)."""
+    c = T.cells()
+    lists = [T.list(w) for w in range(4)]
+
+    def items(w, b):
+        off, it = lists[w]
+        return list(it[off[b]:off[b + 1]])
+    far, near = items(O.LIST_W, leaf), items(O.LIST_U, leaf)
+    a = leaf
+    while a >= 0:
+        far += items(O.LIST_V, a)
+        near += items(O.LIST_X, a)
+        a = c["parent"][a]
+    return c, far, near
+
+
+def test_fmm_list_treecode_single_leaf_is_direct_sum():
+    x, y, z, m = W.uniform(50, 1)
+    t = O.treecode(x, y, z, m, p=3, theta=0.5, leaf_max=64, mode=2)
+    for a, b in zip(t, O.direct(x, y, z, m)):
+        assert np.allclose(a, b, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("dist,n,leaf", [("uniform", 4000, 16), ("plummer", 3000, 8)])
+def test_fmm_list_treecode_converges_to_direct_sum(dist, n, leaf):
+    # the far field is a truncated multipole series whose terms fall as
+    # (r/R)^n with r/R <= 0.76 for these lists: the error must fall
+    # geometrically with p and reach the direct sum (a dropped, doubled or
+    # mis-centred cell would leave an error floor)
+    x, y, z, m = W.make(dist, n, 31)
+    d = O.direct(x, y, z, m)
+    e = [_err(O.treecode(x, y, z, m, p=p, theta=0.5, leaf_max=leaf, mode=2), d)
+         for p in (2, 4, 8, 14)]
+    assert all(b[1] < 0.4 * a[1] for a, b in zip(e, e[1:]))
+    assert e[-1][0] < 1e-7 and e[-1][1] < 1e-6
+    # theta is not used by this mode
+    t1 = O.treecode(x, y, z, m, p=4, theta=0.3, leaf_max=leaf, mode=2)
+    t2 = O.treecode(x, y, z, m, p=4, theta=0.9, leaf_max=leaf, mode=2)
+    for a, b in zip(t1, t2):
+        assert np.array_equal(a, b)
+
+
+def test_fmm_list_treecode_near_field_is_exact():
+    # with every particle outside the near set of one target leaf massless,
+    # each far expansion is exactly zero and the result is the direct sum
+    x, y, z, m = W.plummer(3000, 32)
+    T = O.Tree(x, y, z, 8)
+    perm = T.perm()
+    c = T.cells()
+    leaves = np.nonzero(c["nchild"] == 0)[0]
+    rng = np.random.default_rng(5)
+    checked = 0
+    for leaf in rng.permutation(leaves)[:12]:
+        _, far, near = _fmm_list_sets(T, leaf)
+        mm = np.zeros_like(m)
+        for b in near:
+            idx = perm[c["first"][b]:c["first"][b] + c["count"][b]]
+            mm[idx] = m[idx]
+        tg = perm[c["first"][leaf]:c["first"][leaf] + c["count"][leaf]]
+        got = O.treecode(x, y, z, mm, p=2, theta=0.5, leaf_max=8, targets=tg, mode=2)
+        ref = O.direct(x, y, z, mm, targets=tg)
+        for a, b in zip(got, ref):
+            assert np.allclose(a, b, rtol=1e-13, atol=1e-13 * np.abs(b).max())
+        checked += len(far) > 0 and any(c["nchild"][b] == 0 and b != leaf for b in near)
+    assert checked > 0
+
+
+@pytest.mark.parametrize("p", [2, 4, 7])
+def test_fmm_list_treecode_potential_within_truncation_bound(p):
+    # Greengard-Rokhlin bound of a p-term multipole expansion of charges of
+    # total |mass| A within radius r of the centre, at distance R > r:
+    # |phi - phi_p| <= A / (R - r) * (r / R)^p.  Per target, the error
+    # against the direct sum is at most the sum over its far cells.
+    x, y, z, m = W.plummer(2500, 33)
+    T = O.Tree(x, y, z, 8)
+    perm = T.perm()
+    c = T.cells()
+    cx, cy, cz, _ = T.centres()
+    pos = np.stack([x, y, z], 1)
+    leaves = np.nonzero(c["nchild"] == 0)[0]
+    rng = np.random.default_rng(6)
+    for leaf in rng.permutation(leaves)[:10]:
+        _, far, _ = _fmm_list_sets(T, leaf)
+        tg = perm[c["first"][leaf]:c["first"][leaf] + c["count"][leaf]]
+        got = O.treecode(x, y, z, m, p=p, theta=0.5, leaf_max=8, targets=tg, mode=2)[0]
+        ref = O.direct(x, y, z, m, targets=tg)[0]
+        bound = np.zeros(len(tg))
+        for C in far:
+            idx = perm[c["first"][C]:c["first"][C] + c["count"][C]]
+            ctr = np.array([cx[C], cy[C], cz[C]])
+            r = np.max(np.linalg.norm(pos[idx] - ctr, axis=1))
+            R = np.linalg.norm(pos[tg] - ctr, axis=1)
+            assert np.all(R > r)
+            bound += np.sum(np.abs(m[idx])) / (R - r) * (r / R) ** p
+        assert np.all(np.abs(got - ref) <= bound + 1e-13 * np.abs(ref))
