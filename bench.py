@@ -268,7 +268,7 @@ def main() -> int:
     ap.add_argument("--accuracy-targets", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--method", default="fmm", choices=["fmm", "treecode"])
+    ap.add_argument("--method", default="fmm", choices=["fmm", "treecode", "treecode_fmmlist"])
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--forms", default="bf16x3,fp16x3,bf16,fp16",
                     help="M2L precision forms measured beside the headline one "
@@ -303,6 +303,8 @@ def main() -> int:
     workload = (f"FMM N={n} {args.dist} unit cube, masses 1/N, p={p}, leaf<={leaf}, "
                 f"{args.precision}") if args.method == "fmm" else (
                 f"treecode N={n} {args.dist}, p={p}, theta={args.theta}, leaf<={leaf}, "
+                f"{args.precision}") if args.method == "treecode" else (
+                f"treecode over the FMM lists N={n} {args.dist}, p={p}, leaf<={leaf}, "
                 f"{args.precision}")
 
     # Roofline of the dominant kernel: algorithmic work per launch over the

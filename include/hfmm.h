@@ -18,6 +18,13 @@
  *                  U/V/W/X lists (Sec. 6 cites Cheng, Greengard and Rokhlin);
  *                  on uniform data these are the 27-cell P2P and 189-cell M2L
  *                  lists of Secs. 5.1 and 5.2
+ *   HFMM_TREECODE_FMMLIST
+ *                  the treecode the paper measures (Sec. 4): the FMM's upward
+ *                  pass (geometric centres) and lists, with M2P at the targets
+ *                  in place of M2L + L2L + L2P: M2P from V of the target leaf
+ *                  and of its ancestors and from W of the leaf, P2P with U of
+ *                  the leaf and X of the leaf and its ancestors (an acceptance
+ *                  of theta = 2/3; theta is not used)
  * p is the number of expansion terms: degrees n = 0..p-1 (Eq. 4).
  *
  * Memory and streams.  Every pointer argument named x, y, z, m, phi, ax, ay,
@@ -51,7 +58,12 @@ extern "C" {
 
 typedef struct hfmm_tree_s* hfmm_tree;
 
-enum hfmm_method { HFMM_DIRECT = 0, HFMM_TREECODE = 1, HFMM_FMM = 2 };
+enum hfmm_method {
+    HFMM_DIRECT = 0,
+    HFMM_TREECODE = 1,
+    HFMM_FMM = 2,
+    HFMM_TREECODE_FMMLIST = 3
+};
 
 /* Arithmetic of the far field.  P2P, P2M, L2P, M2P run in FP32 for every
  * precision but HFMM_FP64; M2M and L2L always run in FP64; the M2L variants
@@ -105,15 +117,16 @@ int hfmm_build_tree(const double* x, const double* y, const double* z,
 
 /* Upward pass: P2M at the leaves and M2M to the root (Sec. 2), FP64
  * translation.  m holds the n_src source masses.  method selects the
- * expansion centres: geometric cell centres (FMM) or centres of mass
+ * expansion centres: geometric cell centres (FMM, and the treecode over the
+ * FMM lists, which also builds those lists here) or centres of mass
  * (treecode).  A later call with new masses replaces the expansions. */
 int hfmm_upward(hfmm_tree t, const double* m, int p, int method,
                 int precision, void* stream);
 
 /* Far and near field at the targets (Sec. 2): FMM (M2L, L2L, L2P, P2P) or
- * treecode (M2P, P2P) with acceptance parameter theta.  p, method and
- * precision must match the last hfmm_upward.  Outputs hold n_tgt values (or
- * n_src for self-evaluation). */
+ * treecode (M2P, P2P) with acceptance parameter theta (not used by
+ * HFMM_TREECODE_FMMLIST).  p, method and precision must match the last
+ * hfmm_upward.  Outputs hold n_tgt values (or n_src for self-evaluation). */
 int hfmm_evaluate(hfmm_tree t, int p, double theta, int method, int precision,
                   double eps2, void* phi, void* ax, void* ay, void* az,
                   void* stream);
@@ -190,8 +203,9 @@ int hfmm_export_cells(hfmm_tree t, int32_t* dst, void* stream);
  * items (hfmm_stats.list_* int32), rows in cell order. */
 int hfmm_export_list(hfmm_tree t, int which, int32_t* off, int32_t* items,
                      void* stream);
-/* Treecode lists (0 accepted/M2P, 1 P2P) per cell as CSR, like above;
- * items may be NULL to export the offsets only. */
+/* Treecode lists of the last treecode evaluation (0 accepted/M2P, 1 P2P)
+ * per cell as CSR, like above; items may be NULL to export the offsets
+ * only. */
 int hfmm_export_bh_list(hfmm_tree t, int which, int32_t* off, int32_t* items,
                         void* stream);
 /* Expansions in the paper's normalisation (Eqs. 2 and 3): which 0 = M

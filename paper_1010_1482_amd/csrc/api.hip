@@ -3,7 +3,7 @@
 //   build:    bbox, keys, sort, cells                       (tree.hip)
 //   upward:   P2M at the leaves, M2M to the root            (expansions.hip)
 //   evaluate: FMM      M2L (+P2L), L2L, L2P (+M2P), P2P     (m2l, expansions, p2p)
-//             treecode M2P, P2P
+//             treecode M2P, P2P (Barnes-Hut lists, or the FMM lists)
 #include "common.hpp"
 #include "expansions.hpp"
 
@@ -57,6 +57,14 @@ __global__ void k_offsets_minus(const int32_t* __restrict__ in, int64_t n, int32
 static void check_p(int p) {
     if (p < 1 || p > HFMM_MAX_P) throw Status{HFMM_E_UNSUPPORTED};
 }
+// the methods whose upward pass is the FMM's (geometric centres, FMM lists)
+static bool fmm_upward(int method) {
+    return method == HFMM_FMM || method == HFMM_TREECODE_FMMLIST;
+}
+static bool tree_method(int method) {
+    return method == HFMM_FMM || method == HFMM_TREECODE || method == HFMM_TREECODE_FMMLIST;
+}
+
 static void check_precision(int precision) {
     if (precision < HFMM_FP64 || precision > HFMM_M2L_FP16X3) throw Status{HFMM_E_UNSUPPORTED};
 }
@@ -64,11 +72,11 @@ static void check_precision(int precision) {
 void upward_pass(Tree& t, const double* m, int p, int method, int precision, hipStream_t s) {
     check_p(p);
     check_precision(precision);
-    if (method != HFMM_FMM && method != HFMM_TREECODE) throw Status{HFMM_E_UNSUPPORTED};
+    if (!tree_method(method)) throw Status{HFMM_E_UNSUPPORTED};
     if (!m && t.ns > 0) throw Status{HFMM_E_INVAL};
     Arena& A = t.arena;
     A.release_temps();
-    if (method == HFMM_FMM) {
+    if (fmm_upward(method)) {
         if (!t.fmm_lists) {
             A.lo = t.mark_tree;
             PhaseTimer pt(t, PH_LISTS, s);
@@ -89,7 +97,7 @@ void upward_pass(Tree& t, const double* m, int p, int method, int precision, hip
     m2l_layout(p, precision, RB, KQ, ld);
     t.ldm = (P + 15) / 16 * 16;
     PhaseTimer pt(t, PH_UPWARD, s);
-    if (method == HFMM_FMM) prepare_xlat_ops(t, p, s);
+    if (fmm_upward(method)) prepare_xlat_ops(t, p, s);
     t.cen = (double*)A.up<double4>(t.ncells);
     t.M = A.up<double>((size_t)(t.ncells + 1) * t.ldm);
     HIP_TRY(hipMemsetAsync(t.M + (size_t)t.ncells * t.ldm, 0, sizeof(double) * t.ldm, s));
@@ -99,7 +107,7 @@ void upward_pass(Tree& t, const double* m, int p, int method, int precision, hip
     compute_centres(t, method, s);
     const bool fp64 = precision == HFMM_FP64;
     run_p2m(t, p, fp64, s);
-    if (method == HFMM_FMM)
+    if (fmm_upward(method))
         run_m2m_mfma(t, p, s);
     else
         run_m2m(t, p, s);
@@ -168,13 +176,18 @@ void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi, void* a
     A.release_temps();
 }
 
-void evaluate_treecode(Tree& t, int p, double theta, int precision, double eps2, void* phi,
-                       void* ax, void* ay, void* az, hipStream_t s) {
+// fmm_lists: the treecode of Sec. 4 (M2P and P2P over the FMM lists, theta
+// unused); otherwise Barnes-Hut lists with acceptance theta
+void evaluate_treecode(Tree& t, int p, double theta, bool fmm_lists, int precision, double eps2,
+                       void* phi, void* ax, void* ay, void* az, hipStream_t s) {
     Arena& A = t.arena;
     A.release_temps();
     {
         PhaseTimer pt(t, PH_BH, s);
-        build_bh_lists(t, theta, s);
+        if (fmm_lists)
+            build_fmmlist_treecode_lists(t, s);
+        else
+            build_bh_lists(t, theta, s);
     }
     const bool fp64 = precision == HFMM_FP64;
     void* far = A.down<char>((size_t)4 * t.n * (fp64 ? 8 : 4));
@@ -204,6 +217,15 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
     size_t per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 * 3 +
                       (size_t)ld * 4 * 2 + (size_t)12 * ld * 4 + 64;
     if (method == HFMM_TREECODE) per_cell = 32 + 32 + 32 + (size_t)P * 8 + 512 + 64;
+    // FMM lists and upward data, the FP32 copy of M and the treecode lists:
+    // up to 189 M2P items per level from a leaf to the root (levels taken
+    // as those of a uniform tree plus two)
+    if (method == HFMM_TREECODE_FMMLIST) {
+        const double leaves = std::max(1.0, (double)n / std::max(1, leaf_max));
+        const int levels = (int)std::ceil(std::log(leaves) / std::log(8.0)) + 2;
+        per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 +
+                   (size_t)ld * 4 + 64 + (size_t)4 * 189 * std::max(levels, 3);
+    }
     size_t ops = method == HFMM_FMM ? m2l_ops_bytes(p, precision) : 0;
     if (method == HFMM_FMM) ops += (size_t)2 * 8 * ld * ld * sizeof(double);
     if (method == HFMM_FMM && precision != HFMM_FP64 && !m2l_uses_mfma(p, precision))
@@ -252,7 +274,7 @@ int hfmm_arena_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, int meth
     if (p < 1 || p > HFMM_MAX_P) return HFMM_E_UNSUPPORTED;
     if (precision < HFMM_FP64 || precision > HFMM_M2L_FP16X3) return HFMM_E_UNSUPPORTED;
     if (method == HFMM_DIRECT) return hfmm_direct_bytes(n_src, n_tgt, precision, bytes);
-    if (method != HFMM_FMM && method != HFMM_TREECODE) return HFMM_E_UNSUPPORTED;
+    if (!tree_method(method)) return HFMM_E_UNSUPPORTED;
     *bytes = estimate_bytes(n_src, n_tgt, leaf_max, p, method, precision);
     return HFMM_OK;
 }
@@ -330,7 +352,8 @@ int hfmm_evaluate(hfmm_tree h, int p, double theta, int method, int precision, d
     if (method == HFMM_FMM)
         evaluate_fmm(t, p, precision, eps2, phi, ax, ay, az, s);
     else
-        evaluate_treecode(t, p, theta, precision, eps2, phi, ax, ay, az, s);
+        evaluate_treecode(t, p, theta, method == HFMM_TREECODE_FMMLIST, precision, eps2, phi,
+                          ax, ay, az, s);
     API_END
 }
 

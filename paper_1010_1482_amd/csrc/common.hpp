@@ -159,6 +159,7 @@ struct Tree {
     int32_t *u_off = nullptr, *u_items = nullptr;
     int32_t *w_off = nullptr, *w_items = nullptr;
     int32_t *x_off = nullptr, *x_items = nullptr;
+    int32_t* v_off = nullptr;        // V counts as offsets (items: vsrc)
     int32_t* x_cells = nullptr;  // cells with an X list (P2L targets)
     int32_t n_xcells = 0;
     int64_t n_u = 0, n_v = 0, n_w = 0, n_x = 0;
@@ -167,7 +168,7 @@ struct Tree {
     int32_t* m2l_tiles = nullptr;    // per tile: start into m2l_torder, count, octant
     int32_t n_m2l_tiles = 0;
     size_t mark_lists = 0;
-    // treecode lists
+    // treecode lists (bh_theta = kFmmListTheta: built from the FMM lists)
     double bh_theta = -1.0;
     int32_t *a_off = nullptr, *a_items = nullptr;   // accepted (M2P)
     int32_t *b_off = nullptr, *b_items = nullptr;   // P2P
@@ -227,6 +228,18 @@ __host__ __device__ constexpr int ridx(int n, int m, int part) {
 // squares the relative error), full double precision at a fraction of a
 // correctly rounded sqrt and divide.  x = 0 gives inf (FP32) or NaN (FP64);
 // callers mask such pairs.
+// four-wide vector of the compute type
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+
 __device__ __forceinline__ float rsqrt_fast(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_fast(double x) {
     double y = __builtin_amdgcn_rsq(x);
@@ -393,6 +406,8 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
                 hipStream_t s);
 void build_fmm_lists(Tree& t, hipStream_t s);
 void build_bh_lists(Tree& t, double theta, hipStream_t s);
+void build_fmmlist_treecode_lists(Tree& t, hipStream_t s);
+constexpr double kFmmListTheta = -2.0;
 void upward_pass(Tree& t, const double* m, int p, int method, int precision,
                  hipStream_t s);
 void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi,

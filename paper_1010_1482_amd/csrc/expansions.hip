@@ -547,13 +547,15 @@ __global__ void k_cart3(const double* __restrict__ M, int ld, int ncells, TC* __
     o[11] = TC(0);
 }
 
-template <typename T>
-__device__ __forceinline__ void m2p_cart3(const T* __restrict__ c, T ux, T uy, T uz, T ih,
-                                          T& phi, T& ax, T& ay, T& az) {
-    const T q = c[0], dx = c[1], dy = c[2], dz = c[3];
-    const T qxx = c[4], qyy = c[5], qzz = c[6], qxy = c[7], qxz = c[8], qyz = c[9];
-    const T r2 = ux * ux + uy * uy + uz * uz;
-    const T ir = rsqrt_fast(r2), ir2 = ir * ir;
+// one evaluation from the moments r0 = (q, D), r1 = (Qxx, Qyy, Qzz, Qxy),
+// r2 = (Qxz, Qyz, -, -) at u (in units of the cell side h, ih = 1/h)
+template <typename T, typename V>
+__device__ __forceinline__ void m2p_cart3(const V& r0, const V& r1, const V& r2, T ux, T uy,
+                                          T uz, T ih, T& phi, T& ax, T& ay, T& az) {
+    const T q = r0.x, dx = r0.y, dy = r0.z, dz = r0.w;
+    const T qxx = r1.x, qyy = r1.y, qzz = r1.z, qxy = r1.w, qxz = r2.x, qyz = r2.y;
+    const T r2n = ux * ux + uy * uy + uz * uz;
+    const T ir = rsqrt_fast(r2n), ir2 = ir * ir;
     const T ir3 = ir * ir2, ir5 = ir3 * ir2, ir7 = ir5 * ir2;
     const T du = dx * ux + dy * uy + dz * uz;
     const T qx = qxx * ux + qxy * uy + qxz * uz;
@@ -568,29 +570,106 @@ __device__ __forceinline__ void m2p_cart3(const T* __restrict__ c, T ux, T uy, T
     az += (dz * ir3 + T(2) * qz * ir5 - uz * sc) * ih2;
 }
 
-// Treecode far field at p = 3 from the Cartesian moments (k_cart3).
+// The list of one target leaf, 64 cells at a time: lane j stages cell j's
+// moments and (r3) the offset from the cell's centre to the leaf's reference
+// point cb in units of the cell side, formed in FP64, with 1/h.  The offset
+// of target x from cell C is then (x - cb) / h_C + r3, one multiply-add per
+// axis from the target's own FP64-formed offset.  Lane g * TW + t takes
+// target t and the staged cells g, g + G, ...; the G partial sums are added
+// with cross-lane shuffles.
+template <typename T, int G>
+__device__ __forceinline__ void far3_leaf(const Cell& leaf, const double4& cb,
+                                          const double4* __restrict__ cen,
+                                          const double4* __restrict__ p64,
+                                          const int32_t* __restrict__ items, int e0, int e1,
+                                          const T* __restrict__ C,
+                                          typename Vec4<T>::type* sh, T* __restrict__ far,
+                                          int64_t n) {
+    using V = typename Vec4<T>::type;
+    constexpr int TW = 64 / G;
+    const int lane = threadIdx.x & 63, t = lane % TW, g = lane / TW;
+    for (int c0 = 0; c0 < leaf.count; c0 += TW) {
+        const bool ok = c0 + t < leaf.count;
+        const int64_t s = (int64_t)leaf.first + c0 + t;
+        T rx = T(0), ry = T(0), rz = T(0);
+        if (ok) {
+            const double4 pj = p64[s];
+            rx = (T)(pj.x - cb.x);
+            ry = (T)(pj.y - cb.y);
+            rz = (T)(pj.z - cb.z);
+        }
+        T phi = T(0), ax = T(0), ay = T(0), az = T(0);
+        for (int eb = e0; eb < e1; eb += 64) {
+            const int nb = min(64, e1 - eb);
+            V r0{}, r1{}, r2{}, r3{};
+            if (lane < nb) {
+                const int k = items[eb + lane];
+                const V* ck = (const V*)(C + (int64_t)k * 12);
+                r0 = ck[0];
+                r1 = ck[1];
+                r2 = ck[2];
+                const double4 qc = cen[k];
+                r3 = V{(T)((cb.x - qc.x) * qc.w), (T)((cb.y - qc.y) * qc.w),
+                       (T)((cb.z - qc.z) * qc.w), (T)qc.w};
+            }
+            wave_lds_fence();
+            sh[lane] = r0;
+            sh[64 + lane] = r1;
+            sh[128 + lane] = r2;
+            sh[192 + lane] = r3;
+            wave_lds_fence();
+            for (int j = g; j < nb; j += G) {
+                const V a = sh[j], b = sh[64 + j], c = sh[128 + j], d = sh[192 + j];
+                m2p_cart3<T>(a, b, c, rx * d.w + d.x, ry * d.w + d.y, rz * d.w + d.z, d.w, phi,
+                             ax, ay, az);
+            }
+        }
+#pragma unroll
+        for (int d = TW; d < 64; d <<= 1) {
+            phi += __shfl_xor(phi, d, 64);
+            ax += __shfl_xor(ax, d, 64);
+            ay += __shfl_xor(ay, d, 64);
+            az += __shfl_xor(az, d, 64);
+        }
+        if (ok && lane < TW) {
+            far[s] = phi;
+            far[n + s] = ax;
+            far[2 * n + s] = ay;
+            far[3 * n + s] = az;
+        }
+    }
+}
+
+// Treecode far field at p = 3 from the Cartesian moments (k_cart3), one
+// wave per target leaf (a_off, a_items: the M2P list of each leaf); lane
+// groups sized to the leaf's particle count.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_treecode_far3(int64_t n, const int32_t* __restrict__ leaf_of,
-                const double4* __restrict__ cen, const double4* __restrict__ p64,
+k_treecode_far3(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
+                int nleaves, const double4* __restrict__ cen, const double4* __restrict__ p64,
                 const int32_t* __restrict__ a_off, const int32_t* __restrict__ a_items,
-                const T* __restrict__ C, T* __restrict__ far) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int b = leaf_of[s];
-    const double4 pj = p64[s];
-    T phi = T(0), ax = T(0), ay = T(0), az = T(0);
-    for (int e = a_off[b]; e < a_off[b + 1]; ++e) {
-        const int k = a_items[e];
-        const double4 qc = cen[k];
-        const double ic = qc.w;
-        m2p_cart3<T>(C + (int64_t)k * 12, (T)((pj.x - qc.x) * ic), (T)((pj.y - qc.y) * ic),
-                     (T)((pj.z - qc.z) * ic), (T)ic, phi, ax, ay, az);
-    }
-    far[s] = phi;
-    far[n + s] = ax;
-    far[2 * n + s] = ay;
-    far[3 * n + s] = az;
+                const T* __restrict__ C, T* __restrict__ far, int64_t n) {
+    using V = typename Vec4<T>::type;
+    __shared__ V shm[4][256];
+    const int w = threadIdx.x >> 6;
+    const int li = blockIdx.x * 4 + w;
+    if (li >= nleaves) return;  // uniform per wave
+    const int b = leaves[li];
+    const Cell leaf = cells[b];
+    const double4 cb = cen[b];
+    const int e0 = a_off[b], e1 = a_off[b + 1];
+#define FAR3_LEAF(G) far3_leaf<T, G>(leaf, cb, cen, p64, a_items, e0, e1, C, shm[w], far, n)
+    if (leaf.count <= 4)
+        FAR3_LEAF(16);
+    else if (leaf.count <= 8)
+        FAR3_LEAF(8);
+    else if (leaf.count <= 16)
+        FAR3_LEAF(4);
+    else if (leaf.count <= 32)
+        FAR3_LEAF(2);
+    else
+        FAR3_LEAF(1);
+#undef FAR3_LEAF
 }
 
 __global__ void k_to_float(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
@@ -992,17 +1071,19 @@ void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
             hipLaunchKernelGGL(k_cart3<double>, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
                                t.M, t.ldm, t.ncells, c);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_treecode_far3<double>, dim3(grid_for(t.n, 256)), dim3(256), 0,
-                               s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,
-                               t.a_items, c, (double*)far);
+            hipLaunchKernelGGL(k_treecode_far3<double>, dim3(grid_for(t.nleaves, 4)),
+                               dim3(256), 0, s, t.cells, t.leaves, t.nleaves,
+                               (const double4*)t.cen, t.p64, t.a_off, t.a_items, c,
+                               (double*)far, t.n);
         } else {
             float* c = t.arena.down<float>(nel);
             hipLaunchKernelGGL(k_cart3<float>, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
                                t.M, t.ldm, t.ncells, c);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_treecode_far3<float>, dim3(grid_for(t.n, 256)), dim3(256), 0,
-                               s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.a_off,
-                               t.a_items, c, (float*)far);
+            hipLaunchKernelGGL(k_treecode_far3<float>, dim3(grid_for(t.nleaves, 4)),
+                               dim3(256), 0, s, t.cells, t.leaves, t.nleaves,
+                               (const double4*)t.cen, t.p64, t.a_off, t.a_items, c,
+                               (float*)far, t.n);
         }
         LAUNCH_CHECK();
         return;

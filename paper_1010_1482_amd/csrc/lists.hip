@@ -21,6 +21,12 @@
 // a cell C is accepted when l_C < theta * d, d being the distance from C's
 // centre of mass to the target leaf's closed box; C is never accepted when it
 // contains the target leaf; a leaf that fails goes to P2P.
+//
+// The treecode the paper measures (Sec. 4) takes the FMM's lists instead
+// (an acceptance of theta = 2/3): for a target leaf B, M2P from V(B), V(A)
+// of every ancestor A of B and W(B); P2P with U(B) and X of B and of its
+// ancestors (the leaves the FMM reaches through P2L, too close to B's
+// particles for their own multipole expansions).
 #include "common.hpp"
 
 #include <algorithm>
@@ -339,6 +345,7 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     t.u_off = off;
     t.w_off = off + (nc + 1);
     t.x_off = off + 2 * (nc + 1);
+    t.v_off = off + 3 * (nc + 1);
     // M2L target order
     const int c2 = t.depth >= 2 ? t.level_start[2] : nc;
     const int nm = nc - c2;
@@ -690,6 +697,122 @@ void build_bh_lists(Tree& t, double theta, hipStream_t s) {
     LAUNCH_CHECK();
     A.release_temps();
     t.bh_theta = theta;
+    t.mark_bh = A.lo;
+}
+
+// ---------------------------------------------------------------------
+// Treecode lists from the FMM lists (the treecode of Sec. 4)
+// ---------------------------------------------------------------------
+// per leaf B: M2P count |W(B)| + sum over A in {B, ancestors} of |V(A)|,
+// P2P count |U(B)| + sum over the same A of |X(A)|; tot[0..1] receive the
+// 64-bit totals (one atomic per block), so that the host can refuse lists
+// whose int32 offsets would overflow
+__global__ void __launch_bounds__(256)
+k_tl_count(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
+           const int32_t* __restrict__ u_off, const int32_t* __restrict__ w_off,
+           const int32_t* __restrict__ x_off, const int32_t* __restrict__ v_off,
+           int32_t* __restrict__ ca, int32_t* __restrict__ cb,
+           unsigned long long* __restrict__ tot) {
+    __shared__ int sa[4], sb[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int na = 0, nb = 0;
+    if (i < nleaves) {
+        const int b = leaves[i];
+        na = w_off[b + 1] - w_off[b];
+        nb = u_off[b + 1] - u_off[b];
+        for (int a = b; a >= 0; a = cells[a].parent) {
+            na += v_off[a + 1] - v_off[a];
+            nb += x_off[a + 1] - x_off[a];
+        }
+        ca[b] = na;
+        cb[b] = nb;
+    }
+    for (int d = 32; d > 0; d >>= 1) {
+        na += __shfl_xor(na, d, 64);
+        nb += __shfl_xor(nb, d, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = na;
+        sb[w] = nb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&tot[0], (unsigned long long)((int64_t)sa[0] + sa[1] + sa[2] + sa[3]));
+        atomicAdd(&tot[1], (unsigned long long)((int64_t)sb[0] + sb[1] + sb[2] + sb[3]));
+    }
+}
+
+// a run of list items copied by the wave's lanes
+__device__ __forceinline__ int wave_copy(const int32_t* __restrict__ src, int e0, int e1,
+                                         int32_t* __restrict__ dst, int at, int lane) {
+    for (int e = e0 + lane; e < e1; e += 64) dst[at + e - e0] = src[e];
+    return at + (e1 - e0);
+}
+
+// one wave per leaf: the M2P items in the order W(B), then V(A) slot by slot
+// from B up to the root; the P2P items U(B), then X(A) from B up
+__global__ void __launch_bounds__(256)
+k_tl_fill(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
+          const int32_t* __restrict__ vsrc, const int32_t* __restrict__ u_off,
+          const int32_t* __restrict__ w_off, const int32_t* __restrict__ x_off,
+          const int32_t* __restrict__ items, const int32_t* __restrict__ a_off,
+          const int32_t* __restrict__ b_off, int32_t* __restrict__ a_items,
+          int32_t* __restrict__ b_items) {
+    const int li = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (li >= nleaves) return;
+    const int b = leaves[li];
+    int fa = wave_copy(items, w_off[b], w_off[b + 1], a_items, a_off[b], lane);
+    int fb = wave_copy(items, u_off[b], u_off[b + 1], b_items, b_off[b], lane);
+    const uint64_t below = lanes_below(lane);
+    for (int a = b; a >= 0; a = cells[a].parent) {
+        for (int q0 = 0; q0 < kSlots; q0 += 64) {
+            const int q = q0 + lane;
+            const int v = q < kSlots ? vsrc[(int64_t)a * kSlots + q] : -1;
+            const uint64_t bal = __ballot(v >= 0);
+            if (v >= 0) a_items[fa + __popcll(bal & below)] = v;
+            fa += __popcll(bal);
+        }
+        fb = wave_copy(items, x_off[a], x_off[a + 1], b_items, fb, lane);
+    }
+}
+
+void build_fmmlist_treecode_lists(Tree& t, hipStream_t s) {
+    Arena& A = t.arena;
+    if (t.a_off && t.bh_theta == kFmmListTheta) {
+        A.lo = t.mark_bh;
+        return;
+    }
+    if (!t.fmm_lists) throw Status{HFMM_E_STATE};
+    A.lo = t.mark_up;  // above the FMM lists and the upward data
+    const int nc = t.ncells, nlv = t.nleaves;
+    int32_t* cnt = A.down<int32_t>(2 * (size_t)(nc + 1));
+    int32_t *ca = cnt, *cb = cnt + nc + 1;
+    unsigned long long* tot = A.down<unsigned long long>(2);
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * (nc + 1), s));
+    HIP_TRY(hipMemsetAsync(tot, 0, 2 * sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(k_tl_count, dim3(grid_for(nlv, 256)), dim3(256), 0, s, t.cells, t.leaves,
+                       nlv, t.u_off, t.w_off, t.x_off, t.v_off, ca, cb, tot);
+    LAUNCH_CHECK();
+    unsigned long long h[2];
+    HIP_TRY(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h[0] > (unsigned long long)INT32_MAX || h[1] > (unsigned long long)INT32_MAX)
+        throw Status{HFMM_E_UNSUPPORTED};  // list offsets are int32
+    t.n_a = (int64_t)h[0];
+    t.n_b = (int64_t)h[1];
+    t.a_off = A.up<int32_t>(nc + 1);
+    t.b_off = A.up<int32_t>(nc + 1);
+    scan_exclusive_i32(ca, t.a_off, nc, A, s);
+    scan_exclusive_i32(cb, t.b_off, nc, A, s);
+    t.a_items = A.up<int32_t>(std::max<int64_t>(t.n_a, 1));
+    t.b_items = A.up<int32_t>(std::max<int64_t>(t.n_b, 1));
+    hipLaunchKernelGGL(k_tl_fill, dim3(grid_for(nlv, 4)), dim3(256), 0, s, t.cells, t.leaves,
+                       nlv, t.vsrc, t.u_off, t.w_off, t.x_off, t.u_items, t.a_off, t.b_off,
+                       t.a_items, t.b_items);
+    LAUNCH_CHECK();
+    A.release_temps();
+    t.bh_theta = kFmmListTheta;
     t.mark_bh = A.lo;
 }
 

@@ -17,17 +17,6 @@
 
 namespace hfmm {
 
-template <typename T>
-struct Vec4;
-template <>
-struct Vec4<float> {
-    using type = float4;
-};
-template <>
-struct Vec4<double> {
-    using type = double4;
-};
-
 
 // ZERO: the pair may coincide (r^2 == 0, skipped).  Coincident points share
 // a key, hence a leaf, so only a leaf with itself needs the test.  Across

@@ -3,8 +3,9 @@ launch configuration, on sampled targets the FP64 oracle evaluates one by one:
 
 * N = 2^20 uniform, p = 10, leaf <= 64: FP32 FMM against the oracle FMM (the
   same approximation; differences are FP32 rounding);
-* N = 2^22 Plummer, leaf <= 32: FMM p = 8 and treecode p = 3, theta = 0.5, in
-  FP32 and FP64, against the oracle FMM / treecode (group lists);
+* N = 2^22 Plummer, leaf <= 32: FMM p = 8, treecode p = 3, theta = 0.5, and
+  the treecode over the FMM lists at p = 3, in FP32 and FP64, against the
+  oracle FMM / treecode (group lists) / treecode (FMM lists);
 * N = 2^22 uniform, p = 12: every M2L form against the oracle's exact direct
   sum, at the accuracy bar the metric is quoted at (1e-4 relative).
 """
@@ -88,6 +89,18 @@ def test_plummer_4M_treecode_p3_against_oracle(plummer_4m, prec, tol):
                                       precision=prec, leaf_max=32)]
     ephi, eacc = rel_err(out, ref)
     say(f"  vs oracle treecode: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi <= tol and eacc <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", FP32_TOL), ("fp64", FP64_TOL)])
+def test_plummer_4M_fmmlist_treecode_p3_against_oracle(plummer_4m, prec, tol):
+    x, y, z, m, tg, cache = plummer_4m
+    say(f"full size: plummer n={len(x)} treecode over the FMM lists p=3 leaf=32 {prec}")
+    ref = _oracle(cache, "tl", lambda: O.treecode(x, y, z, m, 3, 0.5, 32, targets=tg, mode=2))
+    out = [o[tg] for o in _gpu_solve(x, y, z, m, p=3, method="treecode_fmmlist",
+                                      precision=prec, leaf_max=32)]
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs oracle treecode (FMM lists): phi {ephi:.2e} acc {eacc:.2e}")
     assert ephi <= tol and eacc <= tol
 
 

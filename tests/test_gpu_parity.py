@@ -229,6 +229,68 @@ def test_treecode_matches_oracle(dist, n, leaf, p, theta):
     assert rel_err(out, d)[1] < 5e-3
 
 
+@pytest.mark.parametrize("dist,n,leaf,p", [("plummer", 8000, 8, 3), ("uniform", 6000, 32, 6),
+                                           ("plummer", 5000, 4, 8)])
+def test_fmmlist_treecode_matches_oracle(dist, n, leaf, p):
+    # the treecode of Sec. 4: M2P over V of the leaf and its ancestors and W
+    # of the leaf, P2P over U of the leaf and X of the leaf and its ancestors
+    say(f"treecode over the FMM lists {dist} n={n} leaf={leaf} p={p}")
+    x, y, z, m = W.make(dist, n, 49)
+    T = O.Tree(x, y, z, leaf)
+    c = T.cells()
+    lists = [T.list(w) for w in range(4)]
+
+    def items(w, b):
+        off, it = lists[w]
+        return list(it[off[b]:off[b + 1]])
+    t = H().Tree(*to_dev(x, y, z), leaf_max=leaf)
+    md = to_dev(m)[0]
+    t.upward(md, p, H().TREECODE_FMMLIST, H().FP64)
+    out = host(t.evaluate())
+    (goff, git), (hoff, hit) = ((a.cpu().numpy() for a in t.bh_list(w)) for w in range(2))
+    for b in range(T.ncells):
+        far, near = [], []
+        if c["nchild"][b] == 0:
+            far, near = items(O.LIST_W, b), items(O.LIST_U, b)
+            a = b
+            while a >= 0:
+                far += items(O.LIST_V, a)
+                near += items(O.LIST_X, a)
+                a = c["parent"][a]
+        assert sorted(git[goff[b]:goff[b + 1]]) == sorted(far), b
+        assert sorted(hit[hoff[b]:hoff[b + 1]]) == sorted(near), b
+    ref = O.treecode(x, y, z, m, p, 0.5, leaf, mode=2)
+    ephi, eacc = rel_err(out, ref)
+    say(f"  fp64 vs oracle: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi <= 1e-12 and eacc <= 1e-12
+    t.upward(md, p, H().TREECODE_FMMLIST, H().FP32)
+    e32 = rel_err(host(t.evaluate()), ref)
+    say(f"  fp32 vs oracle: phi {e32[0]:.2e} acc {e32[1]:.2e}")
+    assert e32[0] < 1e-5 and e32[1] < 1e-5
+    # against the exact sum: the far field's truncation at this p
+    d = O.direct(x, y, z, m)
+    assert rel_err(out, d)[1] < {3: 5e-3, 6: 5e-4, 8: 1e-4}[p]
+
+
+def test_fmmlist_treecode_distinct_targets():
+    # distinct targets enter the tree as massless particles: the oracle on
+    # the joined point set gives the same tree, lists and result
+    say("treecode over the FMM lists: distinct targets")
+    x, y, z, m = W.plummer(4000, 50)
+    tx, ty, tz, _ = W.plummer(700, 51)
+    out = host(H().solve(*to_dev(x, y, z, m), p=10, method="treecode_fmmlist",
+                         precision="fp64", leaf_max=16, targets=to_dev(tx, ty, tz)))
+    X, Y, Z = (np.concatenate(a) for a in ((x, tx), (y, ty), (z, tz)))
+    ref = O.treecode(X, Y, Z, np.concatenate([m, np.zeros(700)]), 10, 0.5, 16,
+                     targets=np.arange(4000, 4700), mode=2)
+    ephi, eacc = rel_err(out, ref)
+    say(f"  vs oracle: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi <= 1e-12 and eacc <= 1e-12
+    ephi, eacc = rel_err(out, O.direct_points(x, y, z, m, tx, ty, tz))
+    say(f"  vs direct: phi {ephi:.2e} acc {eacc:.2e}")
+    assert ephi < 1e-5 and eacc < 1e-4
+
+
 def test_empty_and_single():
     say("empty and single")
     x, y, z, m = to_dev(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0))
