@@ -185,7 +185,7 @@ void evaluate_treecode(Tree& t, int p, double theta, bool fmm_lists, int precisi
     {
         PhaseTimer pt(t, PH_BH, s);
         if (fmm_lists)
-            build_fmmlist_treecode_lists(t, s);
+            build_fmmlist_treecode_lists(t, p != 3, s);
         else
             build_bh_lists(t, theta, s);
     }
@@ -532,8 +532,12 @@ int hfmm_export_bh_list(hfmm_tree h, int which, int32_t* off, int32_t* items, vo
     const int32_t* it = which == 0 ? t.a_items : t.b_items;
     const int64_t nn = which == 0 ? t.n_a : t.n_b;
     HIP_TRY(hipMemcpyAsync(off, o, sizeof(int32_t) * (t.ncells + 1), hipMemcpyDeviceToDevice, s));
-    if (nn > 0 && items)
-        HIP_TRY(hipMemcpyAsync(items, it, sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s));
+    if (nn > 0 && items) {
+        if (it)
+            HIP_TRY(hipMemcpyAsync(items, it, sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s));
+        else  // over the FMM lists at p = 3 the M2P items are not kept
+            fill_fmmlist_far_items(t, items, s);
+    }
     API_END
 }
 

@@ -570,24 +570,78 @@ __device__ __forceinline__ void m2p_cart3(const V& r0, const V& r1, const V& r2,
     az += (dz * ir3 + T(2) * qz * ir5 - uz * sc) * ih2;
 }
 
-// The list of one target leaf, 64 cells at a time: lane j stages cell j's
-// moments and (r3) the offset from the cell's centre to the leaf's reference
-// point cb in units of the cell side, formed in FP64, with 1/h.  The offset
-// of target x from cell C is then (x - cb) / h_C + r3, one multiply-add per
-// axis from the target's own FP64-formed offset.  Lane g * TW + t takes
-// target t and the staged cells g, g + G, ...; the G partial sums are added
-// with cross-lane shuffles.
+// One batch of up to 64 list cells of a target leaf: lane j offers cell k
+// when `valid`; the valid cells are packed at the front of the wave's LDS
+// slice, each as its moments and (r3) the offset from the cell's centre to
+// the leaf's reference point cb in units of the cell side, formed in FP64,
+// with 1/h.  The offset of a target from cell C is then (x - cb) / h_C + r3,
+// one multiply-add per axis from the target's own FP64-formed offset.  Lane
+// g * TW + t takes target t and the packed cells g, g + G, ...; the slots
+// past the batch up to the next multiple of G hold zero moments at unit
+// distance with 1/h = 0, whose terms are exactly zero.
 template <typename T, int G>
-__device__ __forceinline__ void far3_leaf(const Cell& leaf, const double4& cb,
-                                          const double4* __restrict__ cen,
+__device__ __forceinline__ void far3_batch(bool valid, int k, const double4& cb,
+                                           const double4* __restrict__ cen,
+                                           const T* __restrict__ C,
+                                           typename Vec4<T>::type* sh, T rx, T ry, T rz,
+                                           T& phi, T& ax, T& ay, T& az) {
+    using V = typename Vec4<T>::type;
+    constexpr int TW = 64 / G;
+    const int lane = threadIdx.x & 63, g = lane / TW;
+    const uint64_t bal = __ballot(valid);
+    const int nb = __popcll(bal);
+    if (nb == 0) return;  // uniform per wave
+    V r0{}, r1{}, r2{}, r3{};
+    if (valid) {
+        const V* ck = (const V*)(C + (int64_t)k * 12);
+        r0 = ck[0];
+        r1 = ck[1];
+        r2 = ck[2];
+        const double4 qc = cen[k];
+        r3 = V{(T)((cb.x - qc.x) * qc.w), (T)((cb.y - qc.y) * qc.w), (T)((cb.z - qc.z) * qc.w),
+               (T)qc.w};
+    }
+    const int pos = __popcll(bal & lanes_below(lane));
+    const int nr = (nb + G - 1) / G * G;
+    wave_lds_fence();
+    if (valid) {
+        sh[pos] = r0;
+        sh[64 + pos] = r1;
+        sh[128 + pos] = r2;
+        sh[192 + pos] = r3;
+    }
+    if (lane >= nb && lane < nr) {
+        const V z{};
+        sh[lane] = z;
+        sh[64 + lane] = z;
+        sh[128 + lane] = z;
+        sh[192 + lane] = V{T(1), T(0), T(0), T(0)};
+    }
+    wave_lds_fence();
+#pragma unroll 2
+    for (int j0 = 0; j0 < nr; j0 += G) {
+        const int j = j0 + g;
+        const V a = sh[j], b = sh[64 + j], c = sh[128 + j], d = sh[192 + j];
+        m2p_cart3<T>(a, b, c, rx * d.w + d.x, ry * d.w + d.y, rz * d.w + d.z, d.w, phi, ax,
+                     ay, az);
+    }
+}
+
+// The far field of one target leaf, TW targets at a time.  WALK: the M2P
+// cells are read from the FMM lists (W of the leaf from the CSR items, then
+// the V slots of the leaf and of each ancestor, empty slots skipped);
+// otherwise from the leaf's CSR list items[e0, e1).
+template <typename T, int G, bool WALK>
+__device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b, const Cell& leaf,
+                                          const double4& cb, const double4* __restrict__ cen,
                                           const double4* __restrict__ p64,
                                           const int32_t* __restrict__ items, int e0, int e1,
+                                          const int32_t* __restrict__ vsrc,
                                           const T* __restrict__ C,
                                           typename Vec4<T>::type* sh, T* __restrict__ far,
                                           int64_t n) {
-    using V = typename Vec4<T>::type;
     constexpr int TW = 64 / G;
-    const int lane = threadIdx.x & 63, t = lane % TW, g = lane / TW;
+    const int lane = threadIdx.x & 63, t = lane % TW;
     for (int c0 = 0; c0 < leaf.count; c0 += TW) {
         const bool ok = c0 + t < leaf.count;
         const int64_t s = (int64_t)leaf.first + c0 + t;
@@ -600,28 +654,17 @@ __device__ __forceinline__ void far3_leaf(const Cell& leaf, const double4& cb,
         }
         T phi = T(0), ax = T(0), ay = T(0), az = T(0);
         for (int eb = e0; eb < e1; eb += 64) {
-            const int nb = min(64, e1 - eb);
-            V r0{}, r1{}, r2{}, r3{};
-            if (lane < nb) {
-                const int k = items[eb + lane];
-                const V* ck = (const V*)(C + (int64_t)k * 12);
-                r0 = ck[0];
-                r1 = ck[1];
-                r2 = ck[2];
-                const double4 qc = cen[k];
-                r3 = V{(T)((cb.x - qc.x) * qc.w), (T)((cb.y - qc.y) * qc.w),
-                       (T)((cb.z - qc.z) * qc.w), (T)qc.w};
-            }
-            wave_lds_fence();
-            sh[lane] = r0;
-            sh[64 + lane] = r1;
-            sh[128 + lane] = r2;
-            sh[192 + lane] = r3;
-            wave_lds_fence();
-            for (int j = g; j < nb; j += G) {
-                const V a = sh[j], b = sh[64 + j], c = sh[128 + j], d = sh[192 + j];
-                m2p_cart3<T>(a, b, c, rx * d.w + d.x, ry * d.w + d.y, rz * d.w + d.z, d.w, phi,
-                             ax, ay, az);
+            const bool v = eb + lane < e1;
+            far3_batch<T, G>(v, v ? items[eb + lane] : 0, cb, cen, C, sh, rx, ry, rz, phi, ax,
+                             ay, az);
+        }
+        if (WALK) {
+            for (int a = b; a >= 0; a = cells[a].parent) {
+                const int32_t* row = vsrc + (int64_t)a * 216;
+                for (int q0 = 0; q0 < 216; q0 += 64) {
+                    const int k = q0 + lane < 216 ? row[q0 + lane] : -1;
+                    far3_batch<T, G>(k >= 0, k, cb, cen, C, sh, rx, ry, rz, phi, ax, ay, az);
+                }
             }
         }
 #pragma unroll
@@ -641,14 +684,16 @@ __device__ __forceinline__ void far3_leaf(const Cell& leaf, const double4& cb,
 }
 
 // Treecode far field at p = 3 from the Cartesian moments (k_cart3), one
-// wave per target leaf (a_off, a_items: the M2P list of each leaf); lane
-// groups sized to the leaf's particle count.
-template <typename T>
+// wave per target leaf, lane groups sized to the leaf's particle count.
+// off/items: the leaf's M2P list (Barnes-Hut), or with WALK its W list, the
+// V lists being read from vsrc.
+template <typename T, bool WALK>
 __global__ void __launch_bounds__(256)
 k_treecode_far3(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
                 int nleaves, const double4* __restrict__ cen, const double4* __restrict__ p64,
-                const int32_t* __restrict__ a_off, const int32_t* __restrict__ a_items,
-                const T* __restrict__ C, T* __restrict__ far, int64_t n) {
+                const int32_t* __restrict__ off, const int32_t* __restrict__ items,
+                const int32_t* __restrict__ vsrc, const T* __restrict__ C, T* __restrict__ far,
+                int64_t n) {
     using V = typename Vec4<T>::type;
     __shared__ V shm[4][256];
     const int w = threadIdx.x >> 6;
@@ -657,8 +702,9 @@ k_treecode_far3(const Cell* __restrict__ cells, const int32_t* __restrict__ leav
     const int b = leaves[li];
     const Cell leaf = cells[b];
     const double4 cb = cen[b];
-    const int e0 = a_off[b], e1 = a_off[b + 1];
-#define FAR3_LEAF(G) far3_leaf<T, G>(leaf, cb, cen, p64, a_items, e0, e1, C, shm[w], far, n)
+    const int e0 = off[b], e1 = off[b + 1];
+#define FAR3_LEAF(G)                                                                           \
+    far3_leaf<T, G, WALK>(cells, b, leaf, cb, cen, p64, items, e0, e1, vsrc, C, shm[w], far, n)
     if (leaf.count <= 4)
         FAR3_LEAF(16);
     else if (leaf.count <= 8)
@@ -1065,26 +1111,36 @@ void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
 void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
     if (t.n == 0) return;
     if (p == 3) {  // quadrupole moments: the Cartesian form
+        // over the FMM lists the far cells are read from V and W directly
+        const bool walk = t.bh_theta == kFmmListTheta;
+        const int32_t* off = walk ? t.w_off : t.a_off;
+        const int32_t* items = walk ? t.w_items : t.a_items;
         const int64_t nel = (int64_t)t.ncells * 12;
+        const dim3 grid(grid_for(t.nleaves, 4)), block(256);
+#define FAR3(TT, W)                                                                            \
+    hipLaunchKernelGGL((k_treecode_far3<TT, W>), grid, block, 0, s, t.cells, t.leaves,          \
+                       t.nleaves, (const double4*)t.cen, t.p64, off, items, t.vsrc, c,          \
+                       (TT*)far, t.n)
         if (fp64) {
             double* c = t.arena.down<double>(nel);
             hipLaunchKernelGGL(k_cart3<double>, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
                                t.M, t.ldm, t.ncells, c);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_treecode_far3<double>, dim3(grid_for(t.nleaves, 4)),
-                               dim3(256), 0, s, t.cells, t.leaves, t.nleaves,
-                               (const double4*)t.cen, t.p64, t.a_off, t.a_items, c,
-                               (double*)far, t.n);
+            if (walk)
+                FAR3(double, true);
+            else
+                FAR3(double, false);
         } else {
             float* c = t.arena.down<float>(nel);
             hipLaunchKernelGGL(k_cart3<float>, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
                                t.M, t.ldm, t.ncells, c);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_treecode_far3<float>, dim3(grid_for(t.nleaves, 4)),
-                               dim3(256), 0, s, t.cells, t.leaves, t.nleaves,
-                               (const double4*)t.cen, t.p64, t.a_off, t.a_items, c,
-                               (float*)far, t.n);
+            if (walk)
+                FAR3(float, true);
+            else
+                FAR3(float, false);
         }
+#undef FAR3
         LAUNCH_CHECK();
         return;
     }

@@ -751,7 +751,8 @@ __device__ __forceinline__ int wave_copy(const int32_t* __restrict__ src, int e0
 }
 
 // one wave per leaf: the M2P items in the order W(B), then V(A) slot by slot
-// from B up to the root; the P2P items U(B), then X(A) from B up
+// from B up to the root; the P2P items U(B), then X(A) from B up (either
+// output may be null, uniformly)
 __global__ void __launch_bounds__(256)
 k_tl_fill(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
           const int32_t* __restrict__ vsrc, const int32_t* __restrict__ u_off,
@@ -762,24 +763,30 @@ k_tl_fill(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, in
     const int li = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (li >= nleaves) return;
     const int b = leaves[li];
-    int fa = wave_copy(items, w_off[b], w_off[b + 1], a_items, a_off[b], lane);
-    int fb = wave_copy(items, u_off[b], u_off[b + 1], b_items, b_off[b], lane);
     const uint64_t below = lanes_below(lane);
-    for (int a = b; a >= 0; a = cells[a].parent) {
-        for (int q0 = 0; q0 < kSlots; q0 += 64) {
-            const int q = q0 + lane;
-            const int v = q < kSlots ? vsrc[(int64_t)a * kSlots + q] : -1;
-            const uint64_t bal = __ballot(v >= 0);
-            if (v >= 0) a_items[fa + __popcll(bal & below)] = v;
-            fa += __popcll(bal);
-        }
-        fb = wave_copy(items, x_off[a], x_off[a + 1], b_items, fb, lane);
+    if (a_items) {
+        int fa = wave_copy(items, w_off[b], w_off[b + 1], a_items, a_off[b], lane);
+        for (int a = b; a >= 0; a = cells[a].parent)
+            for (int q0 = 0; q0 < kSlots; q0 += 64) {
+                const int q = q0 + lane;
+                const int v = q < kSlots ? vsrc[(int64_t)a * kSlots + q] : -1;
+                const uint64_t bal = __ballot(v >= 0);
+                if (v >= 0) a_items[fa + __popcll(bal & below)] = v;
+                fa += __popcll(bal);
+            }
+    }
+    if (b_items) {
+        int fb = wave_copy(items, u_off[b], u_off[b + 1], b_items, b_off[b], lane);
+        for (int a = b; a >= 0; a = cells[a].parent)
+            fb = wave_copy(items, x_off[a], x_off[a + 1], b_items, fb, lane);
     }
 }
 
-void build_fmmlist_treecode_lists(Tree& t, hipStream_t s) {
+// fill_far: also write the M2P items (the p = 3 far field reads V and W
+// directly and needs only their offsets, for the statistics)
+void build_fmmlist_treecode_lists(Tree& t, bool fill_far, hipStream_t s) {
     Arena& A = t.arena;
-    if (t.a_off && t.bh_theta == kFmmListTheta) {
+    if (t.a_off && t.bh_theta == kFmmListTheta && (t.a_items || !fill_far)) {
         A.lo = t.mark_bh;
         return;
     }
@@ -805,7 +812,7 @@ void build_fmmlist_treecode_lists(Tree& t, hipStream_t s) {
     t.b_off = A.up<int32_t>(nc + 1);
     scan_exclusive_i32(ca, t.a_off, nc, A, s);
     scan_exclusive_i32(cb, t.b_off, nc, A, s);
-    t.a_items = A.up<int32_t>(std::max<int64_t>(t.n_a, 1));
+    t.a_items = fill_far ? A.up<int32_t>(std::max<int64_t>(t.n_a, 1)) : nullptr;
     t.b_items = A.up<int32_t>(std::max<int64_t>(t.n_b, 1));
     hipLaunchKernelGGL(k_tl_fill, dim3(grid_for(nlv, 4)), dim3(256), 0, s, t.cells, t.leaves,
                        nlv, t.vsrc, t.u_off, t.w_off, t.x_off, t.u_items, t.a_off, t.b_off,
@@ -814,6 +821,14 @@ void build_fmmlist_treecode_lists(Tree& t, hipStream_t s) {
     A.release_temps();
     t.bh_theta = kFmmListTheta;
     t.mark_bh = A.lo;
+}
+
+// the M2P items of the lists above written to dst (n_a entries, device)
+void fill_fmmlist_far_items(const Tree& t, int32_t* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_tl_fill, dim3(grid_for(t.nleaves, 4)), dim3(256), 0, s, t.cells,
+                       t.leaves, t.nleaves, t.vsrc, t.u_off, t.w_off, t.x_off, t.u_items,
+                       t.a_off, t.b_off, dst, nullptr);
+    LAUNCH_CHECK();
 }
 
 }  // namespace hfmm

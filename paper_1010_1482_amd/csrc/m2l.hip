@@ -151,18 +151,19 @@ __global__ void k_pack_lp(const Cell* __restrict__ cells, const double* __restri
 }
 
 // ---------------------------------------------------------------------
-// Matrix-core M2L.  Block = 4 waves, tile = up to 256 targets of one
-// (level, octant), 64 per wave (4 column blocks of 16).  blockIdx.y selects a
-// contiguous range of slots; each range writes its own partial result,
-// summed later in the downward pass (deterministic, no atomics).
+// Matrix-core M2L.  Block = 8 waves, tile = up to 256 targets of one
+// octant (levels mixed), 32 per wave (two column blocks of 16).  blockIdx.y
+// selects a contiguous range of slots; each range writes its own partial
+// result, summed later in the downward pass (deterministic, no atomics).
 //
 // Both operands travel in 16-byte chunks: chunk 4 q + g of a row holds the
 // contraction elements that lane group g feeds to step q.  For FP32 a chunk
 // is 4 floats (four 16x16x4 products), for BF16/FP16 8 halves (one 16x16x32
-// product).  Per slot the operator T_d is copied to LDS with direct
-// global-to-LDS loads, the next active slot's source indices and the first
-// source chunks are requested before the barrier, and the source chunks of
-// step q + 1 are in flight while step q runs on the matrix cores.
+// product).  Per slot the operator T_d sits in LDS: FP32, FP64 and the split
+// forms stage the next slot's operator through registers; the single-product
+// forms and the largest orders copy it with direct global-to-LDS loads.  The
+// source chunks of the next contraction steps are in flight while a step
+// runs on the matrix cores.
 // ---------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
