@@ -337,3 +337,31 @@ def rel_l2(a, ref):
     a = np.asarray(a, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return float(np.sqrt(np.sum((a - ref) ** 2)) / np.sqrt(np.sum(ref ** 2)))
+
+
+# ---- time stepping ----------------------------------------------------------
+
+def leapfrog(x, y, z, vx, vy, vz, m, dt, steps, field=None):
+    """Kick-drift-kick leapfrog over `steps` steps of length dt (the paper
+    leaves the integrator of its N-body simulation unnamed; this is the
+    standard second-order symplectic one).  The acceleration of each particle
+    is the field of all the others, a_i = sum_j m_j (x_j - x_i) / r^3
+    (`field(x, y, z, m)` -> (phi, ax, ay, az); the oracle direct sum when
+    None).  Per step: v += a dt/2; x += v dt; a = field(x); v += a dt/2.
+    Returns (x, y, z, vx, vy, vz, phi, ax, ay, az) after the last step, the
+    field being that of the final positions."""
+    if field is None:
+        field = direct
+    pos = [np.array(a, dtype=np.float64) for a in (x, y, z)]
+    vel = [np.array(a, dtype=np.float64) for a in (vx, vy, vz)]
+    m = _f64(m)
+    phi, *acc = field(*pos, m)
+    for _ in range(steps):
+        for v, a in zip(vel, acc):
+            v += 0.5 * dt * a
+        for q, v in zip(pos, vel):
+            q += dt * v
+        phi, *acc = field(*pos, m)
+        for v, a in zip(vel, acc):
+            v += 0.5 * dt * a
+    return (*pos, *vel, phi, *acc)
