@@ -253,6 +253,35 @@ def measure(args, prec_name, x, y, z, m, dev, steps, warmup, accuracy):
     return res
 
 
+def leapfrog_rate(args, x, y, z, m, dev):
+    """Time steps of the N-body loop (kick-drift-kick leapfrog, one force
+    evaluation per step, a new tree each time) at the same configuration,
+    from rest: per-step time = (time of K steps - time of 0 steps) / K, the
+    0-step call being the initial evaluation both make."""
+    import torch
+    from paper_1010_1482_amd import hfmm
+    k = args.leapfrog_steps
+    xd, yd, zd, md = (torch.from_numpy(a).to(dev) for a in (x, y, z, m))
+    v = [torch.zeros_like(xd) for _ in range(3)]
+    kw = dict(p=args.p, method=args.method, precision=args.precision, leaf_max=args.leaf,
+              theta=args.theta)
+    hfmm.leapfrog(xd, yd, zd, *v, md, 1e-3, 1, **kw)  # warm-up
+    times = {}
+    for steps in (0, k):
+        pos = [a.clone() for a in (xd, yd, zd)]
+        vel = [a.clone() for a in v]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hfmm.leapfrog(*pos, *vel, md, 1e-3, steps, **kw)
+        torch.cuda.synchronize()
+        times[steps] = time.perf_counter() - t0
+    ms = (times[k] - times[0]) / k * 1e3
+    return {"steps": k, "dt": 1e-3, "ms_per_step": ms,
+            "particle_steps_per_s": len(x) / (ms * 1e-3),
+            "note": "kick-drift-kick leapfrog from rest, one evaluation and one new tree "
+                    "per step"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -270,6 +299,8 @@ def main() -> int:
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--method", default="fmm", choices=["fmm", "treecode", "treecode_fmmlist"])
     ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--leapfrog-steps", type=int, default=5,
+                    help="time this many steps of the N-body loop (0 skips it)")
     ap.add_argument("--forms", default="bf16x3,fp16x3,bf16,fp16",
                     help="M2L precision forms measured beside the headline one "
                          "('' for none)")
@@ -367,6 +398,8 @@ def main() -> int:
     }
     if "accuracy" in r:
         res["accuracy"] = r["accuracy"]
+    if args.leapfrog_steps > 0:
+        res["leapfrog"] = leapfrog_rate(args, x, y, z, m, dev)
     forms = [f for f in args.forms.split(",") if f and f != args.precision]
     if forms and args.method == "fmm":
         res["precision_forms"] = {}

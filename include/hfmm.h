@@ -151,6 +151,29 @@ int hfmm_direct(const double* x, const double* y, const double* z,
                 int precision, double eps2, void* arena, size_t arena_bytes,
                 void* phi, void* ax, void* ay, void* az, void* stream);
 
+/* N-body time stepping (the simulation of the title; the paper names no
+ * integrator, this is kick-drift-kick leapfrog).  Advances x, y, z, vx, vy,
+ * vz (device, FP64, n each, in place) by `steps` steps of length dt under
+ * the field of all the particles evaluated by `method` (HFMM_DIRECT,
+ * HFMM_TREECODE, HFMM_TREECODE_FMMLIST or HFMM_FMM, with p, theta,
+ * precision, eps2 and leaf_max as for hfmm_solve; every evaluation builds a
+ * new tree).  Per step: v += a dt/2; x += v dt; a = field(x); v += a dt/2.
+ * The field at the initial positions is evaluated first, so a call makes
+ * steps + 1 evaluations; on return phi, ax, ay, az (n each, FP64 for
+ * HFMM_FP64, FP32 otherwise) hold the field at the final positions.  The
+ * arena holds the evaluation's space (hfmm_arena_bytes, or
+ * hfmm_direct_bytes for HFMM_DIRECT) plus 48 bytes per particle for the
+ * state of the last completed step.  *done (may be NULL) receives the
+ * steps completed: after HFMM_E_NOMEM the positions and velocities are
+ * those of step *done and hfmm_last_required_bytes() an arena size that
+ * would have sufficed, so the caller can continue with the remaining
+ * steps. */
+int hfmm_leapfrog(double* x, double* y, double* z, double* vx, double* vy,
+                  double* vz, const double* m, int64_t n, double dt, int steps,
+                  int leaf_max, int p, double theta, int method, int precision,
+                  double eps2, void* arena, size_t arena_bytes, void* phi,
+                  void* ax, void* ay, void* az, int* done, void* stream);
+
 /* Release the host handle (the arena belongs to the caller). */
 void hfmm_tree_release(hfmm_tree t);
 

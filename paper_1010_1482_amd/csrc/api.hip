@@ -237,6 +237,8 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
 static thread_local size_t g_last_required = 0;
 static bool g_timing = false;
 
+void set_last_required(size_t bytes) { g_last_required = bytes; }
+
 }  // namespace hfmm
 
 using namespace hfmm;

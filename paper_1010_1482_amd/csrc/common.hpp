@@ -406,6 +406,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
                 hipStream_t s);
 void build_fmm_lists(Tree& t, hipStream_t s);
 void build_bh_lists(Tree& t, double theta, hipStream_t s);
+void set_last_required(size_t bytes);  // for hfmm_last_required_bytes
 void build_fmmlist_treecode_lists(Tree& t, bool fill_far, hipStream_t s);
 void fill_fmmlist_far_items(const Tree& t, int32_t* dst, hipStream_t s);
 constexpr double kFmmListTheta = -2.0;

@@ -27,7 +27,8 @@ MAX_P = 16
 
 # exported symbols, in the order include/hfmm.h declares them
 SYMBOLS = ("hfmm_arena_bytes", "hfmm_build_tree", "hfmm_upward", "hfmm_evaluate",
-           "hfmm_solve", "hfmm_direct_bytes", "hfmm_direct", "hfmm_tree_release",
+           "hfmm_solve", "hfmm_direct_bytes", "hfmm_direct", "hfmm_leapfrog",
+           "hfmm_tree_release",
            "hfmm_required_bytes", "hfmm_last_required_bytes", "hfmm_get_stats",
            "hfmm_strerror", "hfmm_export_perm", "hfmm_export_cells", "hfmm_export_list",
            "hfmm_export_bh_list", "hfmm_export_expansions", "hfmm_set_timing")
@@ -80,6 +81,9 @@ def _lib():
         L.hfmm_direct_bytes.argtypes = [i64, i64, i32, C.POINTER(sz)]
         L.hfmm_direct.argtypes = [_vp, _vp, _vp, _vp, i64, _vp, _vp, _vp, i64, i32, d, _vp,
                                   sz, _vp, _vp, _vp, _vp, _vp]
+        L.hfmm_leapfrog.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, d, i32, i32, i32,
+                                    d, i32, i32, d, _vp, sz, _vp, _vp, _vp, _vp,
+                                    C.POINTER(i32), _vp]
         L.hfmm_tree_release.argtypes = [_vp]
         L.hfmm_tree_release.restype = None
         L.hfmm_required_bytes.argtypes = [_vp]
@@ -302,6 +306,45 @@ def solve(x, y, z, m, p=10, method=FMM, precision=FP32, leaf_max=64, theta=0.5, 
         _check(rc, "hfmm_solve")
         return out
     raise HfmmError(E_NOMEM, "hfmm_solve")
+
+
+def leapfrog(x, y, z, vx, vy, vz, m, dt, steps, p=10, method=FMM, precision=FP32,
+             leaf_max=64, theta=0.5, eps2=0.0, out=None, stream=None):
+    """`steps` kick-drift-kick steps of length dt on the device, positions and
+    velocities (contiguous float64 CUDA tensors) updated in place; returns
+    the field (phi, ax, ay, az) at the final positions.  When the arena
+    turns out too small the library stops at a whole step and the call
+    continues from there with a larger one."""
+    method, precision = _meth(method), _prec(precision)
+    for nm, t in (("x", x), ("y", y), ("z", z), ("vx", vx), ("vy", vy), ("vz", vz),
+                  ("m", m)):
+        _dev(t, nm)
+    n = x.numel()
+    dt_ = out_dtype(precision)
+    if out is None:
+        out = tuple(torch.empty(n, dtype=dt_, device=x.device) for _ in range(4))
+    if method == DIRECT:
+        sz = C.c_size_t(0)
+        _check(_lib().hfmm_direct_bytes(n, 0, precision, C.byref(sz)), "hfmm_direct_bytes")
+        nbytes = sz.value
+    else:
+        nbytes = arena_bytes(n, 0, leaf_max, p, method, precision)
+    nbytes += 48 * n + (2 << 20)
+    left = int(steps)
+    for _ in range(8):
+        ar = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+        done = C.c_int(0)
+        rc = _lib().hfmm_leapfrog(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz),
+                                  _ptr(m), n, float(dt), left, leaf_max, p, float(theta),
+                                  method, precision, float(eps2), _ptr(ar), ar.numel(),
+                                  *[_ptr(o) for o in out], C.byref(done), _stream(stream))
+        if rc == E_NOMEM:
+            left -= done.value
+            nbytes = max(int(_lib().hfmm_last_required_bytes() * 1.25), nbytes * 2)
+            continue
+        _check(rc, "hfmm_leapfrog")
+        return out
+    raise HfmmError(E_NOMEM, "hfmm_leapfrog")
 
 
 def direct(x, y, z, m, precision=FP32, eps2=0.0, targets=None, out=None, stream=None):

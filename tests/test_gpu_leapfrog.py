@@ -1,0 +1,110 @@
+"""GPU time stepping (kick-drift-kick leapfrog around the force evaluation)
+against the oracle leapfrog with the same field: direct sum (FP64), FMM
+(FP64 and FP32) and the treecode over the FMM lists; the closed-form circular
+orbit; and a call whose arena is too small leaving the state untouched."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1010_1482_amd import workloads as W
+from tests.gpu_util import host, need_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    from paper_1010_1482_amd import hfmm
+    hfmm.library()
+
+
+def H():
+    from paper_1010_1482_amd import hfmm
+    return hfmm
+
+
+def _state(n, seed):
+    x, y, z, m = W.plummer(n, seed)
+    rng = np.random.default_rng(seed + 1000)
+    vx, vy, vz = (0.3 * rng.standard_normal(n) for _ in range(3))
+    return x, y, z, vx, vy, vz, m
+
+
+def _run_gpu(st, dt, steps, **kw):
+    x, y, z, vx, vy, vz, m = to_dev(*st)
+    f = H().leapfrog(x, y, z, vx, vy, vz, m, dt, steps, **kw)
+    torch.cuda.synchronize()
+    return host([x, y, z, vx, vy, vz]) + host(f)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("case", ["direct-fp64", "fmm-fp64", "fmm-fp32", "tl-fp64"])
+def test_leapfrog_matches_oracle(case):
+    meth, prec = case.split("-")
+    n, dt, steps, p, leaf = 3000, 2e-3, 4, 10, 16
+    say(f"leapfrog {meth} {prec} n={n} steps={steps}")
+    st = _state(n, 71)
+    method = {"direct": "direct", "fmm": "fmm", "tl": "treecode_fmmlist"}[meth]
+    got = _run_gpu(st, dt, steps, p=p, method=method, precision=prec, leaf_max=leaf)
+    if meth == "direct":
+        field = None
+    elif meth == "fmm":
+        field = lambda x, y, z, m: O.fmm(x, y, z, m, p, leaf)
+    else:
+        field = lambda x, y, z, m: O.treecode(x, y, z, m, p, 0.5, leaf, mode=2)
+    ref = O.leapfrog(*st, dt, steps, field=field)
+    x0, v0 = st[:3], st[3:6]
+    # displacements and velocity changes over the run, relative
+    ex = _rel(np.stack(got[:3]) - np.stack(x0), np.stack(ref[:3]) - np.stack(x0))
+    ev = _rel(np.stack(got[3:6]) - np.stack(v0), np.stack(ref[3:6]) - np.stack(v0))
+    ea = _rel(np.stack(got[7:10]), np.stack(ref[7:10]))
+    say(f"  vs oracle: dx {ex:.2e} dv {ev:.2e} a {ea:.2e}")
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert ex <= tol and ev <= tol and ea <= tol
+
+
+def test_leapfrog_circular_binary_quarter_period():
+    say("leapfrog circular binary, direct fp64")
+    st = (np.array([0.5, -0.5]), np.zeros(2), np.zeros(2), np.zeros(2),
+          np.array([0.5, -0.5]), np.zeros(2), np.array([0.5, 0.5]))
+    k = 2000
+    got = _run_gpu(st, 0.5 * np.pi / k, k, method="direct", precision="fp64")
+    # a quarter turn: body 0 at (0, 1/2) moving at (-1/2, 0)
+    assert np.allclose([got[0][0], got[1][0], got[3][0], got[4][0]], [0.0, 0.5, -0.5, 0.0],
+                       atol=2e-6)
+    # momentum stays zero
+    assert abs(0.5 * got[3][0] + 0.5 * got[3][1]) < 1e-14
+
+
+def test_leapfrog_small_arena_keeps_state_then_continues():
+    say("leapfrog arena too small: state kept, then continued")
+    st = _state(5000, 72)
+    dev = to_dev(*st)
+    x, y, z, vx, vy, vz, m = dev
+    n = x.numel()
+    out = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4)]
+    small = torch.empty(48 * n + (3 << 19), dtype=torch.uint8, device="cuda")
+    done = C.c_int(-1)
+    L = H()._lib()
+    p = lambda t: C.c_void_p(t.data_ptr())
+    rc = L.hfmm_leapfrog(p(x), p(y), p(z), p(vx), p(vy), p(vz), p(m), n, 2e-3, 3, 16, 8, 0.5,
+                         H().FMM, H().FP32, 0.0, p(small), small.numel(), *[p(o) for o in out],
+                         C.byref(done), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert rc == H().E_NOMEM and done.value == 0
+    assert L.hfmm_last_required_bytes() > small.numel()
+    for a, b in zip(host(dev[:6]), st[:6]):
+        assert np.array_equal(a, b)
+    # the binding grows the arena and gives the same result as a fresh run
+    f1 = host(H().leapfrog(x, y, z, vx, vy, vz, m, 2e-3, 3, p=8, method="fmm",
+                           precision="fp32", leaf_max=16))
+    got2 = _run_gpu(st, 2e-3, 3, p=8, method="fmm", precision="fp32", leaf_max=16)
+    for a, b in zip(host(dev[:6]) + f1, got2):
+        assert np.array_equal(a, b)
