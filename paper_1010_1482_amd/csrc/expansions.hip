@@ -423,16 +423,122 @@ __device__ __forceinline__ void m2p_accumulate(const MT* Mc, T ux, T uy, T uz, T
     az += dz * ih2;
 }
 
-// Far field at every particle: L2P of its leaf (Eq. 3 with its gradient,
-// dR_n^m/dz = R_{n-1}^m, (d/dx + i d/dy) R_n^m = R_{n-1}^{m+1}) plus M2P over
-// the leaf's W list.  One thread per sorted particle; MT: FP32 copy of the
-// multipoles for the FP32 path.
-template <typename T, int NP, typename MT>
+// ---------------------------------------------------------------------
+// Far field of one target leaf per wave, any p.  A batch of up to 64 list
+// cells is packed with a ballot: the cell ids and, per cell, the offset from
+// its centre to the leaf's reference point cb in units of its side (formed
+// in FP64) with 1/h.  Their coefficient rows are then staged FB at a time in
+// the wave's LDS slice (the wave copies the rows with 16-byte loads), and
+// lane g * TW + t evaluates cells g, g + G, ... of the slice at target t.
+// ---------------------------------------------------------------------
+template <int NP, typename MT>
+struct FarShape {
+    static constexpr int LD = (NP * NP + 15) / 16 * 16;  // row length of M
+    // rows staged at once: at most 8 KB of coefficients per wave
+    static constexpr int FB = (8192 / (LD * (int)sizeof(MT))) < 16
+                                  ? (8192 / (LD * (int)sizeof(MT)) < 2 ? 2 : 8192 / (LD * (int)sizeof(MT)))
+                                  : 16;
+};
+
+template <typename T, int NP, typename MT, int G>
+__device__ __forceinline__ void farp_batch(bool valid, int k, const double4& cb,
+                                           const double4* __restrict__ cen,
+                                           const MT* __restrict__ M, int32_t* ids,
+                                           typename Vec4<T>::type* offs, MT* rows, T rx, T ry,
+                                           T rz, T& phi, T& ax, T& ay, T& az) {
+    using V = typename Vec4<T>::type;
+    using S = FarShape<NP, MT>;
+    constexpr int TW = 64 / G, Q = S::LD * (int)sizeof(MT) / 16;  // 16-byte chunks per row
+    const int lane = threadIdx.x & 63, g = lane / TW;
+    const uint64_t bal = __ballot(valid);
+    const int nb = __popcll(bal);
+    if (nb == 0) return;  // uniform per wave
+    V o{};
+    if (valid) {
+        const double4 qc = cen[k];
+        o = V{(T)((cb.x - qc.x) * qc.w), (T)((cb.y - qc.y) * qc.w), (T)((cb.z - qc.z) * qc.w),
+              (T)qc.w};
+    }
+    const int pos = __popcll(bal & lanes_below(lane));
+    wave_lds_fence();
+    if (valid) {
+        ids[pos] = k;
+        offs[pos] = o;
+    }
+    wave_lds_fence();
+    for (int sb = 0; sb < nb; sb += S::FB) {
+        const int ns = min(S::FB, nb - sb);
+        // rows of cells sb .. sb + ns, 16 bytes per lane and load
+        for (int c = lane; c < ns * Q; c += 64) {
+            const int i = c / Q, q = c - i * Q;
+            const uint4 v = *((const uint4*)(M + (int64_t)ids[sb + i] * S::LD) + q);
+            *((uint4*)(rows + i * S::LD) + q) = v;
+        }
+        wave_lds_fence();
+        for (int j0 = 0; j0 < ns; j0 += G) {
+            const int j = j0 + g;
+            if (j < ns) {
+                const V d = offs[sb + j];
+                m2p_accumulate<T, NP>(rows + j * S::LD, rx * d.w + d.x, ry * d.w + d.y,
+                                      rz * d.w + d.z, d.w, phi, ax, ay, az);
+            }
+        }
+        wave_lds_fence();
+    }
+}
+
+// The M2P terms of the leaf's list items[e0, e1) (the FMM's W list).
+template <typename T, int NP, typename MT, int G>
+__device__ __forceinline__ void farp_leaf(const Cell& leaf, const double4& cb,
+                                          const double4* __restrict__ cen,
+                                          const double4* __restrict__ p64,
+                                          const int32_t* __restrict__ items, int e0, int e1,
+                                          const MT* __restrict__ M, int32_t* ids,
+                                          typename Vec4<T>::type* offs, MT* rows,
+                                          T* __restrict__ far, int64_t n) {
+    constexpr int TW = 64 / G;
+    const int lane = threadIdx.x & 63, t = lane % TW;
+    for (int c0 = 0; c0 < leaf.count; c0 += TW) {
+        const bool ok = c0 + t < leaf.count;
+        const int64_t s = (int64_t)leaf.first + c0 + t;
+        T rx = T(0), ry = T(0), rz = T(0);
+        if (ok) {
+            const double4 pj = p64[s];
+            rx = (T)(pj.x - cb.x);
+            ry = (T)(pj.y - cb.y);
+            rz = (T)(pj.z - cb.z);
+        }
+        T phi = T(0), ax = T(0), ay = T(0), az = T(0);
+        for (int eb = e0; eb < e1; eb += 64) {
+            const bool v = eb + lane < e1;
+            farp_batch<T, NP, MT, G>(v, v ? items[eb + lane] : 0, cb, cen, M, ids, offs, rows,
+                                     rx, ry, rz, phi, ax, ay, az);
+        }
+#pragma unroll
+        for (int d = TW; d < 64; d <<= 1) {
+            phi += __shfl_xor(phi, d, 64);
+            ax += __shfl_xor(ax, d, 64);
+            ay += __shfl_xor(ay, d, 64);
+            az += __shfl_xor(az, d, 64);
+        }
+        if (ok && lane < TW) {
+            far[s] = phi;
+            far[n + s] = ax;
+            far[2 * n + s] = ay;
+            far[3 * n + s] = az;
+        }
+    }
+}
+
+// L2P at every particle (Eq. 3 with its gradient, dR_n^m/dz = R_{n-1}^m,
+// (d/dx + i d/dy) R_n^m = R_{n-1}^{m+1}) from its leaf's local expansion,
+// one thread per sorted particle; ADD: add to far (the W-list M2P written
+// there first) instead of storing.
+template <typename T, int NP, bool ADD>
 __global__ void __launch_bounds__(256)
-k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict__ cen,
-      const double4* __restrict__ p64, const double* __restrict__ L,
-      const int32_t* __restrict__ w_off, const int32_t* __restrict__ w_items,
-      const MT* __restrict__ M, int ld, T* __restrict__ far) {
+k_l2p(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict__ cen,
+      const double4* __restrict__ p64, const double* __restrict__ L, int ld,
+      T* __restrict__ far) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int b = leaf_of[s];
@@ -464,20 +570,55 @@ k_far(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
     });
     const T ih = (T)ihd, ih2 = ih * ih;
     T phi = f * ih, ax = gr * ih2, ay = gi * ih2, az = gz * ih2;
-    if (w_off) {
-        for (int e = w_off[b]; e < w_off[b + 1]; ++e) {
-            const int C = w_items[e];
-            const double4 qc = cen[C];
-            const double ic = qc.w;
-            m2p_accumulate<T, NP>(M + (int64_t)C * ld, (T)((pj.x - qc.x) * ic),
-                                  (T)((pj.y - qc.y) * ic), (T)((pj.z - qc.z) * ic), (T)ic, phi,
-                                  ax, ay, az);
-        }
+    if (ADD) {
+        phi += far[s];
+        ax += far[n + s];
+        ay += far[2 * n + s];
+        az += far[3 * n + s];
     }
     far[s] = phi;
     far[n + s] = ax;
     far[2 * n + s] = ay;
     far[3 * n + s] = az;
+}
+
+// W-list M2P of the FMM, one wave per target leaf; MT: the multipoles'
+// type (an FP32 copy for the FP32 path).  Short, uneven lists: a wave per
+// leaf replaces the divergent per-particle loops.  (The treecode's long,
+// even lists keep one thread per particle, k_treecode_far: there every lane
+// has a target, while a wave per leaf of ~10 particles leaves lanes idle.)
+template <typename T, int NP, typename MT>
+__global__ void __launch_bounds__(256)
+k_farp(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
+       const double4* __restrict__ cen, const double4* __restrict__ p64,
+       const int32_t* __restrict__ off, const int32_t* __restrict__ items,
+       const MT* __restrict__ M, T* __restrict__ far, int64_t n) {
+    using V = typename Vec4<T>::type;
+    using S = FarShape<NP, MT>;
+    __shared__ int32_t sid[4][64];
+    __shared__ V soff[4][64];
+    __shared__ __align__(16) MT srow[4][S::FB * S::LD];
+    const int w = threadIdx.x >> 6;
+    const int li = blockIdx.x * 4 + w;
+    if (li >= nleaves) return;  // uniform per wave
+    const int b = leaves[li];
+    const Cell leaf = cells[b];
+    const double4 cb = cen[b];
+    const int e0 = off[b], e1 = off[b + 1];
+#define FARP_LEAF(G)                                                                        \
+    farp_leaf<T, NP, MT, G>(leaf, cb, cen, p64, items, e0, e1, M, sid[w], soff[w], srow[w], \
+                            far, n)
+    if (leaf.count <= 4)
+        FARP_LEAF(16);
+    else if (leaf.count <= 8)
+        FARP_LEAF(8);
+    else if (leaf.count <= 16)
+        FARP_LEAF(4);
+    else if (leaf.count <= 32)
+        FARP_LEAF(2);
+    else
+        FARP_LEAF(1);
+#undef FARP_LEAF
 }
 
 // Treecode far field: M2P over the accepted list of the particle's leaf, one
@@ -1084,25 +1225,46 @@ void run_p2l(Tree& t, int p, double* LX, hipStream_t s) {
     LAUNCH_CHECK();
 }
 
+// FP32 copy of the multipoles (same layout) for the FP32 M2P
+static const float* m_as_float(Tree& t, hipStream_t s) {
+    const int64_t nel = (int64_t)t.ncells * t.ldm;
+    float* m = t.arena.down<float>(nel);
+    hipLaunchKernelGGL(k_to_float, dim3(grid_for(nel, 256)), dim3(256), 0, s, t.M, nel, m);
+    LAUNCH_CHECK();
+    return m;
+}
+
+// FMM far field: M2P over the W lists (one wave per target leaf), then L2P
+// added at every particle
 void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
+    if (t.n == 0) return;
     const bool w = t.n_w > 0;
-    const float* M32 = nullptr;
-    if (!fp64 && w) {  // FP32 copy of the multipoles for the W-list M2P
-        const int64_t nel = (int64_t)t.ncells * t.ldm;
-        float* m = t.arena.down<float>(nel);
-        hipLaunchKernelGGL(k_to_float, dim3(grid_for(nel, 256)), dim3(256), 0, s, t.M, nel, m);
-        LAUNCH_CHECK();
-        M32 = m;
+    const float* M32 = (!fp64 && w) ? m_as_float(t, s) : nullptr;
+    const dim3 grid(grid_for(t.nleaves, 4)), block(256), pgrid(grid_for(t.n, 256));
+#define FAR_CASE(NP)                                                                          \
+    if (fp64) {                                                                               \
+        if (w)                                                                                \
+            hipLaunchKernelGGL((k_farp<double, NP, double>), grid, block, 0, s, t.cells,        \
+                               t.leaves, t.nleaves, (const double4*)t.cen, t.p64, t.w_off,     \
+                               t.w_items, t.M, (double*)far, t.n);                             \
+        if (w)                                                                                \
+            hipLaunchKernelGGL((k_l2p<double, NP, true>), pgrid, block, 0, s, t.n, t.leaf_of,  \
+                               (const double4*)t.cen, t.p64, t.L, t.ldm, (double*)far);        \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_l2p<double, NP, false>), pgrid, block, 0, s, t.n, t.leaf_of, \
+                               (const double4*)t.cen, t.p64, t.L, t.ldm, (double*)far);        \
+    } else {                                                                                  \
+        if (w)                                                                                \
+            hipLaunchKernelGGL((k_farp<float, NP, float>), grid, block, 0, s, t.cells,          \
+                               t.leaves, t.nleaves, (const double4*)t.cen, t.p64, t.w_off,     \
+                               t.w_items, M32, (float*)far, t.n);                              \
+        if (w)                                                                                \
+            hipLaunchKernelGGL((k_l2p<float, NP, true>), pgrid, block, 0, s, t.n, t.leaf_of,   \
+                               (const double4*)t.cen, t.p64, t.L, t.ldm, (float*)far);         \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_l2p<float, NP, false>), pgrid, block, 0, s, t.n, t.leaf_of,  \
+                               (const double4*)t.cen, t.p64, t.L, t.ldm, (float*)far);         \
     }
-#define FAR_CASE(NP)                                                                       \
-    if (fp64)                                                                              \
-        hipLaunchKernelGGL((k_far<double, NP, double>), dim3(grid_for(t.n, 256)), dim3(256), \
-                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,         \
-                           w ? t.w_off : nullptr, t.w_items, t.M, t.ldm, (double*)far);     \
-    else                                                                                    \
-        hipLaunchKernelGGL((k_far<float, NP, float>), dim3(grid_for(t.n, 256)), dim3(256),  \
-                           0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64, t.L,         \
-                           w ? t.w_off : nullptr, t.w_items, M32, t.ldm, (float*)far);
     HFMM_DISPATCH_P(p, FAR_CASE);
 #undef FAR_CASE
     LAUNCH_CHECK();
@@ -1144,14 +1306,8 @@ void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
         LAUNCH_CHECK();
         return;
     }
-    const float* M32 = nullptr;
-    if (!fp64) {  // FP32 copy of the multipoles (same layout)
-        const int64_t nel = (int64_t)t.ncells * t.ldm;
-        float* m = t.arena.down<float>(nel);
-        hipLaunchKernelGGL(k_to_float, dim3(grid_for(nel, 256)), dim3(256), 0, s, t.M, nel, m);
-        LAUNCH_CHECK();
-        M32 = m;
-    }
+    // other orders: the spherical form, one thread per particle
+    const float* M32 = fp64 ? nullptr : m_as_float(t, s);
 #define TF_CASE(NP)                                                                           \
     if (fp64)                                                                                 \
         hipLaunchKernelGGL((k_treecode_far<double, NP, double>), dim3(grid_for(t.n, 256)),     \

@@ -51,7 +51,10 @@ extern "C" int hfmm_leapfrog(double* x, double* y, double* z, double* vx, double
     }
     // the saved state (x, y, z, vx, vy, vz) above the evaluation's arena
     const size_t state = Arena::align((size_t)n * 6 * sizeof(double));
-    if (arena_bytes < state + ((size_t)1 << 20)) return HFMM_E_NOMEM;
+    if (arena_bytes < state + ((size_t)1 << 20)) {
+        set_last_required(state + ((size_t)64 << 20));
+        return HFMM_E_NOMEM;
+    }
     const size_t eval_bytes = (arena_bytes - state) / HFMM_ALIGN * HFMM_ALIGN;
     double* keep = (double*)((char*)arena + eval_bytes);
     double* cur[6] = {x, y, z, vx, vy, vz};
