@@ -446,8 +446,12 @@ __device__ inline double dist_point_box(const double p[3], const double lo[3], d
 // else a leaf goes to P2P and an inner node is opened.  Item order within a list is
 // free (sums over a list are order-insensitive up to rounding).  When a push
 // would overflow the LDS stack, each lane finishes its own node's subtree
-// with a private stack (counted, then written at scanned offsets).
-constexpr int kBhCap = 2048;
+// with a private stack (counted, then written at scanned offsets).  The
+// traversal is bound by the latency of its dependent steps, so the stack is
+// sized for occupancy: 1024 entries (5 KB per wave) let 7 blocks share a CU
+// (2048: 3 blocks, 9.4 -> 8.1 ms at N = 2^22 Plummer); at 512 the private
+// stacks take over and it runs 5x slower.
+constexpr int kBhCap = 1024;
 
 // 0: open, 1: accept (M2P), 2: P2P
 __device__ __forceinline__ int bh_class(const Cell& cc, int C, const Cell& B, int b,
