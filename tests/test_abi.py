@@ -57,3 +57,38 @@ def test_host_only_entry_points(lib):
                                C.byref(out)) == hfmm.E_INVAL
     lib.hfmm_get_stats.argtypes = [C.c_void_p, C.c_void_p]
     assert lib.hfmm_get_stats(None, None) == hfmm.E_INVAL
+
+
+def test_new_methods_and_time_loop_host_checks(lib):
+    from paper_1010_1482_amd import hfmm
+    assert hfmm.arena_bytes(1 << 20, 0, 64, 3, hfmm.TREECODE_FMMLIST, hfmm.FP32) > 0
+    with pytest.raises(hfmm.HfmmError) as e:
+        hfmm.arena_bytes(1000, 0, 64, 4, 7, hfmm.FP32)
+    assert e.value.code == hfmm.E_UNSUPPORTED
+    L = hfmm._lib()
+    done = C.c_int(-1)
+    arena = C.c_void_p(1)  # never dereferenced: every call below fails its checks
+    # negative n, negative steps, NaN dt, null arena: rejected before device work
+    for n, steps, dt, ar in ((-1, 1, 1e-3, arena), (10, -1, 1e-3, arena),
+                             (10, 1, float("nan"), arena), (10, 1, 1e-3, None)):
+        rc = L.hfmm_leapfrog(*([None] * 7), n, dt, steps, 64, 4, 0.5, hfmm.FMM, hfmm.FP32,
+                             0.0, ar, 1 << 30, *([None] * 4), C.byref(done), None)
+        assert rc == hfmm.E_INVAL and done.value == 0
+    # n > 0 with null state pointers
+    rc = L.hfmm_leapfrog(*([None] * 7), 10, 1e-3, 1, 64, 4, 0.5, hfmm.FMM, hfmm.FP32, 0.0,
+                         arena, 1 << 30, *([None] * 4), C.byref(done), None)
+    assert rc == hfmm.E_INVAL
+    # n = 0: nothing to do, every step counted
+    rc = L.hfmm_leapfrog(*([None] * 7), 0, 1e-3, 3, 64, 4, 0.5, hfmm.FMM, hfmm.FP32, 0.0,
+                         arena, 1 << 30, *([None] * 4), C.byref(done), None)
+    assert rc == hfmm.OK and done.value == 3
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
