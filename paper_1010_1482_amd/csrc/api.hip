@@ -152,7 +152,7 @@ void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi, void* a
         PhaseTimer pt(t, PH_DOWN, s);
         if (LX) {
             HIP_TRY(hipMemsetAsync(LX, 0, row * t.ncells, s));
-            run_p2l(t, p, LX, s);
+            run_p2l(t, p, fp64, LX, s);
         }
         HIP_TRY(hipMemsetAsync(t.L, 0, row * t.level_start[2], s));
         const bool lowp = mf && precision >= HFMM_M2L_BF16;

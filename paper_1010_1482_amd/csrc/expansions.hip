@@ -304,14 +304,16 @@ __global__ void k_m2m(const Cell* __restrict__ cells, int c0, int c1,
 // (coefficient-major, so the stores of one term are consecutive), then lane
 // k adds coefficient k (and k + 64, ...) over the chunk: no cross-lane
 // reduction, and every lane is busy however few particles a leaf holds.
+// T: the type of the terms (FP32 for the FP32 path, whose chunks then hold
+// twice as many particles in the same LDS; the sums over chunks are FP64).
 // ---------------------------------------------------------------------
-template <int NP, int CH, int RS, int KPL>
+template <typename T, int NP, int CH, int RS, int KPL>
 __device__ __forceinline__ void p2l_cell(const Cell* __restrict__ cells, int b,
                                          const int32_t* __restrict__ x_off,
                                          const int32_t* __restrict__ x_items,
                                          const double4* __restrict__ cen,
                                          const double4* __restrict__ p64,
-                                         double* __restrict__ LX, int ld, double* sh, int* own,
+                                         double* __restrict__ LX, int ld, T* sh, int* own,
                                          int lane) {
     constexpr int P = NP * NP;
     const int e0 = x_off[b], e1 = x_off[b + 1];
@@ -338,13 +340,12 @@ __device__ __forceinline__ void p2l_cell(const Cell* __restrict__ cells, int b,
             wave_lds_fence();
             if (ok) {
                 const double4 pj = p64[f + (pb + lane - fo)];
-                stream_irregular<double, NP>((pj.x - q.x) * ih, (pj.y - q.y) * ih,
-                                             (pj.z - q.z) * ih,
-                                             [&](int n, int m, double re, double im) {
-                                                 sh[ridx(n, m, 0) * RS + lane] = pj.w * re;
-                                                 if (m > 0)
-                                                     sh[ridx(n, m, 1) * RS + lane] = -pj.w * im;
-                                             });
+                const T w = (T)pj.w;
+                stream_irregular<T, NP>((T)((pj.x - q.x) * ih), (T)((pj.y - q.y) * ih),
+                                        (T)((pj.z - q.z) * ih), [&](int n, int m, T re, T im) {
+                                            sh[ridx(n, m, 0) * RS + lane] = w * re;
+                                            if (m > 0) sh[ridx(n, m, 1) * RS + lane] = -w * im;
+                                        });
             }
             wave_lds_fence();
 #pragma unroll
@@ -352,7 +353,7 @@ __device__ __forceinline__ void p2l_cell(const Cell* __restrict__ cells, int b,
                 const int k = lane + 64 * kk;
                 if (k < P) {
                     double a = 0.0;
-                    for (int j = 0; j < nv; ++j) a += sh[k * RS + j];
+                    for (int j = 0; j < nv; ++j) a += (double)sh[k * RS + j];
                     acc[kk] += a;
                 }
             }
@@ -367,20 +368,21 @@ __device__ __forceinline__ void p2l_cell(const Cell* __restrict__ cells, int b,
     wave_lds_fence();  // the next cell reuses sh and own
 }
 
-template <int NP>
+template <typename T, int NP>
 __global__ void __launch_bounds__(64)
 k_p2l(const Cell* __restrict__ cells, const int32_t* __restrict__ x_cells,
       const int32_t* __restrict__ x_off, const int32_t* __restrict__ x_items,
       const double4* __restrict__ cen, const double4* __restrict__ p64,
       double* __restrict__ LX, int ld) {
     constexpr int P = NP * NP;
-    constexpr int CH = 2048 / P < 64 ? 2048 / P : 64;  // particles per chunk (<= 17 KB)
+    constexpr int PER = 16384 / (int)sizeof(T) / P;    // particles per chunk (<= 17 KB)
+    constexpr int CH = PER < 64 ? PER : 64;
     constexpr int RS = CH + 1;                         // LDS row stride (bank spread)
     constexpr int KPL = (P + 63) / 64;                 // coefficients per lane
-    __shared__ double sh[P * RS];
+    __shared__ T sh[P * RS];
     __shared__ int own[64];
-    p2l_cell<NP, CH, RS, KPL>(cells, x_cells[blockIdx.x], x_off, x_items, cen, p64, LX, ld, sh,
-                              own, threadIdx.x);
+    p2l_cell<T, NP, CH, RS, KPL>(cells, x_cells[blockIdx.x], x_off, x_items, cen, p64, LX, ld,
+                                 sh, own, threadIdx.x);
 }
 
 
@@ -1215,11 +1217,17 @@ void run_pack(const double* M, int ldm, int ncells, int P, int ld, void* out, bo
     LAUNCH_CHECK();
 }
 
-void run_p2l(Tree& t, int p, double* LX, hipStream_t s) {
+void run_p2l(Tree& t, int p, bool fp64, double* LX, hipStream_t s) {
     if (t.n_x == 0 || t.n_xcells == 0) return;
-#define P2L_CASE(NP)                                                                        \
-    hipLaunchKernelGGL((k_p2l<NP>), dim3(t.n_xcells), dim3(64), 0, s, t.cells, t.x_cells,  \
-                       t.x_off, t.x_items, (const double4*)t.cen, t.p64, LX, t.ldm);
+#define P2L_CASE(NP)                                                                         \
+    if (fp64)                                                                                \
+        hipLaunchKernelGGL((k_p2l<double, NP>), dim3(t.n_xcells), dim3(64), 0, s, t.cells,   \
+                           t.x_cells, t.x_off, t.x_items, (const double4*)t.cen, t.p64, LX,  \
+                           t.ldm);                                                           \
+    else                                                                                     \
+        hipLaunchKernelGGL((k_p2l<float, NP>), dim3(t.n_xcells), dim3(64), 0, s, t.cells,    \
+                           t.x_cells, t.x_off, t.x_items, (const double4*)t.cen, t.p64, LX,  \
+                           t.ldm);
     HFMM_DISPATCH_P(p, P2L_CASE);
 #undef P2L_CASE
     LAUNCH_CHECK();
