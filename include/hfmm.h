@@ -66,8 +66,9 @@ enum hfmm_method {
 };
 
 /* Arithmetic of the far field.  P2P, P2M, L2P, M2P run in FP32 for every
- * precision but HFMM_FP64; M2M and L2L always run in FP64; the M2L variants
- * differ only in the multipole-to-local product:
+ * precision but HFMM_FP64, and P2L forms its terms in FP32 there (summed in
+ * FP64); M2M and L2L always run in FP64; the M2L variants differ only in the
+ * multipole-to-local product:
  *   HFMM_FP32        FP32 matrix-core products
  *   HFMM_M2L_BF16    BF16 operands, FP32 accumulation
  *   HFMM_M2L_BF16X3  BF16 hi/lo split: hi*hi + hi*lo + lo*hi, FP32 accumulation
