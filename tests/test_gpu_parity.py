@@ -314,6 +314,44 @@ def test_coincident_points():
         assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(b).max())
 
 
+@pytest.mark.parametrize("method,mode,p", [("treecode", 0, 3), ("treecode", 0, 5),
+                                           ("treecode_fmmlist", 2, 3),
+                                           ("treecode_fmmlist", 2, 5)])
+def test_coincident_points_treecodes(method, mode, p):
+    # 297 coincident points make one leaf at the deepest level, far above
+    # leaf_max: the far kernels' loop over target chunks of a leaf
+    say(f"coincident points {method} p={p}")
+    x = np.zeros(300) + 0.5
+    y = np.zeros(300) + 0.5
+    z = np.zeros(300) + 0.5
+    x[:3] = [0.0, 1.0, 0.25]
+    m = np.full(300, 1.0 / 300)
+    ref = O.treecode(x, y, z, m, p, 0.5, 8, mode=mode)
+    out = host(H().solve(*to_dev(x, y, z, m), p=p, method=method, precision="fp64",
+                         leaf_max=8, theta=0.5))
+    # tolerances on the scale of phi and of the whole acceleration (a_z is
+    # zero exactly: every point has z = 1/2)
+    assert np.allclose(out[0], ref[0], rtol=1e-12, atol=1e-12 * np.abs(ref[0]).max())
+    amax = max(np.abs(a).max() for a in ref[1:])
+    for a, b in zip(out[1:], ref[1:]):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * amax)
+    out32 = host(H().solve(*to_dev(x, y, z, m), p=p, method=method, precision="fp32",
+                           leaf_max=8, theta=0.5))
+    ephi, eacc = rel_err(out32, ref)
+    assert ephi < 1e-5 and eacc < 1e-5
+
+
+@pytest.mark.parametrize("method", ["treecode", "treecode_fmmlist"])
+def test_empty_and_single_treecodes(method):
+    say(f"empty and single {method}")
+    x, y, z, m = to_dev(np.zeros(0), np.zeros(0), np.zeros(0), np.zeros(0))
+    out = H().solve(x, y, z, m, p=3, method=method, precision="fp32")
+    assert all(o.numel() == 0 for o in out)
+    x, y, z, m = to_dev([0.5], [0.25], [0.125], [2.0])
+    out = host(H().solve(x, y, z, m, p=3, method=method, precision="fp64"))
+    assert all(o[0] == 0.0 for o in out)
+
+
 # ---------------------------------------------------------------- precision form
 # Tolerances from the arithmetic: an M2L product with both operands rounded to
 # a format of unit roundoff u is off by at most ~2u relative; the hi/lo split
