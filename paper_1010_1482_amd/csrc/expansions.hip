@@ -713,24 +713,25 @@ __device__ __forceinline__ void m2p_cart3(const V& r0, const V& r1, const V& r2,
     az += (dz * ir3 + T(2) * qz * ir5 - uz * sc) * ih2;
 }
 
-// One batch of up to 64 list cells of a target leaf: lane j offers cell k
+// One batch of list cells of a target leaf: lane j (j < B) offers cell k
 // when `valid`; the valid cells are packed at the front of the wave's LDS
 // slice, each as its moments and (r3) the offset from the cell's centre to
 // the leaf's reference point cb in units of the cell side, formed in FP64,
 // with 1/h.  The offset of a target from cell C is then (x - cb) / h_C + r3,
 // one multiply-add per axis from the target's own FP64-formed offset.  Lane
-// g * TW + t takes target t and the packed cells g, g + G, ...; the slots
-// past the batch up to the next multiple of G hold zero moments at unit
-// distance with 1/h = 0, whose terms are exactly zero.
-template <typename T, int G>
+// g * TW + t (g < G) takes target t and the packed cells g, g + G, ...; the
+// slots past the batch up to the next multiple of G (at most B <= 64, a
+// multiple of G) hold zero moments at unit distance with 1/h = 0, whose
+// terms are exactly zero.  Lanes past G * TW compute on clamped slots and
+// are never summed.
+template <typename T>
 __device__ __forceinline__ void far3_batch(bool valid, int k, const double4& cb,
                                            const double4* __restrict__ cen,
                                            const T* __restrict__ C,
-                                           typename Vec4<T>::type* sh, T rx, T ry, T rz,
-                                           T& phi, T& ax, T& ay, T& az) {
+                                           typename Vec4<T>::type* sh, int G, int g, T rx, T ry,
+                                           T rz, T& phi, T& ax, T& ay, T& az) {
     using V = typename Vec4<T>::type;
-    constexpr int TW = 64 / G;
-    const int lane = threadIdx.x & 63, g = lane / TW;
+    const int lane = threadIdx.x & 63;
     const uint64_t bal = __ballot(valid);
     const int nb = __popcll(bal);
     if (nb == 0) return;  // uniform per wave
@@ -763,18 +764,21 @@ __device__ __forceinline__ void far3_batch(bool valid, int k, const double4& cb,
     wave_lds_fence();
 #pragma unroll 2
     for (int j0 = 0; j0 < nr; j0 += G) {
-        const int j = j0 + g;
+        const int j = min(j0 + g, 63);
         const V a = sh[j], b = sh[64 + j], c = sh[128 + j], d = sh[192 + j];
         m2p_cart3<T>(a, b, c, rx * d.w + d.x, ry * d.w + d.y, rz * d.w + d.z, d.w, phi, ax,
                      ay, az);
     }
 }
 
-// The far field of one target leaf, TW targets at a time.  WALK: the M2P
-// cells are read from the FMM lists (W of the leaf from the CSR items, then
-// the V slots of the leaf and of each ancestor, empty slots skipped);
-// otherwise from the leaf's CSR list items[e0, e1).
-template <typename T, int G, bool WALK>
+// The far field of one target leaf.  Lane groups are sized to the leaf:
+// TW = min(count, 64) lanes per group, G = 64 / TW groups (a leaf of 10
+// particles keeps 60 lanes busy where power-of-two groups of 16 kept 40),
+// batches of B = G * (64 / G) cells.  WALK: the M2P cells are read from the
+// FMM lists (W of the leaf from the CSR items, then the V slots of the leaf
+// and of each ancestor, empty slots skipped); otherwise from the leaf's CSR
+// list items[e0, e1).
+template <typename T, bool WALK>
 __device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b, const Cell& leaf,
                                           const double4& cb, const double4* __restrict__ cen,
                                           const double4* __restrict__ p64,
@@ -783,10 +787,12 @@ __device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b,
                                           const T* __restrict__ C,
                                           typename Vec4<T>::type* sh, T* __restrict__ far,
                                           int64_t n) {
-    constexpr int TW = 64 / G;
-    const int lane = threadIdx.x & 63, t = lane % TW;
+    const int lane = threadIdx.x & 63;
+    const int TW = leaf.count < 64 ? leaf.count : 64;
+    const int G = 64 / TW, B = G * (64 / G);
+    const int g = lane / TW, t = lane - g * TW;  // g == G: an idle lane
     for (int c0 = 0; c0 < leaf.count; c0 += TW) {
-        const bool ok = c0 + t < leaf.count;
+        const bool ok = g < G && c0 + t < leaf.count;
         const int64_t s = (int64_t)leaf.first + c0 + t;
         T rx = T(0), ry = T(0), rz = T(0);
         if (ok) {
@@ -796,32 +802,34 @@ __device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b,
             rz = (T)(pj.z - cb.z);
         }
         T phi = T(0), ax = T(0), ay = T(0), az = T(0);
-        for (int eb = e0; eb < e1; eb += 64) {
-            const bool v = eb + lane < e1;
-            far3_batch<T, G>(v, v ? items[eb + lane] : 0, cb, cen, C, sh, rx, ry, rz, phi, ax,
-                             ay, az);
+        for (int eb = e0; eb < e1; eb += B) {
+            const bool v = lane < B && eb + lane < e1;
+            far3_batch<T>(v, v ? items[eb + lane] : 0, cb, cen, C, sh, G, g, rx, ry, rz, phi,
+                          ax, ay, az);
         }
         if (WALK) {
             for (int a = b; a >= 0; a = cells[a].parent) {
                 const int32_t* row = vsrc + (int64_t)a * 216;
-                for (int q0 = 0; q0 < 216; q0 += 64) {
-                    const int k = q0 + lane < 216 ? row[q0 + lane] : -1;
-                    far3_batch<T, G>(k >= 0, k, cb, cen, C, sh, rx, ry, rz, phi, ax, ay, az);
+                for (int q0 = 0; q0 < 216; q0 += B) {
+                    const int k = (lane < B && q0 + lane < 216) ? row[q0 + lane] : -1;
+                    far3_batch<T>(k >= 0, k, cb, cen, C, sh, G, g, rx, ry, rz, phi, ax, ay, az);
                 }
             }
         }
-#pragma unroll
-        for (int d = TW; d < 64; d <<= 1) {
-            phi += __shfl_xor(phi, d, 64);
-            ax += __shfl_xor(ax, d, 64);
-            ay += __shfl_xor(ay, d, 64);
-            az += __shfl_xor(az, d, 64);
+        // group 0 adds the other groups' partial sums of its target
+        T sphi = phi, sax = ax, say = ay, saz = az;
+        for (int h = 1; h < G; ++h) {
+            const int src = h * TW + (t < TW ? t : 0);
+            sphi += __shfl(phi, src, 64);
+            sax += __shfl(ax, src, 64);
+            say += __shfl(ay, src, 64);
+            saz += __shfl(az, src, 64);
         }
-        if (ok && lane < TW) {
-            far[s] = phi;
-            far[n + s] = ax;
-            far[2 * n + s] = ay;
-            far[3 * n + s] = az;
+        if (ok && g == 0) {
+            far[s] = sphi;
+            far[n + s] = sax;
+            far[2 * n + s] = say;
+            far[3 * n + s] = saz;
         }
     }
 }
@@ -844,21 +852,10 @@ k_treecode_far3(const Cell* __restrict__ cells, const int32_t* __restrict__ leav
     if (li >= nleaves) return;  // uniform per wave
     const int b = leaves[li];
     const Cell leaf = cells[b];
+    if (leaf.count <= 0) return;
     const double4 cb = cen[b];
-    const int e0 = off[b], e1 = off[b + 1];
-#define FAR3_LEAF(G)                                                                           \
-    far3_leaf<T, G, WALK>(cells, b, leaf, cb, cen, p64, items, e0, e1, vsrc, C, shm[w], far, n)
-    if (leaf.count <= 4)
-        FAR3_LEAF(16);
-    else if (leaf.count <= 8)
-        FAR3_LEAF(8);
-    else if (leaf.count <= 16)
-        FAR3_LEAF(4);
-    else if (leaf.count <= 32)
-        FAR3_LEAF(2);
-    else
-        FAR3_LEAF(1);
-#undef FAR3_LEAF
+    far3_leaf<T, WALK>(cells, b, leaf, cb, cen, p64, items, off[b], off[b + 1], vsrc, C, shm[w],
+                       far, n);
 }
 
 __global__ void k_to_float(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
