@@ -776,7 +776,8 @@ __device__ __forceinline__ void far3_batch(bool valid, int k, const double4& cb,
 // particles keeps 60 lanes busy where power-of-two groups of 16 kept 40),
 // batches of B = G * (64 / G) cells.  WALK: the M2P cells are read from the
 // FMM lists (W of the leaf from the CSR items, then the V slots of the leaf
-// and of each ancestor, empty slots skipped); otherwise from the leaf's CSR
+// and of each ancestor, the non-empty ones queued in the wave's id ring `q`
+// so that every batch but the last is full); otherwise from the leaf's CSR
 // list items[e0, e1).
 template <typename T, bool WALK>
 __device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b, const Cell& leaf,
@@ -785,8 +786,8 @@ __device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b,
                                           const int32_t* __restrict__ items, int e0, int e1,
                                           const int32_t* __restrict__ vsrc,
                                           const T* __restrict__ C,
-                                          typename Vec4<T>::type* sh, T* __restrict__ far,
-                                          int64_t n) {
+                                          typename Vec4<T>::type* sh, int* q,
+                                          T* __restrict__ far, int64_t n) {
     const int lane = threadIdx.x & 63;
     const int TW = leaf.count < 64 ? leaf.count : 64;
     const int G = 64 / TW, B = G * (64 / G);
@@ -808,12 +809,30 @@ __device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b,
                           ax, ay, az);
         }
         if (WALK) {
+            // ring of 256 ids: at most B - 1 + 64 <= 127 are queued at once
+            const uint64_t below = lanes_below(lane);
+            int head = 0, tail = 0;
             for (int a = b; a >= 0; a = cells[a].parent) {
                 const int32_t* row = vsrc + (int64_t)a * 216;
-                for (int q0 = 0; q0 < 216; q0 += B) {
-                    const int k = (lane < B && q0 + lane < 216) ? row[q0 + lane] : -1;
-                    far3_batch<T>(k >= 0, k, cb, cen, C, sh, G, g, rx, ry, rz, phi, ax, ay, az);
+                for (int q0 = 0; q0 < 216; q0 += 64) {
+                    const int k = q0 + lane < 216 ? row[q0 + lane] : -1;
+                    const uint64_t bal = __ballot(k >= 0);
+                    wave_lds_fence();
+                    if (k >= 0) q[(tail + __popcll(bal & below)) & 255] = k;
+                    tail += __popcll(bal);
+                    wave_lds_fence();
+                    while (tail - head >= B) {
+                        const int kk = q[(head + lane) & 255];
+                        far3_batch<T>(lane < B, kk, cb, cen, C, sh, G, g, rx, ry, rz, phi, ax,
+                                      ay, az);
+                        head += B;
+                    }
                 }
+            }
+            if (tail > head) {
+                const int kk = q[(head + lane) & 255];
+                far3_batch<T>(lane < tail - head, kk, cb, cen, C, sh, G, g, rx, ry, rz, phi, ax,
+                              ay, az);
             }
         }
         // group 0 adds the other groups' partial sums of its target
@@ -847,6 +866,7 @@ k_treecode_far3(const Cell* __restrict__ cells, const int32_t* __restrict__ leav
                 int64_t n) {
     using V = typename Vec4<T>::type;
     __shared__ V shm[4][256];
+    __shared__ int idq[4][WALK ? 256 : 1];
     const int w = threadIdx.x >> 6;
     const int li = blockIdx.x * 4 + w;
     if (li >= nleaves) return;  // uniform per wave
@@ -855,7 +875,7 @@ k_treecode_far3(const Cell* __restrict__ cells, const int32_t* __restrict__ leav
     if (leaf.count <= 0) return;
     const double4 cb = cen[b];
     far3_leaf<T, WALK>(cells, b, leaf, cb, cen, p64, items, off[b], off[b + 1], vsrc, C, shm[w],
-                       far, n);
+                       idq[w], far, n);
 }
 
 __global__ void k_to_float(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
