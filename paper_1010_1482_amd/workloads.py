@@ -42,6 +42,26 @@ def plummer(n: int, seed: int, a: float = 1.0, r_max: float = 20.0):
     return r * sz * np.cos(ph), r * sz * np.sin(ph), r * cz, m
 
 
+def masses(n: int, seed: int, kind: str = "unequal") -> np.ndarray:
+    """Per-particle masses of total |m| = 1.
+
+    * "equal": 1/N each;
+    * "unequal": positive, log-uniform over two decades (ratio up to 100);
+    * "mixed": the same magnitudes with seeded random signs (about half
+      negative), as for charges; the sum of the signed masses is near zero.
+    """
+    if kind == "equal":
+        return np.full(n, 1.0 / max(n, 1))
+    rng = np.random.default_rng(seed)
+    mag = 10.0 ** rng.uniform(-1.0, 1.0, n)
+    mag /= max(mag.sum(), 1e-300)
+    if kind == "unequal":
+        return mag
+    if kind == "mixed":
+        return np.where(rng.random(n) < 0.5, -mag, mag)
+    raise ValueError(f"unknown mass kind {kind!r}")
+
+
 def sample_targets(n: int, k: int, seed: int) -> np.ndarray:
     """k distinct indices in [0, n), sorted."""
     rng = np.random.default_rng(seed)
