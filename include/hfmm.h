@@ -7,9 +7,12 @@
  * (Eq. 1 of Yokota & Barba, "Treecode and fast multipole method for N-body
  * simulation with CUDA", taken per unit target mass with the sign of the
  * single-pair kernel of Sec. 5.1: a_i is the gradient of phi_i).  Pairs at
- * zero separation are skipped; eps2 is added to r^2 as in Sec. 5.1.
+ * zero separation are skipped.  eps2 is added to r^2 as in the P2P kernel of
+ * Sec. 5.1, in the pairs summed directly (P2P, and every pair of
+ * HFMM_DIRECT) only: the far field (M2L, L2L, L2P, M2P, P2L) is the
+ * expansion of the unsoftened 1/r.
  *
- * Methods (Sec. 2, Fig. flow_chart):
+ * Methods (Sec. 2, Fig. 1):
  *   HFMM_DIRECT    all pairs (the P2P kernel of Sec. 5.1 over one source set)
  *   HFMM_TREECODE  Barnes-Hut: P2M, M2M, M2P under the acceptance criterion
  *                  l < theta * d of Sec. 4 (d from the cell's centre of mass to
@@ -105,7 +108,7 @@ enum hfmm_status {
 int hfmm_arena_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p,
                      int method, int precision, size_t* bytes);
 
-/* Build the octree (Sec. 3 "sort" and "other"): FP64 bounding cube and
+/* Build the octree (Sec. 4, "sort" and "other" of Fig. 6): FP64 bounding cube and
  * 63-bit Morton keys, radix sort, cells split while count > leaf_max (and
  * level < 21).  Targets: tx == NULL evaluates at the sources themselves;
  * otherwise the n_tgt target points are added to the tree as zero-mass

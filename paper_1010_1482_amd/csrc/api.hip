@@ -1,5 +1,5 @@
 // C ABI of the hfmm library: argument checks, arena layout and the order of
-// the passes (Sec. 2, Fig. flow_chart):
+// the passes (Sec. 2, Fig. 1):
 //   build:    bbox, keys, sort, cells                       (tree.hip)
 //   upward:   P2M at the leaves, M2M to the root            (expansions.hip)
 //   evaluate: FMM      M2L (+P2L), L2L, L2P (+M2P), P2P     (m2l, expansions, p2p)

@@ -291,6 +291,14 @@ __device__ __forceinline__ int wave_run_owner(int* own, int off, int cnt, int pb
     return o;
 }
 
+// Exponent of the low-precision M2L operand scale of one level; the
+// per-level maxima start at the byte-fill sentinel 0x80808080, which a level
+// without a nonzero coefficient keeps: its scale is then 2^0.
+__device__ __forceinline__ int level_exp(const int32_t* levexp, int level) {
+    const int e = levexp[level];
+    return e == (int32_t)0x80808080 ? 0 : e;
+}
+
 // cell side and centre from the integer coordinates (FP64, no contraction so
 // that host and device agree bit for bit)
 #pragma clang fp contract(off)

@@ -116,17 +116,30 @@ __device__ inline int degree_of(int r) {
     return n;
 }
 
-// largest monopole exponent per level
-// (block maxima in LDS first: one global atomic per block and level)
+// Per level: the largest exponent of the scaled coefficients
+// Mt_k 2^{-mu_n}, over every cell and every coefficient of the level (not
+// only the monopole: with masses of both signs a near-neutral cell has a
+// small M_0 and larger higher-degree terms), so that every packed entry is
+// below 1 in magnitude.  Block maxima in LDS first: one global atomic per
+// block and level.  A level whose coefficients are all zero keeps the
+// sentinel, which level_exp() reads as 0.
 __global__ void k_level_exp(const Cell* __restrict__ cells, int nc, const double* __restrict__ M,
-                            int ldm, int32_t* __restrict__ levexp) {
+                            int ldm, int p, int32_t* __restrict__ levexp) {
     __shared__ int bmax[32];
     if (threadIdx.x < 32) bmax[threadIdx.x] = INT_MIN;
     __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < nc) {
-        const double v = fabs(M[(int64_t)c * ldm]);
-        if (v > 0.0) atomicMax(&bmax[cells[c].level], ilogb(v));
+        const double* row = M + (int64_t)c * ldm;
+        int e = INT_MIN;
+        for (int n = 0; n < p; ++n) {
+            const int mu = mu_exp(n);
+            for (int k = n * n; k < (n + 1) * (n + 1); ++k) {
+                const double v = fabs(row[k]);
+                if (v > 0.0) e = max(e, ilogb(v) - mu);
+            }
+        }
+        if (e != INT_MIN) atomicMax(&bmax[cells[c].level], e);
     }
     __syncthreads();
     if (threadIdx.x < 32 && bmax[threadIdx.x] != INT_MIN)
@@ -142,7 +155,7 @@ __global__ void k_pack_lp(const Cell* __restrict__ cells, const double* __restri
     const int c = (int)(gid / ld), k = (int)(gid % ld);
     double v = 0.0;
     if (c < ncells && k < P) {
-        const int e = levexp[cells[c].level];
+        const int e = level_exp(levexp, cells[c].level);
         v = ldexp(M[(int64_t)c * ldm + k], -mu_exp(degree_of(k)) - (e + 1));
     }
     const T16 h = (T16)(float)v;
@@ -962,7 +975,7 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     tm.emplace(t, PH_M2L_PREP, s);
     HIP_TRY(hipMemsetAsync(levexp, 0x80, 32 * sizeof(int32_t), s));
     hipLaunchKernelGGL(k_level_exp, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s, t.cells,
-                       t.ncells, t.M, t.ldm, levexp);
+                       t.ncells, t.M, t.ldm, p, levexp);
     LAUNCH_CHECK();
     const size_t nel = (size_t)(t.ncells + 1) * ld;
     const size_t half = (size_t)343 * RB * KQ * 64 * 8;

@@ -2,7 +2,7 @@
 // stable LSD radix sort, and level-by-level cell splitting.
 //
 // The paper sorts particles and builds the tree and lists on the host
-// (Sec. 4, "sort" and "other" in Fig. breakdown); here every step is a
+// (Sec. 4, "sort" and "other" in Fig. 6); here every step is a
 // kernel, so the only host work is reading back the cell count per level.
 #include "common.hpp"
 

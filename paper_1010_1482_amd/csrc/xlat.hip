@@ -257,7 +257,7 @@ k_l2l_f64(const Cell* __restrict__ cells, const int32_t* __restrict__ targets, i
     // block, in 4 chunks of RB; the partial results are read four parts at
     // a time with every load of a batch in flight (the loads are not
     // predicated: a missing part or element re-reads a valid address)
-    const int sc_lev = bexp ? levexp[level] + 2 : 0;
+    const int sc_lev = bexp ? level_exp(levexp, level) + 2 : 0;
 #pragma unroll
     for (int ch = 0; ch < 4; ++ch) {
         int64_t off[RB];

@@ -1,6 +1,7 @@
 """GPU time stepping (kick-drift-kick leapfrog around the force evaluation)
 against the oracle leapfrog with the same field: direct sum (FP64), FMM
-(FP64 and FP32) and the treecode over the FMM lists; the closed-form circular
+(FP64 and FP32), the Barnes-Hut treecode and the treecode over the FMM
+lists; the closed-form circular
 orbit; and a call whose arena is too small leaving the state untouched."""
 import ctypes as C
 
@@ -45,18 +46,27 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("case", ["direct-fp64", "fmm-fp64", "fmm-fp32", "tl-fp64"])
+@pytest.mark.parametrize("case", ["direct-fp64", "fmm-fp64", "fmm-fp32", "tl-fp64",
+                                  "bh-fp64", "bh-fp32"])
 def test_leapfrog_matches_oracle(case):
     meth, prec = case.split("-")
     n, dt, steps, p, leaf = 3000, 2e-3, 4, 10, 16
     say(f"leapfrog {meth} {prec} n={n} steps={steps}")
     st = _state(n, 71)
-    method = {"direct": "direct", "fmm": "fmm", "tl": "treecode_fmmlist"}[meth]
-    got = _run_gpu(st, dt, steps, p=p, method=method, precision=prec, leaf_max=leaf)
+    if meth == "bh":  # centres of mass that move with unequal masses
+        st = st[:6] + (W.masses(n, 171, "unequal"),)
+    method = {"direct": "direct", "fmm": "fmm", "tl": "treecode_fmmlist",
+              "bh": "treecode"}[meth]
+    if meth == "bh":
+        p = 4
+    got = _run_gpu(st, dt, steps, p=p, method=method, precision=prec, leaf_max=leaf,
+                   theta=0.5)
     if meth == "direct":
         field = None
     elif meth == "fmm":
         field = lambda x, y, z, m: O.fmm(x, y, z, m, p, leaf)
+    elif meth == "bh":
+        field = lambda x, y, z, m: O.treecode(x, y, z, m, p, 0.5, leaf, mode=0)
     else:
         field = lambda x, y, z, m: O.treecode(x, y, z, m, p, 0.5, leaf, mode=2)
     ref = O.leapfrog(*st, dt, steps, field=field)
