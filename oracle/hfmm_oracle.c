@@ -1239,3 +1239,353 @@ int oracle_treecode(int64_t n, const double* x, const double* y,
     oracle_tree_free(t);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* separate targets, binned into the source tree                       */
+/* ------------------------------------------------------------------ */
+
+/* The box a target point is binned into.  The point's key prefix is
+ * followed down the source tree as far as cells exist:
+ *   kind 0: it ends in a leaf L: the box is L (host = leaf = L);
+ *   kind 1: it ends in a split cell H whose octant holding the point is
+ *           empty: the box is that octant, a source-free leaf child of H
+ *           (host = H, leaf = -1);
+ *   kind 2: the point lies outside the root cube: the box is the
+ *           root-sized cube of the grid extended beyond the root that holds
+ *           it, at level 0 (host = leaf = -1; coordinates clamped to
+ *           +-2^20 root widths, far beyond any adjacency).
+ * A box of kind 1 or 2 is a leaf without sources added to the tree; the
+ * lists the adaptive FMM defines for a leaf (Cheng, Greengard and Rokhlin,
+ * cited in Sec. 6) are defined for it alike. */
+typedef struct {
+    int kind, level, host, leaf;
+    int64_t q[3];
+} obox;
+
+static int adj_g(int la, const int64_t a[3], int lb, const int64_t b[3]) {
+    if (la > lb) {
+        const int64_t* s = a;
+        a = b;
+        b = s;
+        int l = la;
+        la = lb;
+        lb = l;
+    }
+    int64_t f = (int64_t)1 << (lb - la);
+    for (int k = 0; k < 3; k++) {
+        if (b[k] > (a[k] + 1) * f) return 0;
+        if (b[k] + 1 < a[k] * f) return 0;
+    }
+    return 1;
+}
+
+static void cell_q(const ocell* c, int64_t q[3]) {
+    q[0] = c->ix;
+    q[1] = c->iy;
+    q[2] = c->iz;
+}
+
+static int adj_box_cell(const otree* t, const obox* B, int C) {
+    int64_t q[3];
+    cell_q(&t->c[C], q);
+    return adj_g(B->level, B->q, t->c[C].level, q);
+}
+
+static obox bin_target(const otree* t, const double xt[3]) {
+    const double s = (double)(1 << KBITS) / (2.0 * t->R);
+    const double top = (double)(1 << KBITS);
+    double f[3];
+    int outside = 0;
+    for (int a = 0; a < 3; a++) {
+        f[a] = floor((xt[a] - t->b[a]) * s);
+        /* the upper face belongs to the cube, as for the sources' keys */
+        if (!(f[a] >= 0.0 && f[a] <= top)) outside = 1;
+    }
+    obox B;
+    if (outside) {
+        B.kind = 2;
+        B.level = 0;
+        B.host = B.leaf = -1;
+        for (int a = 0; a < 3; a++) {
+            double c = floor(f[a] / top);
+            if (c > 1048576.0) c = 1048576.0;
+            if (c < -1048576.0) c = -1048576.0;
+            B.q[a] = (int64_t)c;
+        }
+        return B;
+    }
+    int64_t qf[3];
+    for (int a = 0; a < 3; a++) qf[a] = f[a] > top - 1.0 ? (1 << KBITS) - 1 : (int64_t)f[a];
+    int C = 0;
+    for (;;) {
+        const ocell* c = &t->c[C];
+        if (is_leaf(c)) {
+            B.kind = 0;
+            B.level = c->level;
+            B.host = B.leaf = C;
+            cell_q(c, B.q);
+            return B;
+        }
+        const int lev = c->level + 1;
+        int64_t q[3];
+        for (int a = 0; a < 3; a++) q[a] = qf[a] >> (KBITS - lev);
+        int next = -1;
+        for (int k = 0; k < c->nchild; k++) {
+            const ocell* d = &t->c[c->first_child + k];
+            if (d->ix == q[0] && d->iy == q[1] && d->iz == q[2]) next = c->first_child + k;
+        }
+        if (next < 0) {
+            B.kind = 1;
+            B.level = lev;
+            B.host = C;
+            B.leaf = -1;
+            for (int a = 0; a < 3; a++) B.q[a] = q[a];
+            return B;
+        }
+        C = next;
+    }
+}
+
+/* The parent cell of a box (-1 for the root and for boxes outside it). */
+static int box_parent(const otree* t, const obox* B) {
+    if (B->kind == 0) return t->c[B->leaf].parent;
+    return B->kind == 1 ? B->host : -1;
+}
+
+/* Is cell C the box itself or one of its ancestors? */
+static int box_within(const otree* t, const obox* B, int C) {
+    int A = B->kind == 0 ? B->leaf : B->host;
+    for (; A >= 0; A = t->c[A].parent)
+        if (A == C) return 1;
+    return 0;
+}
+
+/* The four lists of box B, straight from their definitions, over every
+ * cell:
+ *   U: leaves adjacent to B (B included when it is a leaf of the tree);
+ *   V: cells of B's level, not adjacent to B, whose parents are adjacent to
+ *      B's parent (outside the root: the root when not adjacent to B);
+ *   W: cells C finer than B, not adjacent to B, whose parent is adjacent to
+ *      B, below a cell of B's level adjacent to B (other than B);
+ *   X: leaves C coarser than B, not adjacent to B but adjacent to B's
+ *      parent, whose cell at C's level on B's ancestor line is adjacent to
+ *      C (and not C): the cells with B in their W list. */
+static void box_lists(const otree* t, const obox* B, ivec L[4]) {
+    const int P = box_parent(t, B);
+    for (int C = 0; C < (int)t->ncells; C++) {
+        const ocell* cc = &t->c[C];
+        const int adj = adj_box_cell(t, B, C);
+        if (is_leaf(cc) && adj) ivec_push(&L[0], C);
+        if (cc->level == B->level && !adj) {
+            if (B->kind == 2 ? C == 0
+                             : (P >= 0 && cc->parent >= 0 && adjacent(&t->c[cc->parent], &t->c[P])))
+                ivec_push(&L[1], C);
+        }
+        if (cc->level > B->level && !adj && adj_box_cell(t, B, cc->parent)) {
+            int A = ancestor_at(t, C, B->level);
+            if (A != B->leaf && adj_box_cell(t, B, A)) ivec_push(&L[2], C);
+        }
+        if (is_leaf(cc) && cc->level < B->level && !adj && P >= 0 && adjacent(cc, &t->c[P])) {
+            int A = ancestor_at(t, B->kind == 0 ? B->leaf : B->host, cc->level);
+            if (A != C && adjacent(&t->c[A], cc)) ivec_push(&L[3], C);
+        }
+    }
+}
+
+void oracle_target_boxes(otree* t, int64_t nt, const double* tx, const double* ty,
+                         const double* tz, int64_t* out) {
+    for (int64_t k = 0; k < nt; k++) {
+        double xt[3] = {tx[k], ty[k], tz[k]};
+        obox B = bin_target(t, xt);
+        int64_t* o = out + 7 * k;
+        o[0] = B.kind;
+        o[1] = B.level;
+        o[2] = B.q[0];
+        o[3] = B.q[1];
+        o[4] = B.q[2];
+        o[5] = B.host;
+        o[6] = B.leaf;
+    }
+}
+
+int64_t oracle_box_list(otree* t, const double xt[3], int which, int32_t* items) {
+    obox B = bin_target(t, xt);
+    ivec L[4] = {{0}, {0}, {0}, {0}};
+    box_lists(t, &B, L);
+    int64_t n = L[which].n;
+    if (items && n) memcpy(items, L[which].v, sizeof(int32_t) * n);
+    for (int w = 0; w < 4; w++) free(L[w].v);
+    return n;
+}
+
+static void m2p_cells(const otree* t, const double* cen, const cplx* M, int p, const ivec* l,
+                      const double xt[3], double acc[4]) {
+    const int64_t pp = (int64_t)p * p;
+    double o[4];
+    for (int64_t q = 0; q < l->n; q++) {
+        int C = l->v[q];
+        oracle_m2p(p, &cen[3 * C], (const double*)(M + C * pp), xt, o);
+        for (int a = 0; a < 4; a++) acc[a] += o[a];
+    }
+}
+
+static void p2p_cells(const otree* t, const double* ms, double eps2, const ivec* l,
+                      const double xt[3], double acc[4]) {
+    for (int64_t q = 0; q < l->n; q++) {
+        const ocell* c = &t->c[l->v[q]];
+        p2p_point(xt, c->first, c->first + c->count, t->xs, t->ys, t->zs, ms, eps2, acc);
+    }
+}
+
+/* FMM at separate target points.  For a target in box B with host H (the
+ * cell whose local expansion covers B):
+ *   phi = L2P(L(H)) + M2P over W(B) + P2P over U(B)          (B a leaf),
+ * and for a box without sources, which has no local expansion of its own,
+ * its V list by M2P and its X list by P2P as well, at the target itself:
+ *   phi = L2P(L(H)) + M2P over V(B), W(B) + P2P over U(B), X(B)
+ * (no L2P outside the root).  Every source is reached once. */
+int oracle_fmm_points(int64_t n, const double* x, const double* y, const double* z,
+                      const double* m, int leaf_max, int p, double eps2, int64_t nt,
+                      const double* tx, const double* ty, const double* tz, double* phi,
+                      double* ax, double* ay, double* az) {
+    if (nt == 0) return 0;
+    if (n == 0) {
+        for (int64_t k = 0; k < nt; k++) phi[k] = ax[k] = ay[k] = az[k] = 0.0;
+        return 0;
+    }
+    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+    build_lists(t);
+    const int64_t nc = t->ncells, pp = (int64_t)p * p;
+    double* ms = sorted_masses(t, m);
+    double* cen = geometric_centres(t);
+    cplx* M = (cplx*)malloc(sizeof(cplx) * nc * pp);
+    cplx* L = (cplx*)malloc(sizeof(cplx) * nc * pp);
+    upward(t, ms, p, cen, M);
+    downward(t, ms, p, cen, M, L, NULL);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; k++) {
+        double xt[3] = {tx[k], ty[k], tz[k]};
+        obox B = bin_target(t, xt);
+        ivec l[4] = {{0}, {0}, {0}, {0}};
+        box_lists(t, &B, l);
+        double acc[4] = {0, 0, 0, 0}, o[4];
+        if (B.host >= 0) {
+            oracle_l2p(p, &cen[3 * B.host], (const double*)(L + B.host * pp), xt, o);
+            for (int a = 0; a < 4; a++) acc[a] += o[a];
+        }
+        m2p_cells(t, cen, M, p, &l[2], xt, acc);
+        p2p_cells(t, ms, eps2, &l[0], xt, acc);
+        if (B.kind != 0) {
+            m2p_cells(t, cen, M, p, &l[1], xt, acc);
+            p2p_cells(t, ms, eps2, &l[3], xt, acc);
+        }
+        for (int w = 0; w < 4; w++) free(l[w].v);
+        phi[k] = acc[0];
+        ax[k] = acc[1];
+        ay[k] = acc[2];
+        az[k] = acc[3];
+    }
+    free(M);
+    free(L);
+    free(cen);
+    free(ms);
+    oracle_tree_free(t);
+    return 0;
+}
+
+/* Barnes-Hut traversal for a target box (the group acceptance of mode 0):
+ * cells containing the box are opened, the box's own leaf goes to P2P, other
+ * cells are accepted when l < theta d (d from the centre of mass to the
+ * box), else a leaf goes to P2P and a split cell is opened. */
+static void bh_box(const otree* t, const double* com, double theta, const obox* B, int C,
+                   ivec* acc, ivec* near) {
+    const ocell* cc = &t->c[C];
+    if (box_within(t, B, C)) {
+        if (C == B->leaf) {
+            ivec_push(near, C);
+            return;
+        }
+        for (int k = 0; k < cc->nchild; k++)
+            bh_box(t, com, theta, B, cc->first_child + k, acc, near);
+        return;
+    }
+    const double hb = cell_side(t, 0) / (double)((int64_t)1 << B->level);
+    double lo[3];
+    for (int a = 0; a < 3; a++) lo[a] = t->b[a] + (double)B->q[a] * hb;
+    double d = dist_point_box(&com[3 * C], lo, hb);
+    if (cell_side(t, cc->level) < theta * d) {
+        ivec_push(acc, C);
+    } else if (is_leaf(cc)) {
+        ivec_push(near, C);
+    } else {
+        for (int k = 0; k < cc->nchild; k++)
+            bh_box(t, com, theta, B, cc->first_child + k, acc, near);
+    }
+}
+
+/* Treecode at separate target points: mode 0, Barnes-Hut group lists of the
+ * target's box about the centres of mass; mode 2, the treecode of Sec. 4
+ * over the FMM lists of the box: M2P over V and W of the box and V of each
+ * ancestor, P2P over U and X of the box and X of each ancestor (expansions
+ * about the geometric centres). */
+int oracle_treecode_points(int64_t n, const double* x, const double* y, const double* z,
+                           const double* m, int leaf_max, int p, double theta, int mode,
+                           double eps2, int64_t nt, const double* tx, const double* ty,
+                           const double* tz, double* phi, double* ax, double* ay,
+                           double* az) {
+    if (nt == 0) return 0;
+    if (mode != 0 && mode != 2) return -1;
+    if (n == 0) {
+        for (int64_t k = 0; k < nt; k++) phi[k] = ax[k] = ay[k] = az[k] = 0.0;
+        return 0;
+    }
+    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+    const int64_t nc = t->ncells, pp = (int64_t)p * p;
+    double* ms = sorted_masses(t, m);
+    double* cen = mode == 2 ? geometric_centres(t) : com_array(t, m);
+    cplx* M = (cplx*)malloc(sizeof(cplx) * nc * pp);
+    if (mode == 2) build_lists(t);
+    upward(t, ms, p, cen, M);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nt; k++) {
+        double xt[3] = {tx[k], ty[k], tz[k]};
+        obox B = bin_target(t, xt);
+        double acc[4] = {0, 0, 0, 0};
+        if (mode == 0) {
+            ivec a = {0}, b = {0};
+            bh_box(t, cen, theta, &B, 0, &a, &b);
+            m2p_cells(t, cen, M, p, &a, xt, acc);
+            p2p_cells(t, ms, eps2, &b, xt, acc);
+            free(a.v);
+            free(b.v);
+        } else {
+            ivec l[4] = {{0}, {0}, {0}, {0}};
+            box_lists(t, &B, l);
+            ivec far = {0}, near = {0};
+            for (int64_t q = 0; q < l[1].n; q++) ivec_push(&far, l[1].v[q]);
+            for (int64_t q = 0; q < l[2].n; q++) ivec_push(&far, l[2].v[q]);
+            for (int64_t q = 0; q < l[0].n; q++) ivec_push(&near, l[0].v[q]);
+            for (int64_t q = 0; q < l[3].n; q++) ivec_push(&near, l[3].v[q]);
+            for (int A = box_parent(t, &B); A >= 0; A = t->c[A].parent) {
+                for (int64_t q = t->loff[1][A]; q < t->loff[1][A + 1]; q++)
+                    ivec_push(&far, t->litem[1][q]);
+                for (int64_t q = t->loff[3][A]; q < t->loff[3][A + 1]; q++)
+                    ivec_push(&near, t->litem[3][q]);
+            }
+            m2p_cells(t, cen, M, p, &far, xt, acc);
+            p2p_cells(t, ms, eps2, &near, xt, acc);
+            for (int w = 0; w < 4; w++) free(l[w].v);
+            free(far.v);
+            free(near.v);
+        }
+        phi[k] = acc[0];
+        ax[k] = acc[1];
+        ay[k] = acc[2];
+        az[k] = acc[3];
+    }
+    free(M);
+    free(cen);
+    free(ms);
+    oracle_tree_free(t);
+    return 0;
+}

@@ -128,6 +128,30 @@ int oracle_treecode(int64_t n, const double* x, const double* y,
                     const int64_t* tidx, double* phi, double* ax, double* ay,
                     double* az);
 
+/* ---- separate targets, binned into the source tree ---- */
+/* Per target point: kind (0 a leaf of the tree, 1 an empty octant of a
+ * split cell, 2 outside the root cube), level, ix, iy, iz of its box, host
+ * (the cell whose local expansion covers the box, -1 none) and leaf (the
+ * box's cell when kind 0, else -1): 7 int64 per target. */
+void oracle_target_boxes(otree* t, int64_t nt, const double* tx,
+                         const double* ty, const double* tz, int64_t* out);
+/* List `which` (0 U, 1 V, 2 W, 3 X) of the box of point xt, from the
+ * definitions; returns its length (items may be NULL). */
+int64_t oracle_box_list(otree* t, const double xt[3], int which,
+                        int32_t* items);
+/* FMM and treecode (mode 0 or 2) at separate target points. */
+int oracle_fmm_points(int64_t n, const double* x, const double* y,
+                      const double* z, const double* m, int leaf_max, int p,
+                      double eps2, int64_t nt, const double* tx,
+                      const double* ty, const double* tz, double* phi,
+                      double* ax, double* ay, double* az);
+int oracle_treecode_points(int64_t n, const double* x, const double* y,
+                           const double* z, const double* m, int leaf_max,
+                           int p, double theta, int mode, double eps2,
+                           int64_t nt, const double* tx, const double* ty,
+                           const double* tz, double* phi, double* ax,
+                           double* ay, double* az);
+
 /* Threads OpenMP will use (1 when built without OpenMP). */
 int oracle_num_threads(void);
 

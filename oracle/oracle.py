@@ -60,6 +60,9 @@ def lib():
         L.oracle_list_size_bruteforce.argtypes = [C.c_void_p, C.c_int]
         L.oracle_bh_lists.restype = C.c_int64
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_box_list.restype = C.c_int64
+        L.oracle_box_list.argtypes = [C.c_void_p, _dp, C.c_int, _i32p]
+        L.oracle_target_boxes.argtypes = [C.c_void_p, C.c_int64, _dp, _dp, _dp, _i64p]
         _lib = L
     return _lib
 
@@ -282,6 +285,24 @@ class Tree:
                               items.ctypes.data_as(_i32p))
         return off, items[:tot]
 
+    def target_boxes(self, tx, ty, tz):
+        """Per target point: (kind, level, ix, iy, iz, host, leaf) of the box
+        it is binned into (kind 0 leaf, 1 empty octant, 2 outside the root)."""
+        tx, ty, tz = map(_f64, (tx, ty, tz))
+        out = np.zeros((len(tx), 7), dtype=np.int64)
+        lib().oracle_target_boxes(C.c_void_p(self.h), C.c_int64(len(tx)), _d(tx), _d(ty),
+                                  _d(tz), out.ctypes.data_as(_i64p))
+        return out
+
+    def box_list(self, point, which):
+        """List U/V/W/X (0..3) of the box of one target point (cell ids)."""
+        pt = (C.c_double * 3)(*[float(v) for v in point])
+        h = C.c_void_p(self.h)
+        n = lib().oracle_box_list(h, pt, C.c_int(which), None)
+        items = np.zeros(max(n, 1), dtype=np.int32)
+        lib().oracle_box_list(h, pt, C.c_int(which), items.ctypes.data_as(_i32p))
+        return items[:n]
+
     def fmm_expansions(self, m, p):
         m = _f64(m)
         nc = self.ncells
@@ -329,6 +350,31 @@ def treecode(x, y, z, m, p, theta, leaf_max, targets=None, mode=0, eps2=0.0):
                           C.c_int(mode), C.c_double(eps2), C.c_int64(nt),
                           None if tg is None else tg.ctypes.data_as(_i64p),
                           *[_d(o) for o in out])
+    return tuple(out)
+
+
+def fmm_points(x, y, z, m, p, leaf_max, tx, ty, tz, eps2=0.0):
+    """Oracle FMM at separate target points binned into the source tree."""
+    x, y, z, m, tx, ty, tz = map(_f64, (x, y, z, m, tx, ty, tz))
+    out = [np.zeros(len(tx)) for _ in range(4)]
+    lib().oracle_fmm_points(C.c_int64(len(x)), _d(x), _d(y), _d(z), _d(m),
+                            C.c_int(leaf_max), C.c_int(p), C.c_double(eps2),
+                            C.c_int64(len(tx)), _d(tx), _d(ty), _d(tz),
+                            *[_d(o) for o in out])
+    return tuple(out)
+
+
+def treecode_points(x, y, z, m, p, theta, leaf_max, tx, ty, tz, mode=0, eps2=0.0):
+    """Oracle treecode (mode 0 Barnes-Hut group lists, mode 2 the FMM lists)
+    at separate target points binned into the source tree."""
+    if mode not in (0, 2):
+        raise ValueError("mode 0 or 2")
+    x, y, z, m, tx, ty, tz = map(_f64, (x, y, z, m, tx, ty, tz))
+    out = [np.zeros(len(tx)) for _ in range(4)]
+    lib().oracle_treecode_points(C.c_int64(len(x)), _d(x), _d(y), _d(z), _d(m),
+                                 C.c_int(leaf_max), C.c_int(p), C.c_double(theta),
+                                 C.c_int(mode), C.c_double(eps2), C.c_int64(len(tx)),
+                                 _d(tx), _d(ty), _d(tz), *[_d(o) for o in out])
     return tuple(out)
 
 
