@@ -155,6 +155,27 @@ int hfmm_direct(const double* x, const double* y, const double* z,
                 int precision, double eps2, void* arena, size_t arena_bytes,
                 void* phi, void* ax, void* ay, void* az, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the direct
+ * sum of hfmm_direct with its staging records in a device array of the
+ * library instead of a caller arena.  The array holds HFMM_SCRATCH_BYTES on
+ * every GPU the library runs on, from the load of the library until the
+ * process ends; its device address is looked up on the first call on each
+ * device.  Same arguments (minus the arena), results and errors as
+ * hfmm_direct; HFMM_E_NOMEM, before any device work, when
+ * hfmm_direct_bytes() of the job exceeds HFMM_SCRATCH_BYTES (2^21 FP64 or
+ * 2^22 FP32 points, sources plus distinct targets, less a little alignment).
+ * No device memory is allocated or freed.  All calls on one GPU share its
+ * array, and nothing in it needs to start at zero: calls that overlap on one
+ * GPU (different streams or threads) race and give wrong results, so the
+ * caller serialises them. */
+#define HFMM_SCRATCH_BYTES (64u << 20)
+int hfmm_direct_noalloc(const double* x, const double* y, const double* z,
+                        const double* m, int64_t n_src, const double* tx,
+                        const double* ty, const double* tz, int64_t n_tgt,
+                        int precision, double eps2, void* phi, void* ax,
+                        void* ay, void* az, void* stream);
+
 /* N-body time stepping (the simulation of the title; the paper names no
  * integrator, this is kick-drift-kick leapfrog).  Advances x, y, z, vx, vy,
  * vz (device, FP64, n each, in place) by `steps` steps of length dt under

@@ -27,7 +27,8 @@ MAX_P = 16
 
 # exported symbols, in the order include/hfmm.h declares them
 SYMBOLS = ("hfmm_arena_bytes", "hfmm_build_tree", "hfmm_upward", "hfmm_evaluate",
-           "hfmm_solve", "hfmm_direct_bytes", "hfmm_direct", "hfmm_leapfrog",
+           "hfmm_solve", "hfmm_direct_bytes", "hfmm_direct", "hfmm_direct_noalloc",
+           "hfmm_leapfrog",
            "hfmm_tree_release",
            "hfmm_required_bytes", "hfmm_last_required_bytes", "hfmm_get_stats",
            "hfmm_strerror", "hfmm_export_perm", "hfmm_export_cells", "hfmm_export_list",
@@ -81,6 +82,8 @@ def _lib():
         L.hfmm_direct_bytes.argtypes = [i64, i64, i32, C.POINTER(sz)]
         L.hfmm_direct.argtypes = [_vp, _vp, _vp, _vp, i64, _vp, _vp, _vp, i64, i32, d, _vp,
                                   sz, _vp, _vp, _vp, _vp, _vp]
+        L.hfmm_direct_noalloc.argtypes = [_vp, _vp, _vp, _vp, i64, _vp, _vp, _vp, i64, i32, d,
+                                          _vp, _vp, _vp, _vp, _vp]
         L.hfmm_leapfrog.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, d, i32, i32, i32,
                                     d, i32, i32, d, _vp, sz, _vp, _vp, _vp, _vp,
                                     C.POINTER(i32), _vp]
