@@ -30,14 +30,25 @@
  *                  of theta = 2/3; theta is not used)
  * p is the number of expansion terms: degrees n = 0..p-1 (Eq. 4).
  *
- * Memory and streams.  Every pointer argument named x, y, z, m, phi, ax, ay,
- * az, arena or dst is a DEVICE pointer.  The caller allocates all device
- * memory: inputs, outputs and one arena per tree; the library never
- * allocates device memory.  Every call enqueues its work on `stream` (a
- * hipStream_t passed as void*); build and evaluate also synchronise that
- * stream for small size read-backs, other streams are never touched.  A tree
- * handle is used by one stream at a time; different handles are independent
- * and may run concurrently on different streams.
+ * Targets.  A tree is built over the sources only.  An evaluation is at the
+ * sources themselves (tx == NULL) or at separate target points, each binned
+ * into the resident tree: its key is followed down the tree to a leaf (the
+ * target is evaluated as that leaf's particles are), to an empty octant of
+ * a split cell (a source-free leaf added to the tree: L2P of the split
+ * cell's local expansion, M2P over the octant's V and W lists and P2P over
+ * its U and X lists, the adaptive lists of Cheng, Greengard and Rokhlin that
+ * Sec. 6 cites), or it lies outside the root cube (a root-sized cube of the
+ * extended grid, no local expansion).  One tree may be evaluated at any
+ * number of target sets.
+ *
+ * Memory and streams.  Every pointer argument named x, y, z, tx, ty, tz, m,
+ * phi, ax, ay, az, arena, off, items or dst is a DEVICE pointer.  The caller
+ * allocates all device memory: inputs, outputs and one arena per tree; the
+ * library never allocates device memory.  Every call enqueues its work on
+ * `stream` (a hipStream_t passed as void*); build and evaluate also
+ * synchronise that stream for small size read-backs, other streams are
+ * never touched.  A tree handle is used by one stream at a time; different
+ * handles are independent and may run concurrently on different streams.
  *
  * Layouts.  Inputs are FP64 structure-of-arrays in the caller's order.
  * Outputs are structure-of-arrays in the caller's order, FP64 when precision
@@ -47,7 +58,11 @@
  * function aborts or throws.  Argument errors are reported at the call;
  * HFMM_E_NOMEM means the arena is too small and hfmm_required_bytes() then
  * gives a size that is enough for the work done so far (retry with at least
- * that much).  HIP runtime failures return HFMM_E_HIP.
+ * that much).  HIP runtime failures return HFMM_E_HIP.  Errors in the data
+ * (non-finite coordinates or masses, an overflowing traversal) are found by
+ * the kernels and kept in the tree's device status word, read with
+ * hfmm_status(); the build also returns HFMM_E_DATA for non-finite source
+ * coordinates, and hfmm_solve reads the status word before it returns.
  */
 #ifndef HFMM_H
 #define HFMM_H
@@ -94,29 +109,35 @@ enum hfmm_status {
     HFMM_E_UNSUPPORTED = -3, /* p outside [1, HFMM_MAX_P] or unknown mode */
     HFMM_E_HIP = -4,         /* HIP runtime error */
     HFMM_E_STATE = -5,       /* call order violated (e.g. evaluate before upward) */
-    HFMM_E_DATA = -6         /* non-finite coordinates */
+    HFMM_E_DATA = -6,        /* non-finite coordinates or masses */
+    HFMM_E_OVERFLOW = -7     /* a traversal stack overflowed: lists incomplete */
 };
+
+/* bits of the device status word (hfmm_status) */
+#define HFMM_ST_SRC_NONFINITE 1u   /* a source coordinate is NaN or infinite */
+#define HFMM_ST_TGT_NONFINITE 2u   /* a target coordinate is NaN or infinite */
+#define HFMM_ST_MASS_NONFINITE 4u  /* a mass is NaN or infinite */
+#define HFMM_ST_OVERFLOW 8u        /* a traversal stack overflowed */
 
 #define HFMM_MAX_P 16
 #define HFMM_KEY_LEVELS 21   /* octree depth limit: 21 bits per axis */
 #define HFMM_PHASES 10
 
-/* Upper estimate of the arena bytes for one tree over n_src sources and
- * n_tgt distinct targets (0 for self-evaluation) at order p.  Host only.  The
- * estimate covers uniform and moderately clustered inputs; a tree that needs
- * more returns HFMM_E_NOMEM. */
+/* Upper estimate of the arena bytes for one tree over n_src sources,
+ * evaluated at up to n_tgt separate targets at a time (0 for
+ * self-evaluation only), at order p.  Host only.  The estimate covers
+ * uniform and moderately clustered inputs; a tree that needs more returns
+ * HFMM_E_NOMEM. */
 int hfmm_arena_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p,
                      int method, int precision, size_t* bytes);
 
-/* Build the octree (Sec. 4, "sort" and "other" of Fig. 6): FP64 bounding cube and
- * 63-bit Morton keys, radix sort, cells split while count > leaf_max (and
- * level < 21).  Targets: tx == NULL evaluates at the sources themselves;
- * otherwise the n_tgt target points are added to the tree as zero-mass
- * particles.  The handle refers to the arena, which must stay alive and
- * untouched until hfmm_tree_release. */
+/* Build the octree over the n_src sources (Sec. 4, "sort" and "other" of
+ * Fig. 6): FP64 bounding cube and 63-bit Morton keys, radix sort, cells
+ * split while count > leaf_max (and level < 21).  HFMM_E_DATA for
+ * non-finite coordinates.  The handle refers to the arena, which must stay
+ * alive and untouched until hfmm_tree_release. */
 int hfmm_build_tree(const double* x, const double* y, const double* z,
-                    int64_t n_src, const double* tx, const double* ty,
-                    const double* tz, int64_t n_tgt, int leaf_max, void* arena,
+                    int64_t n_src, int leaf_max, void* arena,
                     size_t arena_bytes, void* stream, hfmm_tree* out);
 
 /* Upward pass: P2M at the leaves and M2M to the root (Sec. 2), FP64
@@ -129,20 +150,37 @@ int hfmm_upward(hfmm_tree t, const double* m, int p, int method,
 
 /* Far and near field at the targets (Sec. 2): FMM (M2L, L2L, L2P, P2P) or
  * treecode (M2P, P2P) with acceptance parameter theta (not used by
- * HFMM_TREECODE_FMMLIST).  p, method and precision must match the last
- * hfmm_upward.  Outputs hold n_tgt values (or n_src for self-evaluation). */
-int hfmm_evaluate(hfmm_tree t, int p, double theta, int method, int precision,
-                  double eps2, void* phi, void* ax, void* ay, void* az,
-                  void* stream);
+ * HFMM_TREECODE_FMMLIST).  Targets: tx == NULL evaluates at the sources
+ * (outputs hold n_src values in the sources' order); otherwise at the n_tgt
+ * points tx, ty, tz (outputs hold n_tgt values in their order), binned into
+ * the tree as described above (tx == NULL with n_tgt != 0 is
+ * HFMM_E_INVAL; an empty target set needs no call).  p, method and
+ * precision must match the last hfmm_upward.  The tree may be evaluated again, at the same or other
+ * targets; each evaluation needs arena space for its targets
+ * (hfmm_arena_bytes with n_tgt). */
+int hfmm_evaluate(hfmm_tree t, const double* tx, const double* ty,
+                  const double* tz, int64_t n_tgt, int p, double theta,
+                  int method, int precision, double eps2, void* phi, void* ax,
+                  void* ay, void* az, void* stream);
 
 /* build_tree + upward + evaluate in one call (self-evaluation when tx ==
- * NULL).  The tree handle is released before returning. */
+ * NULL); reads the status word before it returns (HFMM_E_DATA,
+ * HFMM_E_OVERFLOW).  The tree handle is released before returning. */
 int hfmm_solve(const double* x, const double* y, const double* z,
                const double* m, int64_t n_src, const double* tx,
                const double* ty, const double* tz, int64_t n_tgt, int leaf_max,
                int p, double theta, int method, int precision, double eps2,
                void* arena, size_t arena_bytes, void* phi, void* ax, void* ay,
                void* az, void* stream);
+
+/* The tree's device status word: waits for the work enqueued on `stream`
+ * and reads it.  Returns HFMM_OK, HFMM_E_DATA (non-finite source or target
+ * coordinates or masses: the results are meaningless) or HFMM_E_OVERFLOW (a
+ * traversal stack overflowed: lists, hence results, are incomplete); *flags
+ * (may be NULL) receives the HFMM_ST_* bits.  Source bits stay for the
+ * tree's life, mass bits until the next hfmm_upward, target and overflow
+ * bits until the next hfmm_evaluate. */
+int hfmm_status(hfmm_tree t, void* stream, uint32_t* flags);
 
 /* Direct sum of Eq. 1 (all pairs, P2P kernel of Sec. 5.1) over n sources at
  * the n_tgt points (tx == NULL: at the sources).  precision HFMM_FP64 or
@@ -209,7 +247,7 @@ size_t hfmm_required_bytes(hfmm_tree t);
 size_t hfmm_last_required_bytes(void);
 
 typedef struct {
-    int64_t n_particles;   /* sources + distinct targets in the tree */
+    int64_t n_particles;   /* sources in the tree */
     int64_t n_cells;
     int64_t n_leaves;
     int32_t depth;         /* deepest level (root = 0) */
@@ -223,9 +261,13 @@ typedef struct {
     /* device time of the phases of the last calls, in ms (-1 when not timed):
      * 0 tree build, 1 FMM lists, 2 upward (P2M, M2M), 3 M2L operator tables,
      * 4 M2L kernel (the matrix products alone), 5 downward (P2L, L2L),
-     * 6 far field (L2P, M2P), 7 P2P (+ output scatter), 8 treecode lists,
+     * 6 far field (L2P, M2P), 7 P2P (+ output scatter), 8 target binning and
+     * the targets' lists (treecode lists for self-evaluation),
      * 9 M2L operand preparation (packing, low-precision scaling) */
     double phase_ms[HFMM_PHASES];
+    /* the last evaluation's targets: points, boxes, and for separate
+     * targets the near (P2P) and far (M2P) list entries of their boxes */
+    int64_t n_targets, n_target_boxes, target_near, target_far;
 } hfmm_stats;
 
 /* Turn per-phase device timers on or off for trees built afterwards
@@ -241,9 +283,19 @@ const char* hfmm_strerror(int code);
  * All dst pointers are device pointers of the stated length; the copies are
  * enqueued on `stream`.  Cells are in level order, Morton order within a
  * level (root first). */
-/* perm[s] = caller index of the particle at sorted position s (n_particles;
- * targets are numbered n_src + k). */
+/* perm[s] = caller index of the source at sorted position s (n_particles). */
 int hfmm_export_perm(hfmm_tree t, int32_t* dst, void* stream);
+/* The boxes of the last evaluation's targets, per target in the caller's
+ * order: kind (0 a leaf, 1 an empty octant of a split cell, 2 outside the
+ * root cube), level, ix, iy, iz, host (the cell whose local expansion
+ * covers the box, -1 none), leaf (the box's own cell, -1 none) and the
+ * box's index: 8 int32 per target (n_targets). */
+int hfmm_export_targets(hfmm_tree t, int32_t* dst, void* stream);
+/* The lists of the last evaluation's separate-target boxes (which 0 far:
+ * M2P, 1 near: P2P) as CSR by box index: off (n_target_boxes + 1 int32) and
+ * items (target_far or target_near int32; may be NULL). */
+int hfmm_export_target_lists(hfmm_tree t, int which, int32_t* off,
+                             int32_t* items, void* stream);
 /* per cell: level, ix, iy, iz, first, count, parent, first_child, nchild
  * (9 int32 per cell, cell-major) */
 int hfmm_export_cells(hfmm_tree t, int32_t* dst, void* stream);

@@ -2,14 +2,18 @@
 // the passes (Sec. 2, Fig. 1):
 //   build:    bbox, keys, sort, cells                       (tree.hip)
 //   upward:   P2M at the leaves, M2M to the root            (expansions.hip)
-//   evaluate: FMM      M2L (+P2L), L2L, L2P (+M2P), P2P     (m2l, expansions, p2p)
+//   evaluate: the targets (the sources, or separate points binned into the
+//             tree: targets.hip), then
+//             FMM      M2L (+P2L), L2L, L2P (+M2P), P2P     (m2l, expansions, p2p)
 //             treecode M2P, P2P (Barnes-Hut lists, or the FMM lists)
 #include "common.hpp"
 #include "expansions.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <new>
+#include <vector>
 
 namespace hfmm {
 
@@ -54,6 +58,33 @@ __global__ void k_offsets_minus(const int32_t* __restrict__ in, int64_t n, int32
     if (i < n) out[i] = in[i] - base;
 }
 
+__global__ void k_status_clear(int32_t* status, int32_t bits) {
+    if (threadIdx.x == 0) atomicAnd(status, ~bits);
+}
+
+// per target, in the caller's order: kind, level, ix, iy, iz, host, leaf and
+// the index of its box
+__global__ void k_export_targets(Targets tg, int32_t* __restrict__ o) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= tg.n) return;
+    const int b = tg.box_of[s];
+    const TBox x = tg.box[b];
+    int32_t* d = o + (int64_t)tg.perm[s] * 8;
+    d[0] = x.kind;
+    d[1] = x.level;
+    d[2] = x.ix;
+    d[3] = x.iy;
+    d[4] = x.iz;
+    d[5] = x.host;
+    d[6] = x.leaf;
+    d[7] = b;
+}
+
+static void clear_status(Tree& t, int32_t bits, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_clear, dim3(1), dim3(64), 0, s, t.status, bits);
+    LAUNCH_CHECK();
+}
+
 static void check_p(int p) {
     if (p < 1 || p > HFMM_MAX_P) throw Status{HFMM_E_UNSUPPORTED};
 }
@@ -73,9 +104,12 @@ void upward_pass(Tree& t, const double* m, int p, int method, int precision, hip
     check_p(p);
     check_precision(precision);
     if (!tree_method(method)) throw Status{HFMM_E_UNSUPPORTED};
-    if (!m && t.ns > 0) throw Status{HFMM_E_INVAL};
+    if (!m && t.n > 0) throw Status{HFMM_E_INVAL};
     Arena& A = t.arena;
     A.release_temps();
+    clear_status(t, ST_MASS_NONFINITE, s);
+    t.tg_sep = false;
+    t.tg = Targets{};
     if (fmm_upward(method)) {
         if (!t.fmm_lists) {
             A.lo = t.mark_tree;
@@ -117,19 +151,14 @@ void upward_pass(Tree& t, const double* m, int p, int method, int precision, hip
     t.up_prec = precision;
 }
 
-void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi, void* ax, void* ay,
-                  void* az, hipStream_t s) {
+// M2L (+ P2L) and L2L: the local expansions of every cell
+static void downward_pass(Tree& t, int p, int precision, hipStream_t s) {
     Arena& A = t.arena;
-    A.release_temps();
-    A.lo = t.mark_up;
-    const int P = p * p;
     const bool fp64 = precision == HFMM_FP64;
     {
         PhaseTimer pt(t, PH_OPS, s);
         prepare_m2l_ops(t, p, precision, s);
     }
-    int RB, KQ, ld;
-    m2l_layout(p, precision, RB, KQ, ld);
     t.L = A.up<double>((size_t)(t.ncells + 1) * t.ldm);
     const size_t row = sizeof(double) * t.ldm;
     HIP_TRY(hipMemsetAsync(t.L + (size_t)t.ncells * t.ldm, 0, row, s));
@@ -161,51 +190,165 @@ void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi, void* a
     } else {
         HIP_TRY(hipMemsetAsync(t.L, 0, row * t.ncells, s));
     }
-    void* far = A.down<char>((size_t)4 * t.n * (fp64 ? 8 : 4));
-    {
-        PhaseTimer pt(t, PH_FAR, s);
-        run_far(t, p, fp64, far, s);
-    }
-    {
-        PhaseTimer pt(t, PH_P2P, s);
-        launch_p2p(t, precision, eps2, t.leaves, t.nleaves, t.u_off, t.u_items, far, phi, ax,
-                   ay, az, s);
-    }
-    t.ev_p = p;
-    t.m2l_pairs = t.n_v;
     A.release_temps();
 }
 
-// fmm_lists: the treecode of Sec. 4 (M2P and P2P over the FMM lists, theta
-// unused); otherwise Barnes-Hut lists with acceptance theta
-void evaluate_treecode(Tree& t, int p, double theta, bool fmm_lists, int precision, double eps2,
-                       void* phi, void* ax, void* ay, void* az, hipStream_t s) {
+// HFMM_VALIDATE=1: the separate targets' boxes and lists are read back and
+// checked on the host before any kernel uses them (ranges, kinds, cell
+// indices, the permutation, list offsets and items); a violation returns
+// HFMM_E_STATE.  A debugging aid, off by default.
+static bool validate_on() {
+    static const bool on = [] {
+        const char* e = std::getenv("HFMM_VALIDATE");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+
+template <typename X>
+static std::vector<X> fetch(const X* d, int64_t n, hipStream_t s) {
+    std::vector<X> h((size_t)std::max<int64_t>(n, 0));
+    if (n > 0) HIP_TRY(hipMemcpyAsync(h.data(), d, sizeof(X) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return h;
+}
+
+static void validate_targets(const Tree& t, const Targets& tg, const int32_t* off_a,
+                             const int32_t* items_a, int64_t na, const int32_t* off_b,
+                             const int32_t* items_b, int64_t nb, hipStream_t s) {
+    const auto box = fetch(tg.box, tg.nbox, s);
+    const auto box_of = fetch(tg.box_of, tg.n, s);
+    const auto perm = fetch(tg.perm, tg.n, s);
+    auto bad = [] { throw Status{HFMM_E_STATE}; };
+    int64_t next = 0;
+    for (int b = 0; b < tg.nbox; ++b) {
+        const TBox& x = box[b];
+        if (x.first != next || x.count < 1 || x.first + (int64_t)x.count > tg.n) bad();
+        next = x.first + (int64_t)x.count;
+        if (x.host < -1 || x.host >= t.ncells || x.leaf < -1 || x.leaf >= t.ncells) bad();
+        if (x.kind == 0 && (x.leaf < 0 || x.host != x.leaf)) bad();
+        if (x.kind == 1 && (x.leaf != -1 || x.host < 0)) bad();
+        if (x.kind == 2 && (x.leaf != -1 || x.host != -1 || x.level != 0)) bad();
+        if (x.kind < 0 || x.kind > 2) bad();
+        for (int64_t k = x.first; k < next; ++k)
+            if (box_of[k] != b) bad();
+    }
+    if (next != tg.n) bad();
+    std::vector<char> seen((size_t)tg.n, 0);
+    for (int64_t k = 0; k < tg.n; ++k) {
+        if (perm[k] < 0 || perm[k] >= tg.n || seen[perm[k]]) bad();
+        seen[perm[k]] = 1;
+    }
+    const int32_t* offs[2] = {off_a, off_b};
+    const int32_t* its[2] = {items_a, items_b};
+    const int64_t tots[2] = {na, nb};
+    for (int w = 0; w < 2; ++w) {
+        const auto off = fetch(offs[w], (int64_t)tg.nbox + 1, s);
+        const auto it = fetch(its[w], tots[w], s);
+        if (off[0] != 0 || off[tg.nbox] != tots[w]) bad();
+        for (int b = 0; b < tg.nbox; ++b)
+            if (off[b + 1] < off[b]) bad();
+        for (int64_t e = 0; e < tots[w]; ++e)
+            if (it[e] < 0 || it[e] >= t.ncells) bad();
+    }
+}
+
+// One evaluation at the sources (tx == nullptr) or at nt separate targets
+// binned into the tree.  FMM: M2L, L2L, then per target box L2P of its host
+// cell's local expansion, M2P over its far list and P2P over its near list
+// (the tree's W and U lists for the leaves; for separate targets the lists
+// of every box, with V by M2P and X by P2P for a box without sources).
+// Treecode: M2P and P2P over the boxes' Barnes-Hut lists, or over the FMM
+// lists (the treecode of Sec. 4).
+void evaluate(Tree& t, const double* tx, const double* ty, const double* tz, int64_t nt, int p,
+              double theta, int method, int precision, double eps2, void* phi, void* ax,
+              void* ay, void* az, hipStream_t s) {
     Arena& A = t.arena;
     A.release_temps();
+    const bool sep = tx != nullptr;
+    const bool fp64 = precision == HFMM_FP64;
+    clear_status(t, ST_TGT_NONFINITE | ST_OVERFLOW, s);
+    t.tg_sep = false;
+    t.tg = Targets{};
+    if (sep || method == HFMM_FMM) {
+        // separate targets live above the upward data (and the local
+        // expansions); the treecodes' cached self lists are given up
+        A.lo = t.mark_up;
+        t.a_off = nullptr;
+        t.bh_theta = -1.0;
+    }
+    if (method == HFMM_FMM) downward_pass(t, p, precision, s);
+    Targets tg;
+    const int32_t *far_off, *far_items, *near_off, *near_items;
+    int64_t n_far;
+    bool walk = false;
     {
         PhaseTimer pt(t, PH_BH, s);
-        if (fmm_lists)
-            build_fmmlist_treecode_lists(t, p != 3, s);
-        else
-            build_bh_lists(t, theta, s);
+        if (sep) {
+            tg = bin_targets(t, tx, ty, tz, nt, s);
+            if (method == HFMM_FMM)
+                build_box_lists(t, tg, BOX_FMM, s);
+            else if (method == HFMM_TREECODE_FMMLIST)
+                build_box_lists(t, tg, p == 3 ? BOX_TREECODE : BOX_TREECODE_FULL, s);
+            else
+                build_bh_box_lists(t, tg, theta, s);
+            far_off = t.tf_off;
+            far_items = t.tf_items;
+            n_far = t.tg_far;
+            near_off = t.tn_off;
+            near_items = t.tn_items;
+            walk = method == HFMM_TREECODE_FMMLIST && p == 3;
+            if (validate_on())
+                validate_targets(t, tg, far_off, far_items, n_far, near_off, near_items,
+                                 t.tg_near, s);
+        } else {
+            tg = self_targets(t);
+            if (method == HFMM_FMM) {
+                far_off = t.w_off;
+                far_items = t.w_items;
+                n_far = t.n_w;
+                near_off = t.u_off;
+                near_items = t.u_items;
+            } else {
+                if (method == HFMM_TREECODE_FMMLIST)
+                    build_fmmlist_treecode_lists(t, p != 3, s);
+                else
+                    build_bh_lists(t, theta, s);
+                walk = method == HFMM_TREECODE_FMMLIST && p == 3;
+                // at p = 3 over the FMM lists the far kernel takes W and
+                // reads the V lists itself
+                far_off = walk ? t.w_off : t.a_off;
+                far_items = walk ? t.w_items : t.a_items;
+                n_far = walk ? t.n_w : t.n_a;
+                near_off = t.b_off;
+                near_items = t.b_items;
+            }
+        }
     }
-    const bool fp64 = precision == HFMM_FP64;
-    void* far = A.down<char>((size_t)4 * t.n * (fp64 ? 8 : 4));
+    void* far = A.down<char>((size_t)4 * tg.n * (fp64 ? 8 : 4));
     {
         PhaseTimer pt(t, PH_FAR, s);
-        run_treecode_far(t, p, fp64, far, s);
+        if (method == HFMM_FMM)
+            run_far(t, tg, p, fp64, far_off, far_items, n_far, far, s);
+        else
+            run_treecode_far(t, tg, p, fp64, walk, far_off, far_items, far, s);
     }
     {
         PhaseTimer pt(t, PH_P2P, s);
-        launch_p2p(t, precision, eps2, t.leaves, t.nleaves, t.b_off, t.b_items, far, phi, ax,
-                   ay, az, s);
+        launch_p2p(t, tg, precision, eps2, near_off, near_items, far, phi, ax, ay, az, s);
     }
+    t.tg = tg;
+    t.tg_sep = sep;
     t.ev_p = p;
+    t.ev_method = method;
+    if (method == HFMM_FMM) t.m2l_pairs = t.n_v;
     A.release_temps();
 }
 
 static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, int method,
                              int precision) {
+    // separate targets: sorted copies (88 bytes), sort and box temporaries,
+    // and up to one box each with its lists (counted as cells below)
     const int64_t n = n_src + n_tgt;
     const int64_t nc = 4 * n / std::max(1, leaf_max) + 4096;
     const int P = p * p;
@@ -282,26 +425,20 @@ int hfmm_arena_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, int meth
 }
 
 int hfmm_build_tree(const double* x, const double* y, const double* z, int64_t n_src,
-                    const double* tx, const double* ty, const double* tz, int64_t n_tgt,
                     int leaf_max, void* arena, size_t arena_bytes, void* stream,
                     hfmm_tree* out) {
     if (!out) return HFMM_E_INVAL;
     *out = nullptr;
-    if (n_src < 0 || n_tgt < 0 || leaf_max < 1 || !arena) return HFMM_E_INVAL;
+    if (n_src < 0 || leaf_max < 1 || !arena) return HFMM_E_INVAL;
     if (n_src > 0 && (!x || !y || !z)) return HFMM_E_INVAL;
-    const bool self = tx == nullptr;
-    if (!self && n_tgt > 0 && (!ty || !tz)) return HFMM_E_INVAL;
-    if (n_src + (self ? 0 : n_tgt) > (int64_t)INT32_MAX / 2) return HFMM_E_UNSUPPORTED;
+    if (n_src > (int64_t)INT32_MAX / 2) return HFMM_E_UNSUPPORTED;
     hfmm_tree_s* h = new (std::nothrow) hfmm_tree_s();
     if (!h) return HFMM_E_NOMEM;
     Tree& t = h->t;
     hipStream_t s = (hipStream_t)stream;
     try {
         HIP_TRY(hipGetDevice(&t.device));
-        t.ns = n_src;
-        t.nt = self ? n_src : n_tgt;
-        t.self = self;
-        t.n = n_src + (self ? 0 : n_tgt);
+        t.n = n_src;
         t.leaf_max = leaf_max;
         t.arena.init(arena, arena_bytes);
         if (g_timing) {
@@ -310,7 +447,10 @@ int hfmm_build_tree(const double* x, const double* y, const double* z, int64_t n
         }
         if (t.n > 0) {
             PhaseTimer pt(t, PH_BUILD, s);
-            build_tree(t, x, y, z, tx, ty, tz, s);
+            build_tree(t, x, y, z, s);
+        } else {
+            t.status = t.arena.up<int32_t>(1);
+            HIP_TRY(hipMemsetAsync(t.status, 0, sizeof(int32_t), s));
         }
         t.mark_tree = t.arena.lo;
         t.mark_lists = t.mark_up = t.arena.lo;
@@ -330,6 +470,9 @@ int hfmm_upward(hfmm_tree h, const double* m, int p, int method, int precision,
                 void* stream) {
     if (!h) return HFMM_E_INVAL;
     API_BEGIN
+    check_p(p);
+    check_precision(precision);
+    if (!tree_method(method)) throw Status{HFMM_E_UNSUPPORTED};
     if (h->t.n == 0) {
         h->t.up_p = p;
         h->t.up_method = method;
@@ -340,22 +483,29 @@ int hfmm_upward(hfmm_tree h, const double* m, int p, int method, int precision,
     API_END
 }
 
-int hfmm_evaluate(hfmm_tree h, int p, double theta, int method, int precision, double eps2,
+int hfmm_evaluate(hfmm_tree h, const double* tx, const double* ty, const double* tz,
+                  int64_t n_tgt, int p, double theta, int method, int precision, double eps2,
                   void* phi, void* ax, void* ay, void* az, void* stream) {
     if (!h) return HFMM_E_INVAL;
     Tree& t = h->t;
-    if (t.nt > 0 && (!phi || !ax || !ay || !az)) return HFMM_E_INVAL;
+    const bool sep = tx != nullptr;
+    if (sep && (n_tgt < 0 || !ty || !tz)) return HFMM_E_INVAL;
+    if (!sep && n_tgt != 0) return HFMM_E_INVAL;  // targets given without coordinates
+    if (sep && n_tgt > (int64_t)INT32_MAX / 2) return HFMM_E_UNSUPPORTED;
+    const int64_t nt = sep ? n_tgt : t.n;
+    if (nt > 0 && (!phi || !ax || !ay || !az)) return HFMM_E_INVAL;
     if (!(eps2 >= 0.0) || !std::isfinite(eps2)) return HFMM_E_INVAL;
     if (t.up_p != p || t.up_method != method || t.up_prec != precision) return HFMM_E_STATE;
     if (method == HFMM_TREECODE && !(theta >= 0.0)) return HFMM_E_INVAL;
     API_BEGIN
-    if (t.n == 0 || t.nt == 0) return HFMM_OK;
     hipStream_t s = (hipStream_t)stream;
-    if (method == HFMM_FMM)
-        evaluate_fmm(t, p, precision, eps2, phi, ax, ay, az, s);
-    else
-        evaluate_treecode(t, p, theta, method == HFMM_TREECODE_FMMLIST, precision, eps2, phi,
-                          ax, ay, az, s);
+    if (nt == 0) return HFMM_OK;
+    if (t.n == 0) {  // no sources: a zero field
+        const size_t e = precision == HFMM_FP64 ? 8 : 4;
+        for (void* o : {phi, ax, ay, az}) HIP_TRY(hipMemsetAsync(o, 0, e * nt, s));
+        return HFMM_OK;
+    }
+    evaluate(t, tx, ty, tz, nt, p, theta, method, precision, eps2, phi, ax, ay, az, s);
     API_END
 }
 
@@ -368,15 +518,33 @@ int hfmm_solve(const double* x, const double* y, const double* z, const double* 
         return hfmm_direct(x, y, z, m, n_src, tx, ty, tz, n_tgt, precision, eps2, arena,
                            arena_bytes, phi, ax, ay, az, stream);
     hfmm_tree h = nullptr;
-    int rc = hfmm_build_tree(x, y, z, n_src, tx, ty, tz, n_tgt, leaf_max, arena, arena_bytes,
-                             stream, &h);
+    int rc = hfmm_build_tree(x, y, z, n_src, leaf_max, arena, arena_bytes, stream, &h);
     if (rc != HFMM_OK) return rc;
     rc = hfmm_upward(h, m, p, method, precision, stream);
-    if (rc == HFMM_OK) rc = hfmm_evaluate(h, p, theta, method, precision, eps2, phi, ax, ay, az,
-                                          stream);
+    if (rc == HFMM_OK)
+        rc = hfmm_evaluate(h, tx, ty, tz, n_tgt, p, theta, method, precision, eps2, phi, ax, ay,
+                           az, stream);
+    if (rc == HFMM_OK) rc = hfmm_status(h, stream, nullptr);
     if (rc == HFMM_E_NOMEM) g_last_required = h->t.arena.need;
     hfmm_tree_release(h);
     return rc;
+}
+
+int hfmm_status(hfmm_tree h, void* stream, uint32_t* flags) {
+    if (flags) *flags = 0;
+    if (!h) return HFMM_E_INVAL;
+    const Tree& t = h->t;
+    int32_t w = 0;
+    if (t.status) {
+        hipStream_t s = (hipStream_t)stream;
+        if (hipMemcpyAsync(&w, t.status, sizeof(w), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return HFMM_E_HIP;
+    }
+    if (flags) *flags = (uint32_t)w;
+    if (w & (ST_SRC_NONFINITE | ST_TGT_NONFINITE | ST_MASS_NONFINITE)) return HFMM_E_DATA;
+    if (w & ST_OVERFLOW) return HFMM_E_OVERFLOW;
+    return HFMM_OK;
 }
 
 int hfmm_direct_bytes(int64_t n_src, int64_t n_tgt, int precision, size_t* bytes) {
@@ -394,6 +562,7 @@ int hfmm_direct(const double* x, const double* y, const double* z, const double*
     if (n_src < 0 || n_tgt < 0) return HFMM_E_INVAL;
     if (precision != HFMM_FP64 && precision != HFMM_FP32) return HFMM_E_UNSUPPORTED;
     const bool self = tx == nullptr;
+    if (self && n_tgt != 0) return HFMM_E_INVAL;  // targets given without coordinates
     const int64_t nt = self ? n_src : n_tgt;
     if (n_src > 0 && (!x || !y || !z || !m)) return HFMM_E_INVAL;
     if (!self && (!ty || !tz)) return HFMM_E_INVAL;
@@ -426,6 +595,10 @@ int hfmm_get_stats(hfmm_tree h, hfmm_stats* st) {
     if (!h || !st) return HFMM_E_INVAL;
     const Tree& t = h->t;
     st->n_particles = t.n;
+    st->n_targets = t.tg_sep ? t.tg.n : t.n;
+    st->n_target_boxes = t.tg_sep ? t.tg.nbox : t.nleaves;
+    st->target_near = t.tg_sep ? t.tg_near : 0;
+    st->target_far = t.tg_sep ? t.tg_far : 0;
     st->n_cells = t.ncells;
     st->n_leaves = t.nleaves;
     st->depth = t.depth;
@@ -463,7 +636,8 @@ const char* hfmm_strerror(int code) {
         case HFMM_E_UNSUPPORTED: return "unsupported order, method or precision";
         case HFMM_E_HIP: return "HIP runtime error";
         case HFMM_E_STATE: return "call order violated";
-        case HFMM_E_DATA: return "non-finite coordinates";
+        case HFMM_E_DATA: return "non-finite coordinates or masses";
+        case HFMM_E_OVERFLOW: return "traversal stack overflow (lists incomplete)";
         default: return "unknown error";
     }
 }
@@ -540,6 +714,37 @@ int hfmm_export_bh_list(hfmm_tree h, int which, int32_t* off, int32_t* items, vo
         else  // over the FMM lists at p = 3 the M2P items are not kept
             fill_fmmlist_far_items(t, items, s);
     }
+    API_END
+}
+
+int hfmm_export_targets(hfmm_tree h, int32_t* dst, void* stream) {
+    if (!h) return HFMM_E_INVAL;
+    const Tree& t = h->t;
+    if (!t.tg.box) return HFMM_E_STATE;
+    if (!dst && t.tg.n > 0) return HFMM_E_INVAL;
+    API_BEGIN
+    if (t.tg.n > 0) {
+        hipLaunchKernelGGL(k_export_targets, dim3(grid_for(t.tg.n, 256)), dim3(256), 0,
+                           (hipStream_t)stream, t.tg, dst);
+        LAUNCH_CHECK();
+    }
+    API_END
+}
+
+int hfmm_export_target_lists(hfmm_tree h, int which, int32_t* off, int32_t* items,
+                             void* stream) {
+    if (!h || !off || which < 0 || which > 1) return HFMM_E_INVAL;
+    const Tree& t = h->t;
+    if (!t.tg_sep) return HFMM_E_STATE;
+    API_BEGIN
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t* o = which == 0 ? t.tf_off : t.tn_off;
+    const int32_t* it = which == 0 ? t.tf_items : t.tn_items;
+    const int64_t nn = which == 0 ? t.tg_far : t.tg_near;
+    HIP_TRY(hipMemcpyAsync(off, o, sizeof(int32_t) * (t.tg.nbox + 1), hipMemcpyDeviceToDevice,
+                           s));
+    if (nn > 0 && items)
+        HIP_TRY(hipMemcpyAsync(items, it, sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s));
     API_END
 }
 

@@ -108,6 +108,61 @@ struct Cell {
 };
 static_assert(sizeof(Cell) == 32, "Cell must be 32 bytes");
 
+// A target box.  Every target is evaluated in the box it is binned into:
+// a leaf of the source tree (kind 0: leaf = host = that cell), a
+// source-free leaf added under a split cell, the octant of the split cell
+// that holds the target (kind 1: leaf = -1, host = the split cell), or,
+// outside the root cube, the level-0 cube of the extended grid holding it
+// (kind 2: leaf = host = -1).  The host is the cell whose local expansion
+// covers the box.  For self-evaluation the boxes are the leaves.
+struct TBox {
+    int32_t first, count;   // targets [first, first + count) in sorted order
+    int32_t host, leaf;
+    int32_t ix, iy, iz;     // coordinates at `level` (any sign outside the root)
+    int16_t level;
+    int16_t kind;
+};
+static_assert(sizeof(TBox) == 32, "TBox must be 32 bytes");
+
+// The box's geometry as a cell record (for adjacency and centres).
+__host__ __device__ inline Cell box_cell(const TBox& b) {
+    Cell c;
+    c.first = c.count = 0;
+    c.parent = c.child = -1;
+    c.ix = b.ix;
+    c.iy = b.iy;
+    c.iz = b.iz;
+    c.level = b.level;
+    c.nchild = 0;
+    c.mask = 0;
+    return c;
+}
+
+// The targets of one evaluation as the kernels see them.  Lists are rows of
+// a CSR either by box (separate targets) or by the box's own leaf (self-
+// evaluation: the tree's lists).
+struct Targets {
+    const TBox* box;
+    const int32_t* box_of;   // sorted target -> box
+    const float4* p32;       // sorted targets, FP32 relative to their box centre
+    const double4* p64;      // sorted targets, FP64
+    const int32_t* perm;     // sorted target -> output index
+    int64_t n;
+    int32_t nbox;
+    int32_t by_leaf;
+};
+__device__ __forceinline__ int list_row(const Targets& tg, int b, const TBox& bx) {
+    return tg.by_leaf ? bx.leaf : b;
+}
+
+// Device status word: data errors found by the kernels (hfmm_status).
+enum StatusBits : int32_t {
+    ST_SRC_NONFINITE = 1,    // a source coordinate is NaN or infinite
+    ST_TGT_NONFINITE = 2,    // a target coordinate is NaN or infinite
+    ST_MASS_NONFINITE = 4,   // a mass is NaN or infinite
+    ST_OVERFLOW = 8          // a traversal stack overflowed (lists incomplete)
+};
+
 struct Root {
     double b[3];   // lower corner of the root cube
     double R;      // half width
@@ -121,8 +176,7 @@ struct Root {
 // is not used; these are filled from hip events when enabled)
 struct Tree {
     int device = 0;
-    int64_t n = 0, ns = 0, nt = 0;  // particles in tree, sources, targets
-    bool self = true;
+    int64_t n = 0;                   // sources (the particles of the tree)
     int leaf_max = 64;
     Arena arena;
     Root root_h;
@@ -134,6 +188,10 @@ struct Tree {
     float4* p32 = nullptr;           // x, y, z, m (FP32)
     double4* p64 = nullptr;          // x, y, z, m (FP64)
     int32_t* leaf_of = nullptr;      // sorted particle -> leaf cell
+    int32_t* status = nullptr;       // device status word (StatusBits)
+    // self-evaluation view: one box per leaf, sorted particle -> leaf index
+    TBox* leaf_boxes = nullptr;
+    int32_t* leaf_box_of = nullptr;
     int sort_bits = 0;
     // cells
     Cell* cells = nullptr;
@@ -184,8 +242,16 @@ struct Tree {
     double* xl_m2m = nullptr;        // 8 octant operators, matrix-core layout
     double* xl_l2l = nullptr;
     std::vector<int32_t> m2l_level_start;  // host: level -> start in m2l_order
-    int ev_p = 0;
+    int ev_p = 0, ev_method = -1;
     int64_t p2p_pairs = 0, m2l_pairs = 0;
+    // the last evaluation's targets (separate targets: boxes, sorted
+    // positions and lists live in the arena until the next upward pass or
+    // evaluation)
+    bool tg_sep = false;
+    Targets tg{};
+    int64_t tg_near = 0, tg_far = 0;     // list entries of the separate targets
+    int32_t *tn_off = nullptr, *tn_items = nullptr;  // near (P2P) lists by box
+    int32_t *tf_off = nullptr, *tf_items = nullptr;  // far (M2P) lists by box
     // phase timers (HIP events on the caller's stream)
     bool timing = false;
     hipEvent_t ev[2 * HFMM_PHASES] = {};
@@ -409,9 +475,7 @@ void radix_sort_pairs(const uint64_t* keys, const int32_t* vals, uint64_t* keys_
                       int32_t* vals_out, int64_t n, int lo_bit, int hi_bit, Arena& A,
                       hipStream_t s);
 
-void build_tree(Tree& t, const double* x, const double* y, const double* z,
-                const double* tx, const double* ty, const double* tz,
-                hipStream_t s);
+void build_tree(Tree& t, const double* x, const double* y, const double* z, hipStream_t s);
 void build_fmm_lists(Tree& t, hipStream_t s);
 void build_bh_lists(Tree& t, double theta, hipStream_t s);
 void set_last_required(size_t bytes);  // for hfmm_last_required_bytes
@@ -420,10 +484,9 @@ void fill_fmmlist_far_items(const Tree& t, int32_t* dst, hipStream_t s);
 constexpr double kFmmListTheta = -2.0;
 void upward_pass(Tree& t, const double* m, int p, int method, int precision,
                  hipStream_t s);
-void evaluate_fmm(Tree& t, int p, int precision, double eps2, void* phi,
-                  void* ax, void* ay, void* az, hipStream_t s);
-void evaluate_treecode(Tree& t, int p, int precision, double eps2, void* phi,
-                       void* ax, void* ay, void* az, hipStream_t s);
+void evaluate(Tree& t, const double* tx, const double* ty, const double* tz, int64_t nt,
+              int p, double theta, int method, int precision, double eps2, void* phi,
+              void* ax, void* ay, void* az, hipStream_t s);
 void direct_sum(const double* x, const double* y, const double* z,
                 const double* m, int64_t ns, const double* tx, const double* ty,
                 const double* tz, int64_t nt, int precision, double eps2,
@@ -431,9 +494,16 @@ void direct_sum(const double* x, const double* y, const double* z,
                 hipStream_t s);
 
 // far-field and near-field kernels (launch wrappers)
-void launch_p2p(const Tree& t, int precision, double eps2, const int32_t* tgt_cells,
-                int32_t n_tgt_cells, const int32_t* src_off, const int32_t* src_items,
-                const void* far, void* phi, void* ax, void* ay, void* az,
-                hipStream_t s);
+void launch_p2p(const Tree& t, const Targets& tg, int precision, double eps2,
+                const int32_t* src_off, const int32_t* src_items, const void* far,
+                void* phi, void* ax, void* ay, void* az, hipStream_t s);
+
+// separate targets (targets.hip)
+Targets self_targets(const Tree& t);
+Targets bin_targets(Tree& t, const double* tx, const double* ty, const double* tz,
+                    int64_t nt, hipStream_t s);
+enum BoxListMode { BOX_FMM = 0, BOX_TREECODE = 1, BOX_TREECODE_FULL = 2 };
+void build_box_lists(Tree& t, const Targets& tg, int mode, hipStream_t s);
+void build_bh_box_lists(Tree& t, const Targets& tg, double theta, hipStream_t s);
 
 }  // namespace hfmm

@@ -94,16 +94,22 @@ __device__ __forceinline__ T cim(const float* X, int n, int m) {
 // ---------------------------------------------------------------------
 // masses and centres
 // ---------------------------------------------------------------------
-__global__ void k_fill_masses(int64_t n, int64_t ns, const int32_t* __restrict__ perm,
+// masses in sorted order into the FP32 and FP64 records; non-finite masses
+// are flagged in the status word
+__global__ void k_fill_masses(int64_t n, const int32_t* __restrict__ perm,
                               const double* __restrict__ m, const double* __restrict__ xs,
                               const double* __restrict__ ys, const double* __restrict__ zs,
-                              float4* __restrict__ p32, double4* __restrict__ p64) {
+                              float4* __restrict__ p32, double4* __restrict__ p64,
+                              int32_t* __restrict__ status) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    int64_t i = perm[s];
-    double q = i < ns ? m[i] : 0.0;
-    p32[s].w = (float)q;
-    p64[s] = make_double4(xs[s], ys[s], zs[s], q);
+    bool bad = false;
+    if (s < n) {
+        const double q = m[perm[s]];
+        bad = !isfinite(q);
+        p32[s].w = (float)q;
+        p64[s] = make_double4(xs[s], ys[s], zs[s], q);
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(status, (int32_t)ST_MASS_NONFINITE);
 }
 
 __global__ void k_centres_geometric(const Cell* __restrict__ cells, int nc,
@@ -489,9 +495,10 @@ __device__ __forceinline__ void farp_batch(bool valid, int k, const double4& cb,
     }
 }
 
-// The M2P terms of the leaf's list items[e0, e1) (the FMM's W list).
+// The M2P terms of the box's list items[e0, e1) (the FMM's W list, and V
+// for a box without sources) at its targets.
 template <typename T, int NP, typename MT, int G>
-__device__ __forceinline__ void farp_leaf(const Cell& leaf, const double4& cb,
+__device__ __forceinline__ void farp_box(const TBox& leaf, const double4& cb,
                                           const double4* __restrict__ cen,
                                           const double4* __restrict__ p64,
                                           const int32_t* __restrict__ items, int e0, int e1,
@@ -532,46 +539,52 @@ __device__ __forceinline__ void farp_leaf(const Cell& leaf, const double4& cb,
     }
 }
 
-// L2P at every particle (Eq. 3 with its gradient, dR_n^m/dz = R_{n-1}^m,
-// (d/dx + i d/dy) R_n^m = R_{n-1}^{m+1}) from its leaf's local expansion,
-// one thread per sorted particle; ADD: add to far (the W-list M2P written
-// there first) instead of storing.
+// L2P at every target (Eq. 3 with its gradient, dR_n^m/dz = R_{n-1}^m,
+// (d/dx + i d/dy) R_n^m = R_{n-1}^{m+1}) from the local expansion of its
+// box's host cell (none outside the root), one thread per sorted target;
+// ADD: add to far (the M2P terms written there first) instead of storing.
 template <typename T, int NP, bool ADD>
 __global__ void __launch_bounds__(256)
-k_l2p(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict__ cen,
-      const double4* __restrict__ p64, const double* __restrict__ L, int ld,
+k_l2p(Targets tg, const double4* __restrict__ cen, const double* __restrict__ L, int ld,
       T* __restrict__ far) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = tg.n;
     if (s >= n) return;
-    const int b = leaf_of[s];
-    const double4 pj = p64[s];
-    const double4 q = cen[b];
-    const double ihd = q.w;
-    const T ux = (T)((pj.x - q.x) * ihd), uy = (T)((pj.y - q.y) * ihd),
-            uz = (T)((pj.z - q.z) * ihd);
-    const double* Lb = L + (int64_t)b * ld;
-    T f = T(0), gz = T(0), gr = T(0), gi = T(0);
-    stream_regular<T, NP>(ux, uy, uz, [&](int k, int l, T rr, T ri) {
-        const T w = l == 0 ? T(1) : T(2);
-        {
-            T lr = cre<T>(Lb, k, l), li = cim<T>(Lb, k, l);
-            f += w * (lr * rr - li * ri);
-        }
-        if (k + 1 < NP) {
-            T ar = cre<T>(Lb, k + 1, l), ai = cim<T>(Lb, k + 1, l);
-            gz += w * (ar * rr - ai * ri);
-            if (l >= 1) {
-                T br = cre<T>(Lb, k + 1, l - 1), bi = cim<T>(Lb, k + 1, l - 1);
-                gr += br * rr - bi * ri;
-                gi += br * ri + bi * rr;
+    const int b = tg.box[tg.box_of[s]].host;
+    T phi = T(0), ax = T(0), ay = T(0), az = T(0);
+    if (b >= 0) {
+        const double4 pj = tg.p64[s];
+        const double4 q = cen[b];
+        const double ihd = q.w;
+        const T ux = (T)((pj.x - q.x) * ihd), uy = (T)((pj.y - q.y) * ihd),
+                uz = (T)((pj.z - q.z) * ihd);
+        const double* Lb = L + (int64_t)b * ld;
+        T f = T(0), gz = T(0), gr = T(0), gi = T(0);
+        stream_regular<T, NP>(ux, uy, uz, [&](int k, int l, T rr, T ri) {
+            const T w = l == 0 ? T(1) : T(2);
+            {
+                T lr = cre<T>(Lb, k, l), li = cim<T>(Lb, k, l);
+                f += w * (lr * rr - li * ri);
             }
-            T cr = cre<T>(Lb, k + 1, l + 1), ci = cim<T>(Lb, k + 1, l + 1);
-            gr -= cr * rr - ci * ri;
-            gi += cr * ri + ci * rr;
-        }
-    });
-    const T ih = (T)ihd, ih2 = ih * ih;
-    T phi = f * ih, ax = gr * ih2, ay = gi * ih2, az = gz * ih2;
+            if (k + 1 < NP) {
+                T ar = cre<T>(Lb, k + 1, l), ai = cim<T>(Lb, k + 1, l);
+                gz += w * (ar * rr - ai * ri);
+                if (l >= 1) {
+                    T br = cre<T>(Lb, k + 1, l - 1), bi = cim<T>(Lb, k + 1, l - 1);
+                    gr += br * rr - bi * ri;
+                    gi += br * ri + bi * rr;
+                }
+                T cr = cre<T>(Lb, k + 1, l + 1), ci = cim<T>(Lb, k + 1, l + 1);
+                gr -= cr * rr - ci * ri;
+                gi += cr * ri + ci * rr;
+            }
+        });
+        const T ih = (T)ihd, ih2 = ih * ih;
+        phi = f * ih;
+        ax = gr * ih2;
+        ay = gi * ih2;
+        az = gz * ih2;
+    }
     if (ADD) {
         phi += far[s];
         ax += far[n + s];
@@ -584,6 +597,13 @@ k_l2p(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
     far[3 * n + s] = az;
 }
 
+// geometric centre of a box as the reference point of its targets' offsets
+__device__ inline double4 box_ref(const Root& r, const TBox& bx) {
+    double c[3];
+    cell_centre(r, box_cell(bx), c);
+    return make_double4(c[0], c[1], c[2], 0.0);
+}
+
 // W-list M2P of the FMM, one wave per target leaf; MT: the multipoles'
 // type (an FP32 copy for the FP32 path).  Short, uneven lists: a wave per
 // leaf replaces the divergent per-particle loops.  (The treecode's long,
@@ -591,10 +611,9 @@ k_l2p(int64_t n, const int32_t* __restrict__ leaf_of, const double4* __restrict_
 // has a target, while a wave per leaf of ~10 particles leaves lanes idle.)
 template <typename T, int NP, typename MT>
 __global__ void __launch_bounds__(256)
-k_farp(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int nleaves,
-       const double4* __restrict__ cen, const double4* __restrict__ p64,
+k_farp(const Root* __restrict__ root, Targets tg, const double4* __restrict__ cen,
        const int32_t* __restrict__ off, const int32_t* __restrict__ items,
-       const MT* __restrict__ M, T* __restrict__ far, int64_t n) {
+       const MT* __restrict__ M, T* __restrict__ far) {
     using V = typename Vec4<T>::type;
     using S = FarShape<NP, MT>;
     __shared__ int32_t sid[4][64];
@@ -602,42 +621,43 @@ k_farp(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves, int n
     __shared__ __align__(16) MT srow[4][S::FB * S::LD];
     const int w = threadIdx.x >> 6;
     const int li = blockIdx.x * 4 + w;
-    if (li >= nleaves) return;  // uniform per wave
-    const int b = leaves[li];
-    const Cell leaf = cells[b];
-    const double4 cb = cen[b];
-    const int e0 = off[b], e1 = off[b + 1];
-#define FARP_LEAF(G)                                                                        \
-    farp_leaf<T, NP, MT, G>(leaf, cb, cen, p64, items, e0, e1, M, sid[w], soff[w], srow[w], \
-                            far, n)
-    if (leaf.count <= 4)
-        FARP_LEAF(16);
-    else if (leaf.count <= 8)
-        FARP_LEAF(8);
-    else if (leaf.count <= 16)
-        FARP_LEAF(4);
-    else if (leaf.count <= 32)
-        FARP_LEAF(2);
+    if (li >= tg.nbox) return;  // uniform per wave
+    const TBox bx = tg.box[li];
+    const int row = list_row(tg, li, bx);
+    const double4 cb = box_ref(*root, bx);
+    const int e0 = off[row], e1 = off[row + 1];
+#define FARP_BOX(G)                                                                           \
+    farp_box<T, NP, MT, G>(bx, cb, cen, tg.p64, items, e0, e1, M, sid[w], soff[w], srow[w], \
+                           far, tg.n)
+    if (bx.count <= 4)
+        FARP_BOX(16);
+    else if (bx.count <= 8)
+        FARP_BOX(8);
+    else if (bx.count <= 16)
+        FARP_BOX(4);
+    else if (bx.count <= 32)
+        FARP_BOX(2);
     else
-        FARP_LEAF(1);
-#undef FARP_LEAF
+        FARP_BOX(1);
+#undef FARP_BOX
 }
 
-// Treecode far field: M2P over the accepted list of the particle's leaf, one
-// thread per sorted particle (neighbouring threads share a leaf and read the
+// Treecode far field: M2P over the accepted list of the target's box, one
+// thread per sorted target (neighbouring threads share a box and read the
 // same cells); MT: FP32 copy of the multipoles for the FP32 path.
 template <typename T, int NP, typename MT>
 __global__ void __launch_bounds__(256)
-k_treecode_far(int64_t n, const int32_t* __restrict__ leaf_of,
-               const double4* __restrict__ cen, const double4* __restrict__ p64,
-               const int32_t* __restrict__ a_off, const int32_t* __restrict__ a_items,
-               const MT* __restrict__ M, int ld, T* __restrict__ far) {
+k_treecode_far(Targets tg, const double4* __restrict__ cen, const int32_t* __restrict__ a_off,
+               const int32_t* __restrict__ a_items, const MT* __restrict__ M, int ld,
+               T* __restrict__ far) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = tg.n;
     if (s >= n) return;
-    const int b = leaf_of[s];
-    const double4 pj = p64[s];
+    const int b = tg.box_of[s];
+    const int row = list_row(tg, b, tg.box[b]);
+    const double4 pj = tg.p64[s];
     T phi = T(0), ax = T(0), ay = T(0), az = T(0);
-    for (int e = a_off[b]; e < a_off[b + 1]; ++e) {
+    for (int e = a_off[row]; e < a_off[row + 1]; ++e) {
         const int C = a_items[e];
         const double4 qc = cen[C];
         const double ic = qc.w;
@@ -771,16 +791,16 @@ __device__ __forceinline__ void far3_batch(bool valid, int k, const double4& cb,
     }
 }
 
-// The far field of one target leaf.  Lane groups are sized to the leaf:
+// The far field of one target box.  Lane groups are sized to the box:
 // TW = min(count, 64) lanes per group, G = 64 / TW groups (a leaf of 10
 // particles keeps 60 lanes busy where power-of-two groups of 16 kept 40),
 // batches of B = G * (64 / G) cells.  WALK: the M2P cells are read from the
-// FMM lists (W of the leaf from the CSR items, then the V slots of the leaf
-// and of each ancestor, the non-empty ones queued in the wave's id ring `q`
-// so that every batch but the last is full); otherwise from the leaf's CSR
-// list items[e0, e1).
+// FMM lists (the box's CSR items: W, and V for a box without sources; then
+// the V slots of cell b, the box's leaf or its host, and of each ancestor,
+// the non-empty ones queued in the wave's id ring `q` so that every batch
+// but the last is full); otherwise from the box's CSR list items[e0, e1).
 template <typename T, bool WALK>
-__device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b, const Cell& leaf,
+__device__ __forceinline__ void far3_box(const Cell* __restrict__ cells, int b, const TBox& leaf,
                                           const double4& cb, const double4* __restrict__ cen,
                                           const double4* __restrict__ p64,
                                           const int32_t* __restrict__ items, int e0, int e1,
@@ -854,28 +874,29 @@ __device__ __forceinline__ void far3_leaf(const Cell* __restrict__ cells, int b,
 }
 
 // Treecode far field at p = 3 from the Cartesian moments (k_cart3), one
-// wave per target leaf, lane groups sized to the leaf's particle count.
-// off/items: the leaf's M2P list (Barnes-Hut), or with WALK its W list, the
-// V lists being read from vsrc.
+// wave per target box, lane groups sized to its target count.  off/items:
+// the box's M2P list (Barnes-Hut), or with WALK its FMM-list part (W, and V
+// for a box without sources), the V lists of the cells above being read
+// from vsrc.
 template <typename T, bool WALK>
 __global__ void __launch_bounds__(256)
-k_treecode_far3(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
-                int nleaves, const double4* __restrict__ cen, const double4* __restrict__ p64,
-                const int32_t* __restrict__ off, const int32_t* __restrict__ items,
-                const int32_t* __restrict__ vsrc, const T* __restrict__ C, T* __restrict__ far,
-                int64_t n) {
+k_treecode_far3(const Cell* __restrict__ cells, const Root* __restrict__ root, Targets tg,
+                const double4* __restrict__ cen, const int32_t* __restrict__ off,
+                const int32_t* __restrict__ items, const int32_t* __restrict__ vsrc,
+                const T* __restrict__ C, T* __restrict__ far) {
     using V = typename Vec4<T>::type;
     __shared__ V shm[4][256];
     __shared__ int idq[4][WALK ? 256 : 1];
     const int w = threadIdx.x >> 6;
     const int li = blockIdx.x * 4 + w;
-    if (li >= nleaves) return;  // uniform per wave
-    const int b = leaves[li];
-    const Cell leaf = cells[b];
-    if (leaf.count <= 0) return;
-    const double4 cb = cen[b];
-    far3_leaf<T, WALK>(cells, b, leaf, cb, cen, p64, items, off[b], off[b + 1], vsrc, C, shm[w],
-                       idq[w], far, n);
+    if (li >= tg.nbox) return;  // uniform per wave
+    const TBox bx = tg.box[li];
+    if (bx.count <= 0) return;
+    const int row = list_row(tg, li, bx);
+    const double4 cb = box_ref(*root, bx);
+    const int walk_from = bx.leaf >= 0 ? bx.leaf : bx.host;
+    far3_box<T, WALK>(cells, walk_from, bx, cb, cen, tg.p64, items, off[row], off[row + 1], vsrc,
+                      C, shm[w], idq[w], far, tg.n);
 }
 
 __global__ void k_to_float(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
@@ -1150,8 +1171,8 @@ __global__ void k_export(const double* __restrict__ X, int ld, int ncells, int p
     }
 
 void fill_masses(Tree& t, const double* m, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_masses, dim3(grid_for(t.n, 256)), dim3(256), 0, s, t.n, t.ns,
-                       t.perm, m, t.xs, t.ys, t.zs, t.p32, t.p64);
+    hipLaunchKernelGGL(k_fill_masses, dim3(grid_for(t.n, 256)), dim3(256), 0, s, t.n, t.perm,
+                       m, t.xs, t.ys, t.zs, t.p32, t.p64, t.status);
     LAUNCH_CHECK();
 }
 
@@ -1259,55 +1280,56 @@ static const float* m_as_float(Tree& t, hipStream_t s) {
     return m;
 }
 
-// FMM far field: M2P over the W lists (one wave per target leaf), then L2P
-// added at every particle
-void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
-    if (t.n == 0) return;
-    const bool w = t.n_w > 0;
+// FMM far field: M2P over the boxes' far lists (the W lists; V too for
+// boxes without sources), one wave per target box, then L2P added at every
+// target
+void run_far(Tree& t, const Targets& tg, int p, bool fp64, const int32_t* off,
+             const int32_t* items, int64_t nitems, void* far, hipStream_t s) {
+    if (tg.n == 0) return;
+    const bool w = nitems > 0;
     const float* M32 = (!fp64 && w) ? m_as_float(t, s) : nullptr;
-    const dim3 grid(grid_for(t.nleaves, 4)), block(256), pgrid(grid_for(t.n, 256));
+    const dim3 grid(grid_for(tg.nbox, 4)), block(256), pgrid(grid_for(tg.n, 256));
+    const double4* cen = (const double4*)t.cen;
 #define FAR_CASE(NP)                                                                          \
     if (fp64) {                                                                               \
         if (w)                                                                                \
-            hipLaunchKernelGGL((k_farp<double, NP, double>), grid, block, 0, s, t.cells,        \
-                               t.leaves, t.nleaves, (const double4*)t.cen, t.p64, t.w_off,     \
-                               t.w_items, t.M, (double*)far, t.n);                             \
+            hipLaunchKernelGGL((k_farp<double, NP, double>), grid, block, 0, s, t.root, tg,     \
+                               cen, off, items, t.M, (double*)far);                            \
         if (w)                                                                                \
-            hipLaunchKernelGGL((k_l2p<double, NP, true>), pgrid, block, 0, s, t.n, t.leaf_of,  \
-                               (const double4*)t.cen, t.p64, t.L, t.ldm, (double*)far);        \
+            hipLaunchKernelGGL((k_l2p<double, NP, true>), pgrid, block, 0, s, tg, cen, t.L,     \
+                               t.ldm, (double*)far);                                           \
         else                                                                                  \
-            hipLaunchKernelGGL((k_l2p<double, NP, false>), pgrid, block, 0, s, t.n, t.leaf_of, \
-                               (const double4*)t.cen, t.p64, t.L, t.ldm, (double*)far);        \
+            hipLaunchKernelGGL((k_l2p<double, NP, false>), pgrid, block, 0, s, tg, cen, t.L,    \
+                               t.ldm, (double*)far);                                           \
     } else {                                                                                  \
         if (w)                                                                                \
-            hipLaunchKernelGGL((k_farp<float, NP, float>), grid, block, 0, s, t.cells,          \
-                               t.leaves, t.nleaves, (const double4*)t.cen, t.p64, t.w_off,     \
-                               t.w_items, M32, (float*)far, t.n);                              \
+            hipLaunchKernelGGL((k_farp<float, NP, float>), grid, block, 0, s, t.root, tg, cen,  \
+                               off, items, M32, (float*)far);                                  \
         if (w)                                                                                \
-            hipLaunchKernelGGL((k_l2p<float, NP, true>), pgrid, block, 0, s, t.n, t.leaf_of,   \
-                               (const double4*)t.cen, t.p64, t.L, t.ldm, (float*)far);         \
+            hipLaunchKernelGGL((k_l2p<float, NP, true>), pgrid, block, 0, s, tg, cen, t.L,      \
+                               t.ldm, (float*)far);                                            \
         else                                                                                  \
-            hipLaunchKernelGGL((k_l2p<float, NP, false>), pgrid, block, 0, s, t.n, t.leaf_of,  \
-                               (const double4*)t.cen, t.p64, t.L, t.ldm, (float*)far);         \
+            hipLaunchKernelGGL((k_l2p<float, NP, false>), pgrid, block, 0, s, tg, cen, t.L,     \
+                               t.ldm, (float*)far);                                            \
     }
     HFMM_DISPATCH_P(p, FAR_CASE);
 #undef FAR_CASE
     LAUNCH_CHECK();
 }
 
-void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
-    if (t.n == 0) return;
+// Treecode far field over the boxes' M2P lists off/items; walk: over the FMM
+// lists at p = 3 the lists hold only the boxes' own part and the V lists of
+// the cells above are read directly
+void run_treecode_far(Tree& t, const Targets& tg, int p, bool fp64, bool walk,
+                      const int32_t* off, const int32_t* items, void* far, hipStream_t s) {
+    if (tg.n == 0) return;
+    const double4* cen = (const double4*)t.cen;
     if (p == 3) {  // quadrupole moments: the Cartesian form
-        // over the FMM lists the far cells are read from V and W directly
-        const bool walk = t.bh_theta == kFmmListTheta;
-        const int32_t* off = walk ? t.w_off : t.a_off;
-        const int32_t* items = walk ? t.w_items : t.a_items;
         const int64_t nel = (int64_t)t.ncells * 12;
-        const dim3 grid(grid_for(t.nleaves, 4)), block(256);
+        const dim3 grid(grid_for(tg.nbox, 4)), block(256);
 #define FAR3(TT, W)                                                                            \
-    hipLaunchKernelGGL((k_treecode_far3<TT, W>), grid, block, 0, s, t.cells, t.leaves,          \
-                       t.nleaves, (const double4*)t.cen, t.p64, off, items, t.vsrc, c,          \
-                       (TT*)far, t.n)
+    hipLaunchKernelGGL((k_treecode_far3<TT, W>), grid, block, 0, s, t.cells, t.root, tg, cen,   \
+                       off, items, t.vsrc, c, (TT*)far)
         if (fp64) {
             double* c = t.arena.down<double>(nel);
             hipLaunchKernelGGL(k_cart3<double>, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
@@ -1331,17 +1353,16 @@ void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s) {
         LAUNCH_CHECK();
         return;
     }
-    // other orders: the spherical form, one thread per particle
+    if (walk) throw Status{HFMM_E_STATE};  // other orders take full lists
+    // other orders: the spherical form, one thread per target
     const float* M32 = fp64 ? nullptr : m_as_float(t, s);
-#define TF_CASE(NP)                                                                           \
-    if (fp64)                                                                                 \
-        hipLaunchKernelGGL((k_treecode_far<double, NP, double>), dim3(grid_for(t.n, 256)),     \
-                           dim3(256), 0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64,     \
-                           t.a_off, t.a_items, t.M, t.ldm, (double*)far);                     \
-    else                                                                                      \
-        hipLaunchKernelGGL((k_treecode_far<float, NP, float>), dim3(grid_for(t.n, 256)),       \
-                           dim3(256), 0, s, t.n, t.leaf_of, (const double4*)t.cen, t.p64,     \
-                           t.a_off, t.a_items, M32, t.ldm, (float*)far);
+#define TF_CASE(NP)                                                                            \
+    if (fp64)                                                                                  \
+        hipLaunchKernelGGL((k_treecode_far<double, NP, double>), dim3(grid_for(tg.n, 256)),     \
+                           dim3(256), 0, s, tg, cen, off, items, t.M, t.ldm, (double*)far);    \
+    else                                                                                       \
+        hipLaunchKernelGGL((k_treecode_far<float, NP, float>), dim3(grid_for(tg.n, 256)),       \
+                           dim3(256), 0, s, tg, cen, off, items, M32, t.ldm, (float*)far);
     HFMM_DISPATCH_P(p, TF_CASE);
 #undef TF_CASE
     LAUNCH_CHECK();

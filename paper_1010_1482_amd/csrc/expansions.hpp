@@ -20,8 +20,10 @@ void run_m2l_ops_lp(int p, int precision, int RB, int KQ, int32_t* bexp, void* h
 void run_pack(const double* M, int ldm, int ncells, int P, int ld, void* out, bool fp64,
               hipStream_t s);
 void run_p2l(Tree& t, int p, bool fp64, double* LX, hipStream_t s);
-void run_far(Tree& t, int p, bool fp64, void* far, hipStream_t s);
-void run_treecode_far(Tree& t, int p, bool fp64, void* far, hipStream_t s);
+void run_far(Tree& t, const Targets& tg, int p, bool fp64, const int32_t* off,
+             const int32_t* items, int64_t nitems, void* far, hipStream_t s);
+void run_treecode_far(Tree& t, const Targets& tg, int p, bool fp64, bool walk,
+                      const int32_t* off, const int32_t* items, void* far, hipStream_t s);
 void run_export(const double* X, int ld, int ncells, int p, const double* cen, int which,
                 double* out, hipStream_t s);
 

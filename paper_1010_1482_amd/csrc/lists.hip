@@ -279,6 +279,189 @@ __global__ void k_x_cells(const int32_t* __restrict__ foff, int nc, int32_t* __r
 }
 
 // ---------------------------------------------------------------------
+// lists of target boxes (separate targets)
+// ---------------------------------------------------------------------
+// A box without sources is a leaf added to the tree, so its lists follow
+// the same definitions as a leaf's.  near: U (+ X for a box without
+// sources, whose P2L the FMM cannot hold in an expansion of its own);
+// far: W (+ V for a box without sources, by M2P at its targets).  For the
+// treecode over the FMM lists (mode != BOX_FMM) near also takes X of the
+// box's own leaf (or host) and of every cell above it, and with
+// BOX_TREECODE_FULL far takes their V lists too (at p = 3 the far kernel
+// reads those from the V table itself).
+__device__ void box_lists_one(const Cell* __restrict__ cells, int ncells,
+                              const int32_t* __restrict__ coll,
+                              const int32_t* __restrict__ vsrc,
+                              const int32_t* __restrict__ x_off,
+                              const int32_t* __restrict__ x_items, const TBox& bx, int mode,
+                              int32_t* pn, int32_t* pf, int& nn, int& nf, bool& over) {
+    const Cell B = box_cell(bx);
+    const bool src = bx.leaf >= 0;
+    const int P = src ? cells[bx.leaf].parent : bx.host;
+    // coarser adjacent leaves: leaf colleagues of the cells above the box
+    for (int A = P; A >= 0; A = cells[A].parent) {
+        const int32_t* ca = coll + (int64_t)A * kColl;
+        for (int q = 0; q < kColl; ++q) {
+            const int C = ca[q];
+            if (C < 0) continue;
+            const Cell cc = cells[C];
+            if (cc.nchild == 0 && cells_adjacent(cc, B)) {
+                if (pn) pn[nn] = C;
+                ++nn;
+            }
+        }
+    }
+    // colleagues of the box: leaves (U), and below the others finer
+    // adjacent leaves (U) and the first non-adjacent cells (W)
+    int stack[kStack];
+    for (int q = 0; q < kColl; ++q) {
+        const int ex = q / 9 - 1, ey = (q / 3) % 3 - 1, ez = q % 3 - 1;
+        int C;
+        if (P >= 0)
+            C = cell_at_offset(cells, coll + (int64_t)P * kColl, B, ex, ey, ez);
+        else  // level 0: the root is the only cell
+            C = (ncells > 0 && B.ix + ex == 0 && B.iy + ey == 0 && B.iz + ez == 0) ? 0 : -1;
+        if (C < 0) continue;
+        const Cell cc = cells[C];
+        if (cc.nchild == 0) {
+            if (pn) pn[nn] = C;
+            ++nn;
+            continue;
+        }
+        int sp = 0;
+        stack[sp++] = C;
+        while (sp > 0) {
+            const Cell cur = cells[stack[--sp]];
+            for (int i = cur.nchild - 1; i >= 0; --i) {
+                const int D = cur.child + i;
+                const Cell d = cells[D];
+                if (cells_adjacent(d, B)) {
+                    if (d.nchild == 0) {
+                        if (pn) pn[nn] = D;
+                        ++nn;
+                    } else if (sp < kStack) {
+                        stack[sp++] = D;
+                    } else {
+                        over = true;
+                    }
+                } else {
+                    if (pf) pf[nf] = D;
+                    ++nf;
+                }
+            }
+        }
+    }
+    if (!src) {
+        // V: children of the colleagues of P not adjacent to the box
+        // (outside the root: the root when it is not adjacent)
+        if (P >= 0) {
+            if (B.level >= 2) {
+                const int32_t* cp = coll + (int64_t)P * kColl;
+                for (int q = 0; q < kColl; ++q) {
+                    const int K = cp[q];
+                    if (K < 0) continue;
+                    const Cell kc = cells[K];
+                    for (int i = 0; i < kc.nchild; ++i) {
+                        const int D = kc.child + i;
+                        if (!cells_adjacent(cells[D], B)) {
+                            if (pf) pf[nf] = D;
+                            ++nf;
+                        }
+                    }
+                }
+            }
+        } else if (ncells > 0 && !cells_adjacent(cells[0], B)) {
+            if (pf) pf[nf] = 0;
+            ++nf;
+        }
+        // X: leaf colleagues of P and of the cells above it, adjacent to P
+        // and not to the box
+        if (P >= 0 && B.level >= 2) {
+            const Cell Pc = cells[P];
+            for (int A = P; A >= 0; A = cells[A].parent) {
+                const int32_t* ca = coll + (int64_t)A * kColl;
+                for (int q = 0; q < kColl; ++q) {
+                    const int C = ca[q];
+                    if (C < 0) continue;
+                    const Cell cc = cells[C];
+                    if (cc.nchild == 0 && cells_adjacent(cc, Pc) && !cells_adjacent(cc, B)) {
+                        if (pn) pn[nn] = C;
+                        ++nn;
+                    }
+                }
+            }
+        }
+    }
+    if (mode != BOX_FMM) {
+        for (int A = src ? bx.leaf : P; A >= 0; A = cells[A].parent) {
+            for (int e = x_off[A]; e < x_off[A + 1]; ++e) {
+                if (pn) pn[nn] = x_items[e];
+                ++nn;
+            }
+            if (mode == BOX_TREECODE_FULL)
+                for (int q = 0; q < kSlots; ++q) {
+                    const int v = vsrc[(int64_t)A * kSlots + q];
+                    if (v >= 0) {
+                        if (pf) pf[nf] = v;
+                        ++nf;
+                    }
+                }
+        }
+    }
+}
+
+// count pass (in == nullptr): cn, cf per box; fill pass: the items
+__global__ void k_box_lists(const Cell* __restrict__ cells, int ncells, Targets tg,
+                            const int32_t* __restrict__ coll, const int32_t* __restrict__ vsrc,
+                            const int32_t* __restrict__ x_off,
+                            const int32_t* __restrict__ x_items, int mode,
+                            int32_t* __restrict__ cn, int32_t* __restrict__ cf,
+                            const int32_t* __restrict__ on, const int32_t* __restrict__ of,
+                            int32_t* __restrict__ in, int32_t* __restrict__ inf,
+                            int32_t* __restrict__ status) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= tg.nbox) return;
+    const TBox bx = tg.box[b];
+    int nn = 0, nf = 0;
+    bool over = false;
+    box_lists_one(cells, ncells, coll, vsrc, x_off, x_items, bx, mode, in ? in + on[b] : nullptr,
+                  inf ? inf + of[b] : nullptr, nn, nf, over);
+    if (!in) {
+        cn[b] = nn;
+        cf[b] = nf;
+        if (over) atomicOr(status, (int32_t)ST_OVERFLOW);
+    }
+}
+
+void build_box_lists(Tree& t, const Targets& tg, int mode, hipStream_t s) {
+    if (!t.fmm_lists) throw Status{HFMM_E_STATE};
+    Arena& A = t.arena;
+    const int nb = tg.nbox;
+    int32_t* cnt = A.down<int32_t>(2 * (size_t)(nb + 1));
+    int32_t *cn = cnt, *cf = cnt + nb + 1;
+    hipLaunchKernelGGL(k_box_lists, dim3(grid_for(nb, 64)), dim3(64), 0, s, t.cells, t.ncells,
+                       tg, t.coll, t.vsrc, t.x_off, t.x_items, mode, cn, cf, nullptr, nullptr,
+                       nullptr, nullptr, t.status);
+    LAUNCH_CHECK();
+    t.tn_off = A.up<int32_t>(nb + 1);
+    t.tf_off = A.up<int32_t>(nb + 1);
+    scan_exclusive_i32(cn, t.tn_off, nb, A, s);
+    scan_exclusive_i32(cf, t.tf_off, nb, A, s);
+    int32_t h[2];
+    HIP_TRY(hipMemcpyAsync(&h[0], t.tn_off + nb, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h[1], t.tf_off + nb, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    t.tg_near = h[0];
+    t.tg_far = h[1];
+    t.tn_items = A.up<int32_t>(std::max<int64_t>(t.tg_near, 1));
+    t.tf_items = A.up<int32_t>(std::max<int64_t>(t.tg_far, 1));
+    hipLaunchKernelGGL(k_box_lists, dim3(grid_for(nb, 64)), dim3(64), 0, s, t.cells, t.ncells,
+                       tg, t.coll, t.vsrc, t.x_off, t.x_items, mode, nullptr, nullptr, t.tn_off,
+                       t.tf_off, t.tn_items, t.tf_items, t.status);
+    LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------
 // M2L tiles: targets of level >= 2 ordered by (level, octant)
 // ---------------------------------------------------------------------
 constexpr int kGroups = 8 * (HFMM_KEY_LEVELS + 2);
@@ -466,15 +649,22 @@ __device__ __forceinline__ int bh_class(const Cell& cc, int C, const Cell& B, in
     return cc.nchild == 0 ? 2 : 0;
 }
 
-// subtree of an opened node C0 with a private stack: counts (or writes)
-__device__ inline void bh_subtree(const Cell* __restrict__ cells, int C0, const Cell& B, int b,
+// subtree of an opened node C0 with a private stack: counts (or writes);
+// returns true when the stack overflowed (entries were dropped)
+__device__ inline bool bh_subtree(const Cell* __restrict__ cells, int C0, const Cell& B, int b,
                                   const Root& r, const double4* __restrict__ cen,
                                   const double lo[3], double hb, double theta, int32_t* pa,
                                   int32_t* pb, int& na, int& np) {
     int stack[kStack];
     int sp = 0;
+    bool over = false;
     const Cell c0 = cells[C0];
-    for (int i = c0.nchild - 1; i >= 0 && sp < kStack; --i) stack[sp++] = c0.child + i;
+    for (int i = c0.nchild - 1; i >= 0; --i) {
+        if (sp < kStack)
+            stack[sp++] = c0.child + i;
+        else
+            over = true;
+    }
     while (sp > 0) {
         const int C = stack[--sp];
         const Cell cc = cells[C];
@@ -486,54 +676,71 @@ __device__ inline void bh_subtree(const Cell* __restrict__ cells, int C0, const 
             if (pb) pb[np] = C;
             ++np;
         } else {
-            for (int i = cc.nchild - 1; i >= 0 && sp < kStack; --i) stack[sp++] = cc.child + i;
+            for (int i = cc.nchild - 1; i >= 0; --i) {
+                if (sp < kStack)
+                    stack[sp++] = cc.child + i;
+                else
+                    over = true;
+            }
         }
     }
+    return over;
 }
 
-// Sibling leaves (the leaf children of one cell, at most 8) are traversed
+// Sibling boxes (the target boxes under one cell, at most 8) are traversed
 // together by one wave: a stack entry carries a node and the set of the
-// group's leaves for which it is visited (all its ancestors opened for
-// them).  Each leaf's lists are exactly those of its own traversal; the
-// tree is read once per group instead of once per leaf.
+// group's boxes for which it is visited (all its ancestors opened for
+// them).  Each box's lists are exactly those of its own traversal; the tree
+// is read once per group instead of once per box.  A box's own leaf (a
+// leaf of the tree) goes to P2P; a box outside the root has no ancestor.
 constexpr int kBhGroup = 8;
 
+// the cell above a box (-1 for the root leaf and for boxes outside the root)
+__device__ __forceinline__ int box_parent(const Cell* __restrict__ cells, const TBox& b) {
+    return b.leaf >= 0 ? cells[b.leaf].parent : b.host;
+}
+
 __global__ void __launch_bounds__(256)
-k_bh_group(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
-           const int32_t* __restrict__ gstart, const int32_t* __restrict__ ngroups,
-           const Root* __restrict__ root, const double4* __restrict__ cen, double theta,
-           int32_t* __restrict__ ca, int32_t* __restrict__ cb, const int32_t* __restrict__ oa,
-           const int32_t* __restrict__ ob, int32_t* __restrict__ ia, int32_t* __restrict__ ib) {
+k_bh_group(const Cell* __restrict__ cells, Targets tg, const int32_t* __restrict__ gstart,
+           const int32_t* __restrict__ ngroups, const Root* __restrict__ root,
+           const double4* __restrict__ cen, double theta, int32_t* __restrict__ ca,
+           int32_t* __restrict__ cb, const int32_t* __restrict__ oa,
+           const int32_t* __restrict__ ob, int32_t* __restrict__ ia, int32_t* __restrict__ ib,
+           int32_t* __restrict__ status) {
 #pragma clang fp contract(off)
     __shared__ int stk[4][kBhCap];
     __shared__ uint8_t msk[4][kBhCap];
-    // per wave: the group's leaves, their box corners and list offsets
+    // per wave: the group's boxes, their corners, own leaves and list offsets
     __shared__ double glo[4][kBhGroup][3];
-    __shared__ int gbl[4][kBhGroup], goa[4][kBhGroup], gob[4][kBhGroup];
+    __shared__ int gbl[4][kBhGroup], grow[4][kBhGroup], goa[4][kBhGroup], gob[4][kBhGroup];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int gi = blockIdx.x * 4 + w;
     if (gi >= *ngroups) return;  // uniform per wave; no block-wide barrier below
     const bool fill = ia != nullptr;
     const int l0 = gstart[gi], nl = gstart[gi + 1] - l0;
     const Root r = *root;
-    const Cell B0 = cells[leaves[l0]];
+    const TBox B0 = tg.box[l0];
     const int lv = B0.level;
     const double hb = cell_side(r, lv);
     if (lane < nl) {
-        const int b = leaves[l0 + lane];
-        const Cell Bi = cells[b];
-        gbl[w][lane] = b;
+        const TBox Bi = tg.box[l0 + lane];
+        const int row = list_row(tg, l0 + lane, Bi);
+        gbl[w][lane] = Bi.leaf;
+        grow[w][lane] = row;
         glo[w][lane][0] = r.b[0] + (double)Bi.ix * hb;
         glo[w][lane][1] = r.b[1] + (double)Bi.iy * hb;
         glo[w][lane][2] = r.b[2] + (double)Bi.iz * hb;
-        goa[w][lane] = fill ? oa[b] : 0;
-        gob[w][lane] = fill ? ob[b] : 0;
+        goa[w][lane] = fill ? oa[row] : 0;
+        gob[w][lane] = fill ? ob[row] : 0;
     }
     int na[kBhGroup], np[kBhGroup];
 #pragma unroll
     for (int i = 0; i < kBhGroup; ++i) na[i] = np[i] = 0;
-    // the common parent (the root for a lone root leaf)
-    const Cell P = B0.parent >= 0 ? cells[B0.parent] : B0;
+    // the common parent contains every box of the group (none outside the
+    // root or for the root leaf)
+    const int pid = box_parent(cells, B0);
+    Cell P;
+    if (pid >= 0) P = cells[pid];
     const uint32_t all = (1u << nl) - 1u;
     int* st = stk[w];
     uint8_t* sm = msk[w];
@@ -543,6 +750,7 @@ k_bh_group(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
         sm[0] = (uint8_t)all;
     }
     wave_lds_fence();
+    bool overflow = false;
     while (sp > 0) {
         const int k = min(sp, 64), base = sp - k;
         const int C = lane < k ? st[base + lane] : -1;
@@ -553,8 +761,8 @@ k_bh_group(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
         int nch = 0, child = 0;
         if (C >= 0) {
             const Cell cc = cells[C];
-            if (cc.level < lv && is_ancestor_or_self(cc, P)) {
-                om = m;  // contains every leaf of the group
+            if (pid >= 0 && cc.level < lv && is_ancestor_or_self(cc, P)) {
+                om = m;  // contains every box of the group
             } else {
                 const double4 q = cen[C];
                 const double pc[3] = {q.x, q.y, q.z};
@@ -563,7 +771,7 @@ k_bh_group(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
                 for (int i = 0; i < nl; ++i) {
                     if (!((m >> i) & 1u)) continue;
                     if (C == gbl[w][i]) {
-                        pm |= 1u << i;  // the leaf itself
+                        pm |= 1u << i;  // the box's own leaf
                     } else if (side < theta * dist_point_box(pc, glo[w][i], hb)) {
                         am |= 1u << i;
                     } else if (cc.nchild == 0) {
@@ -599,23 +807,23 @@ k_bh_group(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
             sp += total;
         } else {
             // stack full: every lane finishes the subtree of its opened node,
-            // leaf by leaf, with a private stack
+            // box by box, with a private stack
 #pragma unroll
             for (int i = 0; i < kBhGroup; ++i) {
                 if (i >= nl) break;
-                const int b = gbl[w][i];
-                const Cell Bi = cells[b];
+                const TBox Bi = tg.box[l0 + i];
+                const Cell Bc = box_cell(Bi);
                 int ka = 0, kp = 0;
                 const bool mine = (om >> i) & 1u;
                 if (mine)
-                    bh_subtree(cells, C, Bi, b, r, cen, glo[w][i], hb, theta, nullptr, nullptr,
-                               ka, kp);
+                    overflow |= bh_subtree(cells, C, Bc, gbl[w][i], r, cen, glo[w][i], hb,
+                                           theta, nullptr, nullptr, ka, kp);
                 int ta, tp;
                 const int oa_l = wave_excl_scan(ka, lane, ta);
                 const int ob_l = wave_excl_scan(kp, lane, tp);
                 if (fill && mine) {
                     int xa = 0, xp = 0;
-                    bh_subtree(cells, C, Bi, b, r, cen, glo[w][i], hb, theta,
+                    bh_subtree(cells, C, Bc, gbl[w][i], r, cen, glo[w][i], hb, theta,
                                ia + goa[w][i] + na[i] + oa_l, ib + gob[w][i] + np[i] + ob_l, xa,
                                xp);
                 }
@@ -625,23 +833,28 @@ k_bh_group(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
         }
         wave_lds_fence();
     }
+    if (status && __ballot(overflow)) {
+        if (lane == 0) atomicOr(status, (int32_t)ST_OVERFLOW);
+    }
     if (!fill) {
 #pragma unroll
         for (int i = 0; i < kBhGroup; ++i)
             if (i < nl && lane == i) {
-                ca[gbl[w][i]] = na[i];
-                cb[gbl[w][i]] = np[i];
+                ca[grow[w][i]] = na[i];
+                cb[grow[w][i]] = np[i];
             }
     }
 }
 
-// groups of sibling leaves: a flag where a leaf's parent differs from the
-// previous leaf's (sibling leaves are adjacent in the leaf array)
-__global__ void k_bh_group_flags(const Cell* __restrict__ cells, const int32_t* __restrict__ leaves,
-                                 int nleaves, int32_t* __restrict__ flag) {
+// groups of sibling boxes: a flag where a box's parent differs from the
+// previous box's (sibling boxes are adjacent in box order); boxes outside
+// the root each form their own group
+__global__ void k_bh_group_flags(const Cell* __restrict__ cells, Targets tg,
+                                 int32_t* __restrict__ flag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nleaves) return;
-    flag[i] = (i == 0 || cells[leaves[i]].parent != cells[leaves[i - 1]].parent) ? 1 : 0;
+    if (i >= tg.nbox) return;
+    const int pi = box_parent(cells, tg.box[i]);
+    flag[i] = (i == 0 || pi < 0 || pi != box_parent(cells, tg.box[i - 1])) ? 1 : 0;
 }
 
 __global__ void k_bh_group_starts(const int32_t* __restrict__ flag,
@@ -653,6 +866,51 @@ __global__ void k_bh_group_starts(const int32_t* __restrict__ flag,
     if (i == nleaves - 1) gstart[gidx[nleaves]] = nleaves;
 }
 
+// Barnes-Hut lists of the boxes of tg into rows of nrows (+1) offsets:
+// counts, scan, one read-back of the totals, fill
+static void bh_lists_rows(Tree& t, const Targets& tg, double theta, int nrows, int32_t*& a_off,
+                          int32_t*& b_off, int32_t*& a_items, int32_t*& b_items, int64_t& n_a,
+                          int64_t& n_b, hipStream_t s) {
+    Arena& A = t.arena;
+    int32_t* cnt = A.down<int32_t>(2 * (size_t)(nrows + 1));
+    int32_t *ca = cnt, *cb = cnt + nrows + 1;
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * (nrows + 1), s));
+    // sibling groups (at most 8 boxes each); the launches cover one wave
+    // per box, the waves past the group count exit
+    const int nb = tg.nbox;
+    int32_t* gflag = A.down<int32_t>(nb);
+    int32_t* gidx = A.down<int32_t>(nb + 1);
+    int32_t* gstart = A.down<int32_t>(nb + 1);
+    hipLaunchKernelGGL(k_bh_group_flags, dim3(grid_for(nb, 256)), dim3(256), 0, s, t.cells, tg,
+                       gflag);
+    LAUNCH_CHECK();
+    scan_exclusive_i32(gflag, gidx, nb, A, s);
+    hipLaunchKernelGGL(k_bh_group_starts, dim3(grid_for(nb, 256)), dim3(256), 0, s, gflag,
+                       gidx, nb, gstart);
+    LAUNCH_CHECK();
+    const int32_t* ngroups = gidx + nb;
+    hipLaunchKernelGGL(k_bh_group, dim3(grid_for(nb, 4)), dim3(256), 0, s, t.cells, tg, gstart,
+                       ngroups, t.root, (const double4*)t.cen, theta, ca, cb, nullptr, nullptr,
+                       nullptr, nullptr, t.status);
+    LAUNCH_CHECK();
+    a_off = A.up<int32_t>(nrows + 1);
+    b_off = A.up<int32_t>(nrows + 1);
+    scan_exclusive_i32(ca, a_off, nrows, A, s);
+    scan_exclusive_i32(cb, b_off, nrows, A, s);
+    int32_t h[2];
+    HIP_TRY(hipMemcpyAsync(&h[0], a_off + nrows, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h[1], b_off + nrows, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    n_a = h[0];
+    n_b = h[1];
+    a_items = A.up<int32_t>(std::max<int64_t>(n_a, 1));
+    b_items = A.up<int32_t>(std::max<int64_t>(n_b, 1));
+    hipLaunchKernelGGL(k_bh_group, dim3(grid_for(nb, 4)), dim3(256), 0, s, t.cells, tg, gstart,
+                       ngroups, t.root, (const double4*)t.cen, theta, nullptr, nullptr, a_off,
+                       b_off, a_items, b_items, nullptr);
+    LAUNCH_CHECK();
+}
+
 void build_bh_lists(Tree& t, double theta, hipStream_t s) {
     Arena& A = t.arena;
     if (t.bh_theta == theta && t.a_off) {
@@ -661,47 +919,18 @@ void build_bh_lists(Tree& t, double theta, hipStream_t s) {
     }
     A.lo = t.mark_up;  // lists live above the upward data
     t.fmm_lists = false;
-    const int nc = t.ncells;
-    int32_t* cnt = A.down<int32_t>(2 * (size_t)(nc + 1));
-    int32_t *ca = cnt, *cb = cnt + nc + 1;
-    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * (nc + 1), s));
-    // sibling groups (at most 8 leaves each); the launches cover one wave
-    // per leaf, the waves past the group count exit
-    const int nlv = t.nleaves;
-    int32_t* gflag = A.down<int32_t>(nlv);
-    int32_t* gidx = A.down<int32_t>(nlv + 1);
-    int32_t* gstart = A.down<int32_t>(nlv + 1);
-    hipLaunchKernelGGL(k_bh_group_flags, dim3(grid_for(nlv, 256)), dim3(256), 0, s, t.cells,
-                       t.leaves, nlv, gflag);
-    LAUNCH_CHECK();
-    scan_exclusive_i32(gflag, gidx, nlv, A, s);
-    hipLaunchKernelGGL(k_bh_group_starts, dim3(grid_for(nlv, 256)), dim3(256), 0, s, gflag,
-                       gidx, nlv, gstart);
-    LAUNCH_CHECK();
-    const int32_t* ngroups = gidx + nlv;
-    hipLaunchKernelGGL(k_bh_group, dim3(grid_for(nlv, 4)), dim3(256), 0, s, t.cells, t.leaves,
-                       gstart, ngroups, t.root, (const double4*)t.cen, theta, ca, cb, nullptr,
-                       nullptr, nullptr, nullptr);
-    LAUNCH_CHECK();
-    t.a_off = A.up<int32_t>(nc + 1);
-    t.b_off = A.up<int32_t>(nc + 1);
-    scan_exclusive_i32(ca, t.a_off, nc, A, s);
-    scan_exclusive_i32(cb, t.b_off, nc, A, s);
-    int32_t h[2];
-    HIP_TRY(hipMemcpyAsync(&h[0], t.a_off + nc, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&h[1], t.b_off + nc, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    t.n_a = h[0];
-    t.n_b = h[1];
-    t.a_items = A.up<int32_t>(std::max<int64_t>(t.n_a, 1));
-    t.b_items = A.up<int32_t>(std::max<int64_t>(t.n_b, 1));
-    hipLaunchKernelGGL(k_bh_group, dim3(grid_for(nlv, 4)), dim3(256), 0, s, t.cells, t.leaves,
-                       gstart, ngroups, t.root, (const double4*)t.cen, theta, nullptr, nullptr,
-                       t.a_off, t.b_off, t.a_items, t.b_items);
-    LAUNCH_CHECK();
+    bh_lists_rows(t, self_targets(t), theta, t.ncells, t.a_off, t.b_off, t.a_items, t.b_items,
+                  t.n_a, t.n_b, s);
     A.release_temps();
     t.bh_theta = theta;
     t.mark_bh = A.lo;
+}
+
+// Barnes-Hut lists of separate target boxes (rows by box), above the
+// current arena mark
+void build_bh_box_lists(Tree& t, const Targets& tg, double theta, hipStream_t s) {
+    bh_lists_rows(t, tg, theta, tg.nbox, t.tf_off, t.tn_off, t.tf_items, t.tn_items, t.tg_far,
+                  t.tg_near, s);
 }
 
 // ---------------------------------------------------------------------

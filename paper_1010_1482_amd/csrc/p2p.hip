@@ -60,8 +60,9 @@ __device__ __forceinline__ typename Vec4<T>::type p2p_pad() {
     return typename Vec4<T>::type{T(1e18), T(1e18), T(1e18), T(0)};
 }
 
-// The target leaf as its own source (coincident points possible).  In FP32
-// positions are relative to the leaf centre, so no offset is added.
+// The target box's own leaf as a source (coincident points possible): the
+// sources of cell c against targets me.  In FP32 both are relative to the
+// same centre (the box is the leaf), so no offset is added.
 template <typename T, int G, bool SOFT>
 __device__ __forceinline__ void p2p_self(const Cell& c, const typename Vec4<T>::type* __restrict__ P,
                                          typename Vec4<T>::type* sh, T xi, T yi, T zi, T eps2,
@@ -142,33 +143,37 @@ __device__ __forceinline__ void p2p_packed(const Cell* __restrict__ cells, int s
     }
 }
 
+// The targets of one box against the list cells items[e0, e1) (the box's
+// own leaf, when it is in the list, summed on its own with the r^2 == 0
+// test).  TP: the sorted targets, P: the sorted sources.
 template <typename T, typename O, int G, bool SOFT>
-__device__ __forceinline__ void p2p_leaf(const Cell& leaf, int self, bool in_list,
-                                         const Root& root,
-                                         const Cell* __restrict__ cells,
-                                         const int32_t* __restrict__ items, int e0, int e1,
-                                         const typename Vec4<T>::type* __restrict__ P,
-                                         typename Vec4<T>::type* sh, int* own,
-                                         const T* __restrict__ far,
-                                         int64_t n, const int32_t* __restrict__ perm,
-                                         int64_t out_shift, T eps2, O* __restrict__ phi_o,
-                                         O* __restrict__ ax_o, O* __restrict__ ay_o,
-                                         O* __restrict__ az_o) {
+__device__ __forceinline__ void p2p_box(const TBox& bx, bool in_list, const Root& root,
+                                        const Cell* __restrict__ cells,
+                                        const int32_t* __restrict__ items, int e0, int e1,
+                                        const typename Vec4<T>::type* __restrict__ P,
+                                        const typename Vec4<T>::type* __restrict__ TP,
+                                        typename Vec4<T>::type* sh, int* own,
+                                        const T* __restrict__ far, int64_t n,
+                                        const int32_t* __restrict__ perm, T eps2,
+                                        O* __restrict__ phi_o, O* __restrict__ ax_o,
+                                        O* __restrict__ ay_o, O* __restrict__ az_o) {
     using V = typename Vec4<T>::type;
     constexpr int TW = 64 / G;
     const int lane = threadIdx.x & 63;
     const int t = lane % TW;
     double cb[3];
-    cell_centre(root, leaf, cb);
-    for (int c0 = 0; c0 < leaf.count; c0 += TW) {
-        const int s = leaf.first + c0 + t;
-        const bool ok = c0 + t < leaf.count;
-        V me = ok ? P[s] : V{T(0), T(0), T(0), T(0)};
+    cell_centre(root, box_cell(bx), cb);
+    Cell own_leaf;
+    if (in_list) own_leaf = cells[bx.leaf];
+    for (int c0 = 0; c0 < bx.count; c0 += TW) {
+        const int s = bx.first + c0 + t;
+        const bool ok = c0 + t < bx.count;
+        V me = ok ? TP[s] : V{T(0), T(0), T(0), T(0)};
         T phi = T(0), ax = T(0), ay = T(0), az = T(0);
         if (in_list)
-            p2p_self<T, G, SOFT>(leaf, P, sh, me.x, me.y, me.z, eps2, phi, ax, ay, az);
-        p2p_packed<T, G, SOFT>(cells, self, items, e0, e1, P, sh, own, root, cb, me.x, me.y, me.z,
-                               eps2, phi, ax, ay, az);
+            p2p_self<T, G, SOFT>(own_leaf, P, sh, me.x, me.y, me.z, eps2, phi, ax, ay, az);
+        p2p_packed<T, G, SOFT>(cells, bx.leaf, items, e0, e1, P, sh, own, root, cb, me.x, me.y,
+                               me.z, eps2, phi, ax, ay, az);
 #pragma unroll
         for (int d = TW; d < 64; d <<= 1) {
             phi += __shfl_xor(phi, d, 64);
@@ -177,93 +182,81 @@ __device__ __forceinline__ void p2p_leaf(const Cell& leaf, int self, bool in_lis
             az += __shfl_xor(az, d, 64);
         }
         if (ok && lane < TW) {
-            const int64_t oi = (int64_t)perm[s] - out_shift;
-            if (oi >= 0) {
-                if (far) {
-                    phi += far[s];
-                    ax += far[n + s];
-                    ay += far[2 * n + s];
-                    az += far[3 * n + s];
-                }
-                phi_o[oi] = (O)phi;
-                ax_o[oi] = (O)ax;
-                ay_o[oi] = (O)ay;
-                az_o[oi] = (O)az;
+            const int64_t oi = perm[s];
+            if (far) {
+                phi += far[s];
+                ax += far[n + s];
+                ay += far[2 * n + s];
+                az += far[3 * n + s];
             }
+            phi_o[oi] = (O)phi;
+            ax_o[oi] = (O)ax;
+            ay_o[oi] = (O)ay;
+            az_o[oi] = (O)az;
         }
     }
 }
 
-// One wave per target leaf; sources from the CSR list (off/items indexed by
-// cell id).  out index = perm[s] - out_shift, skipped when negative.
+// One wave per target box; sources from the box's CSR list row.
 template <typename T, typename O, bool SOFT>
 __global__ void __launch_bounds__(256)
-k_p2p(const Cell* __restrict__ cells, const Root* __restrict__ rootp,
-      const int32_t* __restrict__ tgt, int ntgt,
+k_p2p(const Cell* __restrict__ cells, const Root* __restrict__ rootp, Targets tg,
       const int32_t* __restrict__ off, const int32_t* __restrict__ items,
-      const typename Vec4<T>::type* __restrict__ P, const T* __restrict__ far, int64_t n,
-      const int32_t* __restrict__ perm, int64_t out_shift, T eps2, O* __restrict__ phi_o,
-      O* __restrict__ ax_o, O* __restrict__ ay_o, O* __restrict__ az_o) {
+      const typename Vec4<T>::type* __restrict__ P, const T* __restrict__ far, T eps2,
+      O* __restrict__ phi_o, O* __restrict__ ax_o, O* __restrict__ ay_o, O* __restrict__ az_o) {
     using V = typename Vec4<T>::type;
     __shared__ V shm[4][64];
     __shared__ int owm[4][64];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = blockIdx.x * 4 + w;
-    if (li >= ntgt) return;
-    const int b = tgt[li];
-    const Cell leaf = cells[b];
+    if (li >= tg.nbox) return;
+    const TBox bx = tg.box[li];
+    const int row = list_row(tg, li, bx);
     const Root root = *rootp;
-    const int e0 = off[b], e1 = off[b + 1];
+    const int e0 = off[row], e1 = off[row + 1];
+    const V* TP = sizeof(T) == 4 ? (const V*)tg.p32 : (const V*)tg.p64;
     V* sh = shm[w];
     int* own = owm[w];
-    // is the target leaf in its own list (then it is summed on its own)
+    // is the box's own leaf in its list (then it is summed on its own)
     bool mine = false;
-    for (int e = e0 + lane; e < e1; e += 64) mine |= items[e] == b;
+    if (bx.leaf >= 0)
+        for (int e = e0 + lane; e < e1; e += 64) mine |= items[e] == bx.leaf;
     const bool in_list = __ballot(mine) != 0ull;
-#define P2P_LEAF(G)                                                                            \
-    p2p_leaf<T, O, G, SOFT>(leaf, b, in_list, root, cells, items, e0, e1, P, sh, own, far, n, \
-                            perm, out_shift, eps2, phi_o, ax_o, ay_o, az_o)
-    if (leaf.count <= 8)
-        P2P_LEAF(8);
-    else if (leaf.count <= 16)
-        P2P_LEAF(4);
-    else if (leaf.count <= 32)
-        P2P_LEAF(2);
+#define P2P_BOX(G)                                                                              \
+    p2p_box<T, O, G, SOFT>(bx, in_list, root, cells, items, e0, e1, P, TP, sh, own, far, tg.n, \
+                           tg.perm, eps2, phi_o, ax_o, ay_o, az_o)
+    if (bx.count <= 8)
+        P2P_BOX(8);
+    else if (bx.count <= 16)
+        P2P_BOX(4);
+    else if (bx.count <= 32)
+        P2P_BOX(2);
     else
-        P2P_LEAF(1);
-#undef P2P_LEAF
+        P2P_BOX(1);
+#undef P2P_BOX
 }
 
-void launch_p2p(const Tree& t, int precision, double eps2, const int32_t* tgt_cells,
-                int32_t n_tgt_cells, const int32_t* src_off, const int32_t* src_items,
-                const void* far, void* phi, void* ax, void* ay, void* az, hipStream_t s) {
-    if (n_tgt_cells == 0) return;
-    const int64_t shift = t.self ? 0 : t.ns;
-    dim3 grid((n_tgt_cells + 3) / 4), block(256);
+void launch_p2p(const Tree& t, const Targets& tg, int precision, double eps2,
+                const int32_t* src_off, const int32_t* src_items, const void* far, void* phi,
+                void* ax, void* ay, void* az, hipStream_t s) {
+    if (tg.nbox == 0) return;
+    dim3 grid((tg.nbox + 3) / 4), block(256);
     const bool soft = eps2 != 0.0;
+#define P2P_LAUNCH(T, SOFT, P)                                                                \
+    hipLaunchKernelGGL((k_p2p<T, T, SOFT>), grid, block, 0, s, t.cells, t.root, tg, src_off, \
+                       src_items, P, (const T*)far, (T)eps2, (T*)phi, (T*)ax, (T*)ay, (T*)az)
     if (precision == HFMM_FP64) {
         if (soft)
-            hipLaunchKernelGGL((k_p2p<double, double, true>), grid, block, 0, s, t.cells,
-                               t.root, tgt_cells, n_tgt_cells, src_off, src_items, t.p64,
-                               (const double*)far, t.n, t.perm, shift, eps2, (double*)phi,
-                               (double*)ax, (double*)ay, (double*)az);
+            P2P_LAUNCH(double, true, t.p64);
         else
-            hipLaunchKernelGGL((k_p2p<double, double, false>), grid, block, 0, s, t.cells,
-                               t.root, tgt_cells, n_tgt_cells, src_off, src_items, t.p64,
-                               (const double*)far, t.n, t.perm, shift, eps2, (double*)phi,
-                               (double*)ax, (double*)ay, (double*)az);
+            P2P_LAUNCH(double, false, t.p64);
     } else {
         if (soft)
-            hipLaunchKernelGGL((k_p2p<float, float, true>), grid, block, 0, s, t.cells,
-                               t.root, tgt_cells, n_tgt_cells, src_off, src_items, t.p32,
-                               (const float*)far, t.n, t.perm, shift, (float)eps2, (float*)phi,
-                               (float*)ax, (float*)ay, (float*)az);
+            P2P_LAUNCH(float, true, t.p32);
         else
-            hipLaunchKernelGGL((k_p2p<float, float, false>), grid, block, 0, s, t.cells,
-                               t.root, tgt_cells, n_tgt_cells, src_off, src_items, t.p32,
-                               (const float*)far, t.n, t.perm, shift, (float)eps2, (float*)phi,
-                               (float*)ax, (float*)ay, (float*)az);
+            P2P_LAUNCH(float, false, t.p32);
     }
+#undef P2P_LAUNCH
     LAUNCH_CHECK();
 }
 

@@ -4,6 +4,7 @@
 // The paper sorts particles and builds the tree and lists on the host
 // (Sec. 4, "sort" and "other" in Fig. 6); here every step is a
 // kernel, so the only host work is reading back the cell count per level.
+// Non-finite source coordinates are recorded in the tree's status word.
 #include "common.hpp"
 
 #include <algorithm>
@@ -262,22 +263,15 @@ void radix_sort_pairs(const uint64_t* keys, const int32_t* vals, uint64_t* keys_
 // ---------------------------------------------------------------------
 // bounding cube and keys (FP64)
 // ---------------------------------------------------------------------
-__device__ inline double load_coord(const double* a, const double* ta, int64_t ns,
-                                    int64_t i) {
-    return i < ns ? a[i] : ta[i - ns];
-}
-
 __global__ void k_bbox_partial(const double* __restrict__ x, const double* __restrict__ y,
-                               const double* __restrict__ z, const double* __restrict__ tx,
-                               const double* __restrict__ ty, const double* __restrict__ tz,
-                               int64_t ns, int64_t n, double* __restrict__ part) {
+                               const double* __restrict__ z, int64_t n,
+                               double* __restrict__ part) {
     double lo[3] = {INFINITY, INFINITY, INFINITY};
     double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int nbad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        double v[3] = {load_coord(x, tx, ns, i), load_coord(y, ty, ns, i),
-                       load_coord(z, tz, ns, i)};
+        double v[3] = {x[i], y[i], z[i]};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (!isfinite(v[a])) {
@@ -325,9 +319,10 @@ __global__ void k_bbox_partial(const double* __restrict__ x, const double* __res
     }
 }
 
-// Also writes the root cell (all n particles) as cells[0].
+// Also writes the root cell (all n particles) as cells[0] and flags
+// non-finite source coordinates in the status word.
 __global__ void k_bbox_final(const double* __restrict__ part, int nparts, int64_t n, Root* root,
-                             Cell* __restrict__ cells) {
+                             Cell* __restrict__ cells, int32_t* __restrict__ status) {
 #pragma clang fp contract(off)
     // 256 threads: strided partial min/max, then a tree in LDS (min and max
     // are exact, so the order does not matter)
@@ -360,6 +355,7 @@ __global__ void k_bbox_final(const double* __restrict__ part, int nparts, int64_
     }
     if (threadIdx.x != 0) return;
     root->nbad = (int32_t)sm[6][0];
+    if (root->nbad) atomicOr(status, (int32_t)ST_SRC_NONFINITE);
     Cell rc;
     rc.first = 0;
     rc.count = (int32_t)n;
@@ -405,16 +401,14 @@ __device__ inline uint32_t quantise(double v, double b, double s) {
 }
 
 __global__ void k_keys(const double* __restrict__ x, const double* __restrict__ y,
-                       const double* __restrict__ z, const double* __restrict__ tx,
-                       const double* __restrict__ ty, const double* __restrict__ tz,
-                       int64_t ns, int64_t n, const Root* __restrict__ root,
+                       const double* __restrict__ z, int64_t n, const Root* __restrict__ root,
                        uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double s = root->scale;
-    uint32_t qx = quantise(load_coord(x, tx, ns, i), root->b[0], s);
-    uint32_t qy = quantise(load_coord(y, ty, ns, i), root->b[1], s);
-    uint32_t qz = quantise(load_coord(z, tz, ns, i), root->b[2], s);
+    uint32_t qx = quantise(x[i], root->b[0], s);
+    uint32_t qy = quantise(y[i], root->b[1], s);
+    uint32_t qz = quantise(z[i], root->b[2], s);
     keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
     idx[i] = (int32_t)i;
 }
@@ -423,9 +417,8 @@ __global__ void k_keys(const double* __restrict__ x, const double* __restrict__ 
 // particle's leaf for the near field: a pair separation is then rounded
 // relative to the cell size instead of to |x|.
 __global__ void k_gather_positions(const double* __restrict__ x, const double* __restrict__ y,
-                                   const double* __restrict__ z, const double* __restrict__ tx,
-                                   const double* __restrict__ ty, const double* __restrict__ tz,
-                                   int64_t ns, int64_t n, const int32_t* __restrict__ perm,
+                                   const double* __restrict__ z, int64_t n,
+                                   const int32_t* __restrict__ perm,
                                    const Cell* __restrict__ cells,
                                    const int32_t* __restrict__ leaf_of,
                                    const Root* __restrict__ root, double* __restrict__ xs,
@@ -434,8 +427,7 @@ __global__ void k_gather_positions(const double* __restrict__ x, const double* _
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int64_t i = perm[s];
-    double a = load_coord(x, tx, ns, i), b = load_coord(y, ty, ns, i),
-           c = load_coord(z, tz, ns, i);
+    double a = x[i], b = y[i], c = z[i];
     xs[s] = a;
     ys[s] = b;
     zs[s] = c;
@@ -569,15 +561,32 @@ __global__ void k_leaf_flags(const Cell* __restrict__ cells, int nc, int32_t* __
     if (c < nc) f[c] = cells[c].nchild == 0;
 }
 
+// leaves in cell order; per sorted particle its leaf cell and leaf index;
+// per leaf its box of the self-evaluation (the leaf's own particles)
 __global__ void k_leaf_compact(const Cell* __restrict__ cells, int nc,
                                const int32_t* __restrict__ pos, int32_t* __restrict__ leaves,
-                               int32_t* __restrict__ leaf_of) {
+                               int32_t* __restrict__ leaf_of, TBox* __restrict__ boxes,
+                               int32_t* __restrict__ box_of) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     Cell cell = cells[c];
     if (cell.nchild != 0) return;
-    leaves[pos[c]] = c;
-    for (int s = cell.first; s < cell.first + cell.count; ++s) leaf_of[s] = c;
+    const int li = pos[c];
+    leaves[li] = c;
+    TBox b;
+    b.first = cell.first;
+    b.count = cell.count;
+    b.host = b.leaf = c;
+    b.ix = cell.ix;
+    b.iy = cell.iy;
+    b.iz = cell.iz;
+    b.level = cell.level;
+    b.kind = 0;
+    boxes[li] = b;
+    for (int s = cell.first; s < cell.first + cell.count; ++s) {
+        leaf_of[s] = c;
+        box_of[s] = li;
+    }
 }
 
 // After a sort of the top `sorted_levels` levels: a run of more than
@@ -604,10 +613,11 @@ static int sort_levels_guess(int64_t n, int leaf_max) {
     return std::min(HFMM_KEY_LEVELS, L + 2);
 }
 
-void build_tree(Tree& t, const double* x, const double* y, const double* z,
-                const double* tx, const double* ty, const double* tz, hipStream_t s) {
+void build_tree(Tree& t, const double* x, const double* y, const double* z, hipStream_t s) {
     Arena& A = t.arena;
     const int64_t n = t.n;
+    t.status = A.up<int32_t>(1);
+    HIP_TRY(hipMemsetAsync(t.status, 0, sizeof(int32_t), s));
     t.root = A.up<Root>(1);
     t.keys = A.up<uint64_t>(n);
     t.perm = A.up<int32_t>(n);
@@ -617,6 +627,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
     t.p32 = A.up<float4>(n);
     t.p64 = A.up<double4>(n);
     t.leaf_of = A.up<int32_t>(n);
+    t.leaf_box_of = A.up<int32_t>(n);
     const size_t cells_lo = A.lo;
     t.cells = (Cell*)(A.base + A.lo);
     auto room = [&](int64_t ncell) {
@@ -629,10 +640,10 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
     // bounding cube (and the root cell)
     const int nbb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(n, 256)));
     double* part = A.down<double>((size_t)nbb * 8);
-    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, x, y, z, tx, ty, tz,
-                       t.ns, n, part);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, x, y, z, n, part);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nbb, n, t.root, t.cells);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, part, nbb, n, t.root, t.cells,
+                       t.status);
     LAUNCH_CHECK();
     // the root is read back with the level-0 counts (non-finite inputs only
     // make meaningless keys until then)
@@ -648,8 +659,8 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
     const size_t hi_mark = A.hi;
     int nsplit_total = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, tx, ty,
-                           tz, t.ns, n, t.root, k0, i0);
+        hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n, t.root,
+                           k0, i0);
         LAUNCH_CHECK();
         const int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
         radix_sort_pairs(k0, i0, t.keys, t.perm, n, lo_bit, 63, A, s);
@@ -683,7 +694,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
             int32_t h[3] = {0, 0, 0};
             HIP_TRY(hipMemcpyAsync(h, in, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (t.root_h.nbad) throw Status{HFMM_E_DATA};
+            if (t.root_h.nbad) throw Status{HFMM_E_DATA};  // also in the status word
             if (h[1]) {
                 resort = true;
                 A.hi = hi_mark;
@@ -720,12 +731,13 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
     LAUNCH_CHECK();
     scan_exclusive_i32(f, pos, t.ncells, A, s);
     t.leaves = A.up<int32_t>(t.nleaves);
+    t.leaf_boxes = A.up<TBox>(t.nleaves);
     hipLaunchKernelGGL(k_leaf_compact, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
-                       t.cells, t.ncells, pos, t.leaves, t.leaf_of);
+                       t.cells, t.ncells, pos, t.leaves, t.leaf_of, t.leaf_boxes,
+                       t.leaf_box_of);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gather_positions, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z,
-                       tx, ty, tz, t.ns, n, t.perm, t.cells, t.leaf_of, t.root, t.xs, t.ys,
-                       t.zs, t.p32);
+    hipLaunchKernelGGL(k_gather_positions, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n,
+                       t.perm, t.cells, t.leaf_of, t.root, t.xs, t.ys, t.zs, t.p32);
     LAUNCH_CHECK();
     A.release_temps();
 }

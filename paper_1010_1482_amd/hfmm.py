@@ -22,16 +22,19 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": M2L_BF16, "bf16x3": M2L_BF16X3
               "fp16": M2L_FP16, "fp16x3": M2L_FP16X3}
 METHODS = {"direct": DIRECT, "treecode": TREECODE, "fmm": FMM,
            "treecode_fmmlist": TREECODE_FMMLIST}
-OK, E_INVAL, E_NOMEM, E_UNSUPPORTED, E_HIP, E_STATE, E_DATA = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVAL, E_NOMEM, E_UNSUPPORTED, E_HIP, E_STATE, E_DATA, E_OVERFLOW = \
+    0, -1, -2, -3, -4, -5, -6, -7
+ST_SRC_NONFINITE, ST_TGT_NONFINITE, ST_MASS_NONFINITE, ST_OVERFLOW = 1, 2, 4, 8
 MAX_P = 16
 
 # exported symbols, in the order include/hfmm.h declares them
 SYMBOLS = ("hfmm_arena_bytes", "hfmm_build_tree", "hfmm_upward", "hfmm_evaluate",
-           "hfmm_solve", "hfmm_direct_bytes", "hfmm_direct", "hfmm_direct_noalloc",
+           "hfmm_solve", "hfmm_status", "hfmm_direct_bytes", "hfmm_direct", "hfmm_direct_noalloc",
            "hfmm_leapfrog",
            "hfmm_tree_release",
            "hfmm_required_bytes", "hfmm_last_required_bytes", "hfmm_get_stats",
-           "hfmm_strerror", "hfmm_export_perm", "hfmm_export_cells", "hfmm_export_list",
+           "hfmm_strerror", "hfmm_export_perm", "hfmm_export_targets",
+           "hfmm_export_target_lists", "hfmm_export_cells", "hfmm_export_list",
            "hfmm_export_bh_list", "hfmm_export_expansions", "hfmm_set_timing")
 
 
@@ -48,10 +51,12 @@ class Stats(C.Structure):
                 ("root", C.c_double * 4), ("list_u", C.c_int64), ("list_v", C.c_int64),
                 ("list_w", C.c_int64), ("list_x", C.c_int64), ("list_m2p", C.c_int64),
                 ("list_p2p", C.c_int64), ("p2p_pairs", C.c_int64), ("m2l_pairs", C.c_int64),
-                ("arena_used", C.c_size_t), ("phase_ms", C.c_double * 10)]
+                ("arena_used", C.c_size_t), ("phase_ms", C.c_double * 10),
+                ("n_targets", C.c_int64), ("n_target_boxes", C.c_int64),
+                ("target_near", C.c_int64), ("target_far", C.c_int64)]
 
     PHASES = ("build", "lists", "upward", "m2l_ops", "m2l", "downward", "far", "p2p",
-              "bh_lists", "m2l_prep")
+              "targets", "m2l_prep")
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,10 +78,11 @@ def _lib():
         L = C.CDLL(LIB_PATH)
         i64, i32, d, sz = C.c_int64, C.c_int, C.c_double, C.c_size_t
         L.hfmm_arena_bytes.argtypes = [i64, i64, i32, i32, i32, i32, C.POINTER(sz)]
-        L.hfmm_build_tree.argtypes = [_vp, _vp, _vp, i64, _vp, _vp, _vp, i64, i32, _vp, sz,
-                                      _vp, C.POINTER(_vp)]
+        L.hfmm_build_tree.argtypes = [_vp, _vp, _vp, i64, i32, _vp, sz, _vp, C.POINTER(_vp)]
         L.hfmm_upward.argtypes = [_vp, _vp, i32, i32, i32, _vp]
-        L.hfmm_evaluate.argtypes = [_vp, i32, d, i32, i32, d, _vp, _vp, _vp, _vp, _vp]
+        L.hfmm_evaluate.argtypes = [_vp, _vp, _vp, _vp, i64, i32, d, i32, i32, d, _vp, _vp, _vp,
+                                    _vp, _vp]
+        L.hfmm_status.argtypes = [_vp, _vp, C.POINTER(C.c_uint32)]
         L.hfmm_solve.argtypes = [_vp, _vp, _vp, _vp, i64, _vp, _vp, _vp, i64, i32, i32, d,
                                  i32, i32, d, _vp, sz, _vp, _vp, _vp, _vp, _vp]
         L.hfmm_direct_bytes.argtypes = [i64, i64, i32, C.POINTER(sz)]
@@ -97,6 +103,8 @@ def _lib():
         L.hfmm_strerror.argtypes = [i32]
         L.hfmm_strerror.restype = C.c_char_p
         L.hfmm_export_perm.argtypes = [_vp, _vp, _vp]
+        L.hfmm_export_targets.argtypes = [_vp, _vp, _vp]
+        L.hfmm_export_target_lists.argtypes = [_vp, i32, _vp, _vp, _vp]
         L.hfmm_export_cells.argtypes = [_vp, _vp, _vp]
         L.hfmm_export_list.argtypes = [_vp, i32, _vp, _vp, _vp]
         L.hfmm_export_bh_list.argtypes = [_vp, i32, _vp, _vp, _vp]
@@ -157,31 +165,42 @@ def out_dtype(precision):
     return torch.float64 if _prec(precision) == FP64 else torch.float32
 
 
-class Tree:
-    """A device-resident octree over sources (and optional distinct targets)
-    living in one caller-owned arena tensor."""
+def _targets(targets):
+    """Device target coordinates and their count.  An empty target set never
+    reaches the library: torch gives an empty tensor a null data pointer,
+    and a null tx selects self-evaluation there."""
+    if targets is None:
+        return None, None, None, 0
+    tx, ty, tz = (_dev(t, "target") for t in targets)
+    if not (tx.numel() == ty.numel() == tz.numel()):
+        raise ValueError("target coordinate arrays differ in length")
+    return tx, ty, tz, tx.numel()
 
-    def __init__(self, x, y, z, leaf_max=64, targets=None, arena=None, stream=None,
-                 arena_bytes_hint=None):
+
+def _empty_out(dt, device, out):
+    return out if out is not None else tuple(torch.empty(0, dtype=dt, device=device)
+                                             for _ in range(4))
+
+
+class Tree:
+    """A device-resident octree over the sources, living in one caller-owned
+    arena tensor, evaluated at the sources or at separate target sets of up
+    to `max_targets` points."""
+
+    def __init__(self, x, y, z, leaf_max=64, arena=None, stream=None, arena_bytes_hint=None,
+                 max_targets=0):
         self.ns = x.numel()
-        self.targets = targets
-        self.nt = self.ns if targets is None else targets[0].numel()
         self.leaf_max = leaf_max
         for nm, t in (("x", x), ("y", y), ("z", z)):
             _dev(t, nm)
-        tx = ty = tz = None
-        if targets is not None:
-            tx, ty, tz = (_dev(t, "target") for t in targets)
-        self._keep = (x, y, z, tx, ty, tz)
-        nbytes = arena_bytes_hint or arena_bytes(self.ns, 0 if targets is None else self.nt,
-                                                 leaf_max, 12, FMM, FP32)
+        self._keep = (x, y, z)
+        nbytes = arena_bytes_hint or arena_bytes(self.ns, max_targets, leaf_max, 12, FMM, FP32)
         self.h = None
         for _ in range(6):
             self.arena = arena if arena is not None else torch.empty(
                 nbytes, dtype=torch.uint8, device=x.device)
             h = _vp()
-            rc = _lib().hfmm_build_tree(_ptr(x), _ptr(y), _ptr(z), self.ns, _ptr(tx), _ptr(ty),
-                                        _ptr(tz), 0 if targets is None else self.nt, leaf_max,
+            rc = _lib().hfmm_build_tree(_ptr(x), _ptr(y), _ptr(z), self.ns, leaf_max,
                                         _ptr(self.arena), self.arena.numel(), _stream(stream),
                                         C.byref(h))
             if rc == E_NOMEM and arena is None:
@@ -201,10 +220,6 @@ class Tree:
             _LIB.hfmm_tree_release(h)
             self.h = None
 
-    def _grow(self, stream):
-        raise HfmmError(E_NOMEM, "arena too small for this order; build with a larger "
-                        "arena_bytes_hint")
-
     def upward(self, m, p, method=FMM, precision=FP32, stream=None):
         _dev(m, "m")
         self._m = m
@@ -213,15 +228,30 @@ class Tree:
         _check(rc, "hfmm_upward")
         self.p, self.method, self.precision = p, _meth(method), _prec(precision)
 
-    def evaluate(self, theta=0.5, eps2=0.0, out=None, stream=None):
+    def evaluate(self, theta=0.5, eps2=0.0, targets=None, out=None, stream=None):
+        """phi, ax, ay, az at the sources (targets=None) or at targets=(tx, ty, tz)."""
         dt = out_dtype(self.precision)
         dev = self._keep[0].device
+        tx, ty, tz, nt = _targets(targets)
+        if targets is None:
+            nt = self.ns
+        elif nt == 0:
+            return _empty_out(dt, dev, out)
         if out is None:
-            out = tuple(torch.empty(self.nt, dtype=dt, device=dev) for _ in range(4))
-        rc = _lib().hfmm_evaluate(self.h, self.p, float(theta), self.method, self.precision,
-                                  float(eps2), *[_ptr(o) for o in out], _stream(stream))
+            out = tuple(torch.empty(nt, dtype=dt, device=dev) for _ in range(4))
+        self._tkeep = (tx, ty, tz)
+        rc = _lib().hfmm_evaluate(self.h, _ptr(tx), _ptr(ty), _ptr(tz),
+                                  0 if targets is None else nt, self.p, float(theta),
+                                  self.method, self.precision, float(eps2),
+                                  *[_ptr(o) for o in out], _stream(stream))
         _check(rc, "hfmm_evaluate")
         return out
+
+    def status(self, stream=None):
+        """(code, flags) of the device status word after the enqueued work."""
+        f = C.c_uint32(0)
+        rc = _lib().hfmm_status(self.h, _stream(stream), C.byref(f))
+        return rc, f.value
 
     def stats(self):
         s = Stats()
@@ -237,6 +267,26 @@ class Tree:
         out = torch.empty(n, dtype=torch.int32, device=self.arena.device)
         _check(_lib().hfmm_export_perm(self.h, _ptr(out), _stream(stream)), "export_perm")
         return out
+
+    def target_boxes(self, stream=None):
+        """Per target of the last evaluation (caller order): kind, level, ix,
+        iy, iz, host, leaf, box index."""
+        n = self.stats()["n_targets"]
+        out = torch.empty((n, 8), dtype=torch.int32, device=self.arena.device)
+        _check(_lib().hfmm_export_targets(self.h, _ptr(out), _stream(stream)),
+               "export_targets")
+        return out
+
+    def target_list(self, which, stream=None):
+        """CSR by box of the last separate-target evaluation: which 0 far
+        (M2P), 1 near (P2P)."""
+        st = self.stats()
+        nn = [st["target_far"], st["target_near"]][which]
+        off = torch.empty(st["n_target_boxes"] + 1, dtype=torch.int32, device=self.arena.device)
+        items = torch.empty(max(nn, 1), dtype=torch.int32, device=self.arena.device)
+        _check(_lib().hfmm_export_target_lists(self.h, which, _ptr(off), _ptr(items),
+                                               _stream(stream)), "export_target_lists")
+        return off, items[:nn]
 
     def cells(self, stream=None):
         nc = self.stats()["n_cells"]
@@ -285,12 +335,12 @@ def solve(x, y, z, m, p=10, method=FMM, precision=FP32, leaf_max=64, theta=0.5, 
     for nm, t in (("x", x), ("y", y), ("z", z), ("m", m)):
         _dev(t, nm)
     ns = x.numel()
-    tx = ty = tz = None
-    nt = ns
-    if targets is not None:
-        tx, ty, tz = (_dev(t, "target") for t in targets)
-        nt = tx.numel()
+    tx, ty, tz, nt = _targets(targets)
     dt = out_dtype(precision)
+    if targets is None:
+        nt = ns
+    elif nt == 0:
+        return _empty_out(dt, x.device, out)
     if out is None:
         out = tuple(torch.empty(nt, dtype=dt, device=x.device) for _ in range(4))
     nbytes = arena.numel() if arena is not None else arena_bytes(
@@ -357,8 +407,9 @@ def direct(x, y, z, m, precision=FP32, eps2=0.0, targets=None, out=None, stream=
     tx = ty = tz = None
     nt = ns
     if targets is not None:
-        tx, ty, tz = targets
-        nt = tx.numel()
+        tx, ty, tz, nt = _targets(targets)
+        if nt == 0:
+            return _empty_out(out_dtype(precision), x.device, out)
     sz = C.c_size_t(0)
     _check(_lib().hfmm_direct_bytes(ns, 0 if targets is None else nt, precision, C.byref(sz)),
            "hfmm_direct_bytes")

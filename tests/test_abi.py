@@ -50,13 +50,22 @@ def test_host_only_entry_points(lib):
     lib.hfmm_strerror.restype = C.c_char_p
     assert lib.hfmm_strerror(-2) == b"arena too small"
     out = C.c_void_p()
+    L = hfmm._lib()
     # null arena / negative sizes are rejected before any device work
-    lib.hfmm_build_tree.argtypes = [C.c_void_p] * 3 + [C.c_int64] + [C.c_void_p] * 3 + \
-        [C.c_int64, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]
-    assert lib.hfmm_build_tree(None, None, None, -1, None, None, None, 0, 64, None, 0, None,
-                               C.byref(out)) == hfmm.E_INVAL
-    lib.hfmm_get_stats.argtypes = [C.c_void_p, C.c_void_p]
-    assert lib.hfmm_get_stats(None, None) == hfmm.E_INVAL
+    assert L.hfmm_build_tree(None, None, None, -1, 64, None, 0, None,
+                             C.byref(out)) == hfmm.E_INVAL
+    assert L.hfmm_build_tree(None, None, None, 10, 64, C.c_void_p(1), 1 << 20, None,
+                             C.byref(out)) == hfmm.E_INVAL  # null coordinates
+    assert L.hfmm_get_stats(None, None) == hfmm.E_INVAL
+    # null tree handles
+    assert L.hfmm_evaluate(None, None, None, None, 0, 4, 0.5, hfmm.FMM, hfmm.FP32, 0.0,
+                           None, None, None, None, None) == hfmm.E_INVAL
+    flags = C.c_uint32(7)
+    assert L.hfmm_status(None, None, C.byref(flags)) == hfmm.E_INVAL and flags.value == 0
+    assert L.hfmm_export_targets(None, None, None) == hfmm.E_INVAL
+    assert L.hfmm_export_target_lists(None, 0, None, None, None) == hfmm.E_INVAL
+    L.hfmm_strerror.restype = C.c_char_p
+    assert b"overflow" in L.hfmm_strerror(hfmm.E_OVERFLOW)
 
 
 def test_new_methods_and_time_loop_host_checks(lib):

@@ -197,18 +197,6 @@ def test_fmm_order_boundaries(order_inputs, prec, p):
     assert_close(out, ref, 1e-12 if prec == "fp64" else 1e-5, "vs oracle fmm")
 
 
-def test_fmm_distinct_targets():
-    say("fmm distinct targets")
-    x, y, z, m = W.plummer(5000, 46)
-    tx, ty, tz, _ = W.plummer(700, 47)
-    ref = O.direct_points(x, y, z, m, tx, ty, tz)
-    out = host(H().solve(*to_dev(x, y, z, m), p=10, method="fmm", precision="fp64",
-                         leaf_max=16, targets=to_dev(tx, ty, tz)))
-    ephi, eacc = rel_err(out, ref)
-    say(f"  vs direct: phi {ephi:.2e} acc {eacc:.2e}")
-    assert ephi < 1e-5 and eacc < 1e-4
-
-
 # ---------------------------------------------------------------- treecode
 @pytest.mark.parametrize("dist,n,leaf,p,theta,kind", [("plummer", 8000, 16, 3, 0.5, "equal"),
                                                       ("uniform", 6000, 32, 4, 0.4, "equal"),
@@ -284,25 +272,6 @@ def test_fmmlist_treecode_matches_oracle(dist, n, leaf, p, kind):
     # against the exact sum: the far field's truncation at this p
     d = O.direct(x, y, z, m)
     assert rel_err(out, d)[1] < {3: 5e-3, 6: 5e-4, 8: 1e-4}[p] * kap[1]
-
-
-def test_fmmlist_treecode_distinct_targets():
-    # distinct targets enter the tree as massless particles: the oracle on
-    # the joined point set gives the same tree, lists and result
-    say("treecode over the FMM lists: distinct targets")
-    x, y, z, m = W.plummer(4000, 50)
-    tx, ty, tz, _ = W.plummer(700, 51)
-    out = host(H().solve(*to_dev(x, y, z, m), p=10, method="treecode_fmmlist",
-                         precision="fp64", leaf_max=16, targets=to_dev(tx, ty, tz)))
-    X, Y, Z = (np.concatenate(a) for a in ((x, tx), (y, ty), (z, tz)))
-    ref = O.treecode(X, Y, Z, np.concatenate([m, np.zeros(700)]), 10, 0.5, 16,
-                     targets=np.arange(4000, 4700), mode=2)
-    ephi, eacc = rel_err(out, ref)
-    say(f"  vs oracle: phi {ephi:.2e} acc {eacc:.2e}")
-    assert ephi <= 1e-12 and eacc <= 1e-12
-    ephi, eacc = rel_err(out, O.direct_points(x, y, z, m, tx, ty, tz))
-    say(f"  vs direct: phi {ephi:.2e} acc {eacc:.2e}")
-    assert ephi < 1e-5 and eacc < 1e-4
 
 
 def test_empty_and_single():
