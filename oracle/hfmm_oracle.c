@@ -1589,3 +1589,136 @@ int oracle_treecode_points(int64_t n, const double* x, const double* y, const do
     oracle_tree_free(t);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* rotation-based M2L                                                  */
+/* ------------------------------------------------------------------ */
+
+#define ORACLE_PI 3.14159265358979323846
+
+/* Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_N from the usual
+ * cosine guesses). */
+static void gauss_legendre(int N, double* x, double* w) {
+    for (int i = 0; i < N; i++) {
+        double z = cos(ORACLE_PI * (i + 0.75) / (N + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= N; k++) {
+                double pk = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = pk;
+            }
+            dp = N * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        /* final derivative at the converged node */
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= N; k++) {
+            double pk = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = pk;
+        }
+        dp = N * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* out = R v for a 3x3 row-major R */
+static void mat3(const double R[9], const double v[3], double out[3]) {
+    for (int a = 0; a < 3; a++) out[a] = R[3 * a] * v[0] + R[3 * a + 1] * v[1] + R[3 * a + 2] * v[2];
+}
+
+/* Re-expand the degree-n part of an expansion after a rotation of the frame:
+ * out^m = (2n+1)/(4 pi) * integral over the unit sphere of
+ * g(Q u) conj(Y_n^m(u)), g(v) = sum_k in^k Y_n^k(v), which is exact for the
+ * degree-n harmonic g (the Y_n^m are orthogonal with norm 4 pi / (2n+1)).
+ * The quadrature, Gauss-Legendre in cos a (n + 1 nodes) times the trapezoid
+ * rule in b (2n + 1 nodes), integrates degree 2n exactly. */
+static void rotate_degree(int n, const double Q[9], const cplx* in, cplx* out) {
+    const int nt = n + 1, nb = 2 * n + 1;
+    double* gx = (double*)malloc(sizeof(double) * nt);
+    double* gw = (double*)malloc(sizeof(double) * nt);
+    gauss_legendre(nt, gx, gw);
+    cplx* Yu = (cplx*)malloc(sizeof(cplx) * (n + 1) * (n + 1));
+    cplx* Yq = (cplx*)malloc(sizeof(cplx) * (n + 1) * (n + 1));
+    for (int m = -n; m <= n; m++) out[m + n] = 0;
+    for (int a = 0; a < nt; a++)
+        for (int b = 0; b < nb; b++) {
+            const double ca = gx[a], sa = sqrt(fmax(0.0, 1.0 - ca * ca));
+            const double be = 2.0 * ORACLE_PI * b / nb;
+            const double u[3] = {sa * cos(be), sa * sin(be), ca};
+            double v[3], rho, al, bq;
+            mat3(Q, u, v);
+            cart2sph(v, &rho, &al, &bq);
+            ynm_table(n, acos(ca), be, Yu);
+            ynm_table(n, al, bq, Yq);
+            cplx g = 0;
+            for (int k = -n; k <= n; k++) g += in[k + n] * Yq[CI(n, k)];
+            const double wq = gw[a] * 2.0 * ORACLE_PI / nb;
+            for (int m = -n; m <= n; m++) out[m + n] += wq * g * conj(Yu[CI(n, m)]);
+        }
+    for (int m = -n; m <= n; m++) out[m + n] *= (2.0 * n + 1.0) / (4.0 * ORACLE_PI);
+    free(gx);
+    free(gw);
+    free(Yu);
+    free(Yq);
+}
+
+/* Rotate a whole expansion (degrees < p): coefficients of the field
+ * u -> f(Q u) */
+static void rotate_expansion(int p, const double Q[9], const cplx* in, cplx* out) {
+    cplx* tmp = (cplx*)malloc(sizeof(cplx) * (2 * p + 1));
+    for (int n = 0; n < p; n++) {
+        rotate_degree(n, Q, in + n * n, tmp);
+        for (int m = -n; m <= n; m++) out[CI(n, m)] = tmp[m + n];
+    }
+    free(tmp);
+}
+
+/* The O(p^3) M2L that Sec. 6 lists among the advanced techniques: rotate the
+ * multipole expansion into the frame whose z axis points along
+ * c_tgt - c_src, translate along that axis (Eq. 4 with the translation on
+ * the z axis couples each order m to itself only), and rotate the local
+ * expansion back.  R = R_y(-alpha) R_z(-beta) takes the direction (alpha,
+ * beta) to the z axis. */
+void oracle_m2l_rot(int p, const double c_src[3], const double c_tgt[3], const double* M,
+                    double* L) {
+    const double d[3] = {c_tgt[0] - c_src[0], c_tgt[1] - c_src[1], c_tgt[2] - c_src[2]};
+    double rho, al, be;
+    cart2sph(d, &rho, &al, &be);
+    const double ca = cos(al), sa = sin(al), cb = cos(be), sb = sin(be);
+    /* R = R_y(-al) R_z(-be) */
+    const double Rz[9] = {cb, sb, 0, -sb, cb, 0, 0, 0, 1};
+    const double Ry[9] = {ca, 0, -sa, 0, 1, 0, sa, 0, ca};
+    double R[9], Rt[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            R[3 * i + j] = 0;
+            for (int k = 0; k < 3; k++) R[3 * i + j] += Ry[3 * i + k] * Rz[3 * k + j];
+        }
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) Rt[3 * i + j] = R[3 * j + i];
+    const int pp = p * p;
+    cplx* Mr = (cplx*)calloc(pp, sizeof(cplx));
+    cplx* Lr = (cplx*)calloc(pp, sizeof(cplx));
+    cplx* Lb = (cplx*)malloc(sizeof(cplx) * pp);
+    /* multipole in the rotated frame: the field u -> f(R^T u) */
+    rotate_expansion(p, Rt, (const cplx*)M, Mr);
+    const double zero[3] = {0, 0, 0}, zt[3] = {0, 0, rho};
+    m2l_c(p, zero, zt, Mr, Lr);
+    /* local expansion back in the original frame: u -> g(R u) */
+    rotate_expansion(p, R, Lr, Lb);
+    for (int k = 0; k < pp; k++) ((cplx*)L)[k] += Lb[k];
+    free(Mr);
+    free(Lr);
+    free(Lb);
+}
+
+/* One rotation of an expansion, exposed for the pins: out = coefficients of
+ * u -> f(Q u). */
+void oracle_rotate(int p, const double Q[9], const double* in, double* out) {
+    rotate_expansion(p, Q, (const cplx*)in, (cplx*)out);
+}

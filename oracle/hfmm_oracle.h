@@ -152,6 +152,15 @@ int oracle_treecode_points(int64_t n, const double* x, const double* y,
                            const double* tz, double* phi, double* ax,
                            double* ay, double* az);
 
+/* ---- rotation-based M2L (Sec. 6) ---- */
+/* M2L by rotation to the translation axis, coaxial translation (Eq. 4 along
+ * z) and rotation back; accumulates into L like oracle_m2l. */
+void oracle_m2l_rot(int p, const double c_src[3], const double c_tgt[3],
+                    const double* M, double* L);
+/* Coefficients (degrees < p) of the field u -> f(Q u), Q a 3x3 row-major
+ * rotation, f given by `in` (complex, index n*n + n + m). */
+void oracle_rotate(int p, const double Q[9], const double* in, double* out);
+
 /* Threads OpenMP will use (1 when built without OpenMP). */
 int oracle_num_threads(void);
 

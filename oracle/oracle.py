@@ -136,6 +136,21 @@ def m2l(p, c_src, c_tgt, M):
     return _translate(lib().oracle_m2l, p, c_src, c_tgt, M)
 
 
+def m2l_rot(p, c_src, c_tgt, M):
+    """M2L by rotation to the translation axis, coaxial translation and
+    rotation back (Sec. 6)."""
+    return _translate(lib().oracle_m2l_rot, p, c_src, c_tgt, M)
+
+
+def rotate(p, Q, C_in):
+    """Coefficients of the field u -> f(Q u) (Q: 3x3 rotation)."""
+    Qc = (C.c_double * 9)(*[float(v) for v in np.asarray(Q, dtype=np.float64).ravel()])
+    C_in = np.ascontiguousarray(C_in, dtype=np.complex128)
+    out = np.zeros(p * p, dtype=np.complex128)
+    lib().oracle_rotate(C.c_int(p), Qc, C_in.ctypes.data_as(_dp), out.ctypes.data_as(_dp))
+    return out
+
+
 def l2l(p, c_parent, c_child, L):
     return _translate(lib().oracle_l2l, p, c_parent, c_child, L)
 
