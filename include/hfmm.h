@@ -21,6 +21,14 @@
  *                  U/V/W/X lists (Sec. 6 cites Cheng, Greengard and Rokhlin);
  *                  on uniform data these are the 27-cell P2P and 189-cell M2L
  *                  lists of Secs. 5.1 and 5.2
+ *   HFMM_FMM_ROT   the FMM with the rotation-based M2L Sec. 6 names among
+ *                  the advanced techniques: each multipole expansion rotated
+ *                  to the axis of its translation, translated along it
+ *                  (order by order, O(p^3)) and rotated back; the same
+ *                  result as HFMM_FMM up to rounding (FP64 or FP32 only).
+ *                  HFMM_FMM itself takes this M2L where the matrix cores
+ *                  hold no dense operator (FP32 above p = 13, FP64 above
+ *                  p = 11)
  *   HFMM_TREECODE_FMMLIST
  *                  the treecode the paper measures (Sec. 4): the FMM's upward
  *                  pass (geometric centres) and lists, with M2P at the targets
@@ -80,7 +88,8 @@ enum hfmm_method {
     HFMM_DIRECT = 0,
     HFMM_TREECODE = 1,
     HFMM_FMM = 2,
-    HFMM_TREECODE_FMMLIST = 3
+    HFMM_TREECODE_FMMLIST = 3,
+    HFMM_FMM_ROT = 4
 };
 
 /* Arithmetic of the far field.  P2P, P2M, L2P, M2P run in FP32 for every

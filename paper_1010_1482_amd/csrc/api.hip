@@ -88,12 +88,14 @@ static void clear_status(Tree& t, int32_t bits, hipStream_t s) {
 static void check_p(int p) {
     if (p < 1 || p > HFMM_MAX_P) throw Status{HFMM_E_UNSUPPORTED};
 }
+// the FMM with the dense (matrix-core) or the rotation-based M2L
+static bool is_fmm(int method) { return method == HFMM_FMM || method == HFMM_FMM_ROT; }
 // the methods whose upward pass is the FMM's (geometric centres, FMM lists)
 static bool fmm_upward(int method) {
-    return method == HFMM_FMM || method == HFMM_TREECODE_FMMLIST;
+    return is_fmm(method) || method == HFMM_TREECODE_FMMLIST;
 }
 static bool tree_method(int method) {
-    return method == HFMM_FMM || method == HFMM_TREECODE || method == HFMM_TREECODE_FMMLIST;
+    return is_fmm(method) || method == HFMM_TREECODE || method == HFMM_TREECODE_FMMLIST;
 }
 
 static void check_precision(int precision) {
@@ -104,6 +106,8 @@ void upward_pass(Tree& t, const double* m, int p, int method, int precision, hip
     check_p(p);
     check_precision(precision);
     if (!tree_method(method)) throw Status{HFMM_E_UNSUPPORTED};
+    if (method == HFMM_FMM_ROT && precision != HFMM_FP64 && precision != HFMM_FP32)
+        throw Status{HFMM_E_UNSUPPORTED};
     if (!m && t.n > 0) throw Status{HFMM_E_INVAL};
     Arena& A = t.arena;
     A.release_temps();
@@ -151,20 +155,24 @@ void upward_pass(Tree& t, const double* m, int p, int method, int precision, hip
     t.up_prec = precision;
 }
 
-// M2L (+ P2L) and L2L: the local expansions of every cell
-static void downward_pass(Tree& t, int p, int precision, hipStream_t s) {
+// M2L (+ P2L) and L2L: the local expansions of every cell; rot: the
+// rotation-based M2L instead of the dense operators
+static void downward_pass(Tree& t, int p, int precision, bool rot, hipStream_t s) {
     Arena& A = t.arena;
     const bool fp64 = precision == HFMM_FP64;
     {
         PhaseTimer pt(t, PH_OPS, s);
-        prepare_m2l_ops(t, p, precision, s);
+        if (rot)
+            prepare_rot_ops(t, p, precision, s);
+        else
+            prepare_m2l_ops(t, p, precision, s);
     }
     t.L = A.up<double>((size_t)(t.ncells + 1) * t.ldm);
     const size_t row = sizeof(double) * t.ldm;
     HIP_TRY(hipMemsetAsync(t.L + (size_t)t.ncells * t.ldm, 0, row, s));
     if (t.depth >= 2) {
         // M2L partial results
-        const bool mf = m2l_uses_mfma(p, precision);
+        const bool mf = !rot && m2l_uses_mfma(p, precision);
         int max_parts = 12;
         const size_t esz = fp64 ? 8 : 4;
         while (max_parts > 1 &&
@@ -177,7 +185,8 @@ static void downward_pass(Tree& t, int p, int precision, hipStream_t s) {
         if (t.n_x > 0) LX = A.down<double>((size_t)t.ncells * t.ldm);
         int64_t stride = 0;
         int parts;
-        parts = run_m2l(t, p, precision, lm, stride, parts_cap, levexp, s);
+        parts = rot ? run_m2l_rot(t, p, precision, lm, stride, s)
+                    : run_m2l(t, p, precision, lm, stride, parts_cap, levexp, s);
         PhaseTimer pt(t, PH_DOWN, s);
         if (LX) {
             HIP_TRY(hipMemsetAsync(LX, 0, row * t.ncells, s));
@@ -270,14 +279,19 @@ void evaluate(Tree& t, const double* tx, const double* ty, const double* tz, int
     clear_status(t, ST_TGT_NONFINITE | ST_OVERFLOW, s);
     t.tg_sep = false;
     t.tg = Targets{};
-    if (sep || method == HFMM_FMM) {
+    if (sep || is_fmm(method)) {
         // separate targets live above the upward data (and the local
         // expansions); the treecodes' cached self lists are given up
         A.lo = t.mark_up;
         t.a_off = nullptr;
         t.bh_theta = -1.0;
     }
-    if (method == HFMM_FMM) downward_pass(t, p, precision, s);
+    // the rotation M2L where the matrix cores take no dense operator (FP32
+    // above p = 13, FP64 above p = 11): O(p^3) beats the vector units' p^4
+    const bool rot = method == HFMM_FMM_ROT ||
+                     ((precision == HFMM_FP32 || precision == HFMM_FP64) &&
+                      !m2l_uses_mfma(p, precision));
+    if (is_fmm(method)) downward_pass(t, p, precision, rot, s);
     Targets tg;
     const int32_t *far_off, *far_items, *near_off, *near_items;
     int64_t n_far;
@@ -286,7 +300,7 @@ void evaluate(Tree& t, const double* tx, const double* ty, const double* tz, int
         PhaseTimer pt(t, PH_BH, s);
         if (sep) {
             tg = bin_targets(t, tx, ty, tz, nt, s);
-            if (method == HFMM_FMM)
+            if (is_fmm(method))
                 build_box_lists(t, tg, BOX_FMM, s);
             else if (method == HFMM_TREECODE_FMMLIST)
                 build_box_lists(t, tg, p == 3 ? BOX_TREECODE : BOX_TREECODE_FULL, s);
@@ -303,7 +317,7 @@ void evaluate(Tree& t, const double* tx, const double* ty, const double* tz, int
                                  t.tg_near, s);
         } else {
             tg = self_targets(t);
-            if (method == HFMM_FMM) {
+            if (is_fmm(method)) {
                 far_off = t.w_off;
                 far_items = t.w_items;
                 n_far = t.n_w;
@@ -328,7 +342,7 @@ void evaluate(Tree& t, const double* tx, const double* ty, const double* tz, int
     void* far = A.down<char>((size_t)4 * tg.n * (fp64 ? 8 : 4));
     {
         PhaseTimer pt(t, PH_FAR, s);
-        if (method == HFMM_FMM)
+        if (is_fmm(method))
             run_far(t, tg, p, fp64, far_off, far_items, n_far, far, s);
         else
             run_treecode_far(t, tg, p, fp64, walk, far_off, far_items, far, s);
@@ -341,7 +355,7 @@ void evaluate(Tree& t, const double* tx, const double* ty, const double* tz, int
     t.tg_sep = sep;
     t.ev_p = p;
     t.ev_method = method;
-    if (method == HFMM_FMM) t.m2l_pairs = t.n_v;
+    if (is_fmm(method)) t.m2l_pairs = t.n_v;
     A.release_temps();
 }
 
@@ -369,8 +383,9 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
         per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 +
                    (size_t)ld * 4 + 64 + (size_t)4 * 189 * std::max(levels, 3);
     }
-    size_t ops = method == HFMM_FMM ? m2l_ops_bytes(p, precision) : 0;
-    if (method == HFMM_FMM) ops += (size_t)2 * 8 * ld * ld * sizeof(double);
+    size_t ops = method == HFMM_FMM ? std::max(m2l_ops_bytes(p, precision), rot_ops_bytes(p, precision))
+                 : method == HFMM_FMM_ROT ? rot_ops_bytes(p, precision) : 0;
+    if (is_fmm(method)) ops += (size_t)2 * 8 * ld * ld * sizeof(double);
     if (method == HFMM_FMM && precision != HFMM_FP64 && !m2l_uses_mfma(p, precision))
         ops += (size_t)343 * P * P * 8;
     size_t tot = per_particle * (size_t)n + per_cell * (size_t)nc + ops;
@@ -752,7 +767,7 @@ int hfmm_export_expansions(hfmm_tree h, int which, double* dst, void* stream) {
     if (!h || !dst || which < 0 || which > 1) return HFMM_E_INVAL;
     Tree& t = h->t;
     if (t.up_p == 0 || !t.M) return HFMM_E_STATE;
-    if (which == 1 && (t.up_method != HFMM_FMM || !t.L || t.ev_p != t.up_p)) return HFMM_E_STATE;
+    if (which == 1 && (!is_fmm(t.up_method) || !t.L || t.ev_p != t.up_p)) return HFMM_E_STATE;
     API_BEGIN
     run_export(which == 0 ? t.M : t.L, t.ldm, t.ncells, t.up_p, t.cen, which, dst,
                (hipStream_t)stream);

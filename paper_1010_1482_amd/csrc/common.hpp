@@ -233,6 +233,7 @@ struct Tree {
     int64_t n_a = 0, n_b = 0;
     // operator tables (per p and precision)
     int ops_p = 0, ops_prec = -1;
+    bool ops_rot = false;            // the tables are the rotation M2L's
     void* T = nullptr;               // M2L matrices
     size_t mark_ops = 0;
     int32_t* bexp = nullptr;         // low-precision M2L row exponents

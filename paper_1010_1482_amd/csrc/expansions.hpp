@@ -28,9 +28,14 @@ void run_export(const double* X, int ld, int ncells, int p, const double* cen, i
                 double* out, hipStream_t s);
 
 bool m2l_uses_mfma(int p, int precision);
+// rotation-based M2L (rotation.hip)
+size_t rot_ops_bytes(int p, int precision);
+void run_rot_ops(int p, int precision, void* tab, hipStream_t s);
+int run_m2l_rot(Tree& t, int p, int precision, void* out, int64_t& part_stride, hipStream_t s);
 void m2l_layout(int p, int precision, int& RB, int& KQ, int& ld);
 size_t m2l_ops_bytes(int p, int precision);
 void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s);
+void prepare_rot_ops(Tree& t, int p, int precision, hipStream_t s);
 int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int max_parts,
             int32_t* levexp, hipStream_t s);
 

@@ -817,7 +817,7 @@ __global__ void k_cast_ops(const double* __restrict__ a, int64_t n, T* __restric
 }
 
 void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s) {
-    if (t.ops_p == p && t.ops_prec == precision && t.T) {
+    if (t.ops_p == p && t.ops_prec == precision && t.T && !t.ops_rot) {
         t.arena.lo = t.mark_ops;
         return;
     }
@@ -853,6 +853,22 @@ void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s) {
     }
     t.ops_p = p;
     t.ops_prec = precision;
+    t.ops_rot = false;
+    t.mark_ops = t.arena.lo;
+}
+
+// the rotation M2L's tables, cached like the dense operators
+void prepare_rot_ops(Tree& t, int p, int precision, hipStream_t s) {
+    if (t.ops_p == p && t.ops_prec == precision && t.T && t.ops_rot) {
+        t.arena.lo = t.mark_ops;
+        return;
+    }
+    t.T = t.arena.up<char>(rot_ops_bytes(p, precision));
+    t.bexp = nullptr;
+    run_rot_ops(p, precision, t.T, s);
+    t.ops_p = p;
+    t.ops_prec = precision;
+    t.ops_rot = true;
     t.mark_ops = t.arena.lo;
 }
 

@@ -16,12 +16,12 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhfmm.so")
 
-DIRECT, TREECODE, FMM, TREECODE_FMMLIST = 0, 1, 2, 3
+DIRECT, TREECODE, FMM, TREECODE_FMMLIST, FMM_ROT = 0, 1, 2, 3, 4
 FP64, FP32, M2L_BF16, M2L_BF16X3, M2L_FP16, M2L_FP16X3 = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": M2L_BF16, "bf16x3": M2L_BF16X3,
               "fp16": M2L_FP16, "fp16x3": M2L_FP16X3}
 METHODS = {"direct": DIRECT, "treecode": TREECODE, "fmm": FMM,
-           "treecode_fmmlist": TREECODE_FMMLIST}
+           "treecode_fmmlist": TREECODE_FMMLIST, "fmm_rot": FMM_ROT}
 OK, E_INVAL, E_NOMEM, E_UNSUPPORTED, E_HIP, E_STATE, E_DATA, E_OVERFLOW = \
     0, -1, -2, -3, -4, -5, -6, -7
 ST_SRC_NONFINITE, ST_TGT_NONFINITE, ST_MASS_NONFINITE, ST_OVERFLOW = 1, 2, 4, 8
