@@ -656,6 +656,41 @@ void oracle_tree_centres(const otree* t, double* cx, double* cy, double* cz,
     }
 }
 
+/* ---- a tree kept while its particles move (time stepping) ---- */
+
+/* The particles of the tree take new positions (caller order): the cells,
+ * their membership and order, the root and the lists stay as built, and the
+ * expansions about the unchanged cell centres are formed from the new
+ * positions by the drivers on this tree. */
+void oracle_tree_move(otree* t, const double* x, const double* y,
+                      const double* z) {
+    for (int64_t s = 0; s < t->n; s++) {
+        t->xs[s] = x[t->perm[s]];
+        t->ys[s] = y[t->perm[s]];
+        t->zs[s] = z[t->perm[s]];
+    }
+}
+
+/* 1 when every particle at the new positions (caller order) lies within
+ * (1/2 + slack) leaf sides of the centre of the leaf it was built into,
+ * along each axis, else 0 (non-finite positions give 0).  slack = 0 is the
+ * leaf's own closed box; a kept tree's expansions converge while the slack
+ * leaves room inside the one-cell separation of the lists. */
+int oracle_tree_stays(const otree* t, const double* x, const double* y,
+                      const double* z, double slack) {
+    for (int64_t s = 0; s < t->n; s++) {
+        const ocell* c = &t->c[t->leaf_of[s]];
+        double cc[3];
+        cell_centre(t, c, cc);
+        const double lim = (0.5 + slack) * cell_side(t, c->level);
+        const int64_t i = t->perm[s];
+        const double d[3] = {x[i] - cc[0], y[i] - cc[1], z[i] - cc[2]};
+        for (int a = 0; a < 3; a++)
+            if (!(fabs(d[a]) <= lim)) return 0;
+    }
+    return 1;
+}
+
 /* Closed boxes of A and B intersect (integer test, levels may differ). */
 static int adjacent(const ocell* A, const ocell* B) {
     if (A->level > B->level) {
@@ -1058,13 +1093,11 @@ static int64_t* inverse_perm(const otree* t) {
     return inv;
 }
 
-int oracle_fmm(int64_t n, const double* x, const double* y, const double* z,
-               const double* m, int leaf_max, int p, double eps2, int64_t nt,
-               const int64_t* tidx, double* phi, double* ax, double* ay,
-               double* az) {
-    if (tidx == NULL) nt = n;
-    if (n == 0 || nt == 0) return 0;
-    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+int oracle_fmm_tree(otree* t, const double* m, int p, double eps2, int64_t nt,
+                    const int64_t* tidx, double* phi, double* ax, double* ay,
+                    double* az) {
+    if (tidx == NULL) nt = t->n;
+    if (t->n == 0 || nt == 0) return 0;
     build_lists(t);
     const int64_t nc = t->ncells, pp = (int64_t)p * p;
     double* ms = sorted_masses(t, m);
@@ -1111,8 +1144,19 @@ int oracle_fmm(int64_t n, const double* x, const double* y, const double* z,
     free(inv);
     free(cen);
     free(ms);
-    oracle_tree_free(t);
     return 0;
+}
+
+int oracle_fmm(int64_t n, const double* x, const double* y, const double* z,
+               const double* m, int leaf_max, int p, double eps2, int64_t nt,
+               const int64_t* tidx, double* phi, double* ax, double* ay,
+               double* az) {
+    if (tidx == NULL) nt = n;
+    if (n == 0 || nt == 0) return 0;
+    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+    int rc = oracle_fmm_tree(t, m, p, eps2, nt, tidx, phi, ax, ay, az);
+    oracle_tree_free(t);
+    return rc;
 }
 
 /* per-particle Barnes-Hut traversal for one target at sorted position s */
@@ -1185,14 +1229,12 @@ static void fmm_list_point(const otree* t, const double* cen, const cplx* M,
     }
 }
 
-int oracle_treecode(int64_t n, const double* x, const double* y,
-                    const double* z, const double* m, int leaf_max, int p,
-                    double theta, int mode, double eps2, int64_t nt,
-                    const int64_t* tidx, double* phi, double* ax, double* ay,
-                    double* az) {
-    if (tidx == NULL) nt = n;
-    if (n == 0 || nt == 0) return 0;
-    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+int oracle_treecode_tree(otree* t, const double* m, int p, double theta,
+                         int mode, double eps2, int64_t nt,
+                         const int64_t* tidx, double* phi, double* ax,
+                         double* ay, double* az) {
+    if (tidx == NULL) nt = t->n;
+    if (t->n == 0 || nt == 0) return 0;
     const int64_t nc = t->ncells, pp = (int64_t)p * p;
     double* ms = sorted_masses(t, m);
     /* mode 2 expands about the geometric centres, as the FMM does */
@@ -1236,8 +1278,21 @@ int oracle_treecode(int64_t n, const double* x, const double* y,
     free(inv);
     free(com);
     free(ms);
-    oracle_tree_free(t);
     return 0;
+}
+
+int oracle_treecode(int64_t n, const double* x, const double* y,
+                    const double* z, const double* m, int leaf_max, int p,
+                    double theta, int mode, double eps2, int64_t nt,
+                    const int64_t* tidx, double* phi, double* ax, double* ay,
+                    double* az) {
+    if (tidx == NULL) nt = n;
+    if (n == 0 || nt == 0) return 0;
+    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+    int rc = oracle_treecode_tree(t, m, p, theta, mode, eps2, nt, tidx, phi,
+                                  ax, ay, az);
+    oracle_tree_free(t);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */

@@ -86,6 +86,15 @@ void oracle_tree_cells(const otree* t, int32_t* level, int32_t* ix,
 void oracle_tree_centres(const otree* t, double* cx, double* cy, double* cz,
                          double* side);
 
+/* A tree kept while its particles move: new positions (caller order) for
+ * the same cells, membership, order, root and lists. */
+void oracle_tree_move(otree* t, const double* x, const double* y,
+                      const double* z);
+/* 1 iff every particle at x, y, z lies within (1/2 + slack) leaf sides of
+ * its leaf's centre along each axis (non-finite: 0). */
+int oracle_tree_stays(const otree* t, const double* x, const double* y,
+                      const double* z, double slack);
+
 /* FMM lists U, V, W, X (which = 0..3). CSR: off[ncells+1], items[off[ncells]].
  * Lists are computed on first request. */
 int64_t oracle_list_size(otree* t, int which);
@@ -117,6 +126,16 @@ int oracle_fmm(int64_t n, const double* x, const double* y, const double* z,
                const double* m, int leaf_max, int p, double eps2, int64_t nt,
                const int64_t* tidx, double* phi, double* ax, double* ay,
                double* az);
+/* The FMM and the treecode on a given tree (its particles where
+ * oracle_tree_build or the last oracle_tree_move put them); masses and
+ * target indices in the caller's order. */
+int oracle_fmm_tree(otree* t, const double* m, int p, double eps2, int64_t nt,
+                    const int64_t* tidx, double* phi, double* ax, double* ay,
+                    double* az);
+int oracle_treecode_tree(otree* t, const double* m, int p, double theta,
+                         int mode, double eps2, int64_t nt,
+                         const int64_t* tidx, double* phi, double* ax,
+                         double* ay, double* az);
 /* Treecode. mode 0: group acceptance per target leaf; mode 1: per target
  * particle; expansions centred at centres of mass.  mode 2: the treecode of
  * Sec. 4, M2P over the FMM's V lists (leaf and ancestors) and W list, P2P

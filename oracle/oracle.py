@@ -49,6 +49,9 @@ def lib():
         L.oracle_anm.argtypes = [C.c_int, C.c_int]
         L.oracle_tree_build.restype = C.c_void_p
         L.oracle_tree_build.argtypes = [C.c_int64, _dp, _dp, _dp, C.c_int]
+        L.oracle_tree_move.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.oracle_tree_stays.restype = C.c_int
+        L.oracle_tree_stays.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double]
         L.oracle_tree_free.argtypes = [C.c_void_p]
         L.oracle_tree_ncells.restype = C.c_int64
         L.oracle_tree_ncells.argtypes = [C.c_void_p]
@@ -318,6 +321,40 @@ class Tree:
         lib().oracle_box_list(h, pt, C.c_int(which), items.ctypes.data_as(_i32p))
         return items[:n]
 
+    def move(self, x, y, z):
+        """New positions (caller order) for the same cells, membership,
+        order, root and lists (a tree kept across a time step)."""
+        self._keep = [_f64(x), _f64(y), _f64(z)]
+        lib().oracle_tree_move(C.c_void_p(self.h), *[_d(a) for a in self._keep])
+
+    def stays(self, x, y, z, slack):
+        """Every particle at x, y, z within (1/2 + slack) leaf sides of the
+        centre of its leaf, along each axis."""
+        x, y, z = map(_f64, (x, y, z))
+        return bool(lib().oracle_tree_stays(C.c_void_p(self.h), _d(x), _d(y), _d(z),
+                                            C.c_double(slack)))
+
+    def fmm(self, m, p, targets=None, eps2=0.0):
+        """The FMM on this tree (phi, ax, ay, az) at caller indices."""
+        m = _f64(m)
+        nt, tg = _targets(targets, self.n)
+        out = [np.zeros(nt) for _ in range(4)]
+        lib().oracle_fmm_tree(C.c_void_p(self.h), _d(m), C.c_int(p), C.c_double(eps2),
+                              C.c_int64(nt), None if tg is None else tg.ctypes.data_as(_i64p),
+                              *[_d(o) for o in out])
+        return tuple(out)
+
+    def treecode(self, m, p, theta, mode=0, targets=None, eps2=0.0):
+        """The treecode (modes as `treecode`) on this tree."""
+        m = _f64(m)
+        nt, tg = _targets(targets, self.n)
+        out = [np.zeros(nt) for _ in range(4)]
+        lib().oracle_treecode_tree(C.c_void_p(self.h), _d(m), C.c_int(p), C.c_double(theta),
+                                   C.c_int(mode), C.c_double(eps2), C.c_int64(nt),
+                                   None if tg is None else tg.ctypes.data_as(_i64p),
+                                   *[_d(o) for o in out])
+        return tuple(out)
+
     def fmm_expansions(self, m, p):
         m = _f64(m)
         nc = self.ncells
@@ -426,3 +463,33 @@ def leapfrog(x, y, z, vx, vy, vz, m, dt, steps, field=None):
         for v, a in zip(vel, acc):
             v += 0.5 * dt * a
     return (*pos, *vel, phi, *acc)
+
+
+def leapfrog_tree(x, y, z, vx, vy, vz, m, dt, steps, leaf_max, slack, evaluate):
+    """Kick-drift-kick leapfrog (as `leapfrog`) whose field comes from an
+    octree kept across steps.  After each drift the tree takes the new
+    positions (Tree.move) when every particle lies within (1/2 + slack) leaf
+    sides of its leaf's centre along each axis (Tree.stays), and a new tree
+    is built otherwise; slack < 0 builds one every step.
+    evaluate(tree, m) -> (phi, ax, ay, az) in caller order.  Returns the
+    state and field as `leapfrog` does, then the number of trees built."""
+    pos = [np.array(a, dtype=np.float64) for a in (x, y, z)]
+    vel = [np.array(a, dtype=np.float64) for a in (vx, vy, vz)]
+    m = _f64(m)
+    tree = Tree(*pos, leaf_max)
+    builds = 1
+    phi, *acc = evaluate(tree, m)
+    for _ in range(steps):
+        for v, a in zip(vel, acc):
+            v += 0.5 * dt * a
+        for q, v in zip(pos, vel):
+            q += dt * v
+        if slack >= 0 and tree.stays(*pos, slack):
+            tree.move(*pos)
+        else:
+            tree = Tree(*pos, leaf_max)
+            builds += 1
+        phi, *acc = evaluate(tree, m)
+        for v, a in zip(vel, acc):
+            v += 0.5 * dt * a
+    return (*pos, *vel, phi, *acc, builds)
