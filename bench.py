@@ -255,35 +255,41 @@ def measure(args, prec_name, x, y, z, m, dev, steps, warmup, accuracy):
 
 def leapfrog_rate(args, x, y, z, m, dev):
     """Time steps of the N-body loop (kick-drift-kick leapfrog, one force
-    evaluation per step, a new tree each time) at the same configuration,
-    from rest: per-step time = (time of K steps - time of 0 steps) / K, the
-    0-step call being the initial evaluation both make.  The near field is
-    softened (eps^2 = 1e-6) and dt = 1e-4: unsoftened close pairs of a
-    random cube would be flung out in the first steps and blow up the root
-    cell."""
+    evaluation per step) at the same configuration, from rest, once with a
+    new tree every step and once with the tree kept while every particle
+    stays within 1/2 + 1/16 leaf sides of its leaf's centre: per-step time =
+    (time of K steps - time of 0 steps) / K, the 0-step call being the
+    initial evaluation both make.  The near field is softened
+    (eps^2 = 1e-6) and dt = 1e-4: unsoftened close pairs of a random cube
+    would be flung out in the first steps and blow up the root cell."""
     import torch
     from paper_1010_1482_amd import hfmm
     k = args.leapfrog_steps
     xd, yd, zd, md = (torch.from_numpy(a).to(dev) for a in (x, y, z, m))
     v = [torch.zeros_like(xd) for _ in range(3)]
     dt, eps2 = 1e-4, 1e-6
-    kw = dict(p=args.p, method=args.method, precision=args.precision, leaf_max=args.leaf,
-              theta=args.theta, eps2=eps2)
-    hfmm.leapfrog(xd, yd, zd, *v, md, dt, 1, **kw)  # warm-up
-    times = {}
-    for steps in (0, k):
-        pos = [a.clone() for a in (xd, yd, zd)]
-        vel = [a.clone() for a in v]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        hfmm.leapfrog(*pos, *vel, md, dt, steps, **kw)
-        torch.cuda.synchronize()
-        times[steps] = time.perf_counter() - t0
-    ms = (times[k] - times[0]) / k * 1e3
-    return {"steps": k, "dt": dt, "eps2": eps2, "ms_per_step": ms,
-            "particle_steps_per_s": len(x) / (ms * 1e-3),
-            "note": "kick-drift-kick leapfrog from rest, one evaluation and one new tree "
-                    "per step"}
+    res = {"steps": k, "dt": dt, "eps2": eps2}
+    for name, slack in (("new_tree", -1.0), ("kept_tree", 1.0 / 16.0)):
+        kw = dict(p=args.p, method=args.method, precision=args.precision, leaf_max=args.leaf,
+                  theta=args.theta, eps2=eps2, slack=slack)
+        hfmm.leapfrog(xd.clone(), yd.clone(), zd.clone(), *[a.clone() for a in v], md, dt, 1,
+                      **kw)  # warm-up
+        times, info = {}, {}
+        for steps in (0, k):
+            pos = [a.clone() for a in (xd, yd, zd)]
+            vel = [a.clone() for a in v]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hfmm.leapfrog(*pos, *vel, md, dt, steps, info=info, **kw)
+            torch.cuda.synchronize()
+            times[steps] = time.perf_counter() - t0
+        ms = (times[k] - times[0]) / k * 1e3
+        res[name] = {"slack": slack, "ms_per_step": ms, "trees_built": info.get("builds"),
+                     "particle_steps_per_s": len(x) / (ms * 1e-3)}
+    res["note"] = ("kick-drift-kick leapfrog from rest; new_tree builds a tree per step, "
+                   "kept_tree refits the first one while the particles stay within "
+                   "1/2 + slack leaf sides of their leaves' centres")
+    return res
 
 
 def main() -> int:

@@ -182,6 +182,27 @@ int hfmm_solve(const double* x, const double* y, const double* z,
                void* arena, size_t arena_bytes, void* phi, void* ax, void* ay,
                void* az, void* stream);
 
+/* Move the tree's sources to new positions x, y, z (device, FP64, n_src
+ * each, in the order given to hfmm_build_tree) keeping the tree: the root,
+ * the cells, which sources each holds and in what order, and the FMM lists
+ * stay as built, which lets a time step of the N-body simulation skip the
+ * build.  The expansions of a kept tree stay about the cell centres of the
+ * build and converge only while each source stays near its leaf, hence the
+ * rule: when every source lies within (1/2 + slack) leaf sides of its
+ * leaf's centre along each axis (slack >= 0; 0 is the leaf's closed box),
+ * *kept = 1 and the tree holds the new positions; hfmm_upward (new
+ * expansions, centres of mass and treecode lists) must then run before the
+ * next hfmm_evaluate (HFMM_E_STATE otherwise).  Otherwise, and for
+ * non-finite positions, *kept = 0 and the handle holds no usable tree:
+ * hfmm_upward and hfmm_evaluate return HFMM_E_STATE, and the caller
+ * releases it and builds a new one.  With the one-cell separation of the
+ * FMM lists the kept expansions converge for slack below sqrt(3)/3 - 1/2
+ * (about 0.077); 1/16 keeps the accuracy close to that of a new tree.
+ * Waits for the stream (a 4-byte read back).  HFMM_E_INVAL for null
+ * pointers or a negative or non-finite slack. */
+int hfmm_refit(hfmm_tree t, const double* x, const double* y, const double* z,
+               double slack, void* stream, int* kept);
+
 /* The tree's device status word: waits for the work enqueued on `stream`
  * and reads it.  Returns HFMM_OK, HFMM_E_DATA (non-finite source or target
  * coordinates or masses: the results are meaningless) or HFMM_E_OVERFLOW (a
@@ -227,30 +248,35 @@ int hfmm_direct_noalloc(const double* x, const double* y, const double* z,
  * integrator, this is kick-drift-kick leapfrog).  Advances x, y, z, vx, vy,
  * vz (device, FP64, n each, in place) by `steps` steps of length dt under
  * the field of all the particles evaluated by `method` (HFMM_DIRECT,
- * HFMM_TREECODE, HFMM_TREECODE_FMMLIST or HFMM_FMM, with p, theta,
- * precision, eps2 and leaf_max as for hfmm_solve; every evaluation builds a
- * new tree).  Per step: v += a dt/2; x += v dt; a = field(x); v += a dt/2.
- * The field at the initial positions is evaluated first, so a call makes
- * steps + 1 evaluations; on return phi, ax, ay, az (n each, FP64 for
- * HFMM_FP64, FP32 otherwise) hold the field at the final positions.  The
- * arena holds the evaluation's space (hfmm_arena_bytes, or
- * hfmm_direct_bytes for HFMM_DIRECT) plus 48 bytes per particle for the
- * state of the last completed step.  *done (may be NULL) receives the
- * steps completed: after HFMM_E_NOMEM the positions and velocities are
- * those of step *done and hfmm_last_required_bytes() an arena size that
- * would have sufficed, so the caller can continue with the remaining
- * steps. */
+ * HFMM_TREECODE, HFMM_TREECODE_FMMLIST, HFMM_FMM or HFMM_FMM_ROT, with p,
+ * theta, precision, eps2 and leaf_max as for hfmm_solve).  Per step:
+ * v += a dt/2; x += v dt; a = field(x); v += a dt/2.  The field at the
+ * initial positions is evaluated first, so a call makes steps + 1
+ * evaluations; on return phi, ax, ay, az (n each, FP64 for HFMM_FP64, FP32
+ * otherwise) hold the field at the final positions.  slack < 0 builds a new
+ * tree for every evaluation; slack >= 0 keeps the tree across steps while
+ * the moved particles pass the rule of hfmm_refit with that slack, and
+ * builds a new one when they do not.  The arena holds the evaluation's
+ * space (hfmm_arena_bytes, or hfmm_direct_bytes for HFMM_DIRECT) plus 48
+ * bytes per particle for the state of the last completed step.  *done (may
+ * be NULL) receives the steps completed and *builds (may be NULL) the trees
+ * built: after HFMM_E_NOMEM the positions and velocities are those of step
+ * *done and hfmm_last_required_bytes() an arena size that would have
+ * sufficed, so the caller can continue with the remaining steps (from a new
+ * tree). */
 int hfmm_leapfrog(double* x, double* y, double* z, double* vx, double* vy,
                   double* vz, const double* m, int64_t n, double dt, int steps,
                   int leaf_max, int p, double theta, int method, int precision,
-                  double eps2, void* arena, size_t arena_bytes, void* phi,
-                  void* ax, void* ay, void* az, int* done, void* stream);
+                  double eps2, double slack, void* arena, size_t arena_bytes,
+                  void* phi, void* ax, void* ay, void* az, int* done,
+                  int* builds, void* stream);
 
 /* Release the host handle (the arena belongs to the caller). */
 void hfmm_tree_release(hfmm_tree t);
 
 /* Arena bytes that would have sufficed for the failed call (after
- * HFMM_E_NOMEM), or the bytes in use otherwise. */
+ * HFMM_E_NOMEM), or otherwise the most bytes the handle's calls have held
+ * at once. */
 size_t hfmm_required_bytes(hfmm_tree t);
 /* same, for a failed build that returned no handle (per thread) */
 size_t hfmm_last_required_bytes(void);

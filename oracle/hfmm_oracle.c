@@ -1499,16 +1499,14 @@ static void p2p_cells(const otree* t, const double* ms, double eps2, const ivec*
  * its V list by M2P and its X list by P2P as well, at the target itself:
  *   phi = L2P(L(H)) + M2P over V(B), W(B) + P2P over U(B), X(B)
  * (no L2P outside the root).  Every source is reached once. */
-int oracle_fmm_points(int64_t n, const double* x, const double* y, const double* z,
-                      const double* m, int leaf_max, int p, double eps2, int64_t nt,
-                      const double* tx, const double* ty, const double* tz, double* phi,
-                      double* ax, double* ay, double* az) {
+int oracle_fmm_points_tree(otree* t, const double* m, int p, double eps2, int64_t nt,
+                           const double* tx, const double* ty, const double* tz,
+                           double* phi, double* ax, double* ay, double* az) {
     if (nt == 0) return 0;
-    if (n == 0) {
+    if (t->n == 0) {
         for (int64_t k = 0; k < nt; k++) phi[k] = ax[k] = ay[k] = az[k] = 0.0;
         return 0;
     }
-    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
     build_lists(t);
     const int64_t nc = t->ncells, pp = (int64_t)p * p;
     double* ms = sorted_masses(t, m);
@@ -1544,8 +1542,22 @@ int oracle_fmm_points(int64_t n, const double* x, const double* y, const double*
     free(L);
     free(cen);
     free(ms);
-    oracle_tree_free(t);
     return 0;
+}
+
+int oracle_fmm_points(int64_t n, const double* x, const double* y, const double* z,
+                      const double* m, int leaf_max, int p, double eps2, int64_t nt,
+                      const double* tx, const double* ty, const double* tz, double* phi,
+                      double* ax, double* ay, double* az) {
+    if (nt == 0) return 0;
+    if (n == 0) {
+        for (int64_t k = 0; k < nt; k++) phi[k] = ax[k] = ay[k] = az[k] = 0.0;
+        return 0;
+    }
+    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+    int rc = oracle_fmm_points_tree(t, m, p, eps2, nt, tx, ty, tz, phi, ax, ay, az);
+    oracle_tree_free(t);
+    return rc;
 }
 
 /* Barnes-Hut traversal for a target box (the group acceptance of mode 0):
@@ -1583,18 +1595,16 @@ static void bh_box(const otree* t, const double* com, double theta, const obox* 
  * over the FMM lists of the box: M2P over V and W of the box and V of each
  * ancestor, P2P over U and X of the box and X of each ancestor (expansions
  * about the geometric centres). */
-int oracle_treecode_points(int64_t n, const double* x, const double* y, const double* z,
-                           const double* m, int leaf_max, int p, double theta, int mode,
-                           double eps2, int64_t nt, const double* tx, const double* ty,
-                           const double* tz, double* phi, double* ax, double* ay,
-                           double* az) {
+int oracle_treecode_points_tree(otree* t, const double* m, int p, double theta,
+                                int mode, double eps2, int64_t nt, const double* tx,
+                                const double* ty, const double* tz, double* phi,
+                                double* ax, double* ay, double* az) {
     if (nt == 0) return 0;
     if (mode != 0 && mode != 2) return -1;
-    if (n == 0) {
+    if (t->n == 0) {
         for (int64_t k = 0; k < nt; k++) phi[k] = ax[k] = ay[k] = az[k] = 0.0;
         return 0;
     }
-    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
     const int64_t nc = t->ncells, pp = (int64_t)p * p;
     double* ms = sorted_masses(t, m);
     double* cen = mode == 2 ? geometric_centres(t) : com_array(t, m);
@@ -1641,8 +1651,25 @@ int oracle_treecode_points(int64_t n, const double* x, const double* y, const do
     free(M);
     free(cen);
     free(ms);
-    oracle_tree_free(t);
     return 0;
+}
+
+int oracle_treecode_points(int64_t n, const double* x, const double* y, const double* z,
+                           const double* m, int leaf_max, int p, double theta, int mode,
+                           double eps2, int64_t nt, const double* tx, const double* ty,
+                           const double* tz, double* phi, double* ax, double* ay,
+                           double* az) {
+    if (mode != 0 && mode != 2) return -1;
+    if (nt == 0) return 0;
+    if (n == 0) {
+        for (int64_t k = 0; k < nt; k++) phi[k] = ax[k] = ay[k] = az[k] = 0.0;
+        return 0;
+    }
+    otree* t = oracle_tree_build(n, x, y, z, leaf_max);
+    int rc = oracle_treecode_points_tree(t, m, p, theta, mode, eps2, nt, tx, ty, tz, phi,
+                                          ax, ay, az);
+    oracle_tree_free(t);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */

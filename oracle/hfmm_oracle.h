@@ -171,6 +171,17 @@ int oracle_treecode_points(int64_t n, const double* x, const double* y,
                            const double* tz, double* phi, double* ax,
                            double* ay, double* az);
 
+/* The same on a given tree (see oracle_fmm_tree). */
+int oracle_fmm_points_tree(otree* t, const double* m, int p, double eps2,
+                           int64_t nt, const double* tx, const double* ty,
+                           const double* tz, double* phi, double* ax,
+                           double* ay, double* az);
+int oracle_treecode_points_tree(otree* t, const double* m, int p, double theta,
+                                int mode, double eps2, int64_t nt,
+                                const double* tx, const double* ty,
+                                const double* tz, double* phi, double* ax,
+                                double* ay, double* az);
+
 /* ---- rotation-based M2L (Sec. 6) ---- */
 /* M2L by rotation to the translation axis, coaxial translation (Eq. 4 along
  * z) and rotation back; accumulates into L like oracle_m2l. */

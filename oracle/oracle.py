@@ -355,6 +355,27 @@ class Tree:
                                    *[_d(o) for o in out])
         return tuple(out)
 
+    def fmm_points(self, m, p, tx, ty, tz, eps2=0.0):
+        """The FMM on this tree at separate target points."""
+        m, tx, ty, tz = map(_f64, (m, tx, ty, tz))
+        out = [np.zeros(len(tx)) for _ in range(4)]
+        lib().oracle_fmm_points_tree(C.c_void_p(self.h), _d(m), C.c_int(p), C.c_double(eps2),
+                                     C.c_int64(len(tx)), _d(tx), _d(ty), _d(tz),
+                                     *[_d(o) for o in out])
+        return tuple(out)
+
+    def treecode_points(self, m, p, theta, tx, ty, tz, mode=0, eps2=0.0):
+        """The treecode (mode 0 or 2) on this tree at separate target points."""
+        if mode not in (0, 2):
+            raise ValueError("mode 0 or 2")
+        m, tx, ty, tz = map(_f64, (m, tx, ty, tz))
+        out = [np.zeros(len(tx)) for _ in range(4)]
+        lib().oracle_treecode_points_tree(C.c_void_p(self.h), _d(m), C.c_int(p),
+                                          C.c_double(theta), C.c_int(mode), C.c_double(eps2),
+                                          C.c_int64(len(tx)), _d(tx), _d(ty), _d(tz),
+                                          *[_d(o) for o in out])
+        return tuple(out)
+
     def fmm_expansions(self, m, p):
         m = _f64(m)
         nc = self.ncells

@@ -484,6 +484,7 @@ int hfmm_build_tree(const double* x, const double* y, const double* z, int64_t n
 int hfmm_upward(hfmm_tree h, const double* m, int p, int method, int precision,
                 void* stream) {
     if (!h) return HFMM_E_INVAL;
+    if (h->t.stale) return HFMM_E_STATE;
     API_BEGIN
     check_p(p);
     check_precision(precision);
@@ -545,6 +546,31 @@ int hfmm_solve(const double* x, const double* y, const double* z, const double* 
     return rc;
 }
 
+int hfmm_refit(hfmm_tree h, const double* x, const double* y, const double* z, double slack,
+               void* stream, int* kept) {
+    if (kept) *kept = 0;
+    if (!h || !kept) return HFMM_E_INVAL;
+    Tree& t = h->t;
+    if (t.n > 0 && (!x || !y || !z)) return HFMM_E_INVAL;
+    if (!(slack >= 0.0) || !std::isfinite(slack)) return HFMM_E_INVAL;
+    if (t.stale) return HFMM_E_STATE;
+    API_BEGIN
+    // the expansions, centres of mass and lists of the old positions go
+    t.up_p = 0;
+    t.up_method = t.up_prec = -1;
+    t.tg_sep = false;
+    t.tg = Targets{};
+    if (t.n == 0) {
+        *kept = 1;
+        return HFMM_OK;
+    }
+    t.stale = true;
+    const bool k = refit_tree(t, x, y, z, slack, (hipStream_t)stream);
+    t.stale = !k;
+    *kept = k ? 1 : 0;
+    API_END
+}
+
 int hfmm_status(hfmm_tree h, void* stream, uint32_t* flags) {
     if (flags) *flags = 0;
     if (!h) return HFMM_E_INVAL;
@@ -601,7 +627,7 @@ void hfmm_tree_release(hfmm_tree h) { delete h; }
 
 size_t hfmm_required_bytes(hfmm_tree h) {
     if (!h) return 0;
-    return h->t.arena.need ? h->t.arena.need : h->t.arena.used();
+    return h->t.arena.need ? h->t.arena.need : h->t.arena.peak;
 }
 
 size_t hfmm_last_required_bytes(void) { return g_last_required; }

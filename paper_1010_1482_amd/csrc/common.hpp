@@ -23,6 +23,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "../../include/hfmm.h"
@@ -58,6 +59,7 @@ struct Arena {
     char* base = nullptr;
     size_t cap = 0, lo = 0, hi = 0;
     size_t need = 0;  // bytes that would have sufficed (after a failure)
+    size_t peak = 0;  // the most bytes in use at once so far
 
     static size_t align(size_t b) { return (b + HFMM_ALIGN - 1) / HFMM_ALIGN * HFMM_ALIGN; }
 
@@ -69,6 +71,7 @@ struct Arena {
         lo = 0;
         hi = cap;
         need = 0;
+        peak = 0;
     }
     void fail(size_t bytes) {
         size_t want = lo + align(bytes) + (cap - hi) + HFMM_ALIGN;
@@ -81,6 +84,7 @@ struct Arena {
         if (lo + b > hi) fail(count * sizeof(T));
         T* p = (T*)(base + lo);
         lo += b;
+        peak = std::max(peak, used());
         return p;
     }
     template <typename T>
@@ -88,6 +92,7 @@ struct Arena {
         size_t b = align(count * sizeof(T) + 1);
         if (lo + b > hi) fail(count * sizeof(T));
         hi -= b;
+        peak = std::max(peak, used());
         return (T*)(base + hi);
     }
     size_t free_bytes() const { return hi - lo; }
@@ -189,6 +194,8 @@ struct Tree {
     double4* p64 = nullptr;          // x, y, z, m (FP64)
     int32_t* leaf_of = nullptr;      // sorted particle -> leaf cell
     int32_t* status = nullptr;       // device status word (StatusBits)
+    int32_t* moved = nullptr;        // device flag of the last refit
+    bool stale = false;              // a refit left the tree unusable
     // self-evaluation view: one box per leaf, sorted particle -> leaf index
     TBox* leaf_boxes = nullptr;
     int32_t* leaf_box_of = nullptr;
@@ -379,6 +386,15 @@ __host__ __device__ inline void cell_centre(const Root& r, const Cell& c,
     out[1] = r.b[1] + ((double)c.iy + 0.5) * h;
     out[2] = r.b[2] + ((double)c.iz + 0.5) * h;
 }
+// a position within (1/2 + slack) sides of the centre of cell c along each
+// axis (false for non-finite positions)
+__host__ __device__ inline bool within_cell(const Root& r, const Cell& c, double slack,
+                                            double x, double y, double z) {
+    double o[3];
+    cell_centre(r, c, o);
+    const double lim = (0.5 + slack) * cell_side(r, c.level);
+    return fabs(x - o[0]) <= lim && fabs(y - o[1]) <= lim && fabs(z - o[2]) <= lim;
+}
 #pragma clang fp contract(on)
 
 // closed boxes of two cells intersect (levels may differ)
@@ -477,6 +493,8 @@ void radix_sort_pairs(const uint64_t* keys, const int32_t* vals, uint64_t* keys_
                       hipStream_t s);
 
 void build_tree(Tree& t, const double* x, const double* y, const double* z, hipStream_t s);
+bool refit_tree(Tree& t, const double* x, const double* y, const double* z, double slack,
+                hipStream_t s);
 void build_fmm_lists(Tree& t, hipStream_t s);
 void build_bh_lists(Tree& t, double theta, hipStream_t s);
 void set_last_required(size_t bytes);  // for hfmm_last_required_bytes

@@ -2,10 +2,12 @@
 // gives no integrator): kick-drift-kick leapfrog around the force evaluation,
 //   v += a dt/2;  x += v dt;  a = field(x);  v += a dt/2,
 // a being the field of all the other particles (Eq. 1 per unit mass, the
-// sign of Sec. 5.1).  Every evaluation builds a new tree of the moved
-// particles in the caller's arena; the state of the last completed step is
-// kept at the top of the arena, so that an evaluation that runs out of arena
-// space leaves the caller a whole step to continue from.
+// sign of Sec. 5.1).  The tree of the moved particles is either built anew
+// in the caller's arena or, while every particle stays near the leaf it was
+// built into, kept with the new positions (hfmm_refit); the state of the
+// last completed step is kept at the top of the arena, so that an
+// evaluation that runs out of arena space leaves the caller a whole step to
+// continue from.
 #include "common.hpp"
 
 namespace hfmm {
@@ -39,10 +41,12 @@ using namespace hfmm;
 extern "C" int hfmm_leapfrog(double* x, double* y, double* z, double* vx, double* vy,
                              double* vz, const double* m, int64_t n, double dt, int steps,
                              int leaf_max, int p, double theta, int method, int precision,
-                             double eps2, void* arena, size_t arena_bytes, void* phi, void* ax,
-                             void* ay, void* az, int* done, void* stream) {
+                             double eps2, double slack, void* arena, size_t arena_bytes,
+                             void* phi, void* ax, void* ay, void* az, int* done, int* builds,
+                             void* stream) {
     if (done) *done = 0;
-    if (n < 0 || steps < 0 || !(dt == dt) || !arena) return HFMM_E_INVAL;
+    if (builds) *builds = 0;
+    if (n < 0 || steps < 0 || !(dt == dt) || !(slack == slack) || !arena) return HFMM_E_INVAL;
     if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !m || !phi || !ax || !ay || !az))
         return HFMM_E_INVAL;
     if (n == 0) {
@@ -70,13 +74,50 @@ extern "C" int hfmm_leapfrog(double* x, double* y, double* z, double* vx, double
                                (const float*)ax, (const float*)ay, (const float*)az, hk, d);
         return hipGetLastError() == hipSuccess;
     };
+    // the tree of the current positions (none for the direct sum)
+    hfmm_tree h = nullptr;
+    size_t need = 0;  // arena bytes a failed evaluation asked for
+    auto release = [&]() {
+        if (h) hfmm_tree_release(h);
+        h = nullptr;
+    };
+    auto on_tree = [&]() {
+        int rc = hfmm_upward(h, m, p, method, precision, stream);
+        if (rc == HFMM_OK)
+            rc = hfmm_evaluate(h, nullptr, nullptr, nullptr, 0, p, theta, method, precision,
+                               eps2, phi, ax, ay, az, stream);
+        if (rc == HFMM_OK) rc = hfmm_status(h, stream, nullptr);
+        if (rc == HFMM_E_NOMEM) need = hfmm_required_bytes(h);
+        return rc;
+    };
     auto field = [&]() {
-        return hfmm_solve(x, y, z, m, n, nullptr, nullptr, nullptr, 0, leaf_max, p, theta,
-                          method, precision, eps2, arena, eval_bytes, phi, ax, ay, az, stream);
+        need = 0;
+        if (method == HFMM_DIRECT) {
+            const int rc = hfmm_direct(x, y, z, m, n, nullptr, nullptr, nullptr, 0, precision,
+                                       eps2, arena, eval_bytes, phi, ax, ay, az, stream);
+            if (rc == HFMM_E_NOMEM) need = hfmm_last_required_bytes();
+            return rc;
+        }
+        if (h && slack >= 0.0) {
+            int kept = 0;
+            const int rc = hfmm_refit(h, x, y, z, slack, stream, &kept);
+            if (rc != HFMM_OK) return rc;
+            if (kept) return on_tree();
+        }
+        release();
+        const int rc = hfmm_build_tree(x, y, z, n, leaf_max, arena, eval_bytes, stream, &h);
+        if (rc != HFMM_OK) {
+            h = nullptr;
+            if (rc == HFMM_E_NOMEM) need = hfmm_last_required_bytes();
+            return rc;
+        }
+        if (builds) ++*builds;
+        return on_tree();
     };
     auto fail = [&](int rc) {
+        release();
         // the arena this call needs: the evaluation's and the saved state
-        if (rc == HFMM_E_NOMEM) set_last_required(hfmm_last_required_bytes() + state + (1 << 20));
+        if (rc == HFMM_E_NOMEM) set_last_required(need + state + (1 << 20));
         return rc;
     };
     int rc = field();
@@ -85,19 +126,20 @@ extern "C" int hfmm_leapfrog(double* x, double* y, double* z, double* vx, double
         for (int a = 0; a < 6; ++a)
             if (hipMemcpyAsync(keep + (size_t)a * n, cur[a], sizeof(double) * n,
                                hipMemcpyDeviceToDevice, s) != hipSuccess)
-                return HFMM_E_HIP;
-        if (!kick(0.5 * dt, dt)) return HFMM_E_HIP;
+                return fail(HFMM_E_HIP);
+        if (!kick(0.5 * dt, dt)) return fail(HFMM_E_HIP);
         rc = field();
         if (rc != HFMM_OK) {
             // back to the state of the last completed step
             for (int a = 0; a < 6; ++a)
                 if (hipMemcpyAsync(cur[a], keep + (size_t)a * n, sizeof(double) * n,
                                    hipMemcpyDeviceToDevice, s) != hipSuccess)
-                    return HFMM_E_HIP;
+                    return fail(HFMM_E_HIP);
             return fail(rc);
         }
-        if (!kick(0.5 * dt, 0.0)) return HFMM_E_HIP;
+        if (!kick(0.5 * dt, 0.0)) return fail(HFMM_E_HIP);
         if (done) *done = k + 1;
     }
+    release();
     return HFMM_OK;
 }

@@ -602,6 +602,49 @@ __global__ void k_sort_check(const uint64_t* __restrict__ keys, int64_t n, int l
     if ((keys[i] >> sh) == (keys[i + leaf_max] >> sh)) *flag = 1;
 }
 
+// A kept tree takes new positions: sorted slot s gets the position of its
+// particle perm[s] (FP64, and FP32 about its leaf's centre, the mass lane
+// kept); *moved = 1 when a particle lies beyond (1/2 + slack) leaf sides of
+// its leaf's centre on some axis, or is not finite.
+__global__ void k_refit(const double* __restrict__ x, const double* __restrict__ y,
+                        const double* __restrict__ z, int64_t n,
+                        const int32_t* __restrict__ perm, const Cell* __restrict__ cells,
+                        const int32_t* __restrict__ leaf_of, const Root* __restrict__ root,
+                        double slack, double* __restrict__ xs, double* __restrict__ ys,
+                        double* __restrict__ zs, float4* __restrict__ p32,
+                        int32_t* __restrict__ moved) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    const double a = x[i], b = y[i], c = z[i];
+    xs[s] = a;
+    ys[s] = b;
+    zs[s] = c;
+    const Root r = *root;
+    const Cell cl = cells[leaf_of[s]];
+    double o[3];
+    cell_centre(r, cl, o);
+    float4 q = p32[s];
+    q.x = (float)(a - o[0]);
+    q.y = (float)(b - o[1]);
+    q.z = (float)(c - o[2]);
+    p32[s] = q;
+    if (!within_cell(r, cl, slack, a, b, c)) *moved = 1;
+}
+
+bool refit_tree(Tree& t, const double* x, const double* y, const double* z, double slack,
+                hipStream_t s) {
+    HIP_TRY(hipMemsetAsync(t.moved, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_refit, dim3(grid_for(t.n, 256)), dim3(256), 0, s, x, y, z, t.n,
+                       t.perm, t.cells, t.leaf_of, t.root, slack, t.xs, t.ys, t.zs, t.p32,
+                       t.moved);
+    LAUNCH_CHECK();
+    int32_t h = 1;
+    HIP_TRY(hipMemcpyAsync(&h, t.moved, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return h == 0;
+}
+
 static int sort_levels_guess(int64_t n, int leaf_max) {
     // levels a uniform distribution needs, plus two
     double ratio = (double)n / (double)std::max(1, leaf_max);
@@ -618,6 +661,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     const int64_t n = t.n;
     t.status = A.up<int32_t>(1);
     HIP_TRY(hipMemsetAsync(t.status, 0, sizeof(int32_t), s));
+    t.moved = A.up<int32_t>(1);
     t.root = A.up<Root>(1);
     t.keys = A.up<uint64_t>(n);
     t.perm = A.up<int32_t>(n);

@@ -29,7 +29,7 @@ MAX_P = 16
 
 # exported symbols, in the order include/hfmm.h declares them
 SYMBOLS = ("hfmm_arena_bytes", "hfmm_build_tree", "hfmm_upward", "hfmm_evaluate",
-           "hfmm_solve", "hfmm_status", "hfmm_direct_bytes", "hfmm_direct", "hfmm_direct_noalloc",
+           "hfmm_solve", "hfmm_refit", "hfmm_status", "hfmm_direct_bytes", "hfmm_direct", "hfmm_direct_noalloc",
            "hfmm_leapfrog",
            "hfmm_tree_release",
            "hfmm_required_bytes", "hfmm_last_required_bytes", "hfmm_get_stats",
@@ -91,8 +91,9 @@ def _lib():
         L.hfmm_direct_noalloc.argtypes = [_vp, _vp, _vp, _vp, i64, _vp, _vp, _vp, i64, i32, d,
                                           _vp, _vp, _vp, _vp, _vp]
         L.hfmm_leapfrog.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, i64, d, i32, i32, i32,
-                                    d, i32, i32, d, _vp, sz, _vp, _vp, _vp, _vp,
-                                    C.POINTER(i32), _vp]
+                                    d, i32, i32, d, d, _vp, sz, _vp, _vp, _vp, _vp,
+                                    C.POINTER(i32), C.POINTER(i32), _vp]
+        L.hfmm_refit.argtypes = [_vp, _vp, _vp, _vp, d, _vp, C.POINTER(i32)]
         L.hfmm_tree_release.argtypes = [_vp]
         L.hfmm_tree_release.restype = None
         L.hfmm_required_bytes.argtypes = [_vp]
@@ -247,6 +248,19 @@ class Tree:
         _check(rc, "hfmm_evaluate")
         return out
 
+    def refit(self, x, y, z, slack, stream=None):
+        """Move the sources to x, y, z keeping the tree when every one stays
+        within (1/2 + slack) leaf sides of its leaf's centre on each axis
+        (True; upward must run again before evaluate), else False (the tree
+        is unusable: build a new one)."""
+        for nm, t in (("x", x), ("y", y), ("z", z)):
+            _dev(t, nm)
+        kept = C.c_int(0)
+        _check(_lib().hfmm_refit(self.h, _ptr(x), _ptr(y), _ptr(z), float(slack),
+                                 _stream(stream), C.byref(kept)), "hfmm_refit")
+        self._keep = (x, y, z)
+        return bool(kept.value)
+
     def status(self, stream=None):
         """(code, flags) of the device status word after the enqueued work."""
         f = C.c_uint32(0)
@@ -362,12 +376,15 @@ def solve(x, y, z, m, p=10, method=FMM, precision=FP32, leaf_max=64, theta=0.5, 
 
 
 def leapfrog(x, y, z, vx, vy, vz, m, dt, steps, p=10, method=FMM, precision=FP32,
-             leaf_max=64, theta=0.5, eps2=0.0, out=None, stream=None):
+             leaf_max=64, theta=0.5, eps2=0.0, slack=-1.0, out=None, info=None, stream=None):
     """`steps` kick-drift-kick steps of length dt on the device, positions and
     velocities (contiguous float64 CUDA tensors) updated in place; returns
-    the field (phi, ax, ay, az) at the final positions.  When the arena
-    turns out too small the library stops at a whole step and the call
-    continues from there with a larger one."""
+    the field (phi, ax, ay, az) at the final positions.  slack < 0 builds a
+    tree per evaluation; slack >= 0 keeps it while the particles stay within
+    (1/2 + slack) leaf sides of their leaves' centres (Tree.refit).  When
+    the arena turns out too small the library stops at a whole step and the
+    call continues from there with a larger one.  `info` (a dict) receives
+    the trees built ("builds") and the calls made ("calls")."""
     method, precision = _meth(method), _prec(precision)
     for nm, t in (("x", x), ("y", y), ("z", z), ("vx", vx), ("vy", vy), ("vz", vz),
                   ("m", m)):
@@ -384,13 +401,18 @@ def leapfrog(x, y, z, vx, vy, vz, m, dt, steps, p=10, method=FMM, precision=FP32
         nbytes = arena_bytes(n, 0, leaf_max, p, method, precision)
     nbytes += 48 * n + (2 << 20)
     left = int(steps)
-    for _ in range(8):
+    builds = 0
+    for calls in range(1, 9):
         ar = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
-        done = C.c_int(0)
+        done, nb = C.c_int(0), C.c_int(0)
         rc = _lib().hfmm_leapfrog(_ptr(x), _ptr(y), _ptr(z), _ptr(vx), _ptr(vy), _ptr(vz),
                                   _ptr(m), n, float(dt), left, leaf_max, p, float(theta),
-                                  method, precision, float(eps2), _ptr(ar), ar.numel(),
-                                  *[_ptr(o) for o in out], C.byref(done), _stream(stream))
+                                  method, precision, float(eps2), float(slack), _ptr(ar),
+                                  ar.numel(), *[_ptr(o) for o in out], C.byref(done),
+                                  C.byref(nb), _stream(stream))
+        builds += nb.value
+        if info is not None:
+            info.update(builds=builds, calls=calls)
         if rc == E_NOMEM:
             left -= done.value
             nbytes = max(int(_lib().hfmm_last_required_bytes() * 1.25), nbytes * 2)

@@ -81,16 +81,26 @@ def test_new_methods_and_time_loop_host_checks(lib):
     for n, steps, dt, ar in ((-1, 1, 1e-3, arena), (10, -1, 1e-3, arena),
                              (10, 1, float("nan"), arena), (10, 1, 1e-3, None)):
         rc = L.hfmm_leapfrog(*([None] * 7), n, dt, steps, 64, 4, 0.5, hfmm.FMM, hfmm.FP32,
-                             0.0, ar, 1 << 30, *([None] * 4), C.byref(done), None)
+                             0.0, 0.0625, ar, 1 << 30, *([None] * 4), C.byref(done), None, None)
         assert rc == hfmm.E_INVAL and done.value == 0
     # n > 0 with null state pointers
     rc = L.hfmm_leapfrog(*([None] * 7), 10, 1e-3, 1, 64, 4, 0.5, hfmm.FMM, hfmm.FP32, 0.0,
-                         arena, 1 << 30, *([None] * 4), C.byref(done), None)
+                         -1.0, arena, 1 << 30, *([None] * 4), C.byref(done), None, None)
     assert rc == hfmm.E_INVAL
+    # NaN slack
+    rc = L.hfmm_leapfrog(*([None] * 7), 10, 1e-3, 1, 64, 4, 0.5, hfmm.FMM, hfmm.FP32, 0.0,
+                         float("nan"), arena, 1 << 30, *([None] * 4), C.byref(done), None, None)
+    assert rc == hfmm.E_INVAL
+    # refit: null handle or output, negative or non-finite slack
+    kept = C.c_int(7)
+    assert L.hfmm_refit(None, None, None, None, 0.1, None, C.byref(kept)) == hfmm.E_INVAL
+    assert kept.value == 0
     # n = 0: nothing to do, every step counted
+    builds = C.c_int(-1)
     rc = L.hfmm_leapfrog(*([None] * 7), 0, 1e-3, 3, 64, 4, 0.5, hfmm.FMM, hfmm.FP32, 0.0,
-                         arena, 1 << 30, *([None] * 4), C.byref(done), None)
-    assert rc == hfmm.OK and done.value == 3
+                         0.0625, arena, 1 << 30, *([None] * 4), C.byref(done), C.byref(builds),
+                         None)
+    assert rc == hfmm.OK and done.value == 3 and builds.value == 0
 
 
 def test_bench_refuses_more_than_one_gpu():

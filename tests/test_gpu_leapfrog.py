@@ -1,8 +1,11 @@
 """GPU time stepping (kick-drift-kick leapfrog around the force evaluation)
 against the oracle leapfrog with the same field: direct sum (FP64), FMM
 (FP64 and FP32), the Barnes-Hut treecode and the treecode over the FMM
-lists; the closed-form circular
-orbit; and a call whose arena is too small leaving the state untouched."""
+lists, with a new tree every step and with the tree kept while the
+particles stay near their leaves (the same trees built as the oracle's);
+the closed-form circular orbit; and calls whose arena is too small, at the
+first evaluation and in the middle of the run, leaving the state of the last
+whole step."""
 import ctypes as C
 
 import numpy as np
@@ -105,8 +108,9 @@ def test_leapfrog_small_arena_keeps_state_then_continues():
     L = H()._lib()
     p = lambda t: C.c_void_p(t.data_ptr())
     rc = L.hfmm_leapfrog(p(x), p(y), p(z), p(vx), p(vy), p(vz), p(m), n, 2e-3, 3, 16, 8, 0.5,
-                         H().FMM, H().FP32, 0.0, p(small), small.numel(), *[p(o) for o in out],
-                         C.byref(done), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+                         H().FMM, H().FP32, 0.0, -1.0, p(small), small.numel(),
+                         *[p(o) for o in out], C.byref(done), None,
+                         C.c_void_p(torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     assert rc == H().E_NOMEM and done.value == 0
     assert L.hfmm_last_required_bytes() > small.numel()
@@ -118,3 +122,127 @@ def test_leapfrog_small_arena_keeps_state_then_continues():
     got2 = _run_gpu(st, 2e-3, 3, p=8, method="fmm", precision="fp32", leaf_max=16)
     for a, b in zip(host(dev[:6]) + f1, got2):
         assert np.array_equal(a, b)
+
+
+def _fast_state(n, seed):
+    x, y, z, _ = W.plummer(n, seed)
+    rng = np.random.default_rng(seed + 1000)
+    vx, vy, vz = (rng.standard_normal(n) for _ in range(3))
+    return x, y, z, vx, vy, vz, W.masses(n, seed + 1, "unequal")
+
+
+@pytest.mark.parametrize("case", ["fmm-fp64", "fmm-fp32", "tl-fp64", "bh-fp64", "bh-fp32",
+                                  "rot-fp64"])
+def test_leapfrog_kept_tree_matches_oracle(case):
+    # the tree is kept while every particle stays within 1/2 + 1/16 leaf
+    # sides of its leaf's centre: the same steps keep it as in the oracle
+    meth, prec = case.split("-")
+    n, dt, steps, leaf, slack = 3000, 4e-3, 6, 16, 1.0 / 16.0
+    p = 4 if meth == "bh" else 10
+    say(f"leapfrog kept tree {meth} {prec} n={n} steps={steps}")
+    st = _fast_state(n, 73)
+    method = {"fmm": "fmm", "tl": "treecode_fmmlist", "bh": "treecode", "rot": "fmm_rot"}[meth]
+    info = {}
+    got = _run_gpu(st, dt, steps, p=p, method=method, precision=prec, leaf_max=leaf,
+                   theta=0.5, slack=slack, info=info)
+    if meth in ("fmm", "rot"):
+        ev = lambda T, m: T.fmm(m, p)
+    elif meth == "bh":
+        ev = lambda T, m: T.treecode(m, p, 0.5, mode=0)
+    else:
+        ev = lambda T, m: T.treecode(m, p, 0.5, mode=2)
+    ref = O.leapfrog_tree(*st, dt, steps, leaf, slack, ev)
+    say(f"  builds: gpu {info['builds']} oracle {ref[-1]}")
+    assert info["builds"] == ref[-1] and 1 < ref[-1] < steps + 1
+    x0, v0 = st[:3], st[3:6]
+    ex = _rel(np.stack(got[:3]) - np.stack(x0), np.stack(ref[:3]) - np.stack(x0))
+    ev_ = _rel(np.stack(got[3:6]) - np.stack(v0), np.stack(ref[3:6]) - np.stack(v0))
+    ea = _rel(np.stack(got[7:10]), np.stack(ref[7:10]))
+    say(f"  vs oracle: dx {ex:.2e} dv {ev_:.2e} a {ea:.2e}")
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert ex <= tol and ev_ <= tol and ea <= tol
+
+
+def test_leapfrog_kept_tree_equals_rebuilt_when_never_kept():
+    # a slack that no step passes builds every step: the same bits as slack < 0
+    st = _fast_state(2000, 74)
+    a_info, b_info = {}, {}
+    a = _run_gpu(st, 0.05, 3, p=8, method="fmm", precision="fp32", leaf_max=16, slack=0.0,
+                 info=a_info)
+    b = _run_gpu(st, 0.05, 3, p=8, method="fmm", precision="fp32", leaf_max=16, slack=-1.0,
+                 info=b_info)
+    assert a_info["builds"] == b_info["builds"] == 4
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def _collapsing_clusters(groups, per, seed, dt):
+    """Groups of `per` particles 0.02 wide whose velocities bring each group
+    to a point after two steps: the tree of the second step is far deeper."""
+    rng = np.random.default_rng(seed)
+    c = rng.random((3, groups)).repeat(per, axis=1)
+    pos = c + 0.02 * rng.uniform(-1.0, 1.0, (3, groups * per))
+    vel = (c - pos) / (2.0 * dt)
+    m = np.full(groups * per, 1.0 / (groups * per))
+    return (*pos, *vel, m)
+
+
+def test_leapfrog_arena_runs_out_in_the_middle_of_the_run():
+    say("leapfrog arena too small at step 2: back to step 1, then continued")
+    dt, leaf, p, eps2 = 1e-3, 16, 6, 1e-6
+    st = _collapsing_clusters(600, 17, 75, dt)
+    n = len(st[0])
+    kw = dict(p=p, method="fmm", precision="fp32", leaf_max=leaf, eps2=eps2, slack=-1.0)
+
+    def need(pos):  # the most arena a tree of these positions takes
+        t = H().Tree(*to_dev(*pos), leaf_max=leaf)
+        try:
+            t.upward(to_dev(st[6])[0], p, "fmm", "fp32")
+            t.evaluate(eps2=eps2)
+            torch.cuda.synchronize()
+        except H().HfmmError as e:
+            assert e.code == H().E_NOMEM
+        return t.required_bytes()
+
+    one = _run_gpu(st, dt, 1, **kw)
+    two = _run_gpu(st, dt, 2, **kw)
+    n0, n1, n2 = need(st[:3]), need(one[:3]), need(two[:3])
+    say(f"  arena need by step: {n0} {n1} {n2}")
+    state = (48 * n + 255) // 256 * 256
+    nbytes = state + (int(1.1 * max(n0, n1)) + (2 << 20)) // 256 * 256
+    assert n2 > 2 * max(n0, n1) and n2 > nbytes - state
+    L = H()._lib()
+    ptr = lambda t: C.c_void_p(t.data_ptr())
+    ar = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    def run_c(steps):  # the C entry point in this arena, from the initial state
+        dev = to_dev(*st)
+        out = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4)]
+        done, builds = C.c_int(-1), C.c_int(-1)
+        rc = L.hfmm_leapfrog(*[ptr(a) for a in dev], n, dt, steps, leaf, p, 0.5, H().FMM,
+                             H().FP32, eps2, -1.0, ptr(ar), ar.numel(), *[ptr(o) for o in out],
+                             C.byref(done), C.byref(builds),
+                             C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        say(f"  {steps} steps: rc {rc} done {done.value} builds {builds.value}")
+        return rc, done.value, builds.value, dev
+
+    # one step fits this arena
+    rc, done, builds, dev1 = run_c(1)
+    assert rc == H().OK and done == 1 and builds == 2
+    # two do not: the tree of step 2 is built, its expansions no longer fit,
+    # and the state goes back to that of step 1 (the same bits: the same
+    # arena gives the same evaluation)
+    rc, done, builds, dev = run_c(2)
+    assert rc == H().E_NOMEM and done == 1 and builds == 3
+    assert L.hfmm_last_required_bytes() > ar.numel()
+    for a, b in zip(host(dev[:6]), host(dev1[:6])):
+        assert np.array_equal(a, b)
+    # the remaining step from there, in the binding's larger arena, follows
+    # the uninterrupted two-step run to the FP32 field's rounding
+    x, y, z, vx, vy, vz, m = dev
+    f = H().leapfrog(x, y, z, vx, vy, vz, m, dt, 1, **kw)
+    got = host(dev[:6]) + host(f)
+    x0, v0 = np.stack(st[:3]), np.stack(st[3:6])
+    assert _rel(np.stack(got[:3]) - x0, np.stack(two[:3]) - x0) <= 1e-6
+    assert _rel(np.stack(got[3:6]) - v0, np.stack(two[3:6]) - v0) <= 1e-5
