@@ -32,6 +32,13 @@ PEAK = {  # MI355X published peaks
     "fp16_TFs": 2500.0,
 }
 P2P_FLOPS = 21  # per pair: the paper's 19 (Sec. 5.1) plus the potential
+# Issue ceiling of the FP32 P2P loop (the AMD assembly of this build): per
+# pair 14 VALU operations (3 sub, 5 fma, 4 mul, 1 max, 1 add), one v_rsq_f32
+# at a quarter of the rate, and a quarter of an instruction of loop
+# overhead: 18.25 issue slots of a 16-lane SIMD, 4 SIMDs per CU, 256 CUs,
+# 2.4 GHz
+P2P_SLOTS = 14 + 4 + 0.25
+P2P_CEILING = 256 * 4 * 16 * 2.4e9 / P2P_SLOTS
 
 
 def p2p_pairs(tree) -> int:
@@ -69,24 +76,108 @@ def treecode_work(tree):
     return int(np.sum(cnt[leaf] * alen[leaf])), int(np.sum(cnt[leaf] * src[leaf]))
 
 
-def cpu_baseline(x, y, z, m, p: int, leaf: int, dist: str, ntarget: int = 2048):
-    """The FP64 oracle FMM, as it stands, on a bounded sample of the same
-    workload: the whole tree and upward pass for all N particles, then the
-    far and near field for `ntarget` seeded target particles.  The rate is
-    target particles per second, setup included."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(x, y, z, m, p: int, leaf: int, dist: str, ntarget: int = 1024,
+                 ntarget_1core: int = 16):
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload, on all host threads and on one: the whole tree and upward pass
+    for all N particles, the downward pass for the cells the sampled target
+    particles need (their leaves and ancestors), and their far and near
+    field; and the direct sum at the same targets.  The whole-problem time
+    is estimated from the measured phases: tree + upward + the downward
+    scaled by (all V pairs / V pairs of the needed cells) + the per-target
+    evaluation times N; `value` = N / that time."""
     from oracle import oracle as O
     from paper_1010_1482_amd import workloads as W
     n = len(x)
+    threads = O.num_threads()
     tg = W.sample_targets(n, ntarget, 7)
     t0 = time.perf_counter()
-    O.fmm(x, y, z, m, p, leaf, targets=tg)
-    dt = time.perf_counter() - t0
-    return {"value": ntarget / dt, "unit": "particles/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"oracle FMM (FP64, Eq. 4 M2L as complex sums) on the same N={n} "
-                      f"{dist} particles, p={p}, leaf<={leaf}: full tree and upward pass, "
-                      f"far and near field for {ntarget} seeded targets; {dt:.1f} s; "
-                      f"value = targets / time"}
+    T = O.Tree(x, y, z, leaf)
+    t_tree = time.perf_counter() - t0
+    # V pairs of the cells the targets need, against all V pairs
+    c = T.cells()
+    voff, _ = T.list(1)
+    vlen = voff[1:] - voff[:-1]
+    inv = np.empty(n, dtype=np.int64)
+    inv[T.perm()] = np.arange(n)
+    leaf_of = np.empty(n, dtype=np.int64)
+    for ci in np.nonzero(c["nchild"] == 0)[0]:
+        leaf_of[c["first"][ci]:c["first"][ci] + c["count"][ci]] = ci
+    need = set()
+    for s_ in inv[tg]:
+        ci = int(leaf_of[s_])
+        while ci >= 0 and ci not in need:
+            need.add(ci)
+            ci = int(c["parent"][ci])
+    v_need = int(vlen[list(need)].sum())
+    v_all = int(vlen.sum())
+
+    def fmm_leg(k):
+        t0 = time.perf_counter()
+        T.fmm(m, p, targets=tg[:k])
+        wall = time.perf_counter() - t0
+        up, down, ev = O.fmm_phase_seconds()
+        return wall, up, down, ev
+
+    def direct_leg(k):
+        t0 = time.perf_counter()
+        O.direct(x, y, z, m, targets=tg[:k])
+        return time.perf_counter() - t0
+
+    wall, up, down, ev = fmm_leg(ntarget)
+    td = direct_leg(ntarget)
+    full = t_tree + up + down * v_all / max(v_need, 1) + ev / ntarget * n
+    # one core: fewer targets (the downward of their cells only)
+    O.set_num_threads(1)
+    try:
+        need1 = set()
+        for s_ in inv[tg[:ntarget_1core]]:
+            ci = int(leaf_of[s_])
+            while ci >= 0 and ci not in need1:
+                need1.add(ci)
+                ci = int(c["parent"][ci])
+        v_need1 = int(vlen[list(need1)].sum())
+        t0 = time.perf_counter()
+        T1 = O.Tree(x, y, z, leaf)
+        t_tree1 = time.perf_counter() - t0
+        del T1
+        wall1, up1, down1, ev1 = fmm_leg(ntarget_1core)
+        td1 = direct_leg(ntarget_1core)
+    finally:
+        O.set_num_threads(threads)
+    full1 = t_tree1 + up1 + down1 * v_all / max(v_need1, 1) + ev1 / ntarget_1core * n
+    return {"value": n / full, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": (f"oracle FMM (FP64, Eq. 4 M2L as complex sums) on the same N={n} "
+                       f"{dist} particles, p={p}, leaf<={leaf}: tree and upward pass for all "
+                       f"N, downward for the cells {ntarget} seeded targets need "
+                       f"({v_need} of {v_all} V pairs), their far and near field; "
+                       f"value = N / (tree + upward + downward x {v_all}/{v_need} + "
+                       f"evaluation per target x N), an estimate from measured phases"),
+            "fmm_all_threads": {"targets": ntarget, "wall_s": wall, "tree_s": t_tree,
+                                "upward_s": up, "downward_s": down, "evaluation_s": ev,
+                                "full_n_estimate_s": full},
+            "fmm_one_core": {"targets": ntarget_1core, "wall_s": wall1, "tree_s": t_tree1,
+                             "upward_s": up1, "downward_s": down1, "evaluation_s": ev1,
+                             "full_n_estimate_s": full1, "particles_per_s": n / full1},
+            "direct_all_threads": {"targets": ntarget, "s": td,
+                                   "pairs_per_s": ntarget * n / td,
+                                   "full_n_estimate_s": td * n / ntarget},
+            "direct_one_core": {"targets": ntarget_1core, "s": td1,
+                                "pairs_per_s": ntarget_1core * n / td1,
+                                "full_n_estimate_s": td1 * n / ntarget_1core}}
 
 
 def serving_bench(n_req: int, slots: int, budget_gb: float, plain: bool):
@@ -164,14 +255,20 @@ def copy_probe(mib: int = 1024) -> int:
     return 0
 
 
-def measure(args, prec_name, x, y, z, m, dev, steps, warmup, accuracy):
-    """Time `steps` whole steps (after `warmup`) of one configuration."""
+def measure(args, prec_name, x, y, z, m, dev, steps, warmup, accuracy, p=None, leaf=None,
+            method=None, theta=None, ref=None, host_copies=True):
+    """Time `steps` whole steps (after `warmup`) of one configuration
+    (p, leaf, method and theta default to the command line's); `ref` is a
+    precomputed (targets, FP64 direct sum there) for the accuracy check."""
     import torch
     from paper_1010_1482_amd import hfmm
     from paper_1010_1482_amd import workloads as W
-    n, p, leaf = len(x), args.p, args.leaf
+    n = len(x)
+    p = args.p if p is None else p
+    leaf = args.leaf if leaf is None else leaf
+    theta = args.theta if theta is None else theta
     prec = hfmm.PRECISIONS[prec_name]
-    meth = hfmm.METHODS[args.method]
+    meth = hfmm.METHODS[args.method if method is None else method]
     xd, yd, zd, md = (torch.from_numpy(a).to(dev) for a in (x, y, z, m))
     dt = hfmm.out_dtype(prec)
     out = tuple(torch.empty(n, dtype=dt, device=dev) for _ in range(4))
@@ -188,7 +285,7 @@ def measure(args, prec_name, x, y, z, m, dev, steps, warmup, accuracy):
             raise
         try:
             t.upward(md, p, meth, prec)
-            t.evaluate(theta=args.theta, out=out)
+            t.evaluate(theta=theta, out=out)
         except hfmm.HfmmError as e:
             if sizing and e.code == hfmm.E_NOMEM:
                 return t.required_bytes()
@@ -218,39 +315,107 @@ def measure(args, prec_name, x, y, z, m, dev, steps, warmup, accuracy):
         phases.append(tr.stats()["phase_ms"])
     t1 = time.perf_counter()
     ms = (t1 - t0) / steps * 1e3
-    # the same step with the inputs copied in from pinned host memory and the
-    # outputs copied back (reported beside `value`, never as it)
-    hx = [torch.from_numpy(a).pin_memory() for a in (x, y, z, m)]
-    ho = [torch.empty(n, dtype=dt, pin_memory=True) for _ in range(4)]
-    nh = max(1, min(steps, 3))
-    torch.cuda.synchronize()
-    h0 = time.perf_counter()
-    for _ in range(nh):
-        for d, h in zip((xd, yd, zd, md), hx):
-            d.copy_(h, non_blocking=True)
-        step()
-        for h, d in zip(ho, out):
-            h.copy_(d, non_blocking=True)
-        torch.cuda.synchronize()
-    hms = (time.perf_counter() - h0) / nh * 1e3
     res = {"ms_per_step": ms, "value": n / (ms * 1e-3),
-           "with_host_copies": {"ms_per_step": hms, "particles_per_s": n / (hms * 1e-3),
-                                "note": "FP64 inputs host->device and outputs device->host "
-                                        "(pinned) inside each step"},
            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                           "p99": float(np.percentile(lat, 99) * 1e3)},
            "phase_ms": {k: float(np.mean([d[k] for d in phases])) for k in phases[-1]},
            "stats": tr.stats(), "tree": tr}
+    if host_copies:
+        # the same step with the inputs copied in from pinned host memory and
+        # the outputs copied back (reported beside `value`, never as it)
+        hx = [torch.from_numpy(a).pin_memory() for a in (x, y, z, m)]
+        ho = [torch.empty(n, dtype=dt, pin_memory=True) for _ in range(4)]
+        nh = max(1, min(steps, 3))
+        torch.cuda.synchronize()
+        h0 = time.perf_counter()
+        for _ in range(nh):
+            for d, h in zip((xd, yd, zd, md), hx):
+                d.copy_(h, non_blocking=True)
+            step()
+            for h, d in zip(ho, out):
+                h.copy_(d, non_blocking=True)
+            torch.cuda.synchronize()
+        hms = (time.perf_counter() - h0) / nh * 1e3
+        res["with_host_copies"] = {"ms_per_step": hms, "particles_per_s": n / (hms * 1e-3),
+                                   "note": "FP64 inputs host->device and outputs "
+                                           "device->host (pinned) inside each step"}
     if accuracy:
         from oracle import oracle as O
-        tg = W.sample_targets(n, args.accuracy_targets, 100 + args.seed)
-        ref = O.direct(x, y, z, m, targets=tg)
+        if ref is None:
+            tg = W.sample_targets(n, args.accuracy_targets, 100 + args.seed)
+            ref = (tg, O.direct(x, y, z, m, targets=tg))
+        tg, ref = ref
         got = [o.double().cpu().numpy()[tg] for o in out]
         res["accuracy"] = {
             "targets": len(tg), "reference": "FP64 oracle direct sum over all N",
             "rel_l2_phi": O.rel_l2(got[0], ref[0]),
             "rel_l2_acc": O.rel_l2(np.stack(got[1:]), np.stack(ref[1:]))}
     return res
+
+
+def p2p_line(pairs, ms, peak):
+    """P2P throughput against the FP32 vector peak (21 flops per pair) and
+    against the issue ceiling of its instruction mix."""
+    if not pairs or not ms:
+        return None
+    rate = pairs / (ms * 1e-3)
+    tf = rate * P2P_FLOPS / 1e12
+    return {"pairs": pairs, "ms": ms, "pairs_per_s": rate, "tflops": tf,
+            "frac_of_vector_peak": tf / peak, "instruction_mix_ceiling_pairs_per_s": P2P_CEILING,
+            "frac_of_instruction_mix_ceiling": rate / P2P_CEILING,
+            "note": "21 flops per pair (the paper's 19 plus the potential); ceiling: 14 VALU "
+                    "+ 1 quarter-rate v_rsq_f32 + 0.25 overhead = 18.25 issue slots per pair"}
+
+
+def clustered_and_4m_forms(args, dev):
+    """The two 4M workloads measured beside the headline one (3 timed steps
+    after one warm-up each, accuracy against the FP64 oracle direct sum at
+    the same number of seeded targets):
+    N = 4,194,304 Plummer (scale radius 1, truncated at 20), equal masses,
+    leaf <= 32: FMM p = 8, Barnes-Hut treecode theta = 0.5 with quadrupole
+    moments (p = 3), both in FP32 and FP64, and the treecode over the FMM
+    lists (p = 3, FP32);
+    N = 4,194,304 uniform, p = 12, leaf <= 64: the FMM with the M2L in FP32
+    and in each low-precision form."""
+    from oracle import oracle as O
+    from paper_1010_1482_amd import workloads as W
+    n = 1 << 22
+    keep = ("build", "lists", "upward", "m2l", "downward", "far", "p2p", "bh")
+    out = {}
+
+    def run(x, y, z, m, ref, prec, **kw):
+        r = measure(args, prec, x, y, z, m, dev, 3, 1, True, ref=ref, host_copies=False,
+                    **kw)
+        return {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                "rel_l2_acc": r["accuracy"]["rel_l2_acc"],
+                "rel_l2_phi": r["accuracy"]["rel_l2_phi"],
+                "phase_ms": {k: v for k, v in r["phase_ms"].items() if k in keep and v}}
+
+    x, y, z, m = W.plummer(n, 3)
+    tg = W.sample_targets(n, args.accuracy_targets, 103)
+    ref = (tg, O.direct(x, y, z, m, targets=tg))
+    res = {}
+    for name, meth, p in (("fmm_p8", "fmm", 8), ("treecode_theta0.5_p3", "treecode", 3)):
+        for prec in ("fp32", "fp64"):
+            res[f"{name}_{prec}"] = run(x, y, z, m, ref, prec, p=p, leaf=32, method=meth,
+                                        theta=0.5)
+    res["treecode_fmmlist_p3_fp32"] = run(x, y, z, m, ref, "fp32", p=3, leaf=32,
+                                          method="treecode_fmmlist")
+    out["plummer_4M_leaf32"] = {
+        "workload": "N=4194304 Plummer sphere (a=1, r<=20), masses 1/N, leaf<=32",
+        "results": res}
+    del x, y, z, m
+    x, y, z, m = W.uniform(n, 4)
+    tg = W.sample_targets(n, args.accuracy_targets, 104)
+    ref = (tg, O.direct(x, y, z, m, targets=tg))
+    res = {}
+    for prec in ("fp32", "bf16x3", "fp16x3", "bf16", "fp16"):
+        res[prec] = run(x, y, z, m, ref, prec, p=12, leaf=64, method="fmm")
+    out["uniform_4M_p12"] = {
+        "workload": "FMM N=4194304 uniform unit cube, masses 1/N, p=12, leaf<=64, M2L "
+                    "forms (P2P FP32, M2M/L2L FP64)",
+        "results": res}
+    return out
 
 
 def leapfrog_rate(args, x, y, z, m, dev):
@@ -318,8 +483,10 @@ def main() -> int:
                     help="requests of the serving trace (0 skips the serving form)")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
-    ap.add_argument("--serve-plain", action="store_true",
-                    help="also serve the trace one request at a time")
+    ap.add_argument("--no-serve-plain", action="store_true",
+                    help="skip serving the trace one request at a time")
+    ap.add_argument("--no-4m", action="store_true",
+                    help="skip the 4M Plummer and 4M p=12 workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -401,6 +568,7 @@ def main() -> int:
                  "list_p2p": stats["list_p2p"], "p2p_pairs": pairs,
                  "m2p_evaluations": m2p_evals},
         "p2p_interactions_per_s": pairs / (ph.get("p2p", 1.0) * 1e-3) if pairs else None,
+        "p2p": p2p_line(pairs, ph.get("p2p"), alu_peak),
         "m2l_pairs_per_s": m2l_pairs / (ph.get("m2l", 1.0) * 1e-3) if m2l_pairs else None,
         "m2p_evaluations_per_s": (m2p_evals / (ph.get("far", 1.0) * 1e-3)
                                   if m2p_evals else None),
@@ -423,7 +591,9 @@ def main() -> int:
                 "rel_l2_phi": rf.get("accuracy", {}).get("rel_l2_phi")}
     if args.serve_requests > 0:
         res["serving"] = serving_bench(args.serve_requests, args.serve_slots,
-                                       args.serve_budget_gb, args.serve_plain)
+                                       args.serve_budget_gb, not args.no_serve_plain)
+    if not args.no_4m:
+        res["workloads_4M"] = clustered_and_4m_forms(args, dev)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(x, y, z, m, p, leaf, args.dist)
     print(json.dumps(res), flush=True)

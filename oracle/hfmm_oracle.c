@@ -29,6 +29,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -44,6 +45,29 @@ int oracle_num_threads(void) {
 #else
     return 1;
 #endif
+}
+
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* wall-clock seconds of the phases of the last oracle_fmm_tree call:
+ * upward, downward, evaluation at the targets (timing only; no result
+ * depends on it) */
+static double g_phase_s[3];
+
+static double wall_s(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+void oracle_fmm_phase_seconds(double out[3]) {
+    for (int i = 0; i < 3; i++) out[i] = g_phase_s[i];
 }
 
 /* ------------------------------------------------------------------ */
@@ -1113,8 +1137,13 @@ int oracle_fmm_tree(otree* t, const double* m, int p, double eps2, int64_t nt,
     }
     cplx* M = (cplx*)malloc(sizeof(cplx) * nc * pp);
     cplx* L = (cplx*)malloc(sizeof(cplx) * nc * pp);
+    double t0 = wall_s();
     upward(t, ms, p, cen, M);
+    double t1 = wall_s();
     downward(t, ms, p, cen, M, L, need);
+    double t2 = wall_s();
+    g_phase_s[0] = t1 - t0;
+    g_phase_s[1] = t2 - t1;
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < nt; k++) {
         int64_t s = inv[tidx ? tidx[k] : k];
@@ -1138,6 +1167,7 @@ int oracle_fmm_tree(otree* t, const double* m, int p, double eps2, int64_t nt,
         ay[k] = acc[2];
         az[k] = acc[3];
     }
+    g_phase_s[2] = wall_s() - t2;
     free(need);
     free(M);
     free(L);

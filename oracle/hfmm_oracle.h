@@ -191,8 +191,13 @@ void oracle_m2l_rot(int p, const double c_src[3], const double c_tgt[3],
  * rotation, f given by `in` (complex, index n*n + n + m). */
 void oracle_rotate(int p, const double Q[9], const double* in, double* out);
 
-/* Threads OpenMP will use (1 when built without OpenMP). */
+/* Threads OpenMP will use (1 when built without OpenMP); set them (n > 0). */
 int oracle_num_threads(void);
+void oracle_set_num_threads(int n);
+/* Wall-clock seconds of the last oracle_fmm_tree (or oracle_fmm) call:
+ * out[0] upward, out[1] downward (the cells the targets need), out[2] the
+ * evaluation at the targets. */
+void oracle_fmm_phase_seconds(double out[3]);
 
 #ifdef __cplusplus
 }

@@ -78,6 +78,17 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(C.c_int(n))
+
+
+def fmm_phase_seconds():
+    """(upward, downward, evaluation) wall seconds of the last oracle FMM."""
+    out = np.zeros(3)
+    lib().oracle_fmm_phase_seconds(_d(out))
+    return tuple(float(v) for v in out)
+
+
 def num_threads() -> int:
     return lib().oracle_num_threads()
 

@@ -11,7 +11,11 @@ budget, and the next waiting request is admitted immediately.
 
 Per request the server records the scheduled arrival, admission, start and
 finish times; latency = finish - scheduled arrival.  Each request's tree and
-expansions live in its own arena until the request completes.
+expansions live in its own arena until the request completes.  When the
+arena estimate falls short (clustered data), the executor asks the server
+for the extra bytes (Request.grow) before it allocates them: the budget
+counts what the device actually holds, a growth waits while other requests
+run and fails the request when it can never fit.
 """
 from __future__ import annotations
 
@@ -44,6 +48,7 @@ class Request:
     t_finish: float = float("nan")
     footprint: int = 0
     output: Optional[tuple] = None
+    grow: Optional[Callable[[int], None]] = None  # set by the server at admission
 
     @property
     def latency(self) -> float:
@@ -72,6 +77,33 @@ class Server:
         self.stop = False
         self.t0 = 0.0
         self.done = []
+        self.running = 0   # admitted and not finished
+        self.growing = 0   # of those, waiting for budget to grow their arena
+        self.max_in_use = 0
+
+    def grow(self, req: Request, extra: int) -> None:
+        """Charge `extra` more bytes to a running request (called from its
+        worker before it allocates them).  Waits while other running
+        requests may still free budget; raises MemoryError when the request
+        alone would exceed the budget or nothing else can free any.  New
+        admissions wait while a growth is pending."""
+        extra = int(extra)
+        if extra <= 0:
+            return
+        with self.cv:
+            self.growing += 1
+            try:
+                while self.in_use + extra > self.budget:
+                    if req.footprint + extra > self.budget or self.running - self.growing <= 0:
+                        raise MemoryError(f"arena growth by {extra} bytes does not fit the "
+                                          f"HBM budget {self.budget}")
+                    self.cv.wait(timeout=0.05)
+                self.in_use += extra
+                self.max_in_use = max(self.max_in_use, self.in_use)
+                req.footprint += extra
+            finally:
+                self.growing -= 1
+                self.cv.notify_all()
 
     def _now(self) -> float:
         return time.perf_counter() - self.t0
@@ -96,6 +128,7 @@ class Server:
             req.t_finish = self._now()
             with self.cv:
                 self.in_use -= req.footprint
+                self.running -= 1
                 self.free_slots.append(slot)
                 self.done.append(req)
                 self.cv.notify_all()
@@ -127,11 +160,14 @@ class Server:
                         continue
                     pending.append(r)
                 # admission in arrival order: a slot and the budget must be free
-                while pending and self.free_slots and \
+                while pending and self.free_slots and not self.growing and \
                         self.in_use + pending[0].footprint <= self.budget:
                     r = pending.popleft()
                     slot = self.free_slots.popleft()
                     self.in_use += r.footprint
+                    self.max_in_use = max(self.max_in_use, self.in_use)
+                    self.running += 1
+                    r.grow = (lambda extra, r=r: self.grow(r, extra))
                     r.t_admit = self._now()
                     with self.job_cv[slot]:
                         self.jobs[slot].append(r)
@@ -198,11 +234,30 @@ class HipExecutor:
         s = self.streams[slot]
         host_in = [torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
                    for a in (x, y, z, m)]
+        prec = hfmm.PRECISIONS[req.precision]
+        meth = hfmm.METHODS[req.method]
+        nbytes = hfmm.arena_bytes(req.n, 0, req.leaf_max, req.p, meth, prec)
         with torch.cuda.stream(s):
             dev = [h.to(self.device, non_blocking=True) for h in host_in]
-            prec = hfmm.PRECISIONS[req.precision]
-            out = hfmm.solve(*dev, p=req.p, method=req.method, precision=prec,
-                             leaf_max=req.leaf_max, theta=req.theta, stream=s)
+            for _ in range(4):
+                # the arena the footprint charged; a larger one only once the
+                # server has charged the difference
+                arena = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+                try:
+                    out = hfmm.solve(*dev, p=req.p, method=meth, precision=prec,
+                                     leaf_max=req.leaf_max, theta=req.theta, arena=arena,
+                                     stream=s)
+                    break
+                except hfmm.HfmmError as e:
+                    if e.code != hfmm.E_NOMEM:
+                        raise
+                    need = int(hfmm._lib().hfmm_last_required_bytes() * 1.25)
+                    del arena
+                    if req.grow is not None:
+                        req.grow(need - nbytes)
+                    nbytes = need
+            else:
+                raise MemoryError("arena did not suffice after growing")
             host_out = [torch.empty(o.shape, dtype=o.dtype, pin_memory=True) for o in out]
             for h, o in zip(host_out, out):
                 h.copy_(o, non_blocking=True)

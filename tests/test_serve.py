@@ -98,3 +98,57 @@ def test_latency_includes_queueing():
     assert lat[-1] > 4 * 0.02 * 0.9        # the last one waited for four others
     s = summarize(reqs)
     assert s["latency_ms"]["p99"] >= s["latency_ms"]["p50"] > 0
+
+
+class GrowingExecutor(FakeExecutor):
+    """Asks the server for `extra[rid]` more bytes before it runs."""
+
+    def __init__(self, server_ref, extra):
+        super().__init__(server_ref)
+        self.extra = extra
+
+    def __call__(self, req, slot):
+        if self.extra.get(req.rid):
+            req.grow(self.extra[req.rid])
+        with self.lock:
+            self.max_in_use = max(self.max_in_use, self.server_ref[0].in_use)
+        return super().__call__(req, slot)
+
+
+def test_arena_growth_is_charged_to_the_budget():
+    ref = [None]
+    ex = GrowingExecutor(ref, {i: 500 for i in range(0, 20, 2)})
+    srv = Server(budget_bytes=3000, slots=4, executor=ex, footprint=lambda r: r.n)
+    ref[0] = srv
+    reqs = make(20, [1000] * 20, np.zeros(20))
+    srv.run(reqs, realtime=False)
+    assert all(r.status == "ok" for r in reqs)
+    assert srv.max_in_use <= 3000 and ex.max_in_use <= 3000
+    assert all(r.footprint == (1500 if r.rid % 2 == 0 else 1000) for r in reqs)
+    assert srv.in_use == 0 and srv.running == 0
+
+
+def test_growth_waits_for_other_requests_then_runs():
+    # two requests fill the budget; one needs 1000 more, which only the
+    # other's completion frees
+    ref = [None]
+    ex = GrowingExecutor(ref, {0: 1000})
+    srv = Server(budget_bytes=2500, slots=2, executor=ex, footprint=lambda r: r.n)
+    ref[0] = srv
+    reqs = make(2, [1000, 1200], np.zeros(2))
+    srv.run(reqs, realtime=False)
+    assert [r.status for r in reqs] == ["ok", "ok"]
+    assert srv.max_in_use <= 2500
+    assert reqs[0].t_finish >= reqs[1].t_finish
+
+
+def test_growth_that_can_never_fit_fails_only_that_request():
+    ref = [None]
+    ex = GrowingExecutor(ref, {1: 5000})
+    srv = Server(budget_bytes=3000, slots=2, executor=ex, footprint=lambda r: r.n)
+    ref[0] = srv
+    reqs = make(4, [1000] * 4, np.zeros(4))
+    srv.run(reqs, realtime=False)
+    assert [r.status for r in reqs] == ["ok", "failed", "ok", "ok"]
+    assert "budget" in reqs[1].error
+    assert srv.in_use == 0 and srv.max_in_use <= 3000
