@@ -231,6 +231,7 @@ struct Tree {
     int32_t* m2l_order = nullptr;    // targets (level >= 2) by (level, octant)
     int32_t* m2l_torder = nullptr;   // the same targets by (octant, level)
     int32_t* m2l_tiles = nullptr;    // per tile: start into m2l_torder, count, octant
+    std::vector<int32_t> m2l_tiles_h;  // host copy (the source of the upload)
     int32_t n_m2l_tiles = 0;
     size_t mark_lists = 0;
     // treecode lists (bh_theta = kFmmListTheta: built from the FMM lists)

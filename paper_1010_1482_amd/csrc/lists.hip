@@ -578,7 +578,8 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     // are listed as (k, octant) for the k-th tile of each octant: the eight
     // tiles of one k cover about the same stretch of Morton order and read
     // nearly the same source expansions.
-    std::vector<int32_t> tiles;
+    std::vector<int32_t>& tiles = t.m2l_tiles_h;
+    tiles.clear();
     int ocount[8] = {0}, ostart[9] = {0};
     for (int o = 0; o < 8; ++o)
         for (int l = 0; l <= HFMM_KEY_LEVELS + 1; ++l) ocount[o] += gc[l * 8 + o];
@@ -594,11 +595,9 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
         }
     t.n_m2l_tiles = (int32_t)(tiles.size() / 4);
     t.m2l_tiles = A.up<int32_t>(std::max<size_t>(tiles.size(), 4));
-    if (!tiles.empty()) {
+    if (!tiles.empty())  // (the host copy lives as long as the tree)
         HIP_TRY(hipMemcpyAsync(t.m2l_tiles, tiles.data(), sizeof(int32_t) * tiles.size(),
                                hipMemcpyHostToDevice, s));
-        HIP_TRY(hipStreamSynchronize(s));  // tiles lives on the host stack
-    }
     A.release_temps();
     t.fmm_lists = true;
     t.mark_lists = A.lo;

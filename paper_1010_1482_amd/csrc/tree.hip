@@ -2,8 +2,11 @@
 // stable LSD radix sort, and level-by-level cell splitting.
 //
 // The paper sorts particles and builds the tree and lists on the host
-// (Sec. 4, "sort" and "other" in Fig. 6); here every step is a
-// kernel, so the only host work is reading back the cell count per level.
+// (Sec. 4, "sort" and "other" in Fig. 6); here every step is a kernel.  A
+// census of the sorted keys gives the number of splitting cells of every
+// level before the levels are built, so the level loop runs without host
+// round trips: the host reads back twice (the census, then the level
+// starts).
 // Non-finite source coordinates are recorded in the tree's status word.
 #include "common.hpp"
 
@@ -444,14 +447,16 @@ __global__ void k_gather_positions(const double* __restrict__ x, const double* _
 // together: each round every lane samples one key per boundary inside the
 // current bracket, and the ballot of "digit < o" (a prefix, the keys being
 // sorted) shrinks the bracket 65-fold; a bracket of <= 64 keys is resolved
-// exactly.  bnd[8 c + o - 1] = boundary o, nz[c] = number of nonempty
-// children; info[0] |= 1 when the sort did not order the next digit,
-// info[1] counts the splitting cells.
+// exactly.  The level's cells are [lev[level], lev[level + 1]) (device
+// counts, so no host round trip per level; the grid covers a bound).
+// bnd[8 c + o - 1] = boundary o, nz[c] = number of nonempty children;
+// info[0] |= 1 when the sort did not order the next digit.
 __global__ void __launch_bounds__(1024)
-k_split_find(const Cell* __restrict__ cells, int c0, int c1, int leaf_max, int sorted_levels,
-             const uint64_t* __restrict__ keys, int32_t* __restrict__ nz,
-             int32_t* __restrict__ bnd, int32_t* __restrict__ info) {
+k_split_find(const Cell* __restrict__ cells, const int32_t* __restrict__ lev, int level,
+             int leaf_max, int sorted_levels, const uint64_t* __restrict__ keys,
+             int32_t* __restrict__ nz, int32_t* __restrict__ bnd, int32_t* __restrict__ info) {
     const int lane = threadIdx.x & 63;
+    const int c0 = lev[level], c1 = lev[level + 1];
     const int c = c0 + (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     int nk = 0;
     Cell cell;
@@ -510,18 +515,23 @@ k_split_find(const Cell* __restrict__ cells, int c0, int c1, int leaf_max, int s
         }
     }
     if (c < c1 && lane == 0) nz[c - c0] = nk;
-    // one atomic per block for the count of splitting cells
-    const int k = __syncthreads_count(c < c1 && lane == 0 && nk > 0);
-    if (threadIdx.x == 0 && k) atomicAdd(&info[1], k);
 }
 
-__global__ void k_split_emit(Cell* __restrict__ cells, int c0, int c1, int next0,
-                             const int32_t* __restrict__ bnd,
-                             const int32_t* __restrict__ pos) {
+// (cells beyond `cap`, the room reserved from the census, are not written:
+// flag = 1 instead)
+__global__ void k_split_emit(Cell* __restrict__ cells, const int32_t* __restrict__ lev,
+                             int level, const int32_t* __restrict__ bnd,
+                             const int32_t* __restrict__ pos, int64_t cap,
+                             int32_t* __restrict__ flag) {
+    const int c0 = lev[level], c1 = lev[level + 1], next0 = c1;
     int c = c0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= c1) return;
     int k = pos[c - c0];
     int nk = pos[c - c0 + 1] - k;
+    if ((int64_t)next0 + k + nk > cap) {
+        *flag = 1;
+        return;
+    }
     if (nk == 0) {
         cells[c].child = -1;
         cells[c].nchild = 0;
@@ -563,43 +573,148 @@ __global__ void k_leaf_flags(const Cell* __restrict__ cells, int nc, int32_t* __
 
 // leaves in cell order; per sorted particle its leaf cell and leaf index;
 // per leaf its box of the self-evaluation (the leaf's own particles)
+// (one wave per cell: the lanes fill the leaf's particle range)
 __global__ void k_leaf_compact(const Cell* __restrict__ cells, int nc,
                                const int32_t* __restrict__ pos, int32_t* __restrict__ leaves,
                                int32_t* __restrict__ leaf_of, TBox* __restrict__ boxes,
                                int32_t* __restrict__ box_of) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
     if (c >= nc) return;
-    Cell cell = cells[c];
+    const Cell cell = cells[c];
     if (cell.nchild != 0) return;
     const int li = pos[c];
-    leaves[li] = c;
-    TBox b;
-    b.first = cell.first;
-    b.count = cell.count;
-    b.host = b.leaf = c;
-    b.ix = cell.ix;
-    b.iy = cell.iy;
-    b.iz = cell.iz;
-    b.level = cell.level;
-    b.kind = 0;
-    boxes[li] = b;
-    for (int s = cell.first; s < cell.first + cell.count; ++s) {
+    if (lane == 0) {
+        leaves[li] = c;
+        TBox b;
+        b.first = cell.first;
+        b.count = cell.count;
+        b.host = b.leaf = c;
+        b.ix = cell.ix;
+        b.iy = cell.iy;
+        b.iz = cell.iz;
+        b.level = cell.level;
+        b.kind = 0;
+        boxes[li] = b;
+    }
+    for (int s = cell.first + lane; s < cell.first + cell.count; s += 64) {
         leaf_of[s] = c;
         box_of[s] = li;
     }
 }
 
-// After a sort of the top `sorted_levels` levels: a run of more than
-// leaf_max keys with one prefix at that level is a cell that must split
-// below the sorted bits (its ancestors all split), so the tree needs a
-// deeper sort.  Flags it in info[1] before the level loop starts, instead
-// of at the level where the split finds it (any thread may store the 1).
-__global__ void k_sort_check(const uint64_t* __restrict__ keys, int64_t n, int leaf_max,
-                             int sorted_levels, int32_t* __restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i + leaf_max >= n) return;
-    const int sh = 3 * (HFMM_KEY_LEVELS - sorted_levels);
-    if ((keys[i] >> sh) == (keys[i + leaf_max] >> sh)) *flag = 1;
+// Exclusive scan of the children counts of one level's cells, one block
+// of 1024 threads looping over the level: pos[0..m] (pos[m] = total), the
+// next level's end lev[level + 2] = lev[level + 1] + total, and the level's
+// splitting cells in nsplit[level].  m is at most `cap`, the room the
+// census gave the level.
+__global__ void __launch_bounds__(1024)
+k_level_scan(const int32_t* __restrict__ nz, int32_t* __restrict__ lev, int level,
+             int32_t* __restrict__ pos, int32_t* __restrict__ nsplit, int cap,
+             int32_t* __restrict__ flag) {
+    __shared__ int wsum[16];
+    __shared__ int carry_s, split_s;
+    int m = lev[level + 1] - lev[level];
+    if (m > cap) {  // more cells than the census allows: flagged, clamped
+        if (threadIdx.x == 0) *flag = 1;
+        m = cap;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        carry_s = 0;
+        split_s = 0;
+    }
+    __syncthreads();
+    for (int b0 = 0; b0 < m; b0 += 1024) {
+        const int i = b0 + (int)threadIdx.x;
+        const int v = i < m ? nz[i] : 0;
+        int inc = wave_inclusive_scan(v);
+        const uint64_t sp = __ballot(v > 0);
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        int off = carry_s, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < w) off += wsum[k];
+            tot += wsum[k];
+        }
+        if (i < m) pos[i] = off + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s += tot;
+        if (lane == 0 && sp) atomicAdd(&split_s, __popcll(sp));
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pos[m] = carry_s;
+        lev[level + 2] = lev[level + 1] + carry_s;
+        nsplit[level] = split_s;
+    }
+}
+
+// Census of the splits the tree will make, from the sorted keys alone.  A
+// cell of level l splits iff it holds more than leaf_max keys and l < 21,
+// i.e. iff some window of leaf_max + 1 consecutive keys shares its l-digit
+// prefix.  With w_i the digits keys i and i + leaf_max share (capped at the
+// sorted digits) and d_i those keys i - 1 and i share, the window starting
+// at i is the first of its level-l run exactly when l <= w_i and
+// l > min(w_{i-1}, d_i) (the window at i - 1 would share the prefix
+// otherwise), so each i adds 1 to the split count of the levels
+// (min(w_{i-1}, d_i), min(w_i, 20)].  Per block (grid-stride over the
+// keys) a histogram over levels; part[block * 32 + l].  A window sharing every sorted digit (fewer than 21)
+// means the tree needs a deeper sort: part[block * 32 + 31] = 1.
+__device__ inline int shared_digits(uint64_t a, uint64_t b, int cap) {
+    const uint64_t x = a ^ b;  // 63-bit keys: bit 63 is zero in both
+    const int d = x == 0 ? HFMM_KEY_LEVELS : (__clzll((long long)x) - 1) / 3;
+    return d < cap ? d : cap;
+}
+
+__global__ void __launch_bounds__(256)
+k_split_census(const uint64_t* __restrict__ keys, int64_t n, int leaf_max, int sorted_levels,
+               int32_t* __restrict__ part) {
+    __shared__ int hist[32];
+    if (threadIdx.x < 32) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i + leaf_max < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t ki = keys[i];
+        const int wi = shared_digits(ki, keys[i + leaf_max], sorted_levels);
+        int lo = -1;  // levels above lo are new runs of windows
+        if (i > 0) {
+            const uint64_t kp = keys[i - 1];
+            const int wp = shared_digits(kp, keys[i - 1 + leaf_max], sorted_levels);
+            lo = min(wp, shared_digits(kp, ki, sorted_levels));
+        }
+        const int hi = min(wi, HFMM_KEY_LEVELS - 1);
+        for (int l = lo + 1; l <= hi; ++l) atomicAdd(&hist[l], 1);
+        if (wi >= sorted_levels && sorted_levels < HFMM_KEY_LEVELS) hist[31] = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) part[(int64_t)blockIdx.x * 32 + threadIdx.x] = hist[threadIdx.x];
+}
+
+// sum of the per-block census rows (the resort flag as a maximum); also
+// sets the first level range (the root: lev[0] = 0, lev[1] = 1) and clears
+// the level loop's flag
+__global__ void k_census_reduce(const int32_t* __restrict__ part, int nblocks,
+                                int32_t* __restrict__ census, int32_t* __restrict__ lev,
+                                int32_t* __restrict__ flag) {
+    if (threadIdx.x == 0) {
+        lev[0] = 0;
+        lev[1] = 1;
+        *flag = 0;
+    }
+    const int l = threadIdx.x & 31, g = threadIdx.x >> 5;  // 8 groups of 32
+    int acc = 0;
+    for (int b = g; b < nblocks; b += 8) {
+        const int v = part[(int64_t)b * 32 + l];
+        acc = l == 31 ? max(acc, v) : acc + v;
+    }
+    __shared__ int red[8][32];
+    red[g][l] = acc;
+    __syncthreads();
+    if (g == 0) {
+        for (int k = 1; k < 8; ++k) acc = l == 31 ? max(acc, red[k][l]) : acc + red[k][l];
+        census[l] = acc;
+    }
 }
 
 // A kept tree takes new positions: sorted slot s gets the position of its
@@ -696,88 +811,105 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     // keys, sort (top bits first; a full sort if the tree turns out deeper)
     uint64_t* k0 = A.down<uint64_t>(n);
     int32_t* i0 = A.down<int32_t>(n);
-    // per level and attempt: [children added, re-sort needed, cells split]
-    int32_t* info = A.down<int32_t>(3 * 2 * (HFMM_KEY_LEVELS + 1));
-    HIP_TRY(hipMemsetAsync(info, 0, sizeof(int32_t) * 3 * 2 * (HFMM_KEY_LEVELS + 1), s));
+    // census: split cells per level (0..20) and the re-sort flag (31)
+    int32_t* census = A.down<int32_t>(32);
+    // per level: start of the level's cells (lev[l]) and its splitting cells
+    // (nsplit[l]), and the level loop's flag: one array, one read back
+    constexpr int kLev = HFMM_KEY_LEVELS + 3, kRec = 2 * kLev + 1;
+    int32_t* levrec = A.down<int32_t>(kRec);
+    int32_t* lev = levrec;
+    int32_t* nsplit = levrec + kLev;
+    int32_t* flag = levrec + 2 * kLev;
     int sorted_levels = sort_levels_guess(n, t.leaf_max);
     const size_t hi_mark = A.hi;
-    int nsplit_total = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    int32_t cen_h[32];
+    const int ncb = std::min(512, grid_for(n, 256));  // census blocks
+    for (int attempt = 0;; ++attempt) {
+        if (attempt > 1) throw Status{HFMM_E_STATE};
         hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n, t.root,
                            k0, i0);
         LAUNCH_CHECK();
         const int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
         radix_sort_pairs(k0, i0, t.keys, t.perm, n, lo_bit, 63, A, s);
-        if (sorted_levels < HFMM_KEY_LEVELS) {
-            // read back with the level-0 counts: a deeper tree than sorted
-            // restarts there
-            int32_t* in0 = info + 3 * (attempt * (HFMM_KEY_LEVELS + 1));
-            hipLaunchKernelGGL(k_sort_check, dim3(grid_for(n, 256)), dim3(256), 0, s, t.keys,
-                               n, t.leaf_max, sorted_levels, in0 + 1);
-            LAUNCH_CHECK();
-        }
+        int32_t* part = A.down<int32_t>((size_t)ncb * 32);
+        hipLaunchKernelGGL(k_split_census, dim3(ncb), dim3(256), 0, s, t.keys, n, t.leaf_max,
+                           sorted_levels, part);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_census_reduce, dim3(1), dim3(256), 0, s, part, ncb, census, lev,
+                           flag);
+        LAUNCH_CHECK();
+        // the one read back before the levels (with the root)
+        HIP_TRY(hipMemcpyAsync(cen_h, census, sizeof(cen_h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
         A.hi = hi_mark;
+        if (t.root_h.nbad) throw Status{HFMM_E_DATA};  // also in the status word
         t.sort_bits = 63 - lo_bit;
-        room(1);
-        t.level_start.assign(1, 0);
-        t.level_start.push_back(1);
-        int c0 = 0, c1 = 1, level = 0;
-        bool resort = false;
-        nsplit_total = 0;
-        while (true) {
-            const int nl = c1 - c0;
-            int32_t* in = info + 3 * (attempt * (HFMM_KEY_LEVELS + 1) + level);
-            int32_t* nz = A.down<int32_t>(nl + 1);
-            int32_t* pos = A.down<int32_t>(nl + 1);
-            int32_t* bnd = A.down<int32_t>((size_t)nl * 8);
-            hipLaunchKernelGGL(k_split_find, dim3(grid_for((int64_t)nl * 64, 1024)), dim3(1024),
-                               0, s, t.cells, c0, c1, t.leaf_max, sorted_levels, t.keys, nz,
-                               bnd, in + 1);
-            LAUNCH_CHECK();
-            scan_exclusive_i32(nz, pos, nl, A, s, in);
-            int32_t h[3] = {0, 0, 0};
-            HIP_TRY(hipMemcpyAsync(h, in, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (t.root_h.nbad) throw Status{HFMM_E_DATA};  // also in the status word
-            if (h[1]) {
-                resort = true;
-                A.hi = hi_mark;
-                break;
-            }
-            const int added = h[0];
-            nsplit_total += h[2];
-            if (added > 0) room((int64_t)c1 + added);
-            hipLaunchKernelGGL(k_split_emit, dim3(grid_for(nl, 256)), dim3(256), 0, s,
-                               t.cells, c0, c1, c1, bnd, pos);
-            LAUNCH_CHECK();
-            A.hi = hi_mark;
-            if (added == 0) break;
-            c0 = c1;
-            c1 += added;
-            ++level;
-            t.level_start.push_back(c1);
-        }
-        if (resort) {
+        if (cen_h[31]) {  // a cell splits below the sorted digits
             if (sorted_levels >= HFMM_KEY_LEVELS) throw Status{HFMM_E_STATE};
             sorted_levels = HFMM_KEY_LEVELS;
             continue;
         }
-        t.ncells = c1;
-        t.depth = level;
         break;
     }
+    // levels 0 .. depth - 1 split; a level's cells number at most 8 times
+    // the splits of the level above, so every launch is sized on the host
+    // while the exact ranges stay on the device
+    int depth = 0;
+    int64_t splits = 0, bound_max = 1, bound_total = 1;
+    for (int l = 0; l < HFMM_KEY_LEVELS; ++l)
+        if (cen_h[l] > 0) {
+            depth = l + 1;
+            splits += cen_h[l];
+            bound_max = std::max<int64_t>(bound_max, 8 * (int64_t)cen_h[l]);
+            bound_total += 8 * (int64_t)cen_h[l];
+        }
+    room(bound_total);
+    int32_t* nz = A.down<int32_t>(bound_max + 1);
+    int32_t* pos = A.down<int32_t>(bound_max + 1);
+    int32_t* bnd = A.down<int32_t>((size_t)bound_max * 8);
+    for (int l = 0; l < depth; ++l) {
+        const int64_t cells_l = l == 0 ? 1 : 8 * (int64_t)cen_h[l - 1];
+        hipLaunchKernelGGL(k_split_find, dim3(grid_for(cells_l * 64, 1024)), dim3(1024), 0, s,
+                           t.cells, lev, l, t.leaf_max, sorted_levels, t.keys, nz, bnd, flag);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, nz, lev, l, pos, nsplit,
+                           (int)cells_l, flag);
+        LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_split_emit, dim3(grid_for(cells_l, 256)), dim3(256), 0, s, t.cells,
+                           lev, l, bnd, pos, bound_total, flag);
+        LAUNCH_CHECK();
+    }
+    // the one read back after the levels: their starts and split counts
+    int32_t rec_h[kRec] = {0, 1};
+    if (depth > 0) {
+        HIP_TRY(hipMemcpyAsync(rec_h, levrec, sizeof(rec_h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    const int32_t* lev_h = rec_h;
+    const int32_t* nsplit_h = rec_h + kLev;
+    const int32_t flag_h = rec_h[2 * kLev];
+    // the splits the levels made are the census's, level by level
+    for (int l = 0; l < depth; ++l)
+        if (nsplit_h[l] != cen_h[l]) throw Status{HFMM_E_STATE};
+    if (flag_h) throw Status{HFMM_E_STATE};
+    t.level_start.assign(lev_h, lev_h + depth + 2);
+    t.ncells = lev_h[depth + 1];
+    t.depth = depth;
+    if (t.ncells > bound_total) throw Status{HFMM_E_STATE};
+    room(t.ncells);
+    const int64_t nsplit_total = splits;
     // leaves (cells that did not split), in cell order
     t.nleaves = t.ncells - nsplit_total;
     int32_t* f = A.down<int32_t>(t.ncells + 1);
-    int32_t* pos = A.down<int32_t>(t.ncells + 1);
+    int32_t* lpos = A.down<int32_t>(t.ncells + 1);
     hipLaunchKernelGGL(k_leaf_flags, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s, t.cells,
                        t.ncells, f);
     LAUNCH_CHECK();
-    scan_exclusive_i32(f, pos, t.ncells, A, s);
+    scan_exclusive_i32(f, lpos, t.ncells, A, s);
     t.leaves = A.up<int32_t>(t.nleaves);
     t.leaf_boxes = A.up<TBox>(t.nleaves);
-    hipLaunchKernelGGL(k_leaf_compact, dim3(grid_for(t.ncells, 256)), dim3(256), 0, s,
-                       t.cells, t.ncells, pos, t.leaves, t.leaf_of, t.leaf_boxes,
+    hipLaunchKernelGGL(k_leaf_compact, dim3(grid_for((int64_t)t.ncells * 64, 256)), dim3(256), 0, s,
+                       t.cells, t.ncells, lpos, t.leaves, t.leaf_of, t.leaf_boxes,
                        t.leaf_box_of);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_gather_positions, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n,
