@@ -10,6 +10,7 @@
 #include "expansions.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <new>
@@ -368,7 +369,7 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
     const int P = p * p;
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
-    size_t per_particle = 8 + 4 + 24 + 16 + 32 + 4 + 8 + 4 + 8 + 4 * 8 + 64;
+    size_t per_particle = 8 + 4 + 24 + 16 + 32 + 4 + 8 + 4 + 8 + 4 * 8 + 64 + 32;
     // M, L, LX (FP64), the M2L operand and the FP32 copy of M for the
     // far field (FP32), up to twelve M2L partial results
     size_t per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 * 3 +
@@ -396,6 +397,17 @@ static thread_local size_t g_last_required = 0;
 static bool g_timing = false;
 
 void set_last_required(size_t bytes) { g_last_required = bytes; }
+
+void stream_wait(hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) throw HipError{e};
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(500)) break;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+}
 
 }  // namespace hfmm
 

@@ -47,6 +47,12 @@ struct HipError {
 
 #define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
 
+// Wait for the work enqueued on s before a small read back is used.  A
+// blocking wait wakes the host tens of microseconds after the copy lands;
+// polling the stream for a short while returns within a few, and only
+// longer work falls back to the blocking wait.
+void stream_wait(hipStream_t s);
+
 struct Status {
     int code;
 };

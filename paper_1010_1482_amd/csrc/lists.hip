@@ -450,7 +450,7 @@ void build_box_lists(Tree& t, const Targets& tg, int mode, hipStream_t s) {
     int32_t h[2];
     HIP_TRY(hipMemcpyAsync(&h[0], t.tn_off + nb, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&h[1], t.tf_off + nb, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    stream_wait(s);
     t.tg_near = h[0];
     t.tg_far = h[1];
     t.tn_items = A.up<int32_t>(std::max<int64_t>(t.tg_near, 1));
@@ -547,7 +547,7 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     }
     std::vector<int32_t> h(5 + kGroups);
     HIP_TRY(hipMemcpyAsync(h.data(), hr, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    stream_wait(s);
     t.n_u = h[0];
     t.n_w = h[1];
     t.n_x = h[2];
@@ -899,7 +899,7 @@ static void bh_lists_rows(Tree& t, const Targets& tg, double theta, int nrows, i
     int32_t h[2];
     HIP_TRY(hipMemcpyAsync(&h[0], a_off + nrows, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&h[1], b_off + nrows, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    stream_wait(s);
     n_a = h[0];
     n_b = h[1];
     a_items = A.up<int32_t>(std::max<int64_t>(n_a, 1));
@@ -1035,7 +1035,7 @@ void build_fmmlist_treecode_lists(Tree& t, bool fill_far, hipStream_t s) {
     LAUNCH_CHECK();
     unsigned long long h[2];
     HIP_TRY(hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    stream_wait(s);
     if (h[0] > (unsigned long long)INT32_MAX || h[1] > (unsigned long long)INT32_MAX)
         throw Status{HFMM_E_UNSUPPORTED};  // list offsets are int32
     t.n_a = (int64_t)h[0];

@@ -250,7 +250,7 @@ Targets bin_targets(Tree& t, const double* tx, const double* ty, const double* t
     scan_exclusive_i32(flag, bidx, n, A, s);
     int32_t nbox = 0;
     HIP_TRY(hipMemcpyAsync(&nbox, bidx + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    stream_wait(s);
     TBox* box = A.up<TBox>(std::max(nbox, 1));
     int32_t* end = A.down<int32_t>(std::max(nbox, 1));
     hipLaunchKernelGGL(k_tbox_write, dim3(grid_for(n, 256)), dim3(256), 0, s, g, flag, bidx, n,

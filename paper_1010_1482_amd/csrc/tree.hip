@@ -17,7 +17,11 @@ namespace hfmm {
 
 constexpr int kBlock = 256;
 constexpr int kItems = 4;
-constexpr int kTile = kBlock * kItems;  // elements per block in scan / sort
+constexpr int kTile = kBlock * kItems;  // elements per block in a scan
+// radix sort: elements per thread and per block (with 16 per thread a block
+// writes runs of about 16 keys per digit, so the scatter's stores coalesce)
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kBlock * kSortItems;
 
 // ---------------------------------------------------------------------
 // block-level helpers
@@ -149,9 +153,9 @@ __global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
     __shared__ int cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
-    for (int k = 0; k < kItems; ++k) {
+    for (int k = 0; k < kSortItems; ++k) {
         int64_t i = base + (int64_t)k * kBlock + threadIdx.x;
         if (i < n) atomicAdd(&cnt[key_digit(keys[i], shift, bits)], 1);
     }
@@ -171,13 +175,13 @@ k_radix_scatter(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vi
     for (int d = threadIdx.x; d < (kBlock / 64) * 256; d += kBlock)
         (&wcount[0][0])[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)w * (64 * kItems);
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (64 * kSortItems);
     const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    uint64_t key[kItems];
-    int32_t val[kItems];
-    int dig[kItems], rank[kItems];
+    uint64_t key[kSortItems];
+    int32_t val[kSortItems];
+    int dig[kSortItems], rank[kSortItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         int64_t i = base + (int64_t)r * 64 + lane;
         bool ok = i < n;
         key[r] = ok ? kin[i] : 0ull;
@@ -211,7 +215,7 @@ k_radix_scatter(const uint64_t* __restrict__ kin, const int32_t* __restrict__ vi
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
+    for (int r = 0; r < kSortItems; ++r) {
         int64_t i = base + (int64_t)r * 64 + lane;
         if (i < n) {
             int d = dig[r];
@@ -236,7 +240,7 @@ void radix_sort_pairs(const uint64_t* keys, const int32_t* vals, uint64_t* keys_
         }
         return;
     }
-    const int nb = grid_for(n, kTile);
+    const int nb = grid_for(n, kSortTile);
     uint64_t* k2 = A.down<uint64_t>(n);
     int32_t* v2 = A.down<int32_t>(n);
     int32_t* hist = A.down<int32_t>((int64_t)256 * nb);
@@ -403,24 +407,30 @@ __device__ inline uint32_t quantise(double v, double b, double s) {
     return (uint32_t)f;
 }
 
+// Keys, the identity permutation, and the positions packed as one 32-byte
+// record per particle: the gather into key order then reads one record at
+// random instead of three coordinates (each a separate cache line).
 __global__ void k_keys(const double* __restrict__ x, const double* __restrict__ y,
                        const double* __restrict__ z, int64_t n, const Root* __restrict__ root,
-                       uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+                       uint64_t* __restrict__ keys, int32_t* __restrict__ idx,
+                       double4* __restrict__ rec) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double s = root->scale;
-    uint32_t qx = quantise(x[i], root->b[0], s);
-    uint32_t qy = quantise(y[i], root->b[1], s);
-    uint32_t qz = quantise(z[i], root->b[2], s);
+    const double a = x[i], b = y[i], c = z[i];
+    uint32_t qx = quantise(a, root->b[0], s);
+    uint32_t qy = quantise(b, root->b[1], s);
+    uint32_t qz = quantise(c, root->b[2], s);
     keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
     idx[i] = (int32_t)i;
+    rec[i] = make_double4(a, b, c, 0.0);
 }
 
 // Sorted FP64 positions, and FP32 positions relative to the centre of the
 // particle's leaf for the near field: a pair separation is then rounded
-// relative to the cell size instead of to |x|.
-__global__ void k_gather_positions(const double* __restrict__ x, const double* __restrict__ y,
-                                   const double* __restrict__ z, int64_t n,
+// relative to the cell size instead of to |x|.  rec: the positions packed
+// by k_keys, in the caller's order.
+__global__ void k_gather_positions(const double4* __restrict__ rec, int64_t n,
                                    const int32_t* __restrict__ perm,
                                    const Cell* __restrict__ cells,
                                    const int32_t* __restrict__ leaf_of,
@@ -429,8 +439,8 @@ __global__ void k_gather_positions(const double* __restrict__ x, const double* _
                                    float4* __restrict__ p32) {
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    int64_t i = perm[s];
-    double a = x[i], b = y[i], c = z[i];
+    const double4 r = rec[perm[s]];
+    const double a = r.x, b = r.y, c = r.z;
     xs[s] = a;
     ys[s] = b;
     zs[s] = c;
@@ -704,6 +714,7 @@ __global__ void k_census_reduce(const int32_t* __restrict__ part, int nblocks,
     }
     const int l = threadIdx.x & 31, g = threadIdx.x >> 5;  // 8 groups of 32
     int acc = 0;
+#pragma unroll 8
     for (int b = g; b < nblocks; b += 8) {
         const int v = part[(int64_t)b * 32 + l];
         acc = l == 31 ? max(acc, v) : acc + v;
@@ -727,11 +738,21 @@ __global__ void k_refit(const double* __restrict__ x, const double* __restrict__
                         const int32_t* __restrict__ leaf_of, const Root* __restrict__ root,
                         double slack, double* __restrict__ xs, double* __restrict__ ys,
                         double* __restrict__ zs, float4* __restrict__ p32,
-                        int32_t* __restrict__ moved) {
+                        int32_t* __restrict__ moved, const double4* __restrict__ rec) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
-    const double a = x[i], b = y[i], c = z[i];
+    double a, b, c;
+    if (rec) {
+        const double4 r = rec[i];
+        a = r.x;
+        b = r.y;
+        c = r.z;
+    } else {
+        a = x[i];
+        b = y[i];
+        c = z[i];
+    }
     xs[s] = a;
     ys[s] = b;
     zs[s] = c;
@@ -747,16 +768,35 @@ __global__ void k_refit(const double* __restrict__ x, const double* __restrict__
     if (!within_cell(r, cl, slack, a, b, c)) *moved = 1;
 }
 
+// positions packed as one 32-byte record per particle (caller's order)
+__global__ void k_pack_xyz(const double* __restrict__ x, const double* __restrict__ y,
+                           const double* __restrict__ z, int64_t n, double4* __restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rec[i] = make_double4(x[i], y[i], z[i], 0.0);
+}
+
 bool refit_tree(Tree& t, const double* x, const double* y, const double* z, double slack,
                 hipStream_t s) {
+    Arena& A = t.arena;
+    A.release_temps();
     HIP_TRY(hipMemsetAsync(t.moved, 0, sizeof(int32_t), s));
+    // with room in the arena the positions are packed first (one record
+    // read at random per particle instead of three coordinates)
+    double4* rec = nullptr;
+    if (A.free_bytes() >= Arena::align(sizeof(double4) * t.n + 1)) {
+        rec = A.down<double4>(t.n);
+        hipLaunchKernelGGL(k_pack_xyz, dim3(grid_for(t.n, 256)), dim3(256), 0, s, x, y, z, t.n,
+                           rec);
+        LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_refit, dim3(grid_for(t.n, 256)), dim3(256), 0, s, x, y, z, t.n,
                        t.perm, t.cells, t.leaf_of, t.root, slack, t.xs, t.ys, t.zs, t.p32,
-                       t.moved);
+                       t.moved, (const double4*)rec);
     LAUNCH_CHECK();
+    A.release_temps();
     int32_t h = 1;
     HIP_TRY(hipMemcpyAsync(&h, t.moved, sizeof(h), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    stream_wait(s);
     return h == 0;
 }
 
@@ -811,6 +851,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     // keys, sort (top bits first; a full sort if the tree turns out deeper)
     uint64_t* k0 = A.down<uint64_t>(n);
     int32_t* i0 = A.down<int32_t>(n);
+    double4* rec = A.down<double4>(n);
     // census: split cells per level (0..20) and the re-sort flag (31)
     int32_t* census = A.down<int32_t>(32);
     // per level: start of the level's cells (lev[l]) and its splitting cells
@@ -823,11 +864,11 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     int sorted_levels = sort_levels_guess(n, t.leaf_max);
     const size_t hi_mark = A.hi;
     int32_t cen_h[32];
-    const int ncb = std::min(512, grid_for(n, 256));  // census blocks
+    const int ncb = std::min(256, grid_for(n, 256));  // census blocks
     for (int attempt = 0;; ++attempt) {
         if (attempt > 1) throw Status{HFMM_E_STATE};
         hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n, t.root,
-                           k0, i0);
+                           k0, i0, rec);
         LAUNCH_CHECK();
         const int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
         radix_sort_pairs(k0, i0, t.keys, t.perm, n, lo_bit, 63, A, s);
@@ -840,7 +881,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
         LAUNCH_CHECK();
         // the one read back before the levels (with the root)
         HIP_TRY(hipMemcpyAsync(cen_h, census, sizeof(cen_h), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        stream_wait(s);
         A.hi = hi_mark;
         if (t.root_h.nbad) throw Status{HFMM_E_DATA};  // also in the status word
         t.sort_bits = 63 - lo_bit;
@@ -883,7 +924,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     int32_t rec_h[kRec] = {0, 1};
     if (depth > 0) {
         HIP_TRY(hipMemcpyAsync(rec_h, levrec, sizeof(rec_h), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        stream_wait(s);
     }
     const int32_t* lev_h = rec_h;
     const int32_t* nsplit_h = rec_h + kLev;
@@ -912,7 +953,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
                        t.cells, t.ncells, lpos, t.leaves, t.leaf_of, t.leaf_boxes,
                        t.leaf_box_of);
     LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_gather_positions, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n,
+    hipLaunchKernelGGL(k_gather_positions, dim3(grid_for(n, 256)), dim3(256), 0, s, rec, n,
                        t.perm, t.cells, t.leaf_of, t.root, t.xs, t.ys, t.zs, t.p32);
     LAUNCH_CHECK();
     A.release_temps();
