@@ -23,6 +23,7 @@
  * finite-difference test.  OpenMP only parallelises loops over independent
  * outputs; it never changes the order of a sum.
  */
+#define _POSIX_C_SOURCE 199309L /* clock_gettime under -std=c99 */
 #include "hfmm_oracle.h"
 
 #include <complex.h>
@@ -1016,7 +1017,7 @@ int64_t oracle_bh_lists(otree* t, const double* m, double theta, int which,
         ivec acc = {0}, near = {0};
         bh_group(t, com, theta, (int)b, 0, &acc, &near);
         ivec* L = which == 0 ? &acc : &near;
-        if (items) memcpy(items + tot, L->v, sizeof(int32_t) * L->n);
+        if (items && L->n) memcpy(items + tot, L->v, sizeof(int32_t) * L->n);
         tot += L->n;
         free(acc.v);
         free(near.v);
