@@ -1000,40 +1000,47 @@ __device__ inline double m2l_entry(int ro, int ri, const double (*pt)[kNmax],
     return pi == 0 ? cp.y + cm.y : cp.x - cm.x;
 }
 
-// One block per offset class (343 blocks, 27 of them adjacent offsets that
-// stay zero).  The block tabulates, for this class, the Sec. 5.2 quantity
-// (N-|M|)! P_N^|M|(cos a) / rho^{N+1} for N <= 2p-2 (Eqs. 7-9) and
-// cos(M b), sin(M b) in LDS, then threads fill the real entries.  Writes the
-// FP64 layout T64[cls][ri][ro] and/or the FP32 matrix-core layout
-// Tsw[cls][rb][q][lane][4] with T[16 rb + (lane & 15)][16 q + 4 (lane >> 4) + r].
+// gridDim.y blocks per offset class (343 classes, 27 of them adjacent
+// offsets that stay zero).  Each block tabulates, for its class, the Sec. 5.2
+// quantity (N-|M|)! P_N^|M|(cos a) / rho^{N+1} for N <= 2p-2 (Eqs. 7-9) and
+// cos(M b), sin(M b) in LDS, then its threads fill a share of the real
+// entries in the order they are stored (consecutive threads, consecutive
+// addresses; the padding is written as zeros).  Layouts: FP64
+// T64[cls][ri][ro], or the matrix-core chunks [cls][rb][q][lane][E] holding
+// T[16 rb + (lane & 15)][KS q + 4 r + (lane >> 4)] at element r.
 __global__ void __launch_bounds__(256)
 k_m2l_ops(int p, int layout, void* __restrict__ T, int RB, int KQ) {
     // layout 0: FP64 [class][ri][ro] (vector units); 1: FP32 matrix-core
-    // chunks, contraction element ri = 16 q + 4 r + g at lane group g,
-    // product r; 2: FP64 matrix-core chunks, ri = 8 q + 4 r + g.  The r-major
-    // order puts the padding of the last block into whole products, which
-    // the kernel skips.
+    // chunks (E = 4, KS = 16); 2: FP64 matrix-core chunks (E = 2, KS = 8).
+    // The r-major order puts the padding of the last block into whole
+    // products, which the kernel skips.
     __shared__ double pt[kNmax][kNmax];
     __shared__ double cs[kNmax][2];
     const int P = p * p;
     const int cls = blockIdx.x;
     const bool far = m2l_class_table(p, cls, pt, cs);
     const int64_t per = (int64_t)P * P;
-    for (int64_t e = threadIdx.x; e < per; e += blockDim.x) {
-        const int ro = (int)(e / P), ri = (int)(e % P);
-        const double val = far ? m2l_entry(ro, ri, pt, cs) : 0.0;
-        const int rb = ro / 16, il = ro % 16;
-        if (layout == 0) {
-            ((double*)T)[(int64_t)cls * per + (int64_t)ri * P + ro] = val;
-        } else if (layout == 1) {
-            const int q = ri / 16, g = (ri % 16) % 4, r = (ri % 16) / 4;
-            const int lane = g * 16 + il;
-            ((float*)T)[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 4 + r] = (float)val;
-        } else {
-            const int q = ri / 8, g = (ri % 8) % 4, r = (ri % 8) / 4;
-            const int lane = g * 16 + il;
-            ((double*)T)[((((int64_t)cls * RB + rb) * KQ + q) * 64 + lane) * 2 + r] = val;
+    const int64_t step = (int64_t)gridDim.y * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (layout == 0) {
+        for (int64_t e = first; e < per; e += step) {
+            const int ri = (int)(e / P), ro = (int)(e % P);
+            ((double*)T)[(int64_t)cls * per + e] = far ? m2l_entry(ro, ri, pt, cs) : 0.0;
         }
+        return;
+    }
+    const int E = layout == 1 ? 4 : 2, KS = layout == 1 ? 16 : 8;
+    const int64_t tot = (int64_t)RB * KQ * 64 * E;
+    for (int64_t o = first; o < tot; o += step) {
+        const int r = (int)(o % E);
+        const int64_t u = o / E;
+        const int lane = (int)(u % 64), q = (int)((u / 64) % KQ), rb = (int)(u / (64 * KQ));
+        const int ro = 16 * rb + (lane & 15), ri = KS * q + 4 * r + (lane >> 4);
+        const double val = (far && ro < P && ri < P) ? m2l_entry(ro, ri, pt, cs) : 0.0;
+        if (layout == 1)
+            ((float*)T)[(int64_t)cls * tot + o] = (float)val;
+        else
+            ((double*)T)[(int64_t)cls * tot + o] = val;
     }
 }
 
@@ -1239,7 +1246,10 @@ void run_m2m(Tree& t, int p, hipStream_t s) {
 }
 
 void run_m2l_ops(Tree& t, int p, int layout, void* T, int RB, int KQ, hipStream_t s) {
-    hipLaunchKernelGGL(k_m2l_ops, dim3(343), dim3(256), 0, s, p, layout, T, RB, KQ);
+    // several blocks per class for the larger tables (each recomputes the
+    // class's small Legendre table)
+    const int split = p >= 6 ? 4 : 1;
+    hipLaunchKernelGGL(k_m2l_ops, dim3(343, split), dim3(256), 0, s, p, layout, T, RB, KQ);
     LAUNCH_CHECK();
 }
 

@@ -829,9 +829,7 @@ void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s) {
     if (precision == HFMM_FP64 && !m2l_uses_mfma(p, precision)) {
         run_m2l_ops(t, p, 0, t.T, 0, 0, s);
     } else if (precision == HFMM_FP64) {
-        // the kernel fills the p^2 x p^2 block; the padding must read as zero
-        HIP_TRY(hipMemsetAsync(t.T, 0, bytes, s));
-        run_m2l_ops(t, p, 2, t.T, RB, KQ, s);
+        run_m2l_ops(t, p, 2, t.T, RB, KQ, s);  // (padding written as zeros)
     } else if (!m2l_uses_mfma(p, precision)) {
         const int64_t nn = (int64_t)343 * p * p * p * p;
         double* tmp = t.arena.down<double>(nn);
@@ -847,9 +845,7 @@ void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s) {
         HIP_TRY(hipMemsetAsync(t.bexp, 0x80, 64 * sizeof(int32_t), s));
         run_m2l_ops_lp(p, precision, RB, KQ, t.bexp, hi, lo, s);
     } else {
-        // the kernel fills the p^2 x p^2 block; the padding must read as zero
-        HIP_TRY(hipMemsetAsync(t.T, 0, bytes, s));
-        run_m2l_ops(t, p, 1, t.T, RB, KQ, s);
+        run_m2l_ops(t, p, 1, t.T, RB, KQ, s);  // (padding written as zeros)
     }
     t.ops_p = p;
     t.ops_prec = precision;
