@@ -203,6 +203,59 @@ k_m2m_f64(const Cell* __restrict__ cells, int c0, int ntargets,
     }
 }
 
+// M2M for levels with few parents: block (x, rb) takes 16 parents and only
+// the output rows 16 rb .. 16 rb + 15, so that a level of a few hundred
+// parents still spreads over the GPU (the whole-row kernel above would run
+// one long block per 16 parents).  Same products in the same order, so the
+// same bits.
+template <int RB, int KQ>
+__global__ void __launch_bounds__(512)
+k_m2m_f64_rows(const Cell* __restrict__ cells, int c0, int ntargets,
+               const double* __restrict__ Tsw, double* __restrict__ M, int ld, int zero_row) {
+    constexpr int NTE = RB * KQ * 64;
+    constexpr int LDR = 17;
+    __shared__ double red[16 * LDR];
+    const int rb = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, col = lane & 15;
+    const int ti = blockIdx.x * 16 + col;
+    const int tgt = ti < ntargets ? c0 + ti : -1;
+    int src = -1;
+    if (tgt >= 0) src = child_by_octant(cells[tgt], wave);
+    doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+    if (__ballot(src >= 0)) {
+        const double4* A = (const double4*)Tsw + (int64_t)wave * NTE;
+        const double* B = M + (int64_t)(src >= 0 ? src : zero_row) * ld + 4 * g;
+        for (int q = 0; q < KQ; ++q) {
+            if (!block_live<0>(rb, q)) continue;
+            const double4 b = *(const double4*)(B + 16 * q);
+            const double4 a = A[(rb * KQ + q) * 64 + lane];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.z, b.z, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.w, b.w, acc, 0, 0, 0);
+        }
+    }
+    for (int w = 0; w < 8; ++w) {
+        if (wave == w) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double* d = &red[col * LDR + 4 * r + g];  // f64 16x16x4 output layout
+                *d = (w == 0 ? 0.0 : *d) + acc[r];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 256) {
+        const int c = threadIdx.x >> 4, row = threadIdx.x & 15;
+        const int t = blockIdx.x * 16 + c;
+        if (t < ntargets) {
+            const int cell = c0 + t;
+            if (cells[cell].nchild != 0) M[(int64_t)cell * ld + 16 * rb + row] = red[c * LDR + row];
+        }
+    }
+}
+
 // L2L: a block of 4 waves takes 64 children (16 per wave, listed grouped by
 // octant); out = L2L(parent) + sum of the M2L partial results (+ P2L),
 // combined through LDS so that the partials are read along whole rows.
@@ -336,13 +389,90 @@ void run_m2m_mfma(Tree& t, int p, hipStream_t s) {
     for (int l = t.depth - 1; l >= 0; --l) {
         const int c0 = t.level_start[l], c1 = t.level_start[l + 1];
         const int nt = c1 - c0;
-        dim3 grid((nt + 15) / 16), block(512);
+        // few parents: one block per 16 parents and output row block
+        const bool rows = nt < 2048;
+        dim3 grid((nt + 15) / 16, rows ? RB : 1), block(512);
 #define M2M_CASE(R)                                                                        \
-    hipLaunchKernelGGL((k_m2m_f64<R, R>), grid, block, 0, s, t.cells, c0, nt, t.xl_m2m, t.M, \
-                       t.ldm, t.ncells);
+    if (rows)                                                                              \
+        hipLaunchKernelGGL((k_m2m_f64_rows<R, R>), grid, block, 0, s, t.cells, c0, nt,     \
+                           t.xl_m2m, t.M, t.ldm, t.ncells);                                \
+    else                                                                                   \
+        hipLaunchKernelGGL((k_m2m_f64<R, R>), grid, block, 0, s, t.cells, c0, nt, t.xl_m2m, \
+                           t.M, t.ldm, t.ncells);
         HFMM_DISPATCH_RB16(RB, M2M_CASE);
 #undef M2M_CASE
         LAUNCH_CHECK();
+    }
+}
+
+// L2L for levels with few children: block (x, rb) takes 64 children and only
+// the output rows 16 rb .. 16 rb + 15 (the same products and sums, in the
+// same order, as the whole-row kernel above).
+template <int RB, int KQ, typename TB>
+__global__ void __launch_bounds__(256)
+k_l2l_f64_rows(const Cell* __restrict__ cells, const int32_t* __restrict__ targets,
+               int ntargets, int with_parent, const double* __restrict__ Tsw,
+               double* __restrict__ L, int ld, int zero_row, const TB* __restrict__ parts,
+               int nparts, int64_t part_stride, const double* __restrict__ lx, int P,
+               const int32_t* __restrict__ bexp, const int32_t* __restrict__ levexp,
+               int level) {
+    constexpr int NTE = RB * KQ * 64;
+    constexpr int LDR = 17;
+    __shared__ double red[64 * LDR];
+    __shared__ int scell[64];
+    const int rb = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, col = lane & 15;
+    const int ti = blockIdx.x * 64 + wave * 16 + col;
+    const int tgt = ti < ntargets ? targets[ti] : -1;
+    int src = -1, cls = 0;
+    if (tgt >= 0 && with_parent) {
+        const Cell tc = cells[tgt];
+        cls = octant_of_cell(tc);
+        src = tc.parent;
+    }
+    doublex4 acc = doublex4{0.0, 0.0, 0.0, 0.0};
+    uint64_t todo = __ballot(src >= 0);
+    while (todo) {  // one product per distinct child octant in the wave
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const int c = __shfl(cls, leader, 64);
+        const bool mine = src >= 0 && cls == c;
+        todo &= ~__ballot(mine);
+        doublex4 part = doublex4{0.0, 0.0, 0.0, 0.0};
+        const double4* A = (const double4*)Tsw + (int64_t)c * NTE;
+        const double* B = L + (int64_t)(mine ? src : zero_row) * ld + 4 * g;
+        for (int q = 0; q < KQ; ++q) {
+            if (!block_live<1>(rb, q)) continue;
+            const double4 b = *(const double4*)(B + 16 * q);
+            const double4 a = A[(rb * KQ + q) * 64 + lane];
+            part = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f64_16x16x4f64(a.z, b.z, part, 0, 0, 0);
+            part = __builtin_amdgcn_mfma_f64_16x16x4f64(a.w, b.w, part, 0, 0, 0);
+        }
+        if (mine) acc += part;
+    }
+    const int lc = wave * 16 + col;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[lc * LDR + 4 * r + g] = acc[r];
+    if (g == 0) scell[lc] = tgt;
+    __syncthreads();
+    // epilogue: thread -> elements threadIdx.x + 256 k of the 64 x 16 block
+    const int sc_lev = bexp ? level_exp(levexp, level) + 2 : 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = k * 256 + threadIdx.x;
+        const int c = e >> 4, row = 16 * rb + (e & 15);
+        const int cell = scell[c];
+        if (cell < 0) continue;
+        const int64_t off = (int64_t)cell * ld + row;
+        double ps = 0.0;
+        for (int q = 0; q < nparts; ++q) ps += (double)parts[(int64_t)q * part_stride + off];
+        double v = ps;
+        if (bexp && row < P) v = ldexp(v, bexp[isqrt_c(row)] + sc_lev);
+        v += red[c * LDR + (e & 15)];
+        if (lx) v += lx[off];
+        L[off] = v;
     }
 }
 
@@ -354,10 +484,22 @@ void run_l2l_mfma(Tree& t, int p, const void* parts, bool parts_fp64, int nparts
         const int i0 = t.m2l_level_start[l], i1 = t.m2l_level_start[l + 1];
         const int nt = i1 - i0;
         if (nt == 0) continue;
-        dim3 grid((nt + 63) / 64), block(256);
+        // few children: one block per 64 children and output row block
+        const bool rows = nt < 8192;
+        dim3 grid((nt + 63) / 64, rows ? RB : 1), block(256);
         const int wp = l >= 3 ? 1 : 0;
 #define L2L_CASE(R)                                                                         \
-    if (parts_fp64)                                                                         \
+    if (rows && parts_fp64)                                                                 \
+        hipLaunchKernelGGL((k_l2l_f64_rows<R, R, double>), grid, block, 0, s, t.cells,       \
+                           t.m2l_order + i0, nt, wp, t.xl_l2l, t.L, t.ldm, t.ncells,         \
+                           (const double*)parts, nparts, part_stride, LX, p * p, bexp,      \
+                           levexp, l);                                                      \
+    else if (rows)                                                                          \
+        hipLaunchKernelGGL((k_l2l_f64_rows<R, R, float>), grid, block, 0, s, t.cells,        \
+                           t.m2l_order + i0, nt, wp, t.xl_l2l, t.L, t.ldm, t.ncells,         \
+                           (const float*)parts, nparts, part_stride, LX, p * p, bexp,       \
+                           levexp, l);                                                      \
+    else if (parts_fp64)                                                                    \
         hipLaunchKernelGGL((k_l2l_f64<R, R, double>), grid, block, 0, s, t.cells,            \
                            t.m2l_order + i0, nt, wp, t.xl_l2l, t.L, t.ldm, t.ncells,         \
                            (const double*)parts, nparts, part_stride, LX, p * p, bexp,      \
