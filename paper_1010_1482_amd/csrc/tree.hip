@@ -583,18 +583,23 @@ __global__ void k_leaf_flags(const Cell* __restrict__ cells, int nc, int32_t* __
 
 // leaves in cell order; per sorted particle its leaf cell and leaf index;
 // per leaf its box of the self-evaluation (the leaf's own particles)
-// (one wave per cell: the lanes fill the leaf's particle range)
+// (one wave per 64 cells: lane i writes the record of leaf cell 64 w + i,
+// then the wave fills the particle range of each of its leaves in turn,
+// the lanes over the particles)
 __global__ void k_leaf_compact(const Cell* __restrict__ cells, int nc,
                                const int32_t* __restrict__ pos, int32_t* __restrict__ leaves,
                                int32_t* __restrict__ leaf_of, TBox* __restrict__ boxes,
                                int32_t* __restrict__ box_of) {
-    const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
-    if (c >= nc) return;
-    const Cell cell = cells[c];
-    if (cell.nchild != 0) return;
-    const int li = pos[c];
-    if (lane == 0) {
+    const int c = w * 64 + lane;
+    if (w * 64 >= nc) return;  // uniform per wave
+    Cell cell;
+    cell.nchild = 1;
+    if (c < nc) cell = cells[c];
+    const bool leaf = c < nc && cell.nchild == 0;
+    const int li = leaf ? pos[c] : 0;
+    if (leaf) {
         leaves[li] = c;
         TBox b;
         b.first = cell.first;
@@ -607,11 +612,19 @@ __global__ void k_leaf_compact(const Cell* __restrict__ cells, int nc,
         b.kind = 0;
         boxes[li] = b;
     }
-    for (int s = cell.first + lane; s < cell.first + cell.count; s += 64) {
-        leaf_of[s] = c;
-        box_of[s] = li;
+    uint64_t todo = __ballot(leaf);
+    while (todo) {
+        const int j = __ffsll((unsigned long long)todo) - 1;
+        todo &= todo - 1;
+        const int first = __shfl(cell.first, j, 64), count = __shfl(cell.count, j, 64);
+        const int lj = __shfl(li, j, 64), cj = w * 64 + j;
+        for (int s = first + lane; s < first + count; s += 64) {
+            leaf_of[s] = cj;
+            box_of[s] = lj;
+        }
     }
 }
+
 
 // Exclusive scan of the children counts of one level's cells, one block
 // of 1024 threads looping over the level: pos[0..m] (pos[m] = total), the
@@ -657,6 +670,82 @@ k_level_scan(const int32_t* __restrict__ nz, int32_t* __restrict__ lev, int leve
         pos[m] = carry_s;
         lev[level + 2] = lev[level + 1] + carry_s;
         nsplit[level] = split_s;
+    }
+}
+
+// The same scan over several blocks, for levels with many cells (clustered
+// data): per tile of kTile counts a partial sum and a split count, one block
+// scans the partials, and each tile then scans its counts.  part holds
+// 2 (nb + 1) entries: sums, then split counts.
+__global__ void k_lscan_part(const int32_t* __restrict__ nz, const int32_t* __restrict__ lev,
+                             int level, int cap, int32_t* __restrict__ part, int nb) {
+    const int m = min(lev[level + 1] - lev[level], cap);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int s = 0, c = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * kItems + k;
+        const int v = i < m ? nz[i] : 0;
+        s += v;
+        c += v > 0;
+    }
+    int tot, ctot;
+    block_exclusive_scan(s, &tot);
+    block_exclusive_scan(c, &ctot);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = tot;
+        part[nb + 1 + blockIdx.x] = ctot;
+    }
+}
+
+__global__ void k_lscan_sums(int32_t* __restrict__ part, int nb) {
+    int carry = 0, ccarry = 0;
+    for (int c0 = 0; c0 < nb; c0 += kBlock) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nb ? part[i] : 0;
+        const int w = i < nb ? part[nb + 1 + i] : 0;
+        int tot, ctot;
+        const int ex = block_exclusive_scan(v, &tot);
+        block_exclusive_scan(w, &ctot);
+        if (i < nb) part[i] = carry + ex;
+        carry += tot;
+        ccarry += ctot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[nb] = carry;
+        part[2 * nb + 1] = ccarry;
+    }
+}
+
+__global__ void k_lscan_blocks(const int32_t* __restrict__ nz, int32_t* __restrict__ lev,
+                               int level, int cap, const int32_t* __restrict__ part, int nb,
+                               int32_t* __restrict__ pos, int32_t* __restrict__ nsplit,
+                               int32_t* __restrict__ flag) {
+    const int mraw = lev[level + 1] - lev[level];
+    const int m = min(mraw, cap);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int v[kItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * kItems + k;
+        v[k] = i < m ? nz[i] : 0;
+        s += v[k];
+    }
+    int tot;
+    int ex = block_exclusive_scan(s, &tot) + part[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+        const int64_t i = base + (int64_t)threadIdx.x * kItems + k;
+        if (i < m) pos[i] = ex;
+        ex += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (mraw > cap) *flag = 1;
+        pos[m] = part[nb];
+        lev[level + 2] = lev[level + 1] + part[nb];
+        nsplit[level] = part[2 * nb + 1];
     }
 }
 
@@ -908,14 +997,27 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     int32_t* nz = A.down<int32_t>(bound_max + 1);
     int32_t* pos = A.down<int32_t>(bound_max + 1);
     int32_t* bnd = A.down<int32_t>((size_t)bound_max * 8);
+    int32_t* lpart = A.down<int32_t>(2 * ((size_t)grid_for(bound_max, kTile) + 1));
     for (int l = 0; l < depth; ++l) {
         const int64_t cells_l = l == 0 ? 1 : 8 * (int64_t)cen_h[l - 1];
         hipLaunchKernelGGL(k_split_find, dim3(grid_for(cells_l * 64, 1024)), dim3(1024), 0, s,
                            t.cells, lev, l, t.leaf_max, sorted_levels, t.keys, nz, bnd, flag);
         LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, nz, lev, l, pos, nsplit,
-                           (int)cells_l, flag);
-        LAUNCH_CHECK();
+        if (cells_l <= 16384) {
+            hipLaunchKernelGGL(k_level_scan, dim3(1), dim3(1024), 0, s, nz, lev, l, pos, nsplit,
+                               (int)cells_l, flag);
+            LAUNCH_CHECK();
+        } else {
+            const int nb = grid_for(cells_l, kTile);
+            hipLaunchKernelGGL(k_lscan_part, dim3(nb), dim3(kBlock), 0, s, nz, lev, l,
+                               (int)cells_l, lpart, nb);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_lscan_sums, dim3(1), dim3(kBlock), 0, s, lpart, nb);
+            LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_lscan_blocks, dim3(nb), dim3(kBlock), 0, s, nz, lev, l,
+                               (int)cells_l, lpart, nb, pos, nsplit, flag);
+            LAUNCH_CHECK();
+        }
         hipLaunchKernelGGL(k_split_emit, dim3(grid_for(cells_l, 256)), dim3(256), 0, s, t.cells,
                            lev, l, bnd, pos, bound_total, flag);
         LAUNCH_CHECK();
@@ -949,7 +1051,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     scan_exclusive_i32(f, lpos, t.ncells, A, s);
     t.leaves = A.up<int32_t>(t.nleaves);
     t.leaf_boxes = A.up<TBox>(t.nleaves);
-    hipLaunchKernelGGL(k_leaf_compact, dim3(grid_for((int64_t)t.ncells * 64, 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(k_leaf_compact, dim3(grid_for((int64_t)grid_for(t.ncells, 64) * 64, 256)), dim3(256), 0, s,
                        t.cells, t.ncells, lpos, t.leaves, t.leaf_of, t.leaf_boxes,
                        t.leaf_box_of);
     LAUNCH_CHECK();
