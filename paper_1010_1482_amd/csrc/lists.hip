@@ -99,9 +99,15 @@ __global__ void k_colleagues(const Cell* __restrict__ cells, int c0, int c1,
 // colleagues (child mask and first child) once; each slot then takes the
 // entry of its parent-level offset from the owning lane with a shuffle.
 // Rows of levels 0 and 1 stay empty; cv[c] = number of entries.
+// vcls[c] (0..26) records on which sides of the parent the list has
+// sources: per axis 0 = only above, 1 = both sides (or neither), 2 = only
+// below, the axes' digits in snake order (consecutive values differ on one
+// side of one axis).  Cells with equal values have their sources in the same
+// slab of slots: in a uniform tree the value is the position of the parent
+// against the faces of the domain, which decides every empty slot.
 __global__ void __launch_bounds__(256)
 k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
-        int32_t* __restrict__ vsrc, int32_t* __restrict__ cv) {
+        int32_t* __restrict__ vsrc, int32_t* __restrict__ cv, uint8_t* __restrict__ vcls) {
     const int lane = threadIdx.x & 63;
     const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (c >= nc) return;  // uniform per wave
@@ -109,7 +115,10 @@ k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll
     int32_t* out = vsrc + (int64_t)c * kSlots;
     if (B.level < 2) {
         for (int q = lane; q < kSlots; q += 64) out[q] = -1;
-        if (lane == 0) cv[c] = 0;
+        if (lane == 0) {
+            cv[c] = 0;
+            vcls[c] = 0;
+        }
         return;
     }
     int cm = 0, cch = 0;
@@ -123,6 +132,7 @@ k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll
     }
     const int ox = B.ix & 1, oy = B.iy & 1, oz = B.iz & 1;
     int cnt = 0;
+    uint32_t sides = 0;  // bit 2a: a source below on axis a, bit 2a + 1: above
 #pragma unroll
     for (int s0 = 0; s0 < kSlots; s0 += 64) {
         const int slot = s0 + lane;
@@ -138,8 +148,28 @@ k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll
         const int res = ok && ((m >> o) & 1) ? ch + __popc((unsigned)m & ((1u << o) - 1u)) : -1;
         if (slot < kSlots) out[slot] = res;
         cnt += __popcll(__ballot(res >= 0));
+        if (res >= 0) {
+            const int qa[3] = {(X >> 1) - (B.ix >> 1), (Y >> 1) - (B.iy >> 1),
+                               (Z >> 1) - (B.iz >> 1)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                sides |= (qa[a] < 0 ? 1u : 0u) << (2 * a) | (qa[a] > 0 ? 1u : 0u) << (2 * a + 1);
+        }
     }
-    if (lane == 0) cv[c] = cnt;
+    uint32_t all = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) all |= (__ballot((sides >> b) & 1u) ? 1u : 0u) << b;
+    if (lane == 0) {
+        cv[c] = cnt;
+        int d[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool lo = (all >> (2 * a)) & 1u, hi = (all >> (2 * a + 1)) & 1u;
+            d[a] = lo == hi ? 1 : (hi ? 0 : 2);
+        }
+        const int k1 = d[0] * 3 + ((d[0] & 1) ? 2 - d[1] : d[1]);
+        vcls[c] = (uint8_t)(k1 * 3 + ((k1 & 1) ? 2 - d[2] : d[2]));
+    }
 }
 
 // ---------------------------------------------------------------------
@@ -466,11 +496,13 @@ void build_box_lists(Tree& t, const Targets& tg, int mode, hipStream_t s) {
 // ---------------------------------------------------------------------
 constexpr int kGroups = 8 * (HFMM_KEY_LEVELS + 2);
 
-// keys (level, octant) for the L2L order and (octant, level) for the M2L
-// tiles, with the counts per (level, octant)
-__global__ void k_m2l_keys(const Cell* __restrict__ cells, int c0, int nc,
-                           uint64_t* __restrict__ keys, uint64_t* __restrict__ keys2,
-                           int32_t* __restrict__ vals, int32_t* __restrict__ counts) {
+// keys (level, octant) for the L2L order and (octant, V-list sides) for
+// the M2L tiles (the sort keeps the cells' order, level by level, within
+// one key), with the counts per (level, octant)
+__global__ void k_m2l_keys(const Cell* __restrict__ cells, const uint8_t* __restrict__ vcls,
+                           int c0, int nc, uint64_t* __restrict__ keys,
+                           uint64_t* __restrict__ keys2, int32_t* __restrict__ vals,
+                           int32_t* __restrict__ counts) {
     __shared__ int hist[kGroups];
     for (int k = threadIdx.x; k < kGroups; k += blockDim.x) hist[k] = 0;
     __syncthreads();
@@ -480,7 +512,7 @@ __global__ void k_m2l_keys(const Cell* __restrict__ cells, int c0, int nc,
         Cell B = cells[c];
         int k = B.level * 8 + octant_of(B);
         keys[i] = (uint64_t)k;
-        keys2[i] = (uint64_t)(octant_of(B) * 32 + B.level);
+        keys2[i] = (uint64_t)(octant_of(B) * 27 + vcls[c]);
         vals[i] = c;
         atomicAdd(&hist[k], 1);
     }
@@ -514,8 +546,9 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     int32_t* cnt = A.down<int32_t>(n4);
     int32_t *cu = cnt, *cw = cnt + (nc + 1), *cx = cnt + 2 * (nc + 1), *cv = cnt + 3 * (nc + 1),
             *cf = cnt + 4 * (nc + 1);
+    uint8_t* vcls = A.down<uint8_t>(std::max(nc, 1));
     hipLaunchKernelGGL(k_vlist, dim3(grid_for((int64_t)nc * 64, 256)), dim3(256), 0, s,
-                       t.cells, nc, t.coll, t.vsrc, cv);
+                       t.cells, nc, t.coll, t.vsrc, cv, vcls);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc + 1, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
                        t.cflag, cu, cw, cx, cv, cf, nullptr, nullptr, nullptr, nullptr,
@@ -539,8 +572,8 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     t.m2l_order = A.up<int32_t>(std::max(nm, 1));
     t.m2l_torder = A.up<int32_t>(std::max(nm, 1));
     if (nm > 0) {
-        hipLaunchKernelGGL(k_m2l_keys, dim3(grid_for(nm, 256)), dim3(256), 0, s, t.cells, c2,
-                           nc, mk, mk3, mv, hr + 5);
+        hipLaunchKernelGGL(k_m2l_keys, dim3(grid_for(nm, 256)), dim3(256), 0, s, t.cells,
+                           vcls, c2, nc, mk, mk3, mv, hr + 5);
         LAUNCH_CHECK();
         radix_sort_pairs(mk, mv, mk2, t.m2l_order, nm, 0, 8, A, s);
         radix_sort_pairs(mk3, mv, mk2, t.m2l_torder, nm, 0, 8, A, s);
@@ -574,10 +607,13 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     }
     // M2L tiles: runs of up to 256 targets of one octant, levels mixed (the
     // scaled operators do not depend on the level and every source is read
-    // by index), so only the last tile of an octant is partly filled.  Tiles
-    // are listed as (k, octant) for the k-th tile of each octant: the eight
-    // tiles of one k cover about the same stretch of Morton order and read
-    // nearly the same source expansions.
+    // by index), so only the last tile of an octant is partly filled.  Within
+    // an octant the targets come by the sides of their V-list sources, so
+    // that a tile's targets mostly lack the same slots (a tile skips a slot
+    // only when none of its targets has a source there).  Tiles are listed
+    // as (k, octant) for the k-th tile of each octant: the eight tiles of one
+    // k cover about the same stretch of the order and read nearly the same
+    // source expansions.
     std::vector<int32_t>& tiles = t.m2l_tiles_h;
     tiles.clear();
     int ocount[8] = {0}, ostart[9] = {0};

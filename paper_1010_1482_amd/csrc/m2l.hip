@@ -291,11 +291,22 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
     // Workgroups are handed to the 8 XCDs round-robin; renumber them so that
     // each XCD (own L2) runs one contiguous range of (tile, part), parts
     // fastest: the blocks resident on an XCD then share source expansions.
-    const int nparts = gridDim.y, nb = gridDim.x * nparts;
+    // The ranges run over the tiles taken as 0, 8, 16, ..., 1, 9, ...: the
+    // tiles are listed by (k, octant), so that an XCD gets the tiles of
+    // about one octant, and every octant has the same mix of targets near
+    // and far from the faces (equal work per XCD).
+    const int nparts = gridDim.y, ntiles = gridDim.x, nb = ntiles * nparts;
     const int lin = blockIdx.y * gridDim.x + blockIdx.x;
     const int xcd = lin & 7, q8 = nb >> 3, r8 = nb & 7;
     const int logical = xcd * q8 + min(xcd, r8) + (lin >> 3);
-    const int tile = logical / nparts, part = logical % nparts;
+    const int pos = logical / nparts, part = logical % nparts;
+    int res = 0, base = 0;
+    for (; res < 7; ++res) {
+        const int sz = (ntiles - res + 7) / 8;
+        if (pos < base + sz) break;
+        base += sz;
+    }
+    const int tile = res + 8 * (pos - base);
     const int start = tiles[4 * tile], count = tiles[4 * tile + 1], oct = tiles[4 * tile + 2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, col = lane & 15;
