@@ -239,6 +239,8 @@ struct Tree {
     int32_t* m2l_tiles = nullptr;    // per tile: start into m2l_torder, count, octant
     std::vector<int32_t> m2l_tiles_h;  // host copy (the source of the upload)
     int32_t n_m2l_tiles = 0;
+    uint32_t* m2l_tmask = nullptr;   // per tile: slots with a source (8 words)
+    int32_t* m2l_tpre = nullptr;     // per tile: M2L work items before it (+ total)
     size_t mark_lists = 0;
     // treecode lists (bh_theta = kFmmListTheta: built from the FMM lists)
     double bh_theta = -1.0;

@@ -521,6 +521,41 @@ __global__ void k_m2l_keys(const Cell* __restrict__ cells, const uint8_t* __rest
         if (hist[k]) atomicAdd(&counts[k], hist[k]);
 }
 
+// Per M2L tile: the slots (of 216) in which some target of the tile has a
+// source, bit j % 32 of word j / 32 (8 words, 7 used), and the tile's number
+// of work items, max(1, that many slots).  One block of 256 threads per tile.
+__global__ void __launch_bounds__(256)
+k_tile_masks(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
+             const int32_t* __restrict__ vsrc, uint32_t* __restrict__ tmask,
+             int32_t* __restrict__ items) {
+    __shared__ uint32_t sm[8];
+    const int t = blockIdx.x;
+    const int start = tiles[4 * t], count = tiles[4 * t + 1];
+    if (threadIdx.x < 8) sm[threadIdx.x] = 0u;
+    __syncthreads();
+    if ((int)threadIdx.x < count) {
+        const int4* row = (const int4*)(vsrc + (int64_t)order[start + threadIdx.x] * kSlots);
+        uint32_t bits[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int k = 0; k < kSlots / 4; ++k) {
+            const int4 v = row[k];
+            const uint32_t b4 = (v.x >= 0 ? 1u : 0u) | (v.y >= 0 ? 2u : 0u) |
+                                (v.z >= 0 ? 4u : 0u) | (v.w >= 0 ? 8u : 0u);
+            bits[(4 * k) / 32] |= b4 << ((4 * k) % 32);
+        }
+#pragma unroll
+        for (int w = 0; w < 7; ++w)
+            if (bits[w]) atomicOr(&sm[w], bits[w]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) tmask[8 * t + threadIdx.x] = sm[threadIdx.x];
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int w = 0; w < 7; ++w) n += __popc(sm[w]);
+        items[t] = max(1, n);
+    }
+}
+
 void build_fmm_lists(Tree& t, hipStream_t s) {
     if (t.fmm_lists) return;
     Arena& A = t.arena;
@@ -634,6 +669,16 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     if (!tiles.empty())  // (the host copy lives as long as the tree)
         HIP_TRY(hipMemcpyAsync(t.m2l_tiles, tiles.data(), sizeof(int32_t) * tiles.size(),
                                hipMemcpyHostToDevice, s));
+    // the M2L's work items: slot masks of the tiles and their prefix sums
+    t.m2l_tmask = A.up<uint32_t>((size_t)std::max(t.n_m2l_tiles, 1) * 8);
+    t.m2l_tpre = A.up<int32_t>((size_t)t.n_m2l_tiles + 1);
+    if (t.n_m2l_tiles > 0) {
+        int32_t* titems = A.down<int32_t>(t.n_m2l_tiles);
+        hipLaunchKernelGGL(k_tile_masks, dim3(t.n_m2l_tiles), dim3(256), 0, s, t.m2l_tiles,
+                           t.m2l_torder, t.vsrc, t.m2l_tmask, titems);
+        LAUNCH_CHECK();
+        scan_exclusive_i32(titems, t.m2l_tpre, t.n_m2l_tiles, A, s);
+    }
     A.release_temps();
     t.fmm_lists = true;
     t.mark_lists = A.lo;

@@ -165,9 +165,16 @@ __global__ void k_pack_lp(const Cell* __restrict__ cells, const double* __restri
 
 // ---------------------------------------------------------------------
 // Matrix-core M2L.  Block = 8 waves, tile = up to 256 targets of one
-// octant (levels mixed), 32 per wave (two column blocks of 16).  blockIdx.y
-// selects a contiguous range of slots; each range writes its own partial
-// result, summed later in the downward pass (deterministic, no atomics).
+// octant (levels mixed), 32 per wave (two column blocks of 16).  The work
+// items are the (tile, slot) pairs in which some target of the tile has a
+// source, tile by tile (a tile without any counts as one item, which writes
+// zeros); tpre[t] is the number of items before tile t.  Block b takes items
+// [b W / NB, (b + 1) W / NB) of the W items, so every block has the same
+// share of the products.  The consecutive items of one tile in one block
+// are a segment; segment k of a tile (k-th block that touches it) writes
+// partial result k, and the tile's last segment writes zeros to the partial
+// results after its own; the downward pass sums them (deterministic, no
+// atomics).
 //
 // Both operands travel in 16-byte chunks: chunk 4 q + g of a row holds the
 // contraction elements that lane group g feeds to step q.  For FP32 a chunk
@@ -267,6 +274,19 @@ struct OpF64 {
     }
 };
 
+// bits of m whose rank among the set bits, counted from `base`, lies in
+// [lo, hi)
+__device__ inline uint32_t m2l_rank_range(uint32_t m, int base, int lo, int hi) {
+    for (int k = base; m && k < lo; ++k) m &= m - 1u;  // drop ranks below lo
+    uint32_t keep = 0u;
+    for (int k = max(base, lo); m && k < hi; ++k) {
+        const uint32_t low = m & (0u - m);
+        keep |= low;
+        m ^= low;
+    }
+    return keep;
+}
+
 typedef __attribute__((address_space(3))) void* lds_ptr;
 typedef const __attribute__((address_space(1))) void* gbl_ptr;
 
@@ -275,11 +295,13 @@ typedef const __attribute__((address_space(1))) void* gbl_ptr;
 // LASTR: rows of the last output block that carry data (p^2 - 16 (RB - 1)).
 template <int RB, int KQ, int CB, bool DB, class Op, int LASTS = Op::S, int LASTR = 16>
 __global__ void __launch_bounds__(1024 / CB)
-k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
-          const int32_t* __restrict__ vsrc, const typename Op::E* __restrict__ Mhi,
-          const typename Op::E* __restrict__ Mlo, int ncells,
-          const typename Op::E* __restrict__ Thi, const typename Op::E* __restrict__ Tlo,
-          typename Op::O* __restrict__ out, int64_t part_stride, int slots_per_part) {
+k_m2l_mma(const int32_t* __restrict__ tiles, const uint32_t* __restrict__ tmask,
+          const int32_t* __restrict__ tpre, int ntiles, int nparts,
+          const int32_t* __restrict__ order, const int32_t* __restrict__ vsrc,
+          const typename Op::E* __restrict__ Mhi, const typename Op::E* __restrict__ Mlo,
+          int ncells, const typename Op::E* __restrict__ Thi,
+          const typename Op::E* __restrict__ Tlo, typename Op::O* __restrict__ out,
+          int64_t part_stride) {
     constexpr int NT = RB * KQ * 64;  // 16-byte chunks of one operator
     constexpr int CPR = 4 * KQ;       // 16-byte chunks per operand row
     constexpr int LDO = 16 * RB;      // output row length (floats)
@@ -287,438 +309,452 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
     constexpr int NW = 16 / CB;       // waves per block (CB column blocks each)
     __shared__ u32x4 sT[NS * NT];
     __shared__ u32x4 sT2[DB ? NS * NT : 1];
-    __shared__ uint32_t smask[8];
     // Workgroups are handed to the 8 XCDs round-robin; renumber them so that
-    // each XCD (own L2) runs one contiguous range of (tile, part), parts
-    // fastest: the blocks resident on an XCD then share source expansions.
-    // The ranges run over the tiles taken as 0, 8, 16, ..., 1, 9, ...: the
-    // tiles are listed by (k, octant), so that an XCD gets the tiles of
-    // about one octant, and every octant has the same mix of targets near
-    // and far from the faces (equal work per XCD).
-    const int nparts = gridDim.y, ntiles = gridDim.x, nb = ntiles * nparts;
-    const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+    // each XCD (own L2) runs one contiguous range of blocks, i.e. of items:
+    // the blocks resident on an XCD then share tiles and source expansions.
+    const int nb = gridDim.x, lin = blockIdx.x;
     const int xcd = lin & 7, q8 = nb >> 3, r8 = nb & 7;
-    const int logical = xcd * q8 + min(xcd, r8) + (lin >> 3);
-    const int pos = logical / nparts, part = logical % nparts;
-    int res = 0, base = 0;
-    for (; res < 7; ++res) {
-        const int sz = (ntiles - res + 7) / 8;
-        if (pos < base + sz) break;
-        base += sz;
+    const int b = xcd * q8 + min(xcd, r8) + (lin >> 3);
+    const int64_t W = tpre[ntiles];
+    int item = (int)((int64_t)b * W / nb);
+    const int iend = (int)((int64_t)(b + 1) * W / nb);
+    int tile = 0;  // the last tile with tpre[tile] <= item
+    {
+        int lo = 0, hi = ntiles;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (tpre[mid] <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        tile = lo;
     }
-    const int tile = res + 8 * (pos - base);
-    const int start = tiles[4 * tile], count = tiles[4 * tile + 1], oct = tiles[4 * tile + 2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, col = lane & 15;
-    const int s0 = part * slots_per_part, ns = min(216, s0 + slots_per_part) - s0;
-    const int ox = (oct >> 2) & 1, oy = (oct >> 1) & 1, oz = oct & 1;
-
-    // slots of this range in which some target of the tile has a source
-    if (threadIdx.x < 8) smask[threadIdx.x] = 0u;
-    __syncthreads();
-    if ((int)threadIdx.x < count) {
-        const int32_t* row = vsrc + (int64_t)order[start + threadIdx.x] * 216 + s0;
-        for (int w = 0; w * 32 < ns; ++w) {
-            uint32_t bits = 0u;
-            const int nb = min(32, ns - 32 * w);
-            for (int j = 0; j < nb; ++j) bits |= (row[32 * w + j] >= 0 ? 1u : 0u) << j;
-            if (bits) atomicOr(&smask[w], bits);
-        }
-    }
-    __syncthreads();
-    // kept in registers: LDS reads would have to wait for the operator copies
-    uint32_t mw[7];
+    constexpr int s0 = 0, ns = 216;
+    for (; item < iend; ++tile) {
+        const int p0 = tpre[tile], p1 = tpre[tile + 1];
+        const int seg_end = min(iend, p1);
+        // segment number: blocks before this one that hold items of the tile
+        const int part = b - (int)((((int64_t)p0 + 1) * nb - 1) / W);
+        const bool last_seg = seg_end == p1;
+        const int start = tiles[4 * tile], count = tiles[4 * tile + 1], oct = tiles[4 * tile + 2];
+        const int ox = (oct >> 2) & 1, oy = (oct >> 1) & 1, oz = oct & 1;
+        // this segment's slots: the tile's slots with sources, ranks
+        // [item - p0, seg_end - p0)
+        uint32_t mw[7];
+        {
+            int base = 0;
 #pragma unroll
-    for (int w = 0; w < 7; ++w) mw[w] = __builtin_amdgcn_readfirstlane(smask[w]);
-    auto next_slot = [&](int j) -> int {  // first active slot >= j, else ns
-#pragma unroll
-        for (int w = 0; w < 7; ++w) {
-            if (j < 32 * w + 32) {
-                const uint32_t b = j > 32 * w ? mw[w] & (~0u << (j - 32 * w)) : mw[w];
-                if (b) return 32 * w + __builtin_ctz(b);
+            for (int w = 0; w < 7; ++w) {
+                const uint32_t m = tmask[8 * tile + w];
+                mw[w] = __builtin_amdgcn_readfirstlane(
+                    m2l_rank_range(m, base, item - p0, seg_end - p0));
+                base += __popc(m);
             }
         }
-        return ns;
-    };
+        item = seg_end;
+        auto next_slot = [&](int j) -> int {  // first active slot >= j, else ns
+#pragma unroll
+            for (int w = 0; w < 7; ++w) {
+                if (j < 32 * w + 32) {
+                    const uint32_t bb = j > 32 * w ? mw[w] & (~0u << (j - 32 * w)) : mw[w];
+                    if (bb) return 32 * w + __builtin_ctz(bb);
+                }
+            }
+            return ns;
+        };
+        // the previous segment's products are done before its buffers are
+        // written again
+        __syncthreads();
 
-    int tgt[CB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        const int i = (wave * CB + cb) * 16 + col;
-        tgt[cb] = i < count ? order[start + i] : -1;
-    }
-    // waves past the tile's last target skip the products (small tiles:
-    // edges and corners of the box, the last tile of a group)
-    const bool busy = wave * CB * 16 < count;
-    typename Op::Acc acc[CB][RB];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = Op::zero();
-
-    const u32x4* Mh = (const u32x4*)Mhi;
-    const u32x4* Ml = (const u32x4*)Mlo;
-    // operator of relative slot jj -> LDS buffer (each wave copies every
-    // NW-th 1-KiB chunk with direct global-to-LDS loads)
-    auto stage = [&](u32x4* buf, int jj) {
-        const int slot = s0 + jj;
-        const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
-        const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
-        const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
-        for (int k = wave; k < RB * KQ; k += NW)
-            __builtin_amdgcn_global_load_lds((gbl_ptr)(th + k * 64 + lane),
-                                             (lds_ptr)(buf + k * 64), 16, 0, 0);
-        if (Op::X3) {
-            const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
-            for (int k = wave; k < RB * KQ; k += NW)
-                __builtin_amdgcn_global_load_lds((gbl_ptr)(tl + k * 64 + lane),
-                                                 (lds_ptr)(buf + NT + k * 64), 16, 0, 0);
-        }
-    };
-    auto load_src = [&](int jj, int (&sv)[CB]) {
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-            sv[cb] = (jj < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + jj] : -1;
-    };
-    // the same, issued unconditionally (a valid row stands in), so that every
-    // call issues CB loads
-    auto load_src_u = [&](int jj, int (&sv)[CB]) {
+        int tgt[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            const bool ok = jj < ns && tgt[cb] >= 0;
-            const int v = vsrc[(int64_t)(tgt[cb] >= 0 ? tgt[cb] : 0) * 216 + s0 +
-                               (jj < ns ? jj : 0)];
-            sv[cb] = ok ? v : -1;
+            const int i = (wave * CB + cb) * 16 + col;
+            tgt[cb] = i < count ? order[start + i] : -1;
         }
-    };
-    auto set_boff = [&](const int (&sv)[CB], int64_t (&boff)[CB]) {
+        // waves past the tile's last target skip the products (small tiles:
+        // edges and corners of the box, the last tile of a group)
+        const bool busy = wave * CB * 16 < count;
+        typename Op::Acc acc[CB][RB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-            boff[cb] = (int64_t)(sv[cb] >= 0 ? sv[cb] : ncells) * CPR + g;
-    };
-    // source chunks of step q live in bh[q]; kM2LAhead steps are in flight
-    // ahead of the matrix cores (registers are only allocated for the live
-    // ones, every index being a constant after unrolling)
-    auto first_chunks = [&](const int (&sv)[CB], int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
-                            u32x4 (&bl)[KQ][CB]) {
-        set_boff(sv, boff);
 #pragma unroll
-        for (int q = 0; q < KQ && q < kM2LAhead; ++q)
+            for (int rb = 0; rb < RB; ++rb) acc[cb][rb] = Op::zero();
+
+        const u32x4* Mh = (const u32x4*)Mhi;
+        const u32x4* Ml = (const u32x4*)Mlo;
+        // operator of relative slot jj -> LDS buffer (each wave copies every
+        // NW-th 1-KiB chunk with direct global-to-LDS loads)
+        auto stage = [&](u32x4* buf, int jj) {
+            const int slot = s0 + jj;
+            const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
+            const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
+            const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
+            for (int k = wave; k < RB * KQ; k += NW)
+                __builtin_amdgcn_global_load_lds((gbl_ptr)(th + k * 64 + lane),
+                                                 (lds_ptr)(buf + k * 64), 16, 0, 0);
+            if (Op::X3) {
+                const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
+                for (int k = wave; k < RB * KQ; k += NW)
+                    __builtin_amdgcn_global_load_lds((gbl_ptr)(tl + k * 64 + lane),
+                                                     (lds_ptr)(buf + NT + k * 64), 16, 0, 0);
+            }
+        };
+        auto load_src = [&](int jj, int (&sv)[CB]) {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                sv[cb] = (jj < ns && tgt[cb] >= 0) ? vsrc[(int64_t)tgt[cb] * 216 + s0 + jj] : -1;
+        };
+        // the same, issued unconditionally (a valid row stands in), so that every
+        // call issues CB loads
+        auto load_src_u = [&](int jj, int (&sv)[CB]) {
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                bh[q][cb] = Mh[boff[cb] + 4 * q];
-                if (Op::X3) bl[q][cb] = Ml[boff[cb] + 4 * q];
+                const bool ok = jj < ns && tgt[cb] >= 0;
+                const int v = vsrc[(int64_t)(tgt[cb] >= 0 ? tgt[cb] : 0) * 216 + s0 +
+                                   (jj < ns ? jj : 0)];
+                sv[cb] = ok ? v : -1;
             }
-    };
-    // The single-product forms (BF16/FP16 x1) and FP32 with one operator
-    // buffer read the A chunks of step q + 1 from LDS while step q runs (kept
-    // there by a scheduling barrier); the other forms load A where it is
-    // used, which schedules better for them (measured on the device).
-    constexpr bool kPinA = Op::S == 1 || (Op::S == 4 && !DB);
-    auto products = [&](const u32x4* buf, const int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
-                        u32x4 (&bl)[KQ][CB]) {
-        u32x4 ah[2][RB], al[2][RB];
-        if (kPinA) {
+        };
+        auto set_boff = [&](const int (&sv)[CB], int64_t (&boff)[CB]) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                ah[0][rb] = buf[rb * KQ * 64 + lane];
-                al[0][rb] = Op::X3 ? buf[NT + rb * KQ * 64 + lane] : ah[0][rb];
-            }
-        }
+            for (int cb = 0; cb < CB; ++cb)
+                boff[cb] = (int64_t)(sv[cb] >= 0 ? sv[cb] : ncells) * CPR + g;
+        };
+        // source chunks of step q live in bh[q]; kM2LAhead steps are in flight
+        // ahead of the matrix cores (registers are only allocated for the live
+        // ones, every index being a constant after unrolling)
+        auto first_chunks = [&](const int (&sv)[CB], int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
+                                u32x4 (&bl)[KQ][CB]) {
+            set_boff(sv, boff);
 #pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-            const int cur = q & 1, nxt = cur ^ 1;
-            if (q + kM2LAhead < KQ) {
+            for (int q = 0; q < KQ && q < kM2LAhead; ++q)
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
-                    bh[q + kM2LAhead][cb] = Mh[boff[cb] + 4 * (q + kM2LAhead)];
-                    if (Op::X3) bl[q + kM2LAhead][cb] = Ml[boff[cb] + 4 * (q + kM2LAhead)];
+                    bh[q][cb] = Mh[boff[cb] + 4 * q];
+                    if (Op::X3) bl[q][cb] = Ml[boff[cb] + 4 * q];
+                }
+        };
+        // The single-product forms (BF16/FP16 x1) and FP32 with one operator
+        // buffer read the A chunks of step q + 1 from LDS while step q runs (kept
+        // there by a scheduling barrier); the other forms load A where it is
+        // used, which schedules better for them (measured on the device).
+        constexpr bool kPinA = Op::S == 1 || (Op::S == 4 && !DB);
+        auto products = [&](const u32x4* buf, const int64_t (&boff)[CB], u32x4 (&bh)[KQ][CB],
+                            u32x4 (&bl)[KQ][CB]) {
+            u32x4 ah[2][RB], al[2][RB];
+            if (kPinA) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    ah[0][rb] = buf[rb * KQ * 64 + lane];
+                    al[0][rb] = Op::X3 ? buf[NT + rb * KQ * 64 + lane] : ah[0][rb];
                 }
             }
-            if (kPinA) {
-                if (q + 1 < KQ) {
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) {
-                        ah[nxt][rb] = buf[(rb * KQ + q + 1) * 64 + lane];
-                        al[nxt][rb] =
-                            Op::X3 ? buf[NT + (rb * KQ + q + 1) * 64 + lane] : ah[nxt][rb];
+            for (int q = 0; q < KQ; ++q) {
+                const int cur = q & 1, nxt = cur ^ 1;
+                if (q + kM2LAhead < KQ) {
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        bh[q + kM2LAhead][cb] = Mh[boff[cb] + 4 * (q + kM2LAhead)];
+                        if (Op::X3) bl[q + kM2LAhead][cb] = Ml[boff[cb] + 4 * (q + kM2LAhead)];
                     }
                 }
-                __builtin_amdgcn_sched_barrier(0);
-            }
+                if (kPinA) {
+                    if (q + 1 < KQ) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                if (!kPinA) {
-                    ah[cur][rb] = buf[(rb * KQ + q) * 64 + lane];
-                    al[cur][rb] = Op::X3 ? buf[NT + (rb * KQ + q) * 64 + lane] : ah[cur][rb];
+                        for (int rb = 0; rb < RB; ++rb) {
+                            ah[nxt][rb] = buf[(rb * KQ + q + 1) * 64 + lane];
+                            al[nxt][rb] =
+                                Op::X3 ? buf[NT + (rb * KQ + q + 1) * 64 + lane] : ah[nxt][rb];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    if (!kPinA) {
+                        ah[cur][rb] = buf[(rb * KQ + q) * 64 + lane];
+                        al[cur][rb] = Op::X3 ? buf[NT + (rb * KQ + q) * 64 + lane] : ah[cur][rb];
+                    }
 #define M2L_STEP(s)                                                                        \
     if (s < Op::S && (q + 1 < KQ || s < LASTS)) {                                          \
         _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                     \
             Op::template mma<(s < Op::S ? s : 0)>(ah[cur][rb], al[cur][rb], bh[q][cb],      \
                                                   bl[q][cb], acc[cb][rb]);                  \
     }
-                M2L_STEP(0)
-                M2L_STEP(1)
-                M2L_STEP(2)
-                M2L_STEP(3)
+                    M2L_STEP(0)
+                    M2L_STEP(1)
+                    M2L_STEP(2)
+                    M2L_STEP(3)
 #undef M2L_STEP
-            }
-        }
-    };
-
-    // Register-staged operators (FP32, FP64 and the split forms).  The
-    // operator of the next active slot is read into registers (each wave its
-    // NPW chunks) while this slot runs, and written to the other LDS buffer
-    // before the slot's barrier (with one buffer: between two barriers after
-    // the products): the compiler then tracks every wait itself.  (A direct global-to-LDS copy
-    // would make it wait for the copy before the first LDS read of the
-    // products, since it cannot tell the two buffers apart.)  The source
-    // chunks run kAhead contraction steps ahead across slot boundaries: the
-    // last steps of a slot request the first chunks of the next one.
-    constexpr int kAhead = KQ < m2l_ahead_staged(Op::X3) ? KQ : m2l_ahead_staged(Op::X3);
-    constexpr int NCH = RB * KQ, NPW = (NCH + NW - 1) / NW;
-    constexpr bool kStaged =
-        Op::S != 1 && (DB || m2l_staged_regs(RB, NPW, NS, CB, sizeof(typename Op::Acc) / 4,
-                                             kAhead) <= 160);
-    // FP32: a last output block with at most 12 rows of data runs as
-    // 4-row products (v_mfma_f32_4x4x1f32, 16 blocks of 4 x 4: a quarter of
-    // a 16 x 16 x 4 product's cycles) instead of a padded 16-row block.
-    // Lane (g, col) feeds row 4 u + (col & 3) of the operator and element
-    // 16 q + 4 r + g of target col; each block (4 lanes of one g) sums over
-    // its own contraction elements, and the four lane groups are added at
-    // the end.
-    constexpr int NQ = (kStaged && std::is_same<Op, OpF32>::value && LASTR <= 12)
-                           ? (LASTR + 3) / 4 : 0;
-    constexpr int RBM = NQ > 0 ? RB - 1 : RB;  // row blocks on 16 x 16 products
-    floatx4 accq[CB][NQ > 0 ? NQ : 1];
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-        for (int u = 0; u < (NQ > 0 ? NQ : 1); ++u) accq[cb][u] = floatx4{0.f, 0.f, 0.f, 0.f};
-    auto load_op = [&](int jj, u32x4 (&r)[NPW][NS]) {
-        const int slot = s0 + jj;
-        const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
-        const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
-        const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
-        const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
-#pragma unroll
-        for (int i = 0; i < NPW; ++i) {
-            const int k = min(wave + NW * i, NCH - 1);
-            r[i][0] = th[k * 64 + lane];
-            if (Op::X3) r[i][NS - 1] = tl[k * 64 + lane];
-        }
-    };
-    // (no branches: the loads would be sunk into a conditional store's
-    // block, i.e. issued just before the store; the waves past the last
-    // chunk write that chunk's bytes again)
-    auto store_op = [&](u32x4* buf, const u32x4 (&r)[NPW][NS]) {
-#pragma unroll
-        for (int i = 0; i < NPW; ++i) {
-            const int k = min(wave + NW * i, NCH - 1);
-            buf[k * 64 + lane] = r[i][0];
-            if (Op::X3) buf[NT + k * 64 + lane] = r[i][NS - 1];
-        }
-    };
-    // products of one slot from operator `buf` and source offsets boff; the
-    // first kAhead chunks arrive in bf, which on return holds the first
-    // chunks of the slot at offsets boffn
-    auto products_db = [&](const u32x4* buf, const int64_t (&boff)[CB],
-                           const int64_t (&boffn)[CB], u32x4 (&bfh)[kAhead][CB],
-                           u32x4 (&bfl)[kAhead][CB]) {
-        u32x4 bh[KQ][CB], bl[KQ][CB];
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                bh[q][cb] = bfh[q][cb];
-                bl[q][cb] = bfl[q][cb];
-            }
-#pragma unroll
-        for (int q = 0; q < KQ; ++q) {
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                if (q + kAhead < KQ) {
-                    bh[q + kAhead][cb] = Mh[boff[cb] + 4 * (q + kAhead)];
-                    if (Op::X3) bl[q + kAhead][cb] = Ml[boff[cb] + 4 * (q + kAhead)];
-                } else {
-                    const int qn = q + kAhead - KQ;
-                    bfh[qn][cb] = Mh[boffn[cb] + 4 * qn];
-                    if (Op::X3) bfl[qn][cb] = Ml[boffn[cb] + 4 * qn];
                 }
             }
-            // keeps the optimiser from sinking the next slot's loads to
-            // their use after the barrier (an empty statement, no wait)
-            if (q + kAhead >= KQ) asm volatile("" ::: "memory");
-            if constexpr (NQ > 0) {
+        };
+
+        // Register-staged operators (FP32, FP64 and the split forms).  The
+        // operator of the next active slot is read into registers (each wave its
+        // NPW chunks) while this slot runs, and written to the other LDS buffer
+        // before the slot's barrier (with one buffer: between two barriers after
+        // the products): the compiler then tracks every wait itself.  (A direct global-to-LDS copy
+        // would make it wait for the copy before the first LDS read of the
+        // products, since it cannot tell the two buffers apart.)  The source
+        // chunks run kAhead contraction steps ahead across slot boundaries: the
+        // last steps of a slot request the first chunks of the next one.
+        constexpr int kAhead = KQ < m2l_ahead_staged(Op::X3) ? KQ : m2l_ahead_staged(Op::X3);
+        constexpr int NCH = RB * KQ, NPW = (NCH + NW - 1) / NW;
+        constexpr bool kStaged =
+            Op::S != 1 && (DB || m2l_staged_regs(RB, NPW, NS, CB, sizeof(typename Op::Acc) / 4,
+                                                 kAhead) <= 160);
+        // FP32: a last output block with at most 12 rows of data runs as
+        // 4-row products (v_mfma_f32_4x4x1f32, 16 blocks of 4 x 4: a quarter of
+        // a 16 x 16 x 4 product's cycles) instead of a padded 16-row block.
+        // Lane (g, col) feeds row 4 u + (col & 3) of the operator and element
+        // 16 q + 4 r + g of target col; each block (4 lanes of one g) sums over
+        // its own contraction elements, and the four lane groups are added at
+        // the end.
+        constexpr int NQ = (kStaged && std::is_same<Op, OpF32>::value && LASTR <= 12)
+                               ? (LASTR + 3) / 4 : 0;
+        constexpr int RBM = NQ > 0 ? RB - 1 : RB;  // row blocks on 16 x 16 products
+        floatx4 accq[CB][NQ > 0 ? NQ : 1];
 #pragma unroll
-                for (int u = 0; u < NQ; ++u) {
-                    const floatx4 aq = __builtin_bit_cast(
-                        floatx4, buf[(RBM * KQ + q) * 64 + 16 * g + 4 * u + (lane & 3)]);
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        if (q + 1 < KQ || r < LASTS) {
+            for (int u = 0; u < (NQ > 0 ? NQ : 1); ++u) accq[cb][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+        auto load_op = [&](int jj, u32x4 (&r)[NPW][NS]) {
+            const int slot = s0 + jj;
+            const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
+            const int cls = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
+            const u32x4* th = (const u32x4*)Thi + (int64_t)cls * NT;
+            const u32x4* tl = (const u32x4*)Tlo + (int64_t)cls * NT;
 #pragma unroll
-                            for (int cb = 0; cb < CB; ++cb)
-                                accq[cb][u] = __builtin_amdgcn_mfma_f32_4x4x1f32(
-                                    aq[r], __builtin_bit_cast(floatx4, bh[q][cb])[r],
-                                    accq[cb][u], 0, 0, 0);
+            for (int i = 0; i < NPW; ++i) {
+                const int k = min(wave + NW * i, NCH - 1);
+                r[i][0] = th[k * 64 + lane];
+                if (Op::X3) r[i][NS - 1] = tl[k * 64 + lane];
+            }
+        };
+        // (no branches: the loads would be sunk into a conditional store's
+        // block, i.e. issued just before the store; the waves past the last
+        // chunk write that chunk's bytes again)
+        auto store_op = [&](u32x4* buf, const u32x4 (&r)[NPW][NS]) {
+#pragma unroll
+            for (int i = 0; i < NPW; ++i) {
+                const int k = min(wave + NW * i, NCH - 1);
+                buf[k * 64 + lane] = r[i][0];
+                if (Op::X3) buf[NT + k * 64 + lane] = r[i][NS - 1];
+            }
+        };
+        // products of one slot from operator `buf` and source offsets boff; the
+        // first kAhead chunks arrive in bf, which on return holds the first
+        // chunks of the slot at offsets boffn
+        auto products_db = [&](const u32x4* buf, const int64_t (&boff)[CB],
+                               const int64_t (&boffn)[CB], u32x4 (&bfh)[kAhead][CB],
+                               u32x4 (&bfl)[kAhead][CB]) {
+            u32x4 bh[KQ][CB], bl[KQ][CB];
+#pragma unroll
+            for (int q = 0; q < kAhead; ++q)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    bh[q][cb] = bfh[q][cb];
+                    bl[q][cb] = bfl[q][cb];
+                }
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) {
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    if (q + kAhead < KQ) {
+                        bh[q + kAhead][cb] = Mh[boff[cb] + 4 * (q + kAhead)];
+                        if (Op::X3) bl[q + kAhead][cb] = Ml[boff[cb] + 4 * (q + kAhead)];
+                    } else {
+                        const int qn = q + kAhead - KQ;
+                        bfh[qn][cb] = Mh[boffn[cb] + 4 * qn];
+                        if (Op::X3) bfl[qn][cb] = Ml[boffn[cb] + 4 * qn];
+                    }
+                }
+                // keeps the optimiser from sinking the next slot's loads to
+                // their use after the barrier (an empty statement, no wait)
+                if (q + kAhead >= KQ) asm volatile("" ::: "memory");
+                if constexpr (NQ > 0) {
+#pragma unroll
+                    for (int u = 0; u < NQ; ++u) {
+                        const floatx4 aq = __builtin_bit_cast(
+                            floatx4, buf[(RBM * KQ + q) * 64 + 16 * g + 4 * u + (lane & 3)]);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            if (q + 1 < KQ || r < LASTS) {
+#pragma unroll
+                                for (int cb = 0; cb < CB; ++cb)
+                                    accq[cb][u] = __builtin_amdgcn_mfma_f32_4x4x1f32(
+                                        aq[r], __builtin_bit_cast(floatx4, bh[q][cb])[r],
+                                        accq[cb][u], 0, 0, 0);
+                            }
                         }
                     }
                 }
-            }
 #pragma unroll
-            for (int rb = 0; rb < RBM; ++rb) {
-                const u32x4 ah = buf[(rb * KQ + q) * 64 + lane];
-                const u32x4 al = Op::X3 ? buf[NT + (rb * KQ + q) * 64 + lane] : ah;
+                for (int rb = 0; rb < RBM; ++rb) {
+                    const u32x4 ah = buf[(rb * KQ + q) * 64 + lane];
+                    const u32x4 al = Op::X3 ? buf[NT + (rb * KQ + q) * 64 + lane] : ah;
 #define M2L_STEP(s)                                                                        \
     if (s < Op::S && (q + 1 < KQ || s < LASTS)) {                                          \
         _Pragma("unroll") for (int cb = 0; cb < CB; ++cb) acc[cb][rb] =                     \
             Op::template mma<(s < Op::S ? s : 0)>(ah, al, bh[q][cb], bl[q][cb], acc[cb][rb]); \
     }
-                M2L_STEP(0)
-                M2L_STEP(1)
-                M2L_STEP(2)
-                M2L_STEP(3)
+                    M2L_STEP(0)
+                    M2L_STEP(1)
+                    M2L_STEP(2)
+                    M2L_STEP(3)
 #undef M2L_STEP
-            }
-            // the step's loads stay in the step (the scheduler would move
-            // them down to their use, shortening the distance ahead)
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    };
-
-    int j = next_slot(0);
-    int src[CB];
-    load_src(j, src);
-    if constexpr (kStaged) {
-        // state at the top of a slot j: its operator in `cur`, its source
-        // offsets in boff and first chunks in flight (bfh/bfl), the source
-        // indices of the next active slot jn in srcn
-        int64_t boff[CB];
-        u32x4 bfh[kAhead][CB], bfl[kAhead][CB];
-        u32x4 opr[NPW][NS];
-        int srcn[CB];
-        int jn = next_slot(j + 1);
-        load_src_u(jn, srcn);
-        set_boff(src, boff);
-#pragma unroll
-        for (int q = 0; q < kAhead; ++q)
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                bfh[q][cb] = Mh[boff[cb] + 4 * q];
-                bfl[q][cb] = Op::X3 ? Ml[boff[cb] + 4 * q] : bfh[q][cb];
-            }
-        if (j < ns) {
-            load_op(j, opr);
-            store_op(sT, opr);
-        }
-        __syncthreads();
-        auto body = [&](const u32x4* cur, u32x4* nxt) {
-            const int jnn = jn < ns ? next_slot(jn + 1) : ns;
-            int srcnn[CB];
-            load_src_u(jnn, srcnn);
-            // unconditional loads (past the last slot, the last slot's
-            // operator again), and every wave runs the products, so that
-            // the number of loads in flight is the same on every path and
-            // each wait covers only the load it is for
-            load_op(jn < ns ? jn : j, opr);
-            __builtin_amdgcn_sched_barrier(0);  // issued here, not at their use
-            int64_t boffn[CB];
-            set_boff(srcn, boffn);
-            products_db(cur, boff, boffn, bfh, bfl);
-            if (!DB) __syncthreads();  // the one buffer is no longer read
-            store_op(nxt, opr);
-            __syncthreads();  // nxt holds slot jn; cur is no longer read
-            j = jn;
-            jn = jnn;
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                boff[cb] = boffn[cb];
-                srcn[cb] = srcnn[cb];
+                }
+                // the step's loads stay in the step (the scheduler would move
+                // them down to their use, shortening the distance ahead)
+                __builtin_amdgcn_sched_barrier(0);
             }
         };
-        // one body per iteration, the buffers swapped by parity (with the
-        // loop unrolled by two, the next slot's first loads would be sunk
-        // past the barrier into the second half)
-        if (DB) {
-            for (int par = 0; j < ns; par ^= 1) body(par ? sT2 : sT, par ? sT : sT2);
-        } else {
-            for (; j < ns;) body(sT, sT);
-        }
-    } else if constexpr (DB) {
-        // single-product forms (short slots): two operator buffers filled
-        // by direct global-to-LDS copies, the next active slot's operator
-        // streaming in while this one is on the matrix cores (the compiler
-        // waits for the copy before the first LDS read, which costs less
-        // here than the register staging's shorter reach ahead); one
-        // barrier per slot
-        if (j < ns) stage(sT, j);
-        while (j < ns) {
-            {
-                int64_t boff[CB];
-                u32x4 bh[KQ][CB], bl[KQ][CB];
-                first_chunks(src, boff, bh, bl);
-                const int jn = next_slot(j + 1);
-                load_src(jn, src);
-                __syncthreads();  // sT holds slot j, sT2 is no longer read
-                if (jn < ns) stage(sT2, jn);
-                if (busy) products(sT, boff, bh, bl);
-                j = jn;
-            }
-            if (j >= ns) break;
-            {
-                int64_t boff[CB];
-                u32x4 bh[KQ][CB], bl[KQ][CB];
-                first_chunks(src, boff, bh, bl);
-                const int jn = next_slot(j + 1);
-                load_src(jn, src);
-                __syncthreads();  // sT2 holds slot j, sT is no longer read
-                if (jn < ns) stage(sT, jn);
-                if (busy) products(sT2, boff, bh, bl);
-                j = jn;
-            }
-        }
-    } else {
-        while (j < ns) {
-            stage(sT, j);
+
+        int j = next_slot(0);
+        int src[CB];
+        load_src(j, src);
+        if constexpr (kStaged) {
+            // state at the top of a slot j: its operator in `cur`, its source
+            // offsets in boff and first chunks in flight (bfh/bfl), the source
+            // indices of the next active slot jn in srcn
             int64_t boff[CB];
-            u32x4 bh[KQ][CB], bl[KQ][CB];
-            first_chunks(src, boff, bh, bl);
-            const int jn = next_slot(j + 1);
-            load_src(jn, src);
-            __syncthreads();  // operator in LDS
-            if (busy) products(sT, boff, bh, bl);
-            __syncthreads();  // LDS free for the next operator
-            j = jn;
+            u32x4 bfh[kAhead][CB], bfl[kAhead][CB];
+            u32x4 opr[NPW][NS];
+            int srcn[CB];
+            int jn = next_slot(j + 1);
+            load_src_u(jn, srcn);
+            set_boff(src, boff);
+#pragma unroll
+            for (int q = 0; q < kAhead; ++q)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    bfh[q][cb] = Mh[boff[cb] + 4 * q];
+                    bfl[q][cb] = Op::X3 ? Ml[boff[cb] + 4 * q] : bfh[q][cb];
+                }
+            if (j < ns) {
+                load_op(j, opr);
+                store_op(sT, opr);
+            }
+            __syncthreads();
+            auto body = [&](const u32x4* cur, u32x4* nxt) {
+                const int jnn = jn < ns ? next_slot(jn + 1) : ns;
+                int srcnn[CB];
+                load_src_u(jnn, srcnn);
+                // unconditional loads (past the last slot, the last slot's
+                // operator again), and every wave runs the products, so that
+                // the number of loads in flight is the same on every path and
+                // each wait covers only the load it is for
+                load_op(jn < ns ? jn : j, opr);
+                __builtin_amdgcn_sched_barrier(0);  // issued here, not at their use
+                int64_t boffn[CB];
+                set_boff(srcn, boffn);
+                products_db(cur, boff, boffn, bfh, bfl);
+                if (!DB) __syncthreads();  // the one buffer is no longer read
+                store_op(nxt, opr);
+                __syncthreads();  // nxt holds slot jn; cur is no longer read
+                j = jn;
+                jn = jnn;
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    boff[cb] = boffn[cb];
+                    srcn[cb] = srcnn[cb];
+                }
+            };
+            // one body per iteration, the buffers swapped by parity (with the
+            // loop unrolled by two, the next slot's first loads would be sunk
+            // past the barrier into the second half)
+            if (DB) {
+                for (int par = 0; j < ns; par ^= 1) body(par ? sT2 : sT, par ? sT : sT2);
+            } else {
+                for (; j < ns;) body(sT, sT);
+            }
+        } else if constexpr (DB) {
+            // single-product forms (short slots): two operator buffers filled
+            // by direct global-to-LDS copies, the next active slot's operator
+            // streaming in while this one is on the matrix cores (the compiler
+            // waits for the copy before the first LDS read, which costs less
+            // here than the register staging's shorter reach ahead); one
+            // barrier per slot
+            if (j < ns) stage(sT, j);
+            while (j < ns) {
+                {
+                    int64_t boff[CB];
+                    u32x4 bh[KQ][CB], bl[KQ][CB];
+                    first_chunks(src, boff, bh, bl);
+                    const int jn = next_slot(j + 1);
+                    load_src(jn, src);
+                    __syncthreads();  // sT holds slot j, sT2 is no longer read
+                    if (jn < ns) stage(sT2, jn);
+                    if (busy) products(sT, boff, bh, bl);
+                    j = jn;
+                }
+                if (j >= ns) break;
+                {
+                    int64_t boff[CB];
+                    u32x4 bh[KQ][CB], bl[KQ][CB];
+                    first_chunks(src, boff, bh, bl);
+                    const int jn = next_slot(j + 1);
+                    load_src(jn, src);
+                    __syncthreads();  // sT2 holds slot j, sT is no longer read
+                    if (jn < ns) stage(sT, jn);
+                    if (busy) products(sT2, boff, bh, bl);
+                    j = jn;
+                }
+            }
+        } else {
+            while (j < ns) {
+                stage(sT, j);
+                int64_t boff[CB];
+                u32x4 bh[KQ][CB], bl[KQ][CB];
+                first_chunks(src, boff, bh, bl);
+                const int jn = next_slot(j + 1);
+                load_src(jn, src);
+                __syncthreads();  // operator in LDS
+                if (busy) products(sT, boff, bh, bl);
+                __syncthreads();  // LDS free for the next operator
+                j = jn;
+            }
         }
-    }
-    if constexpr (NQ > 0) {
-        // sum the four lane groups; lane group g keeps rows 4 g .. 4 g + 3
-        // of the last block (the 16 x 16 layout the store expects)
+        if constexpr (NQ > 0) {
+            // sum the four lane groups; lane group g keeps rows 4 g .. 4 g + 3
+            // of the last block (the 16 x 16 layout the store expects)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int u = 0; u < NQ; ++u) {
+                    floatx4 t = accq[cb][u];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        t[i] += __shfl_xor(t[i], 16, 64);
+                        t[i] += __shfl_xor(t[i], 32, 64);
+                    }
+                    if (g == u) v = t;
+                }
+                acc[cb][RB - 1] = v;
+            }
+        }
+        // output block (rb) of column col: the rows this lane holds; the last
+        // segment of the tile clears the partial results after its own
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
-            floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (tgt[cb] < 0) continue;
+            typename Op::O* o = out + part * part_stride + (int64_t)tgt[cb] * LDO;
 #pragma unroll
-            for (int u = 0; u < NQ; ++u) {
-                floatx4 t = accq[cb][u];
+            for (int rb = 0; rb < RB; ++rb) Op::store(o, rb, g, acc[cb][rb]);
+            if (last_seg)
+                for (int q = part + 1; q < nparts; ++q) {
+                    o += part_stride;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    t[i] += __shfl_xor(t[i], 16, 64);
-                    t[i] += __shfl_xor(t[i], 32, 64);
+                    for (int rb = 0; rb < RB; ++rb) Op::store(o, rb, g, Op::zero());
                 }
-                if (g == u) v = t;
-            }
-            acc[cb][RB - 1] = v;
         }
-    }
-    // output block (rb) of column col: the rows this lane holds
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        if (tgt[cb] < 0) continue;
-        typename Op::O* o = out + part * part_stride + (int64_t)tgt[cb] * LDO;
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) Op::store(o, rb, g, acc[cb][rb]);
     }
 }
 
@@ -906,32 +942,32 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     }
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
+    // Blocks and partial results.  The W work items (tile slots with a
+    // source, at least one per tile) number at least n_v / 256, since a slot
+    // of a tile covers at most 256 V pairs; blocks get at least m = floor(W_lb
+    // / NB) items each, so a tile's at most 216 items fall into at most
+    // 1 + ceil(215 / m) blocks, the number of partial results.  One block
+    // per CU (two when the operator buffers take at most 80 KiB of LDS),
+    // fewer when the partial results would exceed max_parts.
     const int ntiles = t.n_m2l_tiles;
-    int parts = std::max(1, std::min(max_parts, (2048 + ntiles - 1) / std::max(ntiles, 1)));
-    {
-        // Blocks run one (two when the operator buffers take at most 80 KiB
-        // of LDS) per CU; among parts .. parts + 4 take the count whose last
-        // round of blocks is the fullest (the tail leaves CUs idle).
-        const int lds_kb = (m2l_double_buffer(RB, KQ, is_x3(precision) ? 2 : 1) ? 2 : 1) *
-                           (is_x3(precision) ? 2 : 1) * RB * KQ;
-        const int slots = m2l_cus(t.device) * (lds_kb <= 80 ? 2 : 1);
-        double best = -1.0;
-        int bp = parts;
-        for (int q = parts; q <= std::min(max_parts, parts + 4); ++q) {
-            const int sq = (216 + q - 1) / q, qq = (216 + sq - 1) / sq;
-            const double rounds = (double)ntiles * qq / slots;
-            const double fill = rounds / std::ceil(rounds);
-            if (fill > best + 1e-9) {
-                best = fill;
-                bp = qq;
-            }
-        }
-        parts = bp;
+    if (ntiles == 0) {
+        part_stride = 0;
+        return 0;
     }
-    const int spp = (216 + parts - 1) / parts;
-    parts = (216 + spp - 1) / spp;
+    const int lds_kb = (m2l_double_buffer(RB, KQ, is_x3(precision) ? 2 : 1) ? 2 : 1) *
+                       (is_x3(precision) ? 2 : 1) * RB * KQ;
+    const int64_t w_lb = std::max<int64_t>(ntiles, (t.n_v + 255) / 256);
+    int nb = m2l_cus(t.device) * (lds_kb <= 80 ? 2 : 1);
+    if (max_parts <= 1) {
+        nb = 1;
+    } else {
+        const int m_min = (215 + max_parts - 2) / (max_parts - 1);
+        nb = (int)std::max<int64_t>(1, std::min<int64_t>(nb, w_lb / m_min));
+    }
+    const int m_lb = (int)(w_lb / nb);
+    const int parts = std::min(nb, 1 + (215 + m_lb - 1) / m_lb);
     part_stride = (int64_t)t.ncells * t.ldm;
-    dim3 grid(ntiles, parts), block(1024 / kM2LCB);
+    dim3 grid(nb), block(1024 / kM2LCB);
     if (precision == HFMM_FP64) {
         double* Mk = A.down<double>((size_t)(t.ncells + 1) * ld);
         {
@@ -945,10 +981,10 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         constexpr int K = ((PP) * (PP) + 7) / 8;                                              \
         constexpr int LS = ((PP) * (PP) - 8 * (K - 1) + 3) / 4;                               \
         hipLaunchKernelGGL((k_m2l_mma<R, K, kM2LCB, m2l_double_buffer(R, K, 1), OpF64, LS>),  \
-                           grid, block, 0, s,                                                 \
-                           t.m2l_tiles, t.m2l_torder, t.vsrc, (const double*)Mk,              \
+                           grid, block, 0, s, t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles,  \
+                           parts, t.m2l_torder, t.vsrc, (const double*)Mk,                    \
                            (const double*)nullptr, t.ncells, (const double*)t.T,              \
-                           (const double*)nullptr, (double*)out, part_stride, spp);           \
+                           (const double*)nullptr, (double*)out, part_stride);                \
     }
         switch (p) {
             case 1: MFMA64_CASE(1); break;
@@ -982,10 +1018,10 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         constexpr int LR = (PP) * (PP) - 16 * (R - 1);                                       \
         hipLaunchKernelGGL((k_m2l_mma<R, R, kM2LCB, m2l_double_buffer(R, R, 1), OpF32, LS,   \
                                       LR>),                                                  \
-                           grid, block, 0, s, t.m2l_tiles, t.m2l_torder, t.vsrc,             \
-                           (const float*)Mk, (const float*)nullptr, t.ncells,                \
-                           (const float*)t.T, (const float*)nullptr, (float*)out,            \
-                           part_stride, spp);                                                \
+                           grid, block, 0, s, t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, \
+                           parts, t.m2l_torder, t.vsrc, (const float*)Mk,                    \
+                           (const float*)nullptr, t.ncells, (const float*)t.T,               \
+                           (const float*)nullptr, (float*)out, part_stride);                 \
     }
         HFMM_DISPATCH_P13(p, MFMA_CASE);
 #undef MFMA_CASE
@@ -1016,12 +1052,12 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
 #define LP_CASE(R)                                                                             \
     if (x3)                                                                                    \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 2), OpLow<__bf16, true>>), grid, block, 0, s,    \
-                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
-                           (float*)out, part_stride, spp);                                      \
+                           t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);         \
     else                                                                                       \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 1), OpLow<__bf16, false>>), grid, block, 0, s,   \
-                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
-                           (float*)out, part_stride, spp);
+                           t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);
         HFMM_DISPATCH_RB(RB, LP_CASE);
 #undef LP_CASE
     } else {
@@ -1037,12 +1073,12 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
 #define LP_CASE(R)                                                                             \
     if (x3)                                                                                    \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 2), OpLow<_Float16, true>>), grid, block, 0, s,  \
-                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
-                           (float*)out, part_stride, spp);                                      \
+                           t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);         \
     else                                                                                       \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 1), OpLow<_Float16, false>>), grid, block, 0, s, \
-                           t.m2l_tiles, t.m2l_torder, t.vsrc, mh, ml, t.ncells, th, tl,          \
-                           (float*)out, part_stride, spp);
+                           t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);
         HFMM_DISPATCH_RB(RB, LP_CASE);
 #undef LP_CASE
     }
