@@ -107,7 +107,8 @@ __global__ void k_colleagues(const Cell* __restrict__ cells, int c0, int c1,
 // against the faces of the domain, which decides every empty slot.
 __global__ void __launch_bounds__(256)
 k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
-        int32_t* __restrict__ vsrc, int32_t* __restrict__ cv, uint8_t* __restrict__ vcls) {
+        int32_t* __restrict__ vsrc, int32_t* __restrict__ cv, uint8_t* __restrict__ vcls,
+        uint32_t* __restrict__ vmask) {
     const int lane = threadIdx.x & 63;
     const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (c >= nc) return;  // uniform per wave
@@ -119,6 +120,7 @@ k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll
             cv[c] = 0;
             vcls[c] = 0;
         }
+        if (lane < 8) vmask[(int64_t)c * 8 + lane] = 0u;
         return;
     }
     int cm = 0, cch = 0;
@@ -133,6 +135,7 @@ k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll
     const int ox = B.ix & 1, oy = B.iy & 1, oz = B.iz & 1;
     int cnt = 0;
     uint32_t sides = 0;  // bit 2a: a source below on axis a, bit 2a + 1: above
+    uint64_t occ[4];     // slots with a source, 64 per word
 #pragma unroll
     for (int s0 = 0; s0 < kSlots; s0 += 64) {
         const int slot = s0 + lane;
@@ -147,7 +150,8 @@ k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll
         const int o = ((X & 1) << 2) | ((Y & 1) << 1) | (Z & 1);
         const int res = ok && ((m >> o) & 1) ? ch + __popc((unsigned)m & ((1u << o) - 1u)) : -1;
         if (slot < kSlots) out[slot] = res;
-        cnt += __popcll(__ballot(res >= 0));
+        occ[s0 / 64] = __ballot(res >= 0);
+        cnt += __popcll(occ[s0 / 64]);
         if (res >= 0) {
             const int qa[3] = {(X >> 1) - (B.ix >> 1), (Y >> 1) - (B.iy >> 1),
                                (Z >> 1) - (B.iz >> 1)};
@@ -159,6 +163,10 @@ k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll
     uint32_t all = 0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) all |= (__ballot((sides >> b) & 1u) ? 1u : 0u) << b;
+    if (lane < 8) {
+        const uint64_t o = occ[min(lane >> 1, 3)];
+        vmask[(int64_t)c * 8 + lane] = lane < 7 ? (uint32_t)(o >> (32 * (lane & 1))) : 0u;
+    }
     if (lane == 0) {
         cv[c] = cnt;
         int d[3];
@@ -522,38 +530,38 @@ __global__ void k_m2l_keys(const Cell* __restrict__ cells, const uint8_t* __rest
 }
 
 // Per M2L tile: the slots (of 216) in which some target of the tile has a
-// source, bit j % 32 of word j / 32 (8 words, 7 used), and the tile's number
-// of work items, max(1, that many slots).  One block of 256 threads per tile.
+// source (the OR of the targets' slot masks, bit j % 32 of word j / 32, 8
+// words, 7 used), and the tile's number of work items, max(1, that many
+// slots).  One wave per tile.
 __global__ void __launch_bounds__(256)
-k_tile_masks(const int32_t* __restrict__ tiles, const int32_t* __restrict__ order,
-             const int32_t* __restrict__ vsrc, uint32_t* __restrict__ tmask,
+k_tile_masks(const int32_t* __restrict__ tiles, int ntiles, const int32_t* __restrict__ order,
+             const uint32_t* __restrict__ vmask, uint32_t* __restrict__ tmask,
              int32_t* __restrict__ items) {
-    __shared__ uint32_t sm[8];
-    const int t = blockIdx.x;
+    const int t = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6), lane = threadIdx.x & 63;
+    if (t >= ntiles) return;  // uniform per wave
     const int start = tiles[4 * t], count = tiles[4 * t + 1];
-    if (threadIdx.x < 8) sm[threadIdx.x] = 0u;
-    __syncthreads();
-    if ((int)threadIdx.x < count) {
-        const int4* row = (const int4*)(vsrc + (int64_t)order[start + threadIdx.x] * kSlots);
-        uint32_t bits[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int k = 0; k < kSlots / 4; ++k) {
-            const int4 v = row[k];
-            const uint32_t b4 = (v.x >= 0 ? 1u : 0u) | (v.y >= 0 ? 2u : 0u) |
-                                (v.z >= 0 ? 4u : 0u) | (v.w >= 0 ? 8u : 0u);
-            bits[(4 * k) / 32] |= b4 << ((4 * k) % 32);
-        }
-#pragma unroll
-        for (int w = 0; w < 7; ++w)
-            if (bits[w]) atomicOr(&sm[w], bits[w]);
+    uint32_t m[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    for (int i = lane; i < count; i += 64) {
+        const uint4* r = (const uint4*)(vmask + (int64_t)order[start + i] * 8);
+        const uint4 a = r[0], b = r[1];
+        m[0] |= a.x, m[1] |= a.y, m[2] |= a.z, m[3] |= a.w;
+        m[4] |= b.x, m[5] |= b.y, m[6] |= b.z, m[7] |= b.w;
     }
-    __syncthreads();
-    if (threadIdx.x < 8) tmask[8 * t + threadIdx.x] = sm[threadIdx.x];
-    if (threadIdx.x == 0) {
-        int n = 0;
-        for (int w = 0; w < 7; ++w) n += __popc(sm[w]);
-        items[t] = max(1, n);
+    int n = 0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m[w] |= __shfl_xor(m[w], off, 64);
+        n += __popc(m[w]);
     }
+    if (lane < 8) {
+        uint32_t v = m[0];
+#pragma unroll
+        for (int w = 1; w < 8; ++w)
+            if (lane == w) v = m[w];
+        tmask[8 * t + lane] = v;
+    }
+    if (lane == 0) items[t] = max(1, n);
 }
 
 void build_fmm_lists(Tree& t, hipStream_t s) {
@@ -582,8 +590,9 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     int32_t *cu = cnt, *cw = cnt + (nc + 1), *cx = cnt + 2 * (nc + 1), *cv = cnt + 3 * (nc + 1),
             *cf = cnt + 4 * (nc + 1);
     uint8_t* vcls = A.down<uint8_t>(std::max(nc, 1));
+    uint32_t* vmask = A.down<uint32_t>((size_t)std::max(nc, 1) * 8);
     hipLaunchKernelGGL(k_vlist, dim3(grid_for((int64_t)nc * 64, 256)), dim3(256), 0, s,
-                       t.cells, nc, t.coll, t.vsrc, cv, vcls);
+                       t.cells, nc, t.coll, t.vsrc, cv, vcls, vmask);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc + 1, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
                        t.cflag, cu, cw, cx, cv, cf, nullptr, nullptr, nullptr, nullptr,
@@ -674,8 +683,9 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
     t.m2l_tpre = A.up<int32_t>((size_t)t.n_m2l_tiles + 1);
     if (t.n_m2l_tiles > 0) {
         int32_t* titems = A.down<int32_t>(t.n_m2l_tiles);
-        hipLaunchKernelGGL(k_tile_masks, dim3(t.n_m2l_tiles), dim3(256), 0, s, t.m2l_tiles,
-                           t.m2l_torder, t.vsrc, t.m2l_tmask, titems);
+        hipLaunchKernelGGL(k_tile_masks, dim3(grid_for((int64_t)t.n_m2l_tiles * 64, 256)),
+                           dim3(256), 0, s, t.m2l_tiles, t.n_m2l_tiles, t.m2l_torder, vmask,
+                           t.m2l_tmask, titems);
         LAUNCH_CHECK();
         scan_exclusive_i32(titems, t.m2l_tpre, t.n_m2l_tiles, A, s);
     }
