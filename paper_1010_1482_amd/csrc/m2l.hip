@@ -287,6 +287,71 @@ __device__ inline uint32_t m2l_rank_range(uint32_t m, int base, int lo, int hi) 
     return keep;
 }
 
+// This block's range of work items and the tile of its first item (the
+// items and blocks are described at k_m2l_mma).  Workgroups are handed to
+// the 8 XCDs round-robin; they are renumbered so that each XCD (own L2)
+// runs one contiguous range of blocks, i.e. of items: the blocks resident
+// on an XCD then share tiles and source expansions.
+struct M2lItems {
+    int b, item, iend, tile;
+    int64_t W;
+};
+__device__ inline M2lItems m2l_items(const int32_t* __restrict__ tpre, int ntiles) {
+    M2lItems it;
+    const int nb = gridDim.x, lin = blockIdx.x;
+    const int xcd = lin & 7, q8 = nb >> 3, r8 = nb & 7;
+    it.b = xcd * q8 + min(xcd, r8) + (lin >> 3);
+    it.W = tpre[ntiles];
+    it.item = (int)((int64_t)it.b * it.W / nb);
+    it.iend = (int)((int64_t)(it.b + 1) * it.W / nb);
+    int lo = 0, hi = ntiles;  // the last tile with tpre[tile] <= item
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tpre[mid] <= it.item)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    it.tile = lo;
+    return it;
+}
+
+// The segment of tile it.tile that starts at it.item: its partial-result
+// number (blocks before this one that hold items of the tile), whether it
+// is the tile's last, and its slots (the tile's slots with a source whose
+// ranks fall in the segment) as a mask, the same in every lane.  Moves
+// it.item to the segment's end.
+__device__ inline void m2l_segment(const uint32_t* __restrict__ tmask,
+                                   const int32_t* __restrict__ tpre, M2lItems& it, int& part,
+                                   bool& last, uint32_t (&mw)[7]) {
+    const int nb = gridDim.x;
+    const int p0 = tpre[it.tile], p1 = tpre[it.tile + 1];
+    const int seg_end = min(it.iend, p1);
+    part = it.b - (int)((((int64_t)p0 + 1) * nb - 1) / it.W);
+    last = seg_end == p1;
+    int base = 0;
+#pragma unroll
+    for (int w = 0; w < 7; ++w) {
+        const uint32_t m = tmask[8 * it.tile + w];
+        mw[w] = __builtin_amdgcn_readfirstlane(
+            m2l_rank_range(m, base, it.item - p0, seg_end - p0));
+        base += __popc(m);
+    }
+    it.item = seg_end;
+}
+
+// first slot >= j of the mask, else 216
+__device__ inline int m2l_next_slot(const uint32_t (&mw)[7], int j) {
+#pragma unroll
+    for (int w = 0; w < 7; ++w) {
+        if (j < 32 * w + 32) {
+            const uint32_t bb = j > 32 * w ? mw[w] & (~0u << (j - 32 * w)) : mw[w];
+            if (bb) return 32 * w + __builtin_ctz(bb);
+        }
+    }
+    return 216;
+}
+
 typedef __attribute__((address_space(3))) void* lds_ptr;
 typedef const __attribute__((address_space(1))) void* gbl_ptr;
 
@@ -309,62 +374,19 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const uint32_t* __restrict__ tmask,
     constexpr int NW = 16 / CB;       // waves per block (CB column blocks each)
     __shared__ u32x4 sT[NS * NT];
     __shared__ u32x4 sT2[DB ? NS * NT : 1];
-    // Workgroups are handed to the 8 XCDs round-robin; renumber them so that
-    // each XCD (own L2) runs one contiguous range of blocks, i.e. of items:
-    // the blocks resident on an XCD then share tiles and source expansions.
-    const int nb = gridDim.x, lin = blockIdx.x;
-    const int xcd = lin & 7, q8 = nb >> 3, r8 = nb & 7;
-    const int b = xcd * q8 + min(xcd, r8) + (lin >> 3);
-    const int64_t W = tpre[ntiles];
-    int item = (int)((int64_t)b * W / nb);
-    const int iend = (int)((int64_t)(b + 1) * W / nb);
-    int tile = 0;  // the last tile with tpre[tile] <= item
-    {
-        int lo = 0, hi = ntiles;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (tpre[mid] <= item)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        tile = lo;
-    }
+    M2lItems it = m2l_items(tpre, ntiles);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, col = lane & 15;
     constexpr int s0 = 0, ns = 216;
-    for (; item < iend; ++tile) {
-        const int p0 = tpre[tile], p1 = tpre[tile + 1];
-        const int seg_end = min(iend, p1);
-        // segment number: blocks before this one that hold items of the tile
-        const int part = b - (int)((((int64_t)p0 + 1) * nb - 1) / W);
-        const bool last_seg = seg_end == p1;
+    for (; it.item < it.iend; ++it.tile) {
+        const int tile = it.tile;
+        int part;
+        bool last_seg;
+        uint32_t mw[7];
+        m2l_segment(tmask, tpre, it, part, last_seg, mw);
         const int start = tiles[4 * tile], count = tiles[4 * tile + 1], oct = tiles[4 * tile + 2];
         const int ox = (oct >> 2) & 1, oy = (oct >> 1) & 1, oz = oct & 1;
-        // this segment's slots: the tile's slots with sources, ranks
-        // [item - p0, seg_end - p0)
-        uint32_t mw[7];
-        {
-            int base = 0;
-#pragma unroll
-            for (int w = 0; w < 7; ++w) {
-                const uint32_t m = tmask[8 * tile + w];
-                mw[w] = __builtin_amdgcn_readfirstlane(
-                    m2l_rank_range(m, base, item - p0, seg_end - p0));
-                base += __popc(m);
-            }
-        }
-        item = seg_end;
-        auto next_slot = [&](int j) -> int {  // first active slot >= j, else ns
-#pragma unroll
-            for (int w = 0; w < 7; ++w) {
-                if (j < 32 * w + 32) {
-                    const uint32_t bb = j > 32 * w ? mw[w] & (~0u << (j - 32 * w)) : mw[w];
-                    if (bb) return 32 * w + __builtin_ctz(bb);
-                }
-            }
-            return ns;
-        };
+        auto next_slot = [&](int j) -> int { return m2l_next_slot(mw, j); };
         // the previous segment's products are done before its buffers are
         // written again
         __syncthreads();
