@@ -172,14 +172,18 @@ static void downward_pass(Tree& t, int p, int precision, bool rot, hipStream_t s
     const size_t row = sizeof(double) * t.ldm;
     HIP_TRY(hipMemsetAsync(t.L + (size_t)t.ncells * t.ldm, 0, row, s));
     if (t.depth >= 2) {
-        // M2L partial results
+        // M2L partial results: at most as many as half the free arena holds
+        // (up to 64: small problems spread their few tiles over more blocks),
+        // as many as the launch uses
         const bool mf = !rot && m2l_uses_mfma(p, precision);
-        int max_parts = 12;
+        int max_parts = 64;
         const size_t esz = fp64 ? 8 : 4;
         while (max_parts > 1 &&
                (size_t)max_parts * t.ncells * t.ldm * esz > A.free_bytes() / 2)
             --max_parts;
-        const int parts_cap = mf ? max_parts : 1;
+        int nb_unused = 0;
+        const int parts_cap =
+            mf ? std::max(1, m2l_plan(t, p, precision, max_parts, nb_unused)) : 1;
         void* lm = A.down<char>((size_t)parts_cap * t.ncells * t.ldm * esz);
         int32_t* levexp = A.down<int32_t>(32);
         double* LX = nullptr;
@@ -187,7 +191,7 @@ static void downward_pass(Tree& t, int p, int precision, bool rot, hipStream_t s
         int64_t stride = 0;
         int parts;
         parts = rot ? run_m2l_rot(t, p, precision, lm, stride, s)
-                    : run_m2l(t, p, precision, lm, stride, parts_cap, levexp, s);
+                    : run_m2l(t, p, precision, lm, stride, mf ? max_parts : 1, levexp, s);
         PhaseTimer pt(t, PH_DOWN, s);
         if (LX) {
             HIP_TRY(hipMemsetAsync(LX, 0, row * t.ncells, s));

@@ -38,5 +38,6 @@ void prepare_m2l_ops(Tree& t, int p, int precision, hipStream_t s);
 void prepare_rot_ops(Tree& t, int p, int precision, hipStream_t s);
 int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int max_parts,
             int32_t* levexp, hipStream_t s);
+int m2l_plan(const Tree& t, int p, int precision, int max_parts, int& nb);
 
 }  // namespace hfmm

@@ -304,13 +304,17 @@ __device__ inline M2lItems m2l_items(const int32_t* __restrict__ tpre, int ntile
     it.W = tpre[ntiles];
     it.item = (int)((int64_t)it.b * it.W / nb);
     it.iend = (int)((int64_t)(it.b + 1) * it.W / nb);
-    int lo = 0, hi = ntiles;  // the last tile with tpre[tile] <= item
+    // the last tile with tpre[tile] <= item: a 64-way search, every lane
+    // probing one point of [lo, hi) per round (tpre[lo] <= item < tpre[hi])
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = ntiles;
     while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (tpre[mid] <= it.item)
-            lo = mid;
-        else
-            hi = mid;
+        const int step = (hi - lo + 63) / 64;
+        const int idx = lo + lane * step;
+        const bool le = idx < hi && tpre[idx] <= it.item;
+        const int k = __popcll(__ballot(le));  // lanes 0 .. k-1 (lane 0 always)
+        hi = min(hi, lo + k * step);
+        lo = lo + (k - 1) * step;
     }
     it.tile = lo;
     return it;
@@ -366,7 +370,7 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const uint32_t* __restrict__ tmask,
           const typename Op::E* __restrict__ Mhi, const typename Op::E* __restrict__ Mlo,
           int ncells, const typename Op::E* __restrict__ Thi,
           const typename Op::E* __restrict__ Tlo, typename Op::O* __restrict__ out,
-          int64_t part_stride) {
+          int64_t part_stride, int zero_fill) {
     constexpr int NT = RB * KQ * 64;  // 16-byte chunks of one operator
     constexpr int CPR = 4 * KQ;       // 16-byte chunks per operand row
     constexpr int LDO = 16 * RB;      // output row length (floats)
@@ -762,15 +766,16 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const uint32_t* __restrict__ tmask,
                 acc[cb][RB - 1] = v;
             }
         }
-        // output block (rb) of column col: the rows this lane holds; the last
-        // segment of the tile clears the partial results after its own
+        // output block (rb) of column col: the rows this lane holds; with
+        // zero_fill, the last segment of the tile clears the partial results
+        // after its own (without, k_m2l_sum_parts adds the tile's own ones)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             if (tgt[cb] < 0) continue;
             typename Op::O* o = out + part * part_stride + (int64_t)tgt[cb] * LDO;
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) Op::store(o, rb, g, acc[cb][rb]);
-            if (last_seg)
+            if (last_seg && zero_fill)
                 for (int q = part + 1; q < nparts; ++q) {
                     o += part_stride;
 #pragma unroll
@@ -778,6 +783,48 @@ k_m2l_mma(const int32_t* __restrict__ tiles, const uint32_t* __restrict__ tmask,
                 }
         }
     }
+}
+
+// Many partial results (small problems spread over many blocks): instead of
+// clearing the partial results its segments did not write, each tile's
+// segments 1 .. S-1 are added to partial result 0, in order (S = the blocks
+// that held the tile's items, from the same item ranges as the M2L launch of
+// nb blocks).  Block (t, y) takes elements 4 y .. 4 y + 3 of the rows of tile
+// t's targets, one thread per target, eight partial results in flight.
+template <typename TO>
+__global__ void __launch_bounds__(256)
+k_m2l_sum_parts(const int32_t* __restrict__ tiles, const int32_t* __restrict__ tpre, int nb,
+                const int32_t* __restrict__ order, TO* __restrict__ out, int64_t part_stride,
+                int ldo) {
+    const int t = blockIdx.x;
+    const int64_t W = tpre[gridDim.x];
+    const int p0 = tpre[t], p1 = tpre[t + 1];
+    const int b0 = (int)((((int64_t)p0 + 1) * nb - 1) / W);
+    const int b1 = (int)((((int64_t)p1) * nb - 1) / W);  // block of item p1 - 1
+    const int segs = b1 - b0 + 1;
+    const int start = tiles[4 * t], count = tiles[4 * t + 1];
+    if (segs <= 1 || (int)threadIdx.x >= count) return;
+    const int64_t off = (int64_t)order[start + threadIdx.x] * ldo + 4 * blockIdx.y;
+    double acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = (double)out[off + k];
+    int q = 1;
+    for (; q + 7 < segs; q += 8) {
+        TO v[8][4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[u][k] = out[(q + u) * part_stride + off + k];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] += (double)v[u][k];
+    }
+    for (; q < segs; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] += (double)out[q * part_stride + off + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[off + k] = (TO)acc[k];
 }
 
 // ---------------------------------------------------------------------
@@ -937,6 +984,36 @@ void prepare_rot_ops(Tree& t, int p, int precision, hipStream_t s) {
     t.mark_ops = t.arena.lo;
 }
 
+// Blocks and partial results of the matrix-core M2L.  The W work items
+// (tile slots with a source, at least one per tile) number at least n_v / c,
+// c the largest tile, since a slot of a tile covers at most c V pairs;
+// blocks get at least m = floor(W_lb / NB) items each, so a tile's at most
+// 216 items fall into at most 1 + ceil(215 / m) blocks, the number of partial
+// results.  One block per CU (two when the operator buffers take at most
+// 80 KiB of LDS), fewer when the partial results would exceed max_parts.
+// Returns the number of partial results (0 without M2L targets).
+int m2l_plan(const Tree& t, int p, int precision, int max_parts, int& nb) {
+    const int ntiles = t.n_m2l_tiles;
+    nb = 0;
+    if (t.depth < 2 || ntiles == 0) return 0;
+    int RB, KQ, ld;
+    m2l_layout(p, precision, RB, KQ, ld);
+    const int lds_kb = (m2l_double_buffer(RB, KQ, is_x3(precision) ? 2 : 1) ? 2 : 1) *
+                       (is_x3(precision) ? 2 : 1) * RB * KQ;
+    int cmax = 1;
+    for (int k = 0; k < ntiles; ++k) cmax = std::max(cmax, t.m2l_tiles_h[4 * k + 1]);
+    const int64_t w_lb = std::max<int64_t>(ntiles, (t.n_v + cmax - 1) / cmax);
+    nb = m2l_cus(t.device) * (lds_kb <= 80 ? 2 : 1);
+    if (max_parts <= 1) {
+        nb = 1;
+    } else {
+        const int m_min = (215 + max_parts - 2) / (max_parts - 1);
+        nb = (int)std::max<int64_t>(1, std::min<int64_t>(nb, w_lb / m_min));
+    }
+    const int m_lb = (int)(w_lb / nb);
+    return std::min(nb, 1 + (215 + m_lb - 1) / m_lb);
+}
+
 // Runs M2L for every cell of level >= 2 into `out` (rows of t.ldm); returns
 // the number of partial results (summed in the L2L epilogue) and their
 // stride.  Low precision also fills levexp (per-level monopole exponents).
@@ -964,32 +1041,27 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     }
     int RB, KQ, ld;
     m2l_layout(p, precision, RB, KQ, ld);
-    // Blocks and partial results.  The W work items (tile slots with a
-    // source, at least one per tile) number at least n_v / 256, since a slot
-    // of a tile covers at most 256 V pairs; blocks get at least m = floor(W_lb
-    // / NB) items each, so a tile's at most 216 items fall into at most
-    // 1 + ceil(215 / m) blocks, the number of partial results.  One block
-    // per CU (two when the operator buffers take at most 80 KiB of LDS),
-    // fewer when the partial results would exceed max_parts.
     const int ntiles = t.n_m2l_tiles;
-    if (ntiles == 0) {
+    int nb;
+    const int parts = m2l_plan(t, p, precision, max_parts, nb);
+    if (parts == 0) {
         part_stride = 0;
         return 0;
     }
-    const int lds_kb = (m2l_double_buffer(RB, KQ, is_x3(precision) ? 2 : 1) ? 2 : 1) *
-                       (is_x3(precision) ? 2 : 1) * RB * KQ;
-    const int64_t w_lb = std::max<int64_t>(ntiles, (t.n_v + 255) / 256);
-    int nb = m2l_cus(t.device) * (lds_kb <= 80 ? 2 : 1);
-    if (max_parts <= 1) {
-        nb = 1;
-    } else {
-        const int m_min = (215 + max_parts - 2) / (max_parts - 1);
-        nb = (int)std::max<int64_t>(1, std::min<int64_t>(nb, w_lb / m_min));
-    }
-    const int m_lb = (int)(w_lb / nb);
-    const int parts = std::min(nb, 1 + (215 + m_lb - 1) / m_lb);
     part_stride = (int64_t)t.ncells * t.ldm;
     dim3 grid(nb), block(1024 / kM2LCB);
+    // up to kDirectParts partial results go to the L2L epilogue as they are
+    // (the segments clear the ones they do not write); more are first summed
+    // into the first
+    constexpr int kDirectParts = 4;
+    const int fill = parts <= kDirectParts ? 1 : 0;
+    auto finish = [&](auto* o) -> int {
+        if (fill) return parts;
+        hipLaunchKernelGGL(k_m2l_sum_parts, dim3(ntiles, 4 * RB), dim3(256), 0, s,
+                           t.m2l_tiles, t.m2l_tpre, nb, t.m2l_torder, o, part_stride, 16 * RB);
+        LAUNCH_CHECK();
+        return 1;
+    };
     if (precision == HFMM_FP64) {
         double* Mk = A.down<double>((size_t)(t.ncells + 1) * ld);
         {
@@ -1006,7 +1078,7 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
                            grid, block, 0, s, t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles,  \
                            parts, t.m2l_torder, t.vsrc, (const double*)Mk,                    \
                            (const double*)nullptr, t.ncells, (const double*)t.T,              \
-                           (const double*)nullptr, (double*)out, part_stride);                \
+                           (const double*)nullptr, (double*)out, part_stride, fill);          \
     }
         switch (p) {
             case 1: MFMA64_CASE(1); break;
@@ -1024,7 +1096,7 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
         }
 #undef MFMA64_CASE
         LAUNCH_CHECK();
-        return parts;
+        return finish((double*)out);
     }
     if (!is_lowp(precision)) {
         float* Mk = A.down<float>((size_t)(t.ncells + 1) * ld);
@@ -1043,12 +1115,12 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
                            grid, block, 0, s, t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, \
                            parts, t.m2l_torder, t.vsrc, (const float*)Mk,                    \
                            (const float*)nullptr, t.ncells, (const float*)t.T,               \
-                           (const float*)nullptr, (float*)out, part_stride);                 \
+                           (const float*)nullptr, (float*)out, part_stride, fill);          \
     }
         HFMM_DISPATCH_P13(p, MFMA_CASE);
 #undef MFMA_CASE
         LAUNCH_CHECK();
-        return parts;
+        return finish((float*)out);
     }
     // low precision: per-level scale, packed hi/lo operand, matrix cores
     const bool x3 = is_x3(precision);
@@ -1075,11 +1147,11 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     if (x3)                                                                                    \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 2), OpLow<__bf16, true>>), grid, block, 0, s,    \
                            t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
-                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);         \
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride, fill);   \
     else                                                                                       \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 1), OpLow<__bf16, false>>), grid, block, 0, s,   \
                            t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
-                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride, fill);
         HFMM_DISPATCH_RB(RB, LP_CASE);
 #undef LP_CASE
     } else {
@@ -1096,16 +1168,16 @@ int run_m2l(Tree& t, int p, int precision, void* out, int64_t& part_stride, int 
     if (x3)                                                                                    \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 2), OpLow<_Float16, true>>), grid, block, 0, s,  \
                            t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
-                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);         \
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride, fill);   \
     else                                                                                       \
         hipLaunchKernelGGL((k_m2l_mma<R, (R + 1) / 2, kM2LCB, m2l_double_buffer(R, (R + 1) / 2, 1), OpLow<_Float16, false>>), grid, block, 0, s, \
                            t.m2l_tiles, t.m2l_tmask, t.m2l_tpre, ntiles, parts, t.m2l_torder,    \
-                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride);
+                           t.vsrc, mh, ml, t.ncells, th, tl, (float*)out, part_stride, fill);
         HFMM_DISPATCH_RB(RB, LP_CASE);
 #undef LP_CASE
     }
     LAUNCH_CHECK();
-    return parts;
+    return finish((float*)out);
 }
 
 }  // namespace hfmm

@@ -117,25 +117,35 @@ __device__ __forceinline__ void p2p_packed(const Cell* __restrict__ cells, int s
         }
         int tot;
         const int off = wave_excl_scan(cnt, lane, tot);
-        for (int pb = 0; pb < tot; pb += 64) {
+        // lane's source of the run [pb, pb + 64) of the batch's particles;
+        // the next run's load is issued before the current run's pairs
+        auto fetch = [&](int pb, V& v, T& sx, T& sy, T& sz) {
             int o = wave_run_owner(own, off, cnt, pb, 64, lane);
             const bool ok = pb + lane < tot;
             o = ok ? o : 0;
             const int f = __shfl(first, o, 64), fo = __shfl(off, o, 64);
-            V v = p2p_pad<T>();
+            v = p2p_pad<T>();
             if (REL) {
-                const T sx = __shfl(ox, o, 64), sy = __shfl(oy, o, 64), sz = __shfl(oz, o, 64);
-                if (ok) {
-                    v = P[f + (pb + lane - fo)];
-                    v.x += sx;
-                    v.y += sy;
-                    v.z += sz;
-                }
-            } else if (ok) {
-                v = P[f + (pb + lane - fo)];
+                sx = __shfl(ox, o, 64);
+                sy = __shfl(oy, o, 64);
+                sz = __shfl(oz, o, 64);
             }
+            if (ok) v = P[f + (pb + lane - fo)];
+            if (!ok) sx = sy = sz = T(0);
+        };
+        V v;
+        T sx = T(0), sy = T(0), sz = T(0);
+        if (tot > 0) fetch(0, v, sx, sy, sz);
+        for (int pb = 0; pb < tot; pb += 64) {
+            V cur = v;
+            if (REL) {
+                cur.x += sx;
+                cur.y += sy;
+                cur.z += sz;
+            }
+            if (pb + 64 < tot) fetch(pb + 64, v, sx, sy, sz);
             wave_lds_fence();
-            sh[lane] = v;
+            sh[lane] = cur;
             wave_lds_fence();
             p2p_staged<T, G, SOFT, false>(sh, min(64, tot - pb), g, xi, yi, zi, eps2, phi, ax,
                                           ay, az);
