@@ -21,16 +21,23 @@ namespace hfmm {
 // ZERO: the pair may coincide (r^2 == 0, skipped).  Coincident points share
 // a key, hence a leaf, so only a leaf with itself needs the test.  Across
 // leaves FP64 separations are never 0; FP32 ones can round to 0 for points
-// closer than FP32 resolves at the leaf size, and r^2 is clamped there so
-// that the (then meaningless) pair stays finite.
+// closer than FP32 resolves at the leaf size, and r^2 starts from 1e-24
+// there so that the (then meaningless) pair stays finite: r^2 (+ eps^2) is
+// one chain of fused multiply-adds from that start, which leaves r^2 above
+// 2e-17 unchanged and needs no separate clamp instruction in the loop.
 template <typename T, bool SOFT, bool ZERO>
 __device__ __forceinline__ void pair(T xi, T yi, T zi, const typename Vec4<T>::type& s,
                                      T eps2, T& phi, T& ax, T& ay, T& az) {
     const T dx = s.x - xi, dy = s.y - yi, dz = s.z - zi;
-    T r2 = dx * dx + dy * dy + dz * dz;
-    if (!ZERO && sizeof(T) == 4) r2 = fmaxf(r2, 1e-24f);
-    T rinv = rsqrt_fast(SOFT ? r2 + eps2 : r2);
-    if (ZERO) rinv = r2 > T(0) ? rinv : T(0);
+    T rinv;
+    if (ZERO) {  // the test is on the unsoftened r^2
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        rinv = rsqrt_fast(SOFT ? r2 + eps2 : r2);
+        rinv = r2 > T(0) ? rinv : T(0);
+    } else {
+        const T r0 = SOFT ? eps2 : (sizeof(T) == 4 ? T(1e-24) : T(0));
+        rinv = rsqrt_fast(fma(dx, dx, fma(dy, dy, fma(dz, dz, r0))));
+    }
     const T mr = s.w * rinv;
     phi += mr;
     const T sc = mr * rinv * rinv;
