@@ -216,7 +216,7 @@ __device__ __forceinline__ void p2p_box(const TBox& bx, bool in_list, const Root
 
 // One wave per target box; sources from the box's CSR list row.
 template <typename T, typename O, bool SOFT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 8)
 k_p2p(const Cell* __restrict__ cells, const Root* __restrict__ rootp, Targets tg,
       const int32_t* __restrict__ off, const int32_t* __restrict__ items,
       const typename Vec4<T>::type* __restrict__ P, const T* __restrict__ far, T eps2,
