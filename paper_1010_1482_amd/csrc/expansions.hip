@@ -879,7 +879,7 @@ __device__ __forceinline__ void far3_box(const Cell* __restrict__ cells, int b, 
 // for a box without sources), the V lists of the cells above being read
 // from vsrc.
 template <typename T, bool WALK>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 6)
 k_treecode_far3(const Cell* __restrict__ cells, const Root* __restrict__ root, Targets tg,
                 const double4* __restrict__ cen, const int32_t* __restrict__ off,
                 const int32_t* __restrict__ items, const int32_t* __restrict__ vsrc,
