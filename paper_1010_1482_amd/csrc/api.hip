@@ -375,7 +375,8 @@ static size_t estimate_bytes(int64_t n_src, int64_t n_tgt, int leaf_max, int p, 
     m2l_layout(p, precision, RB, KQ, ld);
     size_t per_particle = 8 + 4 + 24 + 16 + 32 + 4 + 8 + 4 + 8 + 4 * 8 + 64 + 32;
     // M, L, LX (FP64), the M2L operand and the FP32 copy of M for the
-    // far field (FP32), up to twelve M2L partial results
+    // far field (FP32), room for twelve M2L partial results (the launch plans
+    // fewer for large trees, more for small ones when the arena has room)
     size_t per_cell = 32 + 27 * 4 + 216 * 4 + 3 * 4 + 200 + 16 + 32 + (size_t)ld * 8 * 3 +
                       (size_t)ld * 4 * 2 + (size_t)12 * ld * 4 + 64;
     if (method == HFMM_TREECODE) per_cell = 32 + 32 + 32 + (size_t)P * 8 + 512 + 64;
