@@ -955,7 +955,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     int32_t cen_h[32];
     const int ncb = std::min(256, grid_for(n, 256));  // census blocks
     for (int attempt = 0;; ++attempt) {
-        if (attempt > 1) throw Status{HFMM_E_STATE};
+        if (attempt > 2) throw Status{HFMM_E_STATE};
         hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n, t.root,
                            k0, i0, rec);
         LAUNCH_CHECK();
@@ -976,7 +976,11 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
         t.sort_bits = 63 - lo_bit;
         if (cen_h[31]) {  // a cell splits below the sorted digits
             if (sorted_levels >= HFMM_KEY_LEVELS) throw Status{HFMM_E_STATE};
-            sorted_levels = HFMM_KEY_LEVELS;
+            // six more levels (two more 8-bit passes) first: clustered sets
+            // such as a Plummer sphere need a few levels beyond the uniform
+            // guess, seldom all 21
+            sorted_levels = attempt == 0 ? std::min(HFMM_KEY_LEVELS, sorted_levels + 6)
+                                         : HFMM_KEY_LEVELS;
             continue;
         }
         break;
