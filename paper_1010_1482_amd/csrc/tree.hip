@@ -956,9 +956,11 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     const int ncb = std::min(256, grid_for(n, 256));  // census blocks
     for (int attempt = 0;; ++attempt) {
         if (attempt > 2) throw Status{HFMM_E_STATE};
-        hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n, t.root,
-                           k0, i0, rec);
-        LAUNCH_CHECK();
+        if (attempt == 0) {  // (the sort leaves its input keys as they are)
+            hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, z, n,
+                               t.root, k0, i0, rec);
+            LAUNCH_CHECK();
+        }
         const int lo_bit = 3 * (HFMM_KEY_LEVELS - sorted_levels);
         radix_sort_pairs(k0, i0, t.keys, t.perm, n, lo_bit, 63, A, s);
         int32_t* part = A.down<int32_t>((size_t)ncb * 32);
