@@ -381,7 +381,7 @@ k_p2l(const Cell* __restrict__ cells, const int32_t* __restrict__ x_cells,
       const double4* __restrict__ cen, const double4* __restrict__ p64,
       double* __restrict__ LX, int ld) {
     constexpr int P = NP * NP;
-    constexpr int PER = 16384 / (int)sizeof(T) / P;    // particles per chunk (<= 17 KB)
+    constexpr int PER = 8192 / (int)sizeof(T) / P;     // particles per chunk (<= 9 KB)
     constexpr int CH = PER < 64 ? PER : 64;
     constexpr int RS = CH + 1;                         // LDS row stride (bank spread)
     constexpr int KPL = (P + 63) / 64;                 // coefficients per lane
