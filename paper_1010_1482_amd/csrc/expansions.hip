@@ -610,7 +610,7 @@ __device__ inline double4 box_ref(const Root& r, const TBox& bx) {
 // even lists keep one thread per particle, k_treecode_far: there every lane
 // has a target, while a wave per leaf of ~10 particles leaves lanes idle.)
 template <typename T, int NP, typename MT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 6 : 1)
 k_farp(const Root* __restrict__ root, Targets tg, const double4* __restrict__ cen,
        const int32_t* __restrict__ off, const int32_t* __restrict__ items,
        const MT* __restrict__ M, T* __restrict__ far) {
