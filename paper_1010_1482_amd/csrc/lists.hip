@@ -95,7 +95,7 @@ __global__ void k_colleagues(const Cell* __restrict__ cells, int c0, int c1,
     }
 }
 
-// V list by slot, one wave per cell.  Lanes 0..26 fetch the parent's
+// V list by slot, two cells per wave.  27 lanes per cell fetch the parent's
 // colleagues (child mask and first child) once; each slot then takes the
 // entry of its parent-level offset from the owning lane with a shuffle.
 // Rows of levels 0 and 1 stay empty; cv[c] = number of entries.
@@ -109,74 +109,96 @@ __global__ void __launch_bounds__(256)
 k_vlist(const Cell* __restrict__ cells, int nc, const int32_t* __restrict__ coll,
         int32_t* __restrict__ vsrc, int32_t* __restrict__ cv, uint8_t* __restrict__ vcls,
         uint32_t* __restrict__ vmask) {
-    const int lane = threadIdx.x & 63;
-    const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (c >= nc) return;  // uniform per wave
-    const Cell B = cells[c];
-    int32_t* out = vsrc + (int64_t)c * kSlots;
-    if (B.level < 2) {
-        for (int q = lane; q < kSlots; q += 64) out[q] = -1;
-        if (lane == 0) {
-            cv[c] = 0;
-            vcls[c] = 0;
-        }
-        if (lane < 8) vmask[(int64_t)c * 8 + lane] = 0u;
-        return;
-    }
+    // two cells per wave: the dependent loads of both (cell, its parent's
+    // colleagues, their child masks) are in flight together, lanes 32 h ..
+    // 32 h + 26 fetching the colleagues of cell 2 w + h
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    const int w = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int cfirst = 2 * w;
+    if (cfirst >= nc) return;  // uniform per wave
+    const int cmine = cfirst + half;
+    Cell Bm;
+    Bm.level = 0;
+    Bm.parent = -1;
+    if (cmine < nc) Bm = cells[cmine];
     int cm = 0, cch = 0;
-    if (lane < kColl) {
-        const int C = coll[(int64_t)B.parent * kColl + lane];
+    if ((lane & 31) < kColl && cmine < nc && Bm.level >= 2) {
+        const int C = coll[(int64_t)Bm.parent * kColl + (lane & 31)];
         if (C >= 0) {
             const Cell cc = cells[C];
             cm = cc.mask;
             cch = cc.child;
         }
     }
-    const int ox = B.ix & 1, oy = B.iy & 1, oz = B.iz & 1;
-    int cnt = 0;
-    uint32_t sides = 0;  // bit 2a: a source below on axis a, bit 2a + 1: above
-    uint64_t occ[4];     // slots with a source, 64 per word
 #pragma unroll
-    for (int s0 = 0; s0 < kSlots; s0 += 64) {
-        const int slot = s0 + lane;
-        const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy, dz = slot % 6 - 2 - oz;
-        const int X = B.ix + dx, Y = B.iy + dy, Z = B.iz + dz;
-        const bool ok = slot < kSlots && max(abs(dx), max(abs(dy), abs(dz))) > 1 && X >= 0 &&
-                        Y >= 0 && Z >= 0;
-        const int q = ok ? ((X >> 1) - (B.ix >> 1) + 1) * 9 + ((Y >> 1) - (B.iy >> 1) + 1) * 3 +
-                               ((Z >> 1) - (B.iz >> 1) + 1)
-                         : 0;
-        const int m = __shfl(cm, q, 64), ch = __shfl(cch, q, 64);
-        const int o = ((X & 1) << 2) | ((Y & 1) << 1) | (Z & 1);
-        const int res = ok && ((m >> o) & 1) ? ch + __popc((unsigned)m & ((1u << o) - 1u)) : -1;
-        if (slot < kSlots) out[slot] = res;
-        occ[s0 / 64] = __ballot(res >= 0);
-        cnt += __popcll(occ[s0 / 64]);
-        if (res >= 0) {
-            const int qa[3] = {(X >> 1) - (B.ix >> 1), (Y >> 1) - (B.iy >> 1),
-                               (Z >> 1) - (B.iz >> 1)};
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                sides |= (qa[a] < 0 ? 1u : 0u) << (2 * a) | (qa[a] > 0 ? 1u : 0u) << (2 * a + 1);
+    for (int h = 0; h < 2; ++h) {
+        const int c = cfirst + h;
+        if (c >= nc) break;  // uniform
+        Cell B;
+        B.ix = __shfl(Bm.ix, 32 * h, 64);
+        B.iy = __shfl(Bm.iy, 32 * h, 64);
+        B.iz = __shfl(Bm.iz, 32 * h, 64);
+        B.level = (int16_t)__shfl((int)Bm.level, 32 * h, 64);
+        int32_t* out = vsrc + (int64_t)c * kSlots;
+        if (B.level < 2) {
+            for (int q = lane; q < kSlots; q += 64) out[q] = -1;
+            if (lane == 0) {
+                cv[c] = 0;
+                vcls[c] = 0;
+            }
+            if (lane < 8) vmask[(int64_t)c * 8 + lane] = 0u;
+            continue;
         }
-    }
-    uint32_t all = 0;
+        const int ox = B.ix & 1, oy = B.iy & 1, oz = B.iz & 1;
+        int cnt = 0;
+        uint32_t sides = 0;  // bit 2a: a source below on axis a, bit 2a + 1: above
+        uint64_t occ[4];     // slots with a source, 64 per word
 #pragma unroll
-    for (int b = 0; b < 6; ++b) all |= (__ballot((sides >> b) & 1u) ? 1u : 0u) << b;
-    if (lane < 8) {
-        const uint64_t o = occ[min(lane >> 1, 3)];
-        vmask[(int64_t)c * 8 + lane] = lane < 7 ? (uint32_t)(o >> (32 * (lane & 1))) : 0u;
-    }
-    if (lane == 0) {
-        cv[c] = cnt;
-        int d[3];
+        for (int s0 = 0; s0 < kSlots; s0 += 64) {
+            const int slot = s0 + lane;
+            const int dx = slot / 36 - 2 - ox, dy = (slot / 6) % 6 - 2 - oy,
+                      dz = slot % 6 - 2 - oz;
+            const int X = B.ix + dx, Y = B.iy + dy, Z = B.iz + dz;
+            const bool ok = slot < kSlots && max(abs(dx), max(abs(dy), abs(dz))) > 1 &&
+                            X >= 0 && Y >= 0 && Z >= 0;
+            const int q = ok ? ((X >> 1) - (B.ix >> 1) + 1) * 9 +
+                                   ((Y >> 1) - (B.iy >> 1) + 1) * 3 +
+                                   ((Z >> 1) - (B.iz >> 1) + 1)
+                             : 0;
+            const int m = __shfl(cm, 32 * h + q, 64), ch = __shfl(cch, 32 * h + q, 64);
+            const int o = ((X & 1) << 2) | ((Y & 1) << 1) | (Z & 1);
+            const int res =
+                ok && ((m >> o) & 1) ? ch + __popc((unsigned)m & ((1u << o) - 1u)) : -1;
+            if (slot < kSlots) out[slot] = res;
+            occ[s0 / 64] = __ballot(res >= 0);
+            cnt += __popcll(occ[s0 / 64]);
+            if (res >= 0) {
+                const int qa[3] = {(X >> 1) - (B.ix >> 1), (Y >> 1) - (B.iy >> 1),
+                                   (Z >> 1) - (B.iz >> 1)};
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const bool lo = (all >> (2 * a)) & 1u, hi = (all >> (2 * a + 1)) & 1u;
-            d[a] = lo == hi ? 1 : (hi ? 0 : 2);
+                for (int a = 0; a < 3; ++a)
+                    sides |= (qa[a] < 0 ? 1u : 0u) << (2 * a) |
+                             (qa[a] > 0 ? 1u : 0u) << (2 * a + 1);
+            }
         }
-        const int k1 = d[0] * 3 + ((d[0] & 1) ? 2 - d[1] : d[1]);
-        vcls[c] = (uint8_t)(k1 * 3 + ((k1 & 1) ? 2 - d[2] : d[2]));
+        uint32_t all = 0;
+#pragma unroll
+        for (int b = 0; b < 6; ++b) all |= (__ballot((sides >> b) & 1u) ? 1u : 0u) << b;
+        if (lane < 8) {
+            const uint64_t o = occ[min(lane >> 1, 3)];
+            vmask[(int64_t)c * 8 + lane] = lane < 7 ? (uint32_t)(o >> (32 * (lane & 1))) : 0u;
+        }
+        if (lane == 0) {
+            cv[c] = cnt;
+            int d[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const bool lo = (all >> (2 * a)) & 1u, hi = (all >> (2 * a + 1)) & 1u;
+                d[a] = lo == hi ? 1 : (hi ? 0 : 2);
+            }
+            const int k1 = d[0] * 3 + ((d[0] & 1) ? 2 - d[1] : d[1]);
+            vcls[c] = (uint8_t)(k1 * 3 + ((k1 & 1) ? 2 - d[2] : d[2]));
+        }
     }
 }
 
@@ -591,8 +613,8 @@ void build_fmm_lists(Tree& t, hipStream_t s) {
             *cf = cnt + 4 * (nc + 1);
     uint8_t* vcls = A.down<uint8_t>(std::max(nc, 1));
     uint32_t* vmask = A.down<uint32_t>((size_t)std::max(nc, 1) * 8);
-    hipLaunchKernelGGL(k_vlist, dim3(grid_for((int64_t)nc * 64, 256)), dim3(256), 0, s,
-                       t.cells, nc, t.coll, t.vsrc, cv, vcls, vmask);
+    hipLaunchKernelGGL(k_vlist, dim3(grid_for((int64_t)(nc + 1) / 2 * 64, 256)), dim3(256), 0,
+                       s, t.cells, nc, t.coll, t.vsrc, cv, vcls, vmask);
     LAUNCH_CHECK();
     hipLaunchKernelGGL(k_uwx, dim3(grid_for(nc + 1, 64)), dim3(64), 0, s, t.cells, nc, t.coll,
                        t.cflag, cu, cw, cx, cv, cf, nullptr, nullptr, nullptr, nullptr,
